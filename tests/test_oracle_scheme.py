@@ -1,0 +1,278 @@
+"""Scheme-level pins of the oracle: checks (a)-(e), linearisation, conservation,
+symmetry, dense LU and dense Newton tie-outs.  CPU only."""
+import itertools
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import m1_oracle as O
+
+BC2 = [
+    ("periodic", "periodic", "periodic", "periodic"),
+    ("outflow", "reflect", "dirichlet", "outflow"),
+    ("dirichlet", "dirichlet", "reflect", "reflect"),
+]
+
+
+def _lin(p):
+    sch = O.Scheme.from_problem(p)
+    U = O.state_from_problem(p, "U")
+    Un = O.state_from_problem(p, "n")
+    return O.linearize(sch, p["sigma"], p.get("rho_cv"), U, Un, p["dt"])
+
+
+CASES = [((5, 4), bc, src, fs) for bc in BC2 for src in ["none", "coupled_t"] for fs in ["wb", "centered"]]
+CASES += [((3, 4, 3), ("outflow", "periodic", "reflect", "dirichlet", "periodic", "periodic"), src, "wb")
+          for src in ["none", "absorption", "coupled_t"]]
+CASES += [((4, 1), ("outflow", "outflow", "periodic", "periodic"), "none", "wb"),
+          ((1, 3), ("periodic", "periodic", "dirichlet", "outflow"), "absorption", "centered")]
+
+
+@pytest.mark.parametrize("n,bc,src,fs", CASES)
+def test_dense_assembly_and_diagonal_blocks(n, bc, src, fs):
+    p = W.random_problem(n, 7, source=src, flux_source=fs, bc=bc)
+    lin = _lin(p)
+    A = O.assemble_dense(lin)
+    x = np.random.default_rng(2).standard_normal(A.shape[0])
+    assert np.allclose(A @ x, O.apply_operator(lin, x), rtol=1e-15, atol=1e-13)
+    nu, N = lin.sch.nu, int(np.prod(lin.sch.shape))
+    B = O.diagonal_blocks(lin)
+    for i in range(N):
+        rows = [c * N + i for c in range(nu)]
+        assert np.allclose(A[np.ix_(rows, rows)], B[i], rtol=1e-14, atol=1e-14)
+    # block structure: the gas-temperature row couples only to (E, T), and no F row to T
+    nr = lin.sch.nrad
+    if nu > nr:
+        assert np.all(B[:, nr, 1:nr] == 0.0) and np.all(B[:, 1:nr, nr] == 0.0)
+    # with the tensor frozen (Picard) the block is an arrowhead with E as hub
+    lin.sch.linearization = "picard"
+    B = O.diagonal_blocks(lin)
+    for r in range(1, nu):
+        for k in range(1, nu):
+            if r != k:
+                assert np.all(B[:, r, k] == 0.0)
+    lin.sch.linearization = "newton"
+
+
+@pytest.mark.parametrize("n,bc,src,fs", CASES[::3])
+def test_linearisation_is_derivative_of_residual(n, bc, src, fs):
+    """(A v) equals the central difference of R with the coefficients frozen (T^4 included)."""
+    p = W.random_problem(n, 9, source=src, flux_source=fs, bc=bc)
+    lin = _lin(p)
+    U = lin.Ulin
+    v = np.random.default_rng(4).standard_normal(U.shape)
+    h = 1e-5
+    fd = (O.residual(lin, U + h * v) - O.residual(lin, U - h * v)) / (2 * h)
+    Av = O.apply_operator(lin, v)
+    assert np.allclose(fd, Av, rtol=1e-8, atol=1e-8 * np.abs(Av).max())
+
+
+def test_gmres_matches_dense_lu_2d_and_3d():
+    for n, bc, src in [((8, 8), BC2[1], "none"), ((8, 8), BC2[0], "coupled_t"),
+                       ((4, 4, 4), ("periodic",) * 6, "coupled_t"),
+                       ((4, 4, 4), ("outflow", "dirichlet", "reflect", "outflow", "periodic", "periodic"), "absorption")]:
+        p = W.random_problem(n, 3, source=src, bc=bc, dt=5.0)
+        lin = _lin(p)
+        A = O.assemble_dense(lin)
+        b = -O.residual(lin).reshape(-1)
+        x_lu = np.linalg.solve(A, b)
+        res = O.gmres(lambda v: O.apply_operator(lin, v), O.BlockJacobi(lin), b, restart=30, rtol=1e-14)
+        assert res.converged
+        # forward error <= cond(A) * backward error (residual 1e-14)
+        bound = max(1e-12, 10.0 * np.linalg.cond(A) * 1e-14)
+        assert np.linalg.norm(res.x - x_lu) <= bound * np.linalg.norm(x_lu)
+
+
+def test_picard_newton_reaches_the_root_of_the_full_nonlinear_residual():
+    """Dense Newton with the finite-difference Jacobian of the FULL residual
+    (closure re-evaluated) converges to the same root as the frozen-closure iteration."""
+    p = W.random_problem((6, 5), 21, source="coupled_t", bc=BC2[1], dt=2.0, fmax=0.5)
+    sch = O.Scheme.from_problem(p)
+    Un = O.state_from_problem(p, "n")
+    sig, rc = p["sigma"], p["rho_cv"]
+    step = O.implicit_step(sch, sig, rc, Un, p["dt"], rtol=1e-14, newton_rtol=1e-13, newton_max=60)
+    assert step.converged
+
+    def Rfull(u):
+        U = u.reshape(Un.shape)
+        return O.residual(O.linearize(sch, sig, rc, U, Un, p["dt"])).reshape(-1)
+
+    u = Un.reshape(-1).copy()
+    for _ in range(30):
+        r = Rfull(u)
+        if np.linalg.norm(r) < 1e-14:
+            break
+        J = np.zeros((u.size, u.size))
+        for k in range(u.size):
+            h = 1e-7 * max(1.0, abs(u[k]))
+            e = np.zeros(u.size)
+            e[k] = h
+            J[:, k] = (Rfull(u + e) - Rfull(u - e)) / (2 * h)
+        u = u - np.linalg.solve(J, r)
+    assert np.linalg.norm(Rfull(u)) < 1e-12
+    assert np.linalg.norm(u - step.U.reshape(-1)) <= 1e-10 * np.linalg.norm(u)
+
+
+def test_conservation_of_total_energy_periodic():
+    p = W.random_problem((7, 6), 5, source="coupled_t", dt=4.0)
+    lin = _lin(p)
+    x = np.random.default_rng(8).standard_normal(lin.Ulin.shape)
+    Ax = O.apply_operator(lin, x)
+    nr = lin.sch.nrad
+    lhs = Ax[0].sum() + Ax[nr].sum()
+    rhs = x[0].sum() + (p["rho_cv"] * x[nr]).sum()
+    assert lhs == pytest.approx(rhs, rel=1e-12, abs=1e-12)
+    sch = O.Scheme.from_problem(p)
+    Un = O.state_from_problem(p, "n")
+    st = O.implicit_step(sch, p["sigma"], p["rho_cv"], Un, p["dt"], rtol=1e-13)
+    tot = lambda U: U[0].sum() + (p["rho_cv"] * U[nr]).sum()
+    assert tot(st.U) == pytest.approx(tot(Un), rel=1e-11)
+
+
+def test_absorption_removes_exactly_c_sigma_dt_E():
+    p = W.random_problem((6, 6), 6, source="absorption", dt=3.0)
+    sch = O.Scheme.from_problem(p)
+    Un = O.state_from_problem(p, "n")
+    st = O.implicit_step(sch, p["sigma"], None, Un, p["dt"], rtol=1e-13)
+    lost = (p["sigma"] * p["dt"] * st.U[0]).sum()
+    assert st.U[0].sum() == pytest.approx(Un[0].sum() - lost, rel=1e-11)
+
+
+def test_one_dimensional_data_reproduces_the_1d_scheme():
+    """y-invariant data on 3 rows equals the same data on a 1-row periodic grid."""
+    p1 = W.random_problem((9, 1), 12, bc=("outflow", "dirichlet", "periodic", "periodic"), dt=2.0)
+    sch1 = O.Scheme.from_problem(p1)
+    Un1 = O.state_from_problem(p1, "n")
+    Un1[2] = 0.0                                  # no transverse flux
+    st1 = O.implicit_step(sch1, p1["sigma"], None, Un1, 2.0, rtol=1e-14, newton_rtol=1e-13)
+    Un3 = np.repeat(Un1, 3, axis=1)
+    sch3 = O.Scheme.from_problem(p1)
+    sch3.n = (9, 3)
+    sch3.ghost = {1: np.repeat(p1["ghost"][1], 3, axis=1)}
+    st3 = O.implicit_step(sch3, np.repeat(p1["sigma"], 3, axis=0), None, Un3, 2.0, rtol=1e-14, newton_rtol=1e-13)
+    for j in range(3):
+        assert np.allclose(st3.U[:, j], st1.U[:, 0], rtol=1e-11, atol=1e-13)
+
+
+def test_check_a_c_diffusive_gaussian_64():
+    """Diffusive 64x64 Gaussian (sigma dx = 1e3, dt = 100): realisability (a),
+    mirror symmetry, and the discrete diffusion limit (c1) and analytic solution (c2)."""
+    p = W.diffusive_gaussian()
+    sch = O.Scheme.from_problem(p)
+    Un = O.state_from_problem(p, "U")
+    st = O.implicit_step(sch, p["sigma"], None, Un, p["dt"], rtol=1e-10)
+    assert st.converged
+    U = st.U
+    f = np.sqrt(U[1] ** 2 + U[2] ** 2) / U[0]
+    assert f.max() <= 1.0 + 1e-12                              # (a), state level
+    # mirror and transpose symmetry
+    assert np.allclose(U[0], U[0][::-1, :], rtol=1e-9) and np.allclose(U[0], U[0].T, rtol=1e-9)
+    assert np.allclose(U[1], -U[1][:, ::-1], atol=1e-12)
+    # (c1) discrete diffusion limit
+    dE = U[0] - Un[0]
+    Ed = O.discrete_diffusion_step(p["sigma"], Un[0], p["dt"])
+    err1 = np.linalg.norm(dE - (Ed - Un[0])) / np.linalg.norm(Ed - Un[0])
+    assert err1 <= 1e-3
+    # (c2) analytic Gaussian, summed over the periodic images
+    D = 1.0 / (3.0 * 1e3)
+    err2 = _analytic_increment_error(U[0] - Un[0], 64, 8.0, D, p["dt"])
+    assert err2 <= 5e-2
+
+
+def _analytic_increment_error(dE, N, s, D, t, floor=1e-6):
+    x = np.arange(N) + 0.5 - N / 2
+    def gauss(var):
+        tot = 0
+        for ix, iy in itertools.product([-1, 0, 1], repeat=2):
+            r2 = (x[None, :] + ix * N) ** 2 + (x[:, None] + iy * N) ** 2
+            tot = tot + s * s / var * np.exp(-r2 / (2 * var))
+        return tot
+    exact = gauss(s * s + 2 * D * t) - gauss(s * s)
+    return np.linalg.norm(dE - exact) / np.linalg.norm(exact)
+
+
+@pytest.mark.slow
+def test_check_c2_refinement():
+    """The error to the analytic Gaussian falls under 2x refinement (s, N, sigma dx, dt rescaled)."""
+    errs = []
+    for N, s, sig, dt in [(32, 4.0, 2e3, 50.0), (64, 8.0, 1e3, 100.0)]:
+        p = W.diffusive_gaussian(n=(N, N), sigma=sig, width=s, dt=dt)
+        sch = O.Scheme.from_problem(p)
+        Un = O.state_from_problem(p, "U")
+        st = O.implicit_step(sch, p["sigma"], None, Un, dt, rtol=1e-12)
+        errs.append(_analytic_increment_error(st.U[0] - Un[0], N, s, 1 / (3 * sig), dt))
+    assert errs[1] < errs[0] / 2.5
+
+
+def test_check_b_free_streaming_pulse():
+    """sigma = 0, f = 1 along +x: implicit upwind.  Excess centroid moves by c dt, excess is
+    conserved, F = cE is kept and nothing spreads across y.
+
+    At f = 1 both speeds equal c, so lambda- = 0 and the combination E - F/c is carried
+    downwind; for c dt/dx > 1/2 the preconditioned operator on that mode has a spectrum
+    around the origin and GMRES amplifies its rounding.  The exact solution never holds
+    that mode, so the check is made at c dt/dx = 0.4, where the solve reaches 1e-14."""
+    nx, ny, floor, dt = 96, 4, 1e-6, 0.4
+    x = np.arange(nx) + 0.5
+    y = np.arange(ny)
+    prof = np.exp(-((x - 30.0) / 3.0) ** 2)
+    E = floor + prof[None, :] * (1.0 + 0.5 * np.cos(2 * np.pi * y / ny))[:, None]
+    Un = np.stack([E, E.copy(), np.zeros_like(E)])
+    sch = O.Scheme(n=(nx, ny))
+    st = O.implicit_step(sch, np.zeros((ny, nx)), None, Un, dt, rtol=1e-14, newton_rtol=1e-13)
+    U = st.U
+    assert np.allclose(U[1], U[0], rtol=1e-12)                 # F = cE kept
+    assert np.abs(U[2]).max() <= 1e-15                         # no transverse flux
+    f = np.sqrt(U[1] ** 2 + U[2] ** 2) / U[0]
+    assert f.max() <= 1.0 + 1e-12
+    for j in range(ny):
+        e0, e1 = Un[0, j] - floor, U[0, j] - floor
+        assert e1.sum() == pytest.approx(e0.sum(), rel=1e-12)
+        c0 = (x * e0).sum() / e0.sum()
+        c1 = (x * e1).sum() / e1.sum()
+        assert c1 - c0 == pytest.approx(dt, abs=1e-9)
+    # rows keep their own amplitude ratio (no transverse mixing)
+    sel = (U[0, 0] - floor) > 1e-6
+    ratio = (U[0, 1, sel] - floor) / (U[0, 0, sel] - floor)
+    assert np.allclose(ratio, (Un[0, 1, 30] - floor) / (Un[0, 0, 30] - floor), rtol=1e-8)
+
+
+def test_check_e_explicit_limit():
+    """||U_implicit - U_explicit|| = O(dt^2) as dt -> 0 with sigma dx = O(1)."""
+    p = W.random_problem((12, 10), 31, source="coupled_t", sigma_range=(0.1, 1.0),
+                         bc=("periodic",) * 4, fmax=0.5)
+    # the exchange term is stiff (c sigma 4 T^3 / rho c_v up to ~60 here): the dt^2
+    # regime needs dt well below its inverse
+    sch = O.Scheme.from_problem(p)
+    Un = O.state_from_problem(p, "n")
+    diffs = []
+    for k in range(7, 12):
+        dt = 2.0 ** -k
+        st = O.implicit_step(sch, p["sigma"], p["rho_cv"], Un, dt, rtol=1e-14, newton_rtol=1e-14, newton_max=40)
+        ex = O.explicit_step(sch, p["sigma"], p["rho_cv"], Un, dt)
+        diffs.append(np.linalg.norm(st.U - ex))
+    ratios = [diffs[i] / diffs[i + 1] for i in range(len(diffs) - 1)]
+    assert 3.5 < ratios[-1] < 4.5, ratios
+
+
+def test_gmres_fixed_iterations_is_the_krylov_minimiser():
+    """Fixed-iteration GMRES returns the minimiser of ||b - A M^-1 y|| over the Krylov space."""
+    p = W.random_problem((6, 6), 14, bc=BC2[2], dt=4.0)
+    lin = _lin(p)
+    A = O.assemble_dense(lin)
+    M = O.BlockJacobi(lin)
+    b = -O.residual(lin).reshape(-1)
+    k = 7
+    res = O.gmres(lambda v: O.apply_operator(lin, v), M, b, restart=30, fixed_iters=k)
+    Minv = np.stack([M(e) for e in np.eye(b.size)], axis=1)
+    B = A @ Minv
+    K = [b]
+    for _ in range(k - 1):
+        K.append(B @ K[-1])
+    Q, _ = np.linalg.qr(np.stack(K, axis=1))
+    c, *_ = np.linalg.lstsq(B @ Q, b, rcond=None)
+    x_ref = Minv @ (Q @ c)
+    assert res.iters == k
+    assert np.linalg.norm(res.x - x_ref) <= 1e-9 * np.linalg.norm(x_ref)
