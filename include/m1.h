@@ -1,0 +1,202 @@
+/*
+ * m1.h -- C ABI of the MI355X implicit M1 radiative-transfer step.
+ *
+ * The library advances the gray, LTE, scattering-free M1 moment system
+ * (E, F) -- optionally coupled to the gas internal energy rho c_v T -- by one
+ * backward-Euler step of the asymptotic-preserving, well-balanced finite-volume
+ * scheme of Bloch et al. (A&A 2021):
+ *   - HLL fluxes F* and P* with the M1 closure (Sect. 2.2) and the wave speeds of
+ *     Eq. "eigenvalues" (Sect. 3.1.1);
+ *   - the asymptotic correction alpha on the energy flux (Eq.
+ *     "asymptoticCorrection", Sect. 3.1.3);
+ *   - the flux source term {sigma F}, well balanced (Eq. "wb_smart") or centred
+ *     (Eq. "wb_naive"), Sect. 3.1.2;
+ *   - radiation/matter exchange c sigma (a_r T^4 - E) on the E and T rows
+ *     (Eqs. "momentModel", "internalEnergyEqua"), or pure absorption -c sigma E;
+ *   - the implicit system of Sect. 3.1.1 solved by Newton iterations (Sect. 3.3.1)
+ *     with restarted, right-preconditioned GMRES (right preconditioning as in
+ *     Sect. 3.3.2) and a block-Jacobi preconditioner.
+ * Hydrodynamics is frozen during the step (Sect. 3.2, step 2 of the splitting).
+ *
+ * Memory: every array argument is a DEVICE pointer unless marked "host".  Fields
+ * are structure-of-arrays, component-major, x fastest:
+ *     value(comp, i, j, k) = a[((comp * nz + k) * ny + j) * nx + i]      (nz = 1 in 2D)
+ * A "vector" (x, y, r, z below) holds n_u * N doubles in the component order
+ * (E, F_x, F_y[, F_z][, T]), N = nx*ny*nz, n_u = 1 + ndim (+1 with the T row).
+ * Caller arrays carry no ghost cells; boundaries are described by m1_config.bc.
+ *
+ * Ownership: the caller owns every buffer it passes; buffers are borrowed for the
+ * duration of the call.  The context copies sigma, rho_cv and the boundary planes
+ * at m1_setup and owns all workspace (coefficients, Krylov basis, scratch).
+ * Everything is enqueued on the HIP stream given to m1_setup; m1_apply_operator
+ * and m1_precondition return once the work is enqueued, m1_implicit_step and
+ * m1_residual_norm block until their result is known.  A context is bound to one
+ * stream and one device and is not thread safe.
+ *
+ * Errors: every call returns an m1_status; nothing aborts or throws across the
+ * ABI.  Host-side arguments are validated before any launch.  On M1_NOT_CONVERGED
+ * m1_implicit_step leaves the caller's state unchanged and still fills the stats.
+ * m1_last_error() gives a human-readable message for the last failure.
+ */
+#ifndef M1_H
+#define M1_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct m1_ctx m1_ctx;
+
+typedef enum {
+  M1_OK = 0,
+  M1_NOT_CONVERGED = 1,     /* Newton or GMRES hit its iteration cap */
+  M1_ERR_INVALID_ARG = -1,  /* bad pointer, size, enum or scalar */
+  M1_ERR_OUT_OF_MEMORY = -2,
+  M1_ERR_HIP = -3,          /* a HIP runtime call failed */
+  M1_ERR_NONFINITE = -4,    /* NaN/Inf in an input field or in the iteration */
+  M1_ERR_STATE = -5         /* call made before the context holds a linearisation */
+} m1_status;
+
+/* Source on the energy row (and the gas-temperature row). */
+typedef enum {
+  M1_SRC_NONE = 0,        /* radiation only: S_E = 0 */
+  M1_SRC_ABSORPTION = 1,  /* S_E = -c sigma E (the absorption form of the ionisation model, Sect. 5.6) */
+  M1_SRC_COUPLED_T = 2    /* S_E = c sigma (a_r T^4 - E) with the T row (Eq. "internalEnergyEqua") */
+} m1_source;
+
+typedef enum {
+  M1_FSRC_WELL_BALANCED = 0, /* Eq. "wb_smart": face-averaged sigma and F */
+  M1_FSRC_CENTERED = 1       /* Eq. "wb_naive": sigma_i F_i */
+} m1_flux_source;
+
+typedef enum {
+  M1_CLOSURE_M1 = 0,  /* chi = (3 + 4f^2) / (5 + 2 sqrt(4 - 3f^2)) (Sect. 2.2) */
+  M1_CLOSURE_P1 = 1   /* D = I/3, speeds +-c/sqrt(3) (the f = 0 limit) */
+} m1_closure;
+
+/* How the Newton linearisation treats the Eddington tensor; the HLL speeds
+ * and alpha are always lagged at the iterate.  The converged root is the same. */
+typedef enum {
+  M1_LIN_NEWTON = 0,  /* dP/d(E,F) of P = D(E,F) E is differentiated (default) */
+  M1_LIN_PICARD = 1   /* the tensor D is frozen at the iterate */
+} m1_linearization;
+
+/* Boundary conditions through one layer of ghost cells. */
+typedef enum {
+  M1_BC_PERIODIC = 0,  /* wrap (must be set on both faces of a direction) */
+  M1_BC_OUTFLOW = 1,   /* zero-gradient copy of the boundary cell */
+  M1_BC_DIRICHLET = 2, /* ghost (E, F) given by m1_fields.bc_ghost (optionally masked) */
+  M1_BC_REFLECT = 3    /* copy with the normal flux component negated */
+} m1_bc;
+
+typedef enum { M1_FP64 = 0, M1_MIXED = 1 } m1_precision;
+typedef enum { M1_PC_BLOCK_JACOBI = 0, M1_PC_NONE = 1, M1_PC_LEARNED = 2 } m1_pc;
+
+typedef struct {
+  int32_t ndim;            /* 2 or 3 */
+  int32_t reserved0;
+  int64_t n[3];            /* nx, ny, nz (nz ignored in 2D); each >= 1 */
+  double dx;               /* cell size (> 0) */
+  double c;                /* speed of light (> 0) */
+  double a_r;              /* radiation constant (> 0) */
+  int32_t source;          /* m1_source */
+  int32_t flux_source;     /* m1_flux_source */
+  int32_t closure;         /* m1_closure */
+  int32_t ap_correction;   /* 1: alpha of Eq. "asymptoticCorrection"; 0: alpha = 1 (plain HLL) */
+  double lambda_floor;     /* >= 0: lambda+ >= floor*c, lambda- <= -floor*c (shadow test, Sect. 5.4) */
+  int32_t bc[6];           /* m1_bc for faces -x,+x,-y,+y,-z,+z */
+  int32_t linearization;   /* m1_linearization */
+  int32_t precision;       /* m1_precision */
+  int32_t pc;              /* m1_pc */
+  int32_t restart;         /* GMRES restart length m, 1..48 (30 by default) */
+  int32_t max_iters;       /* total GMRES iterations per linear solve */
+  int32_t newton_max;      /* Newton iterations per step */
+  int32_t fixed_iters;     /* > 0: every linear solve runs exactly this many GMRES iterations and
+                              every step exactly newton_max Newton iterations (no early exit) */
+  int32_t basis_fp32;      /* mixed precision only: 1 stores the Krylov basis in FP32 */
+  double rtol;             /* linear: ||b - A x|| <= rtol ||b|| (true residual) */
+  double newton_rtol;      /* nonlinear: ||R(U^k)|| <= newton_rtol ||R(U^0)|| */
+  double inner_rtol;       /* mixed precision: a GMRES cycle stops once its own estimate drops by this */
+  const char* nn_weights_path; /* host string or NULL (learned preconditioner) */
+} m1_config;
+
+typedef struct {
+  double* E;        /* N */
+  double* F[3];     /* F[d] for d < ndim, each N */
+  double* T;        /* N, required iff source == M1_SRC_COUPLED_T, else ignored */
+} m1_state;
+
+typedef struct {
+  const double* sigma;       /* N, opacity (>= 0, finite), fixed over the step */
+  const double* rho_cv;      /* N, gas heat capacity per volume (> 0); COUPLED_T only */
+  /* Dirichlet faces: ghost (E, F_0..F_{ndim-1}) on the face plane, component-major,
+   * plane index in grid order with the normal direction removed (x fastest).
+   * Optional mask (same plane, values 0 or 1): 1 takes the given ghost, 0 takes
+   * the outflow copy of the boundary cell.  NULL mask = all ones. */
+  const double* bc_ghost[6];
+  const double* bc_mask[6];
+} m1_fields;
+
+typedef struct {
+  int32_t newton_iters;      /* linear solves made */
+  int32_t krylov_iters;      /* GMRES iterations summed over the step */
+  int32_t restarts;          /* GMRES restarts summed over the step */
+  int32_t fell_back;         /* 1 if the learned preconditioner fell back to block-Jacobi */
+  double rel_residual;       /* last linear solve's true relative residual */
+  double nonlinear_residual; /* ||R(U_final)|| / ||R(U^n)|| */
+  int64_t cells_f_gt_1;      /* cells with |F| > (1 + 1e-12) c E after the step (Sect. 3.1.3 caveat) */
+  double seconds;            /* wall time of the call */
+} m1_stats;
+
+/* Size of m1_config / m1_stats as compiled (ABI check for bindings). */
+size_t m1_config_size(void);
+size_t m1_stats_size(void);
+const char* m1_status_string(int32_t status);
+
+/*
+ * m1_setup -- validate the configuration, allocate the workspace, copy the fields
+ * and (when U_lin and U_n are both non-NULL) linearise the scheme at U_lin with
+ * the time-level state U_n and time step dt (dt > 0).  U_lin = U_n is the first
+ * Newton iterate of a step.  hip_stream is a hipStream_t (NULL = default stream).
+ * On success *out holds a new context; on failure *out is NULL.
+ */
+m1_status m1_setup(const m1_config* cfg, const m1_fields* fields, const m1_state* U_lin,
+                   const m1_state* U_n, double dt, void* hip_stream, m1_ctx** out);
+
+/* Re-linearise an existing context at (U_lin, U_n, dt) (Newton iterate update). */
+m1_status m1_linearize(m1_ctx* ctx, const m1_state* U_lin, const m1_state* U_n, double dt);
+
+/* y = A x with A the Jacobian of the scheme's residual at the current linearisation
+ * (HLL speeds, alpha lagged; tensor per m1_config.linearization; T^4 linearised).
+ * x, y: vectors (n_u*N), must not overlap.  M1_ERR_STATE before a linearisation. */
+m1_status m1_apply_operator(m1_ctx* ctx, const double* x, double* y);
+
+/* z = M^{-1} r with M the block diagonal of A (one n_u x n_u block per cell, boundary
+ * ghost contributions included).  r, z: vectors; may be the same buffer. */
+m1_status m1_precondition(m1_ctx* ctx, const double* r, double* z);
+
+/* R = R(U_lin), the residual of the backward-Euler scheme (Sect. 3.1.1) at the
+ * linearisation state; R is a vector (n_u*N). */
+m1_status m1_residual(m1_ctx* ctx, double* R);
+
+/* One implicit step: U holds U^n on entry and U^{n+1} on M1_OK.  dt > 0.
+ * stats may be NULL.  Blocks until the step's status is known. */
+m1_status m1_implicit_step(m1_ctx* ctx, m1_state* U, double dt, m1_stats* stats);
+
+void m1_destroy(m1_ctx* ctx);
+const char* m1_last_error(const m1_ctx* ctx);
+
+/* Per-kernel-class timing with HIP events on the context's stream (for
+ * measurement; off by default).  class ids: see m1_kernel_class_name. */
+m1_status m1_profile_enable(m1_ctx* ctx, int32_t on);
+m1_status m1_profile_query(m1_ctx* ctx, int32_t kclass, int64_t* launches, double* total_ms);
+const char* m1_kernel_class_name(int32_t kclass);
+int32_t m1_kernel_class_count(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* M1_H */

@@ -1,0 +1,714 @@
+// C ABI of the implicit M1 step: context management, argument validation, the
+// Newton loop (Sect. 3.3.1) and the restarted GMRES driver (one host read-back
+// per GMRES cycle; everything else stays on the device).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/m1.h"
+#include "m1_internal.h"
+
+using namespace m1;
+
+namespace {
+
+const char* kClassNames[KC_COUNT] = {"setup",   "setup_bj", "residual",   "apply",         "block_jacobi",
+                                     "arnoldi_dot", "arnoldi_scalar", "arnoldi_update", "x_update",
+                                     "true_residual", "newton_update", "norm", "convert"};
+
+struct Profiler {
+  bool on = false;
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+  struct Rec { int kc; hipEvent_t a, b; };
+  std::vector<Rec> pending;
+  int64_t launches[KC_COUNT] = {};
+  double ms[KC_COUNT] = {};
+};
+
+}  // namespace
+
+struct m1_ctx {
+  m1_config cfg;
+  int nd = 2, nu = 3, nrad = 3, njac = 9, m = 30;
+  bool cpl = false;
+  Geom g;
+  Scheme sc;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  std::string err;
+  bool linearized = false;
+  // boundary copies
+  double* plane[6] = {};
+  double* mask[6] = {};
+  // states
+  double* Uk = nullptr;
+  double* Un = nullptr;
+  double* fn = nullptr;
+  // coefficients
+  double* coef64 = nullptr;
+  float* coef32 = nullptr;
+  int64_t coef_len = 0;
+  Coefs<double> cf64;
+  Coefs<float> cf32;
+  // Krylov workspace
+  void* V = nullptr;
+  int64_t n = 0;        // vector length n_u*N
+  double* b = nullptr;
+  double* x = nullptr;
+  void* u[2] = {};
+  void* p = nullptr;
+  void* z = nullptr;
+  double* part = nullptr;
+  int nb = 1;
+  GmresState* gs = nullptr;
+  double* dscal = nullptr;
+  unsigned long long* dcount = nullptr;
+  // pinned host read-back
+  double* hscal = nullptr;
+  Profiler prof;
+};
+
+namespace {
+
+bool hip_ok(m1_ctx* c, hipError_t e, const char* what) {
+  if (e == hipSuccess) return true;
+  if (c) c->err = std::string(what) + ": " + hipGetErrorString(e);
+  return false;
+}
+
+#define HIPCHK(ctx, call)                                   \
+  do {                                                      \
+    if (!hip_ok((ctx), (call), #call)) return M1_ERR_HIP;   \
+  } while (0)
+
+hipEvent_t prof_event(m1_ctx* c) {
+  Profiler& p = c->prof;
+  if (p.used == p.pool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    p.pool.push_back(e);
+  }
+  return p.pool[p.used++];
+}
+
+template <typename F>
+void timed(m1_ctx* c, int kc, F&& launch) {
+  if (!c->prof.on) {
+    launch();
+    return;
+  }
+  hipEvent_t a = prof_event(c), b = prof_event(c);
+  if (a) hipEventRecord(a, c->stream);
+  launch();
+  if (b) hipEventRecord(b, c->stream);
+  if (a && b) c->prof.pending.push_back({kc, a, b});
+}
+
+void prof_collect(m1_ctx* c) {
+  Profiler& p = c->prof;
+  if (p.pending.empty()) return;
+  hipEventSynchronize(p.pending.back().b);
+  for (auto& r : p.pending) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+      p.launches[r.kc] += 1;
+      p.ms[r.kc] += ms;
+    }
+  }
+  p.pending.clear();
+  p.used = 0;
+}
+
+int nu_of(const m1_config& c) { return 1 + c.ndim + (c.source == M1_SRC_COUPLED_T ? 1 : 0); }
+
+bool finite(double v) { return std::isfinite(v); }
+
+m1_status validate_config(const m1_config* c, std::string& err) {
+  if (!c) { err = "cfg is NULL"; return M1_ERR_INVALID_ARG; }
+  if (c->ndim != 2 && c->ndim != 3) { err = "ndim must be 2 or 3"; return M1_ERR_INVALID_ARG; }
+  int64_t N = 1;
+  for (int d = 0; d < c->ndim; ++d) {
+    if (c->n[d] < 1 || c->n[d] > (1 << 20)) { err = "grid size out of range"; return M1_ERR_INVALID_ARG; }
+    N *= c->n[d];
+  }
+  if (N > (int64_t)1 << 31) { err = "too many cells (max 2^31)"; return M1_ERR_INVALID_ARG; }
+  if (!(finite(c->dx) && c->dx > 0) || !(finite(c->c) && c->c > 0) || !(finite(c->a_r) && c->a_r > 0)) {
+    err = "dx, c and a_r must be finite and > 0";
+    return M1_ERR_INVALID_ARG;
+  }
+  if (c->source < 0 || c->source > 2 || c->flux_source < 0 || c->flux_source > 1 || c->closure < 0 ||
+      c->closure > 1 || c->linearization < 0 || c->linearization > 1 || c->precision < 0 || c->precision > 1 ||
+      c->pc < 0 || c->pc > 2) {
+    err = "enum value out of range";
+    return M1_ERR_INVALID_ARG;
+  }
+  if (c->pc == M1_PC_LEARNED) { err = "learned preconditioner is not available in this build"; return M1_ERR_INVALID_ARG; }
+  if (!(finite(c->lambda_floor) && c->lambda_floor >= 0)) { err = "lambda_floor must be >= 0"; return M1_ERR_INVALID_ARG; }
+  for (int f = 0; f < 2 * c->ndim; ++f) {
+    if (c->bc[f] < 0 || c->bc[f] > 3) { err = "bc value out of range"; return M1_ERR_INVALID_ARG; }
+  }
+  for (int d = 0; d < c->ndim; ++d) {
+    if ((c->bc[2 * d] == M1_BC_PERIODIC) != (c->bc[2 * d + 1] == M1_BC_PERIODIC)) {
+      err = "periodic must be set on both faces of a direction";
+      return M1_ERR_INVALID_ARG;
+    }
+  }
+  if (c->restart < 1 || c->restart > kMaxRestart) { err = "restart must be in 1..48"; return M1_ERR_INVALID_ARG; }
+  if (c->max_iters < 1 || c->newton_max < 1 || c->fixed_iters < 0) {
+    err = "max_iters and newton_max must be >= 1, fixed_iters >= 0";
+    return M1_ERR_INVALID_ARG;
+  }
+  if (!(finite(c->rtol) && c->rtol >= 0) || !(finite(c->newton_rtol) && c->newton_rtol >= 0) ||
+      !(finite(c->inner_rtol) && c->inner_rtol >= 0 && c->inner_rtol < 1)) {
+    err = "tolerances must be finite, >= 0 (inner_rtol < 1)";
+    return M1_ERR_INVALID_ARG;
+  }
+  return M1_OK;
+}
+
+__global__ void k_check(const double* a, int64_t n, int positive, unsigned long long* bad) {
+  bool b = false;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const double v = a[i];
+    b = b || !isfinite(v) || (positive == 1 && !(v > 0.0)) || (positive == 2 && !(v >= 0.0));
+  }
+  const unsigned long long ballot = __ballot(b);
+  if ((threadIdx.x & 63) == 0 && ballot) atomicAdd(bad, 1ull);
+}
+
+__global__ void k_zero_u64(unsigned long long* p) {
+  if (threadIdx.x == 0) p[0] = 0ull;
+}
+
+// Count entries that are non-finite (positive = 0), or also <= 0 (1), or < 0 (2).
+m1_status check_array(m1_ctx* c, const double* a, int64_t n, int positive, const char* name, m1_status code) {
+  k_zero_u64<<<1, 64, 0, c->stream>>>(c->dcount);
+  const int64_t grd = std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 2048));
+  k_check<<<grd, 256, 0, c->stream>>>(a, n, positive, c->dcount);
+  unsigned long long bad = 0;
+  HIPCHK(c, hipMemcpyAsync(&bad, c->dcount, sizeof(bad), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (bad) {
+    c->err = std::string(name) + (positive == 1 ? " has non-finite or non-positive entries"
+                                                : positive == 2 ? " has non-finite or negative entries"
+                                                                : " has non-finite entries");
+    return code;
+  }
+  return M1_OK;
+}
+
+template <typename T>
+m1_status dalloc(m1_ctx* c, T** p, int64_t count) {
+  *p = nullptr;
+  if (count <= 0) return M1_OK;
+  hipError_t e = hipMalloc((void**)p, sizeof(T) * (size_t)count);
+  if (e != hipSuccess) {
+    c->err = std::string("hipMalloc failed: ") + hipGetErrorString(e);
+    *p = nullptr;
+    return e == hipErrorOutOfMemory ? M1_ERR_OUT_OF_MEMORY : M1_ERR_HIP;
+  }
+  return M1_OK;
+}
+
+void free_all(m1_ctx* c) {
+  for (int f = 0; f < 6; ++f) {
+    if (c->plane[f]) hipFree(c->plane[f]);
+    if (c->mask[f]) hipFree(c->mask[f]);
+  }
+  void* bufs[] = {c->Uk, c->Un, c->fn, c->coef64, c->coef32, c->V, c->b, c->x, c->u[0], c->u[1],
+                  c->p, c->z, c->part, c->gs, c->dscal, c->dcount};
+  for (void* b : bufs)
+    if (b) hipFree(b);
+  if (c->hscal) hipHostFree(c->hscal);
+  for (auto e : c->prof.pool) hipEventDestroy(e);
+}
+
+bool mixed(const m1_ctx* c) { return c->cfg.precision == M1_MIXED; }
+bool basis32(const m1_ctx* c) { return mixed(c) && c->cfg.basis_fp32; }
+
+template <typename R> void layout(m1_ctx* c, R* base, Coefs<R>& cf) {
+  const int64_t N = c->g.N;
+  int64_t off = 0;
+  cf.jac = base + off; off += (int64_t)c->njac * N;
+  cf.face = base + off; off += (int64_t)3 * c->nd * N;
+  cf.lowface = base;
+  for (int d = 0; d < c->nd; ++d) { cf.lowoff[d] = off; off += (int64_t)3 * c->g.plane_n[d]; }
+  cf.gjac = base;
+  for (int f = 0; f < 6; ++f) {
+    cf.gjoff[f] = off;
+    if (f < 2 * c->nd) off += (int64_t)c->njac * c->g.plane_n[f / 2];
+  }
+  cf.sigma = base + off; off += N;
+  cf.kap = base + off; off += c->cpl ? N : 0;
+  cf.rcv = base + off; off += c->cpl ? N : 0;
+  cf.bjinv = base + off; off += (int64_t)c->nu * c->nu * N;
+  c->coef_len = off;
+}
+
+Bdry bdry(const m1_ctx* c) {
+  Bdry b;
+  for (int f = 0; f < 6; ++f) {
+    b.plane[f] = c->plane[f];
+    b.mask[f] = c->mask[f];
+  }
+  return b;
+}
+
+void set_dt(m1_ctx* c, double dt) {
+  c->sc.dt = dt;
+  c->sc.s = dt / c->cfg.dx;
+  c->sc.cdt = c->cfg.c * dt;
+}
+
+m1_status copy_state_in(m1_ctx* c, const m1_state* U, double* dst) {
+  const size_t bytes = sizeof(double) * (size_t)c->g.N;
+  if (!U || !U->E) { c->err = "state E is NULL"; return M1_ERR_INVALID_ARG; }
+  for (int d = 0; d < c->nd; ++d)
+    if (!U->F[d]) { c->err = "state F[d] is NULL"; return M1_ERR_INVALID_ARG; }
+  if (c->cpl && !U->T) { c->err = "state T is NULL (coupled source)"; return M1_ERR_INVALID_ARG; }
+  HIPCHK(c, hipMemcpyAsync(dst, U->E, bytes, hipMemcpyDeviceToDevice, c->stream));
+  for (int d = 0; d < c->nd; ++d)
+    HIPCHK(c, hipMemcpyAsync(dst + (1 + d) * c->g.N, U->F[d], bytes, hipMemcpyDeviceToDevice, c->stream));
+  if (c->cpl) HIPCHK(c, hipMemcpyAsync(dst + (1 + c->nd) * c->g.N, U->T, bytes, hipMemcpyDeviceToDevice, c->stream));
+  return M1_OK;
+}
+
+m1_status copy_state_out(m1_ctx* c, const double* src, m1_state* U) {
+  const size_t bytes = sizeof(double) * (size_t)c->g.N;
+  HIPCHK(c, hipMemcpyAsync(U->E, src, bytes, hipMemcpyDeviceToDevice, c->stream));
+  for (int d = 0; d < c->nd; ++d)
+    HIPCHK(c, hipMemcpyAsync(U->F[d], src + (1 + d) * c->g.N, bytes, hipMemcpyDeviceToDevice, c->stream));
+  if (c->cpl) HIPCHK(c, hipMemcpyAsync(U->T, src + (1 + c->nd) * c->g.N, bytes, hipMemcpyDeviceToDevice, c->stream));
+  return M1_OK;
+}
+
+// Linearise at c->Uk with time-level state c->Un (|f^n| already in c->fn).
+m1_status linearize_internal(m1_ctx* c) {
+  const Bdry bd = bdry(c);
+  timed(c, KC_SETUP, [&] { launch_setup(c->nd, c->cpl, c->g, c->sc, c->cf64, bd, c->Uk, c->Un, c->fn, c->stream); });
+  timed(c, KC_SETUP_BJ, [&] { launch_setup_bj(c->nd, c->cpl, c->g, c->sc, c->cf64, bd, c->stream); });
+  if (mixed(c)) timed(c, KC_CONVERT, [&] { launch_convert(c->coef64, c->coef32, c->coef_len, c->stream); });
+  HIPCHK(c, hipGetLastError());
+  c->linearized = true;
+  return M1_OK;
+}
+
+// ||v||^2 of an FP64 vector into c->dscal[slot] (device)
+void norm2_into(m1_ctx* c, const double* v, int slot) {
+  timed(c, KC_NORM, [&] {
+    launch_dot<double>(0, nullptr, 0, v, nullptr, c->n, c->part, c->nb, nullptr, c->stream);
+    launch_reduce(c->part, 1, c->nb, c->dscal + slot, c->stream);
+  });
+}
+
+struct SolveResult {
+  int iters = 0, restarts = 0;
+  double rel = 0.0;
+  bool converged = false;
+  bool nonfinite = false;
+};
+
+// GMRES(m) on A x = b (b = c->b, x = c->x), x0 = 0.  TV: basis storage; R: type of
+// the preconditioner and of the operator inside the Arnoldi process.
+template <typename TV, typename R>
+m1_status gmres(m1_ctx* c, double bnorm, SolveResult& res, const Coefs<R>& cfi) {
+  const Bdry bd = bdry(c);
+  const int64_t n = c->n;
+  const int64_t vs = n;
+  TV* V = (TV*)c->V;
+  TV* u[2] = {(TV*)c->u[0], (TV*)c->u[1]};
+  TV* p = (TV*)c->p;
+  R* z = (R*)c->z;
+  const bool fixed = c->cfg.fixed_iters > 0;
+  const int budget = fixed ? c->cfg.fixed_iters : c->cfg.max_iters;
+  const double rtol = c->cfg.rtol;
+  const double tol_rel = (mixed(c) && !fixed) ? c->cfg.inner_rtol : 0.0;
+  const int use_pc = c->cfg.pc == M1_PC_BLOCK_JACOBI;
+  HIPCHK(c, hipMemsetAsync(c->x, 0, sizeof(double) * n, c->stream));
+  // r = b
+  launch_copy_cast<double, TV>(c->b, u[0], n, c->stream);
+  double beta = bnorm;
+  // device copy of beta^2 for the cycle's relative tolerance
+  HIPCHK(c, hipMemcpyAsync(c->dscal + 1, c->dscal + 0, sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  int total = 0, cycles = 0;
+  res = SolveResult();
+  while (true) {
+    if (!fixed && beta <= rtol * bnorm) { res.converged = true; break; }
+    if (total >= budget) { res.converged = fixed || beta <= rtol * bnorm; break; }
+    ++cycles;
+    const int steps = std::min(c->m, budget - total);
+    launch_cycle_init(c->gs, c->dscal + 1, fixed ? 0.0 : rtol * bnorm, tol_rel, c->stream);
+    for (int j = 0; j < steps; ++j) {
+      TV* uj = u[j & 1];
+      TV* un = u[(j + 1) & 1];
+      if (use_pc) {
+        timed(c, KC_BJ, [&] { launch_bj<R, TV, R>(c->nd, c->cpl, c->g, cfi, uj, z, c->stream); });
+        timed(c, KC_APPLY, [&] { launch_apply<R, R, TV>(c->nd, c->cpl, 0, c->g, c->sc, cfi, bd, z, nullptr, p, c->stream); });
+      } else {
+        timed(c, KC_APPLY, [&] { launch_apply<R, TV, TV>(c->nd, c->cpl, 0, c->g, c->sc, cfi, bd, uj, nullptr, p, c->stream); });
+      }
+      timed(c, KC_DOT, [&] { launch_dot<TV>(j, V, vs, uj, p, n, c->part, c->nb, c->gs, c->stream); });
+      timed(c, KC_SCALAR, [&] { launch_scalar(j, 0, c->part, c->nb, c->gs, c->stream); });
+      timed(c, KC_UPDATE, [&] { launch_update<TV>(j, V, vs, uj, p, un, n, c->gs, c->stream); });
+    }
+    timed(c, KC_DOT, [&] { launch_dot<TV>(steps, V, vs, u[steps & 1], nullptr, n, c->part, c->nb, c->gs, c->stream); });
+    timed(c, KC_SCALAR, [&] { launch_scalar(steps, 1, c->part, c->nb, c->gs, c->stream); });
+    timed(c, KC_XUPDATE, [&] { launch_xupdate<R, TV>(c->nd, c->cpl, c->g, cfi, V, vs, c->gs, c->x, use_pc, c->stream); });
+    // true residual in FP64: r = b - A x, stored as the next cycle's u_0
+    timed(c, KC_TRUE_RESID, [&] {
+      launch_apply<double, double, TV>(c->nd, c->cpl, 1, c->g, c->sc, c->cf64, bd, c->x, c->b, u[0], c->stream);
+    });
+    timed(c, KC_NORM, [&] {
+      launch_dot<TV>(0, nullptr, 0, u[0], nullptr, n, c->part, c->nb, nullptr, c->stream);
+      launch_reduce(c->part, 1, c->nb, c->dscal + 1, c->stream);
+    });
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipMemcpyAsync(c->hscal, c->dscal + 1, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    int hk[4];
+    HIPCHK(c, hipMemcpyAsync(hk, c->gs, sizeof(int) * 4, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    prof_collect(c);
+    const int k = hk[1];
+    total += fixed ? steps : std::max(k, 1);
+    beta = std::sqrt(std::max(c->hscal[0], 0.0));
+    if (!std::isfinite(beta) || hk[3]) { res.nonfinite = true; break; }
+  }
+  res.iters = total;
+  res.restarts = std::max(cycles - 1, 0);
+  res.rel = bnorm > 0 ? beta / bnorm : 0.0;
+  return M1_OK;
+}
+
+m1_status solve(m1_ctx* c, double bnorm, SolveResult& res) {
+  if (!mixed(c)) return gmres<double, double>(c, bnorm, res, c->cf64);
+  if (basis32(c)) return gmres<float, float>(c, bnorm, res, c->cf32);
+  return gmres<double, float>(c, bnorm, res, c->cf32);
+}
+
+}  // namespace
+
+// ============================================================================
+// C ABI
+// ============================================================================
+extern "C" {
+
+size_t m1_config_size(void) { return sizeof(m1_config); }
+size_t m1_stats_size(void) { return sizeof(m1_stats); }
+
+const char* m1_status_string(int32_t s) {
+  switch (s) {
+    case M1_OK: return "M1_OK";
+    case M1_NOT_CONVERGED: return "M1_NOT_CONVERGED";
+    case M1_ERR_INVALID_ARG: return "M1_ERR_INVALID_ARG";
+    case M1_ERR_OUT_OF_MEMORY: return "M1_ERR_OUT_OF_MEMORY";
+    case M1_ERR_HIP: return "M1_ERR_HIP";
+    case M1_ERR_NONFINITE: return "M1_ERR_NONFINITE";
+    case M1_ERR_STATE: return "M1_ERR_STATE";
+  }
+  return "unknown status";
+}
+
+const char* m1_kernel_class_name(int32_t kc) { return (kc >= 0 && kc < KC_COUNT) ? kClassNames[kc] : ""; }
+int32_t m1_kernel_class_count(void) { return KC_COUNT; }
+
+static thread_local std::string g_setup_err;
+
+m1_status m1_setup(const m1_config* cfg, const m1_fields* fields, const m1_state* U_lin, const m1_state* U_n,
+                   double dt, void* hip_stream, m1_ctx** out) {
+  if (!out) return M1_ERR_INVALID_ARG;
+  *out = nullptr;
+  std::string err;
+  m1_status st = validate_config(cfg, err);
+  if (st != M1_OK) { g_setup_err = err; return st; }
+  if (!fields || !fields->sigma) { g_setup_err = "fields or fields->sigma is NULL"; return M1_ERR_INVALID_ARG; }
+  if (cfg->source == M1_SRC_COUPLED_T && !fields->rho_cv) { g_setup_err = "rho_cv is NULL"; return M1_ERR_INVALID_ARG; }
+  for (int f = 0; f < 2 * cfg->ndim; ++f)
+    if (cfg->bc[f] == M1_BC_DIRICHLET && !fields->bc_ghost[f]) { g_setup_err = "Dirichlet face without bc_ghost"; return M1_ERR_INVALID_ARG; }
+  if ((U_lin == nullptr) != (U_n == nullptr)) { g_setup_err = "U_lin and U_n must both be given or both NULL"; return M1_ERR_INVALID_ARG; }
+  if (U_lin && !(std::isfinite(dt) && dt > 0)) { g_setup_err = "dt must be finite and > 0"; return M1_ERR_INVALID_ARG; }
+
+  m1_ctx* c = new m1_ctx();
+  c->cfg = *cfg;
+  c->cfg.nn_weights_path = nullptr;
+  c->nd = cfg->ndim;
+  c->cpl = cfg->source == M1_SRC_COUPLED_T;
+  c->nrad = 1 + c->nd;
+  c->nu = nu_of(*cfg);
+  c->njac = (c->nd * (c->nd + 1) / 2) * (1 + c->nd);
+  c->m = cfg->restart;
+  c->stream = (hipStream_t)hip_stream;
+  hipGetDevice(&c->device);
+  Geom& g = c->g;
+  g.n[0] = (int)cfg->n[0];
+  g.n[1] = (int)cfg->n[1];
+  g.n[2] = c->nd == 3 ? (int)cfg->n[2] : 1;
+  g.rows = g.n[1] * g.n[2];
+  g.N = (int64_t)g.n[0] * g.n[1] * g.n[2];
+  g.stride[0] = 1;
+  g.stride[1] = g.n[0];
+  g.stride[2] = (int64_t)g.n[0] * g.n[1];
+  for (int f = 0; f < 6; ++f) g.bc[f] = f < 2 * c->nd ? cfg->bc[f] : M1_BC_PERIODIC;
+  g.plane_n[0] = g.n[1] * g.n[2];
+  g.plane_n[1] = g.n[0] * g.n[2];
+  g.plane_n[2] = g.n[0] * g.n[1];
+  Scheme& sc = c->sc;
+  sc.c = cfg->c;
+  sc.c2 = cfg->c * cfg->c;
+  sc.a_r = cfg->a_r;
+  sc.dx = cfg->dx;
+  sc.lambda_floor = cfg->lambda_floor;
+  sc.src = cfg->source;
+  sc.wb = cfg->flux_source == M1_FSRC_WELL_BALANCED;
+  sc.ap = cfg->ap_correction != 0;
+  sc.p1 = cfg->closure == M1_CLOSURE_P1;
+  sc.newton = cfg->linearization == M1_LIN_NEWTON;
+  set_dt(c, U_lin ? dt : 1.0);
+  c->n = (int64_t)c->nu * g.N;
+  c->nb = dot_blocks(c->n);
+
+  auto fail = [&](m1_status s) {
+    g_setup_err = c->err;
+    free_all(c);
+    delete c;
+    return s;
+  };
+  const int64_t N = g.N;
+  // workspace
+  layout<double>(c, nullptr, c->cf64);
+  if ((st = dalloc(c, &c->coef64, c->coef_len)) != M1_OK) return fail(st);
+  layout<double>(c, c->coef64, c->cf64);
+  if (mixed(c)) {
+    if ((st = dalloc(c, &c->coef32, c->coef_len)) != M1_OK) return fail(st);
+    layout<float>(c, c->coef32, c->cf32);
+  }
+  if ((st = dalloc(c, &c->Uk, c->n)) != M1_OK) return fail(st);
+  if ((st = dalloc(c, &c->Un, c->n)) != M1_OK) return fail(st);
+  if ((st = dalloc(c, &c->fn, N)) != M1_OK) return fail(st);
+  if ((st = dalloc(c, &c->b, c->n)) != M1_OK) return fail(st);
+  if ((st = dalloc(c, &c->x, c->n)) != M1_OK) return fail(st);
+  const size_t tvs = basis32(c) ? sizeof(float) : sizeof(double);
+  const size_t rs = mixed(c) ? sizeof(float) : sizeof(double);
+  {
+    char* v = nullptr;
+    if ((st = dalloc(c, &v, (int64_t)(c->m + 1) * c->n * (int64_t)tvs)) != M1_OK) return fail(st);
+    c->V = v;
+    char* a = nullptr;
+    if ((st = dalloc(c, &a, c->n * (int64_t)tvs)) != M1_OK) return fail(st);
+    c->u[0] = a;
+    if ((st = dalloc(c, &a, c->n * (int64_t)tvs)) != M1_OK) return fail(st);
+    c->u[1] = a;
+    if ((st = dalloc(c, &a, c->n * (int64_t)tvs)) != M1_OK) return fail(st);
+    c->p = a;
+    if ((st = dalloc(c, &a, c->n * (int64_t)rs)) != M1_OK) return fail(st);
+    c->z = a;
+  }
+  if ((st = dalloc(c, &c->part, (int64_t)(2 * kMaxRestart + 2) * c->nb)) != M1_OK) return fail(st);
+  if ((st = dalloc(c, &c->gs, 1)) != M1_OK) return fail(st);
+  if ((st = dalloc(c, &c->dscal, 8)) != M1_OK) return fail(st);
+  if ((st = dalloc(c, &c->dcount, 1)) != M1_OK) return fail(st);
+  if (!hip_ok(c, hipHostMalloc((void**)&c->hscal, 8 * sizeof(double)), "hipHostMalloc")) return fail(M1_ERR_HIP);
+  if (!hip_ok(c, hipMemsetAsync(c->gs, 0, sizeof(GmresState), c->stream), "memset")) return fail(M1_ERR_HIP);
+  if (!hip_ok(c, hipMemsetAsync(c->coef64, 0, sizeof(double) * c->coef_len, c->stream), "memset")) return fail(M1_ERR_HIP);
+
+  // field copies and their validation
+  if (!hip_ok(c, hipMemcpyAsync(c->cf64.sigma, fields->sigma, sizeof(double) * N, hipMemcpyDeviceToDevice, c->stream), "copy sigma"))
+    return fail(M1_ERR_HIP);
+  if ((st = check_array(c, c->cf64.sigma, N, 2, "sigma", M1_ERR_NONFINITE)) != M1_OK) return fail(st);
+  if (c->cpl) {
+    if (!hip_ok(c, hipMemcpyAsync(c->cf64.rcv, fields->rho_cv, sizeof(double) * N, hipMemcpyDeviceToDevice, c->stream), "copy rho_cv"))
+      return fail(M1_ERR_HIP);
+    if ((st = check_array(c, c->cf64.rcv, N, 1, "rho_cv", M1_ERR_NONFINITE)) != M1_OK) return fail(st);
+  }
+  for (int f = 0; f < 2 * c->nd; ++f) {
+    if (g.bc[f] != M1_BC_DIRICHLET) continue;
+    const int64_t pn = g.plane_n[f / 2];
+    if ((st = dalloc(c, &c->plane[f], (int64_t)c->nrad * pn)) != M1_OK) return fail(st);
+    if (!hip_ok(c, hipMemcpyAsync(c->plane[f], fields->bc_ghost[f], sizeof(double) * c->nrad * pn, hipMemcpyDeviceToDevice, c->stream), "copy ghost"))
+      return fail(M1_ERR_HIP);
+    if ((st = check_array(c, c->plane[f], (int64_t)c->nrad * pn, 0, "bc_ghost", M1_ERR_NONFINITE)) != M1_OK) return fail(st);
+    if (fields->bc_mask[f]) {
+      if ((st = dalloc(c, &c->mask[f], pn)) != M1_OK) return fail(st);
+      if (!hip_ok(c, hipMemcpyAsync(c->mask[f], fields->bc_mask[f], sizeof(double) * pn, hipMemcpyDeviceToDevice, c->stream), "copy mask"))
+        return fail(M1_ERR_HIP);
+      std::vector<double> hm(pn);
+      if (!hip_ok(c, hipMemcpyAsync(hm.data(), c->mask[f], sizeof(double) * pn, hipMemcpyDeviceToHost, c->stream), "mask readback") ||
+          !hip_ok(c, hipStreamSynchronize(c->stream), "sync"))
+        return fail(M1_ERR_HIP);
+      for (double v : hm)
+        if (!(v == 0.0 || v == 1.0)) { c->err = "bc_mask values must be 0 or 1"; return fail(M1_ERR_INVALID_ARG); }
+    }
+  }
+  if (U_lin) {
+    if ((st = copy_state_in(c, U_lin, c->Uk)) != M1_OK) return fail(st);
+    if ((st = copy_state_in(c, U_n, c->Un)) != M1_OK) return fail(st);
+    if ((st = check_array(c, c->Uk, c->n, 0, "U_lin", M1_ERR_NONFINITE)) != M1_OK) return fail(st);
+    if ((st = check_array(c, c->Un, c->n, 0, "U_n", M1_ERR_NONFINITE)) != M1_OK) return fail(st);
+    launch_fn(c->nd, g, c->sc, c->Un, c->fn, c->stream);
+    if ((st = linearize_internal(c)) != M1_OK) return fail(st);
+  }
+  if (!hip_ok(c, hipStreamSynchronize(c->stream), "setup sync")) return fail(M1_ERR_HIP);
+  *out = c;
+  return M1_OK;
+}
+
+m1_status m1_linearize(m1_ctx* c, const m1_state* U_lin, const m1_state* U_n, double dt) {
+  if (!c) return M1_ERR_INVALID_ARG;
+  if (!U_lin || !U_n || !(std::isfinite(dt) && dt > 0)) { c->err = "U_lin, U_n and dt > 0 are required"; return M1_ERR_INVALID_ARG; }
+  m1_status st;
+  if ((st = copy_state_in(c, U_lin, c->Uk)) != M1_OK) return st;
+  if ((st = copy_state_in(c, U_n, c->Un)) != M1_OK) return st;
+  if ((st = check_array(c, c->Uk, c->n, 0, "U_lin", M1_ERR_NONFINITE)) != M1_OK) return st;
+  if ((st = check_array(c, c->Un, c->n, 0, "U_n", M1_ERR_NONFINITE)) != M1_OK) return st;
+  set_dt(c, dt);
+  launch_fn(c->nd, c->g, c->sc, c->Un, c->fn, c->stream);
+  if ((st = linearize_internal(c)) != M1_OK) return st;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  prof_collect(c);
+  return M1_OK;
+}
+
+m1_status m1_apply_operator(m1_ctx* c, const double* x, double* y) {
+  if (!c) return M1_ERR_INVALID_ARG;
+  if (!x || !y) { c->err = "x or y is NULL"; return M1_ERR_INVALID_ARG; }
+  if (x == y) { c->err = "x and y must not overlap"; return M1_ERR_INVALID_ARG; }
+  if (!c->linearized) { c->err = "no linearisation yet"; return M1_ERR_STATE; }
+  timed(c, KC_APPLY, [&] {
+    launch_apply<double, double, double>(c->nd, c->cpl, 0, c->g, c->sc, c->cf64, bdry(c), x, nullptr, y, c->stream);
+  });
+  HIPCHK(c, hipGetLastError());
+  return M1_OK;
+}
+
+m1_status m1_precondition(m1_ctx* c, const double* r, double* z) {
+  if (!c) return M1_ERR_INVALID_ARG;
+  if (!r || !z) { c->err = "r or z is NULL"; return M1_ERR_INVALID_ARG; }
+  if (!c->linearized) { c->err = "no linearisation yet"; return M1_ERR_STATE; }
+  if (c->cfg.pc == M1_PC_NONE) {
+    if (r != z) HIPCHK(c, hipMemcpyAsync(z, r, sizeof(double) * c->n, hipMemcpyDeviceToDevice, c->stream));
+    return M1_OK;
+  }
+  timed(c, KC_BJ, [&] { launch_bj<double, double, double>(c->nd, c->cpl, c->g, c->cf64, r, z, c->stream); });
+  HIPCHK(c, hipGetLastError());
+  return M1_OK;
+}
+
+m1_status m1_residual(m1_ctx* c, double* R) {
+  if (!c) return M1_ERR_INVALID_ARG;
+  if (!R) { c->err = "R is NULL"; return M1_ERR_INVALID_ARG; }
+  if (!c->linearized) { c->err = "no linearisation yet"; return M1_ERR_STATE; }
+  timed(c, KC_RESIDUAL, [&] { launch_residual(c->nd, c->cpl, c->g, c->sc, c->cf64, bdry(c), c->Uk, c->Un, R, c->stream); });
+  // the residual kernel writes -R (the Newton right-hand side); flip the sign
+  launch_scale(R, -1.0, c->n, c->stream);
+  HIPCHK(c, hipGetLastError());
+  return M1_OK;
+}
+
+m1_status m1_implicit_step(m1_ctx* c, m1_state* U, double dt, m1_stats* stats) {
+  if (!c) return M1_ERR_INVALID_ARG;
+  const auto t0 = std::chrono::steady_clock::now();
+  if (!(std::isfinite(dt) && dt > 0)) { c->err = "dt must be finite and > 0"; return M1_ERR_INVALID_ARG; }
+  m1_status st;
+  if ((st = copy_state_in(c, U, c->Un)) != M1_OK) return st;
+  if ((st = check_array(c, c->Un, c->n, 0, "U", M1_ERR_NONFINITE)) != M1_OK) return st;
+  if ((st = check_array(c, c->Un, c->g.N, 1, "U.E", M1_ERR_INVALID_ARG)) != M1_OK) return st;
+  HIPCHK(c, hipMemcpyAsync(c->Uk, c->Un, sizeof(double) * c->n, hipMemcpyDeviceToDevice, c->stream));
+  set_dt(c, dt);
+  launch_fn(c->nd, c->g, c->sc, c->Un, c->fn, c->stream);
+  const bool fixed = c->cfg.fixed_iters > 0;
+  double r0 = -1.0, rel = 1.0;
+  int it = 0, kry = 0, rst = 0;
+  bool converged = false, nonfinite = false;
+  double lin_rel = 0.0;
+  while (true) {
+    if ((st = linearize_internal(c)) != M1_OK) return st;
+    timed(c, KC_RESIDUAL, [&] { launch_residual(c->nd, c->cpl, c->g, c->sc, c->cf64, bdry(c), c->Uk, c->Un, c->b, c->stream); });
+    norm2_into(c, c->b, 0);
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipMemcpyAsync(c->hscal, c->dscal, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    prof_collect(c);
+    const double rn = std::sqrt(std::max(c->hscal[0], 0.0));
+    if (!std::isfinite(rn)) { nonfinite = true; break; }
+    if (r0 < 0) r0 = rn;
+    rel = r0 > 0 ? rn / r0 : 0.0;
+    if (fixed) {
+      if (it >= c->cfg.newton_max) { converged = true; break; }
+    } else if (rn == 0.0 || (it > 0 && rel <= c->cfg.newton_rtol)) {
+      converged = true;
+      break;
+    } else if (it >= c->cfg.newton_max) {
+      break;
+    }
+    SolveResult sr;
+    if ((st = solve(c, rn, sr)) != M1_OK) return st;
+    kry += sr.iters;
+    rst += sr.restarts;
+    lin_rel = sr.rel;
+    if (sr.nonfinite) { nonfinite = true; break; }
+    timed(c, KC_NEWTON_UPDATE, [&] {
+      k_zero_u64<<<1, 64, 0, c->stream>>>(c->dcount);
+      launch_newton_update(c->nd, c->g, c->Uk, c->x, c->nu, c->cfg.c, c->dcount, c->stream);
+    });
+    ++it;
+  }
+  unsigned long long nf = 0;
+  k_zero_u64<<<1, 64, 0, c->stream>>>(c->dcount);
+  launch_count_f(c->nd, c->g, c->Uk, c->cfg.c, c->dcount, c->stream);
+  HIPCHK(c, hipMemcpyAsync(&nf, c->dcount, sizeof(nf), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  prof_collect(c);
+  if (converged) {
+    if ((st = copy_state_out(c, c->Uk, U)) != M1_OK) return st;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+  }
+  if (stats) {
+    stats->newton_iters = it;
+    stats->krylov_iters = kry;
+    stats->restarts = rst;
+    stats->fell_back = 0;
+    stats->rel_residual = lin_rel;
+    stats->nonlinear_residual = rel;
+    stats->cells_f_gt_1 = (int64_t)nf;
+    stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+  if (nonfinite) { c->err = "non-finite value in the Newton/GMRES iteration"; return M1_ERR_NONFINITE; }
+  if (!converged) { c->err = "Newton iteration did not converge"; return M1_NOT_CONVERGED; }
+  return M1_OK;
+}
+
+void m1_destroy(m1_ctx* c) {
+  if (!c) return;
+  if (c->stream) hipStreamSynchronize(c->stream);
+  free_all(c);
+  delete c;
+}
+
+const char* m1_last_error(const m1_ctx* c) { return c ? c->err.c_str() : g_setup_err.c_str(); }
+
+m1_status m1_profile_enable(m1_ctx* c, int32_t on) {
+  if (!c) return M1_ERR_INVALID_ARG;
+  prof_collect(c);
+  c->prof.on = on != 0;
+  for (int k = 0; k < KC_COUNT; ++k) {
+    c->prof.launches[k] = 0;
+    c->prof.ms[k] = 0.0;
+  }
+  return M1_OK;
+}
+
+m1_status m1_profile_query(m1_ctx* c, int32_t kc, int64_t* launches, double* total_ms) {
+  if (!c || kc < 0 || kc >= KC_COUNT || !launches || !total_ms) return M1_ERR_INVALID_ARG;
+  prof_collect(c);
+  *launches = c->prof.launches[kc];
+  *total_ms = c->prof.ms[kc];
+  return M1_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,93 @@
+// Host-side internals shared by the kernel translation units and the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "m1_device.h"
+
+namespace m1 {
+
+// Pointers into one coefficient slab (FP64 master or FP32 shadow, same layout).
+template <typename R> struct Coefs {
+  R* jac;        // njac x N        : c^2 dP_pair/d(E,F_l) per cell
+  R* face;       // 3*ND x N        : (a, dd, alpha) of the +face of each cell, direction-major
+  R* lowface;    // per direction d : 3 x plane_n[d] at lowoff[d] (-face of the first cell, non-periodic)
+  R* gjac;       // per face f      : njac x plane_n[f/2] at gjoff[f] (ghost Jacobians, non-periodic)
+  R* sigma;      // N
+  R* kap;        // N  : 4 a_r T_k^3 (coupled)
+  R* rcv;        // N  : rho c_v (coupled)
+  R* bjinv;      // nu*nu x N : inverse of the diagonal block, row-major per cell
+  int64_t lowoff[3];
+  int64_t gjoff[6];
+};
+
+// Boundary data and time-level state needed by the residual and the setup.
+struct Bdry {
+  const double* plane[6];  // Dirichlet ghost (E, F) planes (context copies)
+  const double* mask[6];   // optional masks
+};
+
+struct GmresState {
+  int done;       // cycle finished (estimate below tolerance, breakdown, or final step)
+  int k;          // columns used for the solution
+  int breakdown;
+  int nonfinite;
+  double beta;    // residual norm at the cycle start
+  double tol;     // absolute tolerance on the least-squares estimate
+  double est;     // current least-squares residual estimate |g_k|
+  double inv_nu;
+  double cc;
+  double hprev[kMaxRestart + 1];
+  double Hraw[(kMaxRestart + 1) * kMaxRestart];  // unrotated Hessenberg, column-major (ld = kMaxRestart+1)
+  double Rm[(kMaxRestart + 1) * kMaxRestart];    // rotated (upper triangular) Hessenberg
+  double cs[kMaxRestart], sn[kMaxRestart];
+  double g[kMaxRestart + 1];
+  double coef_s[kMaxRestart];
+  double coef_t[kMaxRestart];
+  double y[kMaxRestart];
+};
+
+enum KernelClass {
+  KC_SETUP = 0, KC_SETUP_BJ, KC_RESIDUAL, KC_APPLY, KC_BJ, KC_DOT, KC_SCALAR, KC_UPDATE, KC_XUPDATE,
+  KC_TRUE_RESID, KC_NEWTON_UPDATE, KC_NORM, KC_CONVERT, KC_COUNT
+};
+
+// ---- launchers (defined in m1_kernels.hip / m1_krylov.hip) ----
+void launch_fn(int nd, const Geom& g, const Scheme& sc, const double* Un, double* fn, hipStream_t s);
+void launch_setup(int nd, bool cpl, const Geom& g, const Scheme& sc, const Coefs<double>& cf, const Bdry& bd,
+                  const double* Uk, const double* Un, const double* fn, hipStream_t s);
+void launch_setup_bj(int nd, bool cpl, const Geom& g, const Scheme& sc, const Coefs<double>& cf, const Bdry& bd,
+                     hipStream_t s);
+// mode: 0 y = A x, 1 y = b - A x
+template <typename R, typename VI, typename VO>
+void launch_apply(int nd, bool cpl, int mode, const Geom& g, const Scheme& sc, const Coefs<R>& cf, const Bdry& bd,
+                  const VI* x, const double* b, VO* y, hipStream_t s);
+void launch_residual(int nd, bool cpl, const Geom& g, const Scheme& sc, const Coefs<double>& cf, const Bdry& bd,
+                     const double* Uk, const double* Un, double* out_negR, hipStream_t s);
+template <typename R, typename VI, typename VO>
+void launch_bj(int nd, bool cpl, const Geom& g, const Coefs<R>& cf, const VI* r, VO* z, hipStream_t s);
+void launch_convert(const double* src, float* dst, int64_t n, hipStream_t s);
+
+// Krylov pieces
+int dot_blocks(int64_t n);
+template <typename TV>
+void launch_dot(int j, const TV* V, int64_t vstride, const TV* u, const TV* p, int64_t n, double* partials, int nb,
+                const GmresState* gs, hipStream_t s);
+void launch_scalar(int j, int final_step, const double* partials, int nb, GmresState* gs, hipStream_t s);
+template <typename TV>
+void launch_update(int j, TV* V, int64_t vstride, const TV* u, const TV* p, TV* unext, int64_t n,
+                   const GmresState* gs, hipStream_t s);
+template <typename R, typename TV>
+void launch_xupdate(int nd, bool cpl, const Geom& g, const Coefs<R>& cf, const TV* V, int64_t vstride,
+                    const GmresState* gs, double* x, int use_pc, hipStream_t s);
+void launch_reduce(const double* partials, int nv, int nb, double* out, hipStream_t s);
+void launch_cycle_init(GmresState* gs, const double* beta2, double tol_abs, double tol_rel, hipStream_t s);
+void launch_newton_update(int nd, const Geom& g, double* Uk, const double* dx, int nu, double c,
+                          unsigned long long* fcount, hipStream_t s);
+void launch_count_f(int nd, const Geom& g, const double* U, double c, unsigned long long* fcount, hipStream_t s);
+void launch_scale(double* v, double a, int64_t n, hipStream_t s);
+template <typename TS, typename TD>
+void launch_copy_cast(const TS* src, TD* dst, int64_t n, hipStream_t s);
+
+}  // namespace m1

@@ -1,0 +1,621 @@
+// Scheme kernels for gfx950: linearisation setup (closure, HLL weights, alpha,
+// tensor Jacobian), block-Jacobi assembly and apply, and the stencil kernel that
+// evaluates the residual R(U) or applies the linearised operator A.
+//
+// Thread mapping of the stencil kernels: a 64 x 4 block covers 64 consecutive x
+// cells (one wavefront per grid row, coalesced SoA loads) on 4 rows; blockIdx.y
+// walks rows (j + ny*k).
+#include <algorithm>
+
+#include "m1_internal.h"
+
+namespace m1 {
+
+constexpr int TX = 64;
+constexpr int TY = 4;
+
+struct CellPos {
+  int idx[3];
+  int64_t cell;
+};
+
+__device__ __forceinline__ bool cell_pos(const Geom& g, CellPos& p) {
+  const int i = blockIdx.x * TX + threadIdx.x;
+  const int row = blockIdx.y * TY + threadIdx.y;
+  if (i >= g.n[0] || row >= g.rows) return false;
+  p.idx[0] = i;
+  p.idx[1] = row % g.n[1];
+  p.idx[2] = row / g.n[1];
+  p.cell = (int64_t)row * g.n[0] + i;
+  return true;
+}
+
+// Neighbour along direction d on side (0 = lower, 1 = upper).
+// kind: 0 interior/periodic neighbour (index in nb), 1 ghost.
+struct Nb {
+  int kind;
+  int64_t nb;
+  int64_t pidx;
+};
+
+__device__ __forceinline__ Nb neighbour(const Geom& g, const CellPos& p, int d, int side) {
+  Nb r;
+  const int id = p.idx[d];
+  const int n = g.n[d];
+  const int bc = g.bc[2 * d + side];
+  r.pidx = plane_index(d, p.idx[0], p.idx[1], p.idx[2], g);
+  if (side == 1) {
+    if (id < n - 1) { r.kind = 0; r.nb = p.cell + g.stride[d]; }
+    else if (bc == BC_PERIODIC) { r.kind = 0; r.nb = p.cell - (int64_t)(n - 1) * g.stride[d]; }
+    else { r.kind = 1; r.nb = p.cell; }
+  } else {
+    if (id > 0) { r.kind = 0; r.nb = p.cell - g.stride[d]; }
+    else if (bc == BC_PERIODIC) { r.kind = 0; r.nb = p.cell + (int64_t)(n - 1) * g.stride[d]; }
+    else { r.kind = 1; r.nb = p.cell; }
+  }
+  return r;
+}
+
+// ----------------------------------------------------------------------------
+// |f^n| per cell (the reduced flux alpha averages, Sect. 3.1.3)
+// ----------------------------------------------------------------------------
+template <int ND>
+__global__ __launch_bounds__(256) void k_fn(Geom g, Scheme sc, const double* __restrict__ Un, double* __restrict__ fn) {
+  CellPos p;
+  if (!cell_pos(g, p)) return;
+  double F[ND];
+#pragma unroll
+  for (int m = 0; m < ND; ++m) F[m] = Un[(1 + m) * g.N + p.cell];
+  fn[p.cell] = closure<ND>(Un[p.cell], F, sc.c, sc.p1).f;
+}
+
+void launch_fn(int nd, const Geom& g, const Scheme& sc, const double* Un, double* fn, hipStream_t s) {
+  dim3 blk(TX, TY), grd((g.n[0] + TX - 1) / TX, (g.rows + TY - 1) / TY);
+  if (nd == 2) k_fn<2><<<grd, blk, 0, s>>>(g, sc, Un, fn);
+  else k_fn<3><<<grd, blk, 0, s>>>(g, sc, Un, fn);
+}
+
+// ----------------------------------------------------------------------------
+// a1: linearisation setup at the iterate U^k
+// ----------------------------------------------------------------------------
+template <int ND>
+__device__ __forceinline__ void load_rad(const double* U, int64_t N, int64_t cell, double* out) {
+#pragma unroll
+  for (int c = 0; c < 1 + ND; ++c) out[c] = U[c * N + cell];
+}
+
+template <int ND, bool CPL>
+__global__ __launch_bounds__(256) void k_setup(Geom g, Scheme sc, Coefs<double> cf, Bdry bd,
+                                               const double* __restrict__ Uk, const double* __restrict__ Un,
+                                               const double* __restrict__ fn) {
+  using D = Dims<ND>;
+  CellPos p;
+  if (!cell_pos(g, p)) return;
+  const int64_t N = g.N;
+  double Us[1 + ND];
+  load_rad<ND>(Uk, N, p.cell, Us);
+  const ClosureState<ND> cs = closure<ND>(Us[0], Us + 1, sc.c, sc.p1);
+  {
+    double J[D::njac];
+    pressure_jacobian<ND>(cs, sc.c, sc.c2, sc.p1, sc.newton, J);
+#pragma unroll
+    for (int q = 0; q < D::njac; ++q) cf.jac[q * N + p.cell] = J[q];
+  }
+  const double sig = cf.sigma[p.cell];
+  const double fself = fn[p.cell];
+#pragma unroll
+  for (int d = 0; d < ND; ++d) {
+    double lmax, lmin;
+    wave_speeds<ND>(cs, d, sc.c, sc.p1, lmax, lmin);
+    // + face: right neighbour or ghost
+    const Nb r = neighbour(g, p, d, 1);
+    double lmaxR, lminR, sigR, fR;
+    if (r.kind == 0) {
+      double UR[1 + ND];
+      load_rad<ND>(Uk, N, r.nb, UR);
+      const ClosureState<ND> cr = closure<ND>(UR[0], UR + 1, sc.c, sc.p1);
+      wave_speeds<ND>(cr, d, sc.c, sc.p1, lmaxR, lminR);
+      sigR = cf.sigma[r.nb];
+      fR = fn[r.nb];
+    } else {
+      const int face = 2 * d + 1;
+      const int64_t pn = g.plane_n[d];
+      double UG[1 + ND], UnS[1 + ND], UnG[1 + ND];
+      ghost_state<ND>(g.bc[face], d, bd.plane[face], bd.mask[face], r.pidx, pn, Us, UG);
+      const ClosureState<ND> cg = closure<ND>(UG[0], UG + 1, sc.c, sc.p1);
+      wave_speeds<ND>(cg, d, sc.c, sc.p1, lmaxR, lminR);
+      load_rad<ND>(Un, N, p.cell, UnS);
+      ghost_state<ND>(g.bc[face], d, bd.plane[face], bd.mask[face], r.pidx, pn, UnS, UnG);
+      fR = closure<ND>(UnG[0], UnG + 1, sc.c, sc.p1).f;
+      sigR = sig;
+      double J[D::njac];
+      pressure_jacobian<ND>(cg, sc.c, sc.c2, sc.p1, sc.newton, J);
+#pragma unroll
+      for (int q = 0; q < D::njac; ++q) cf.gjac[cf.gjoff[face] + q * pn + r.pidx] = J[q];
+    }
+    const FaceCoef fc = face_coef(lmax, lmin, lmaxR, lminR, 0.5 * (sig + sigR), 0.5 * (fself + fR), sc);
+    cf.face[(3 * d + 0) * N + p.cell] = fc.a;
+    cf.face[(3 * d + 1) * N + p.cell] = fc.dd;
+    cf.face[(3 * d + 2) * N + p.cell] = fc.alpha;
+    // - face of the first cell on a non-periodic direction: ghost on the left
+    const Nb l = neighbour(g, p, d, 0);
+    if (l.kind == 1) {
+      const int face = 2 * d;
+      const int64_t pn = g.plane_n[d];
+      double UG[1 + ND], UnS[1 + ND], UnG[1 + ND];
+      ghost_state<ND>(g.bc[face], d, bd.plane[face], bd.mask[face], l.pidx, pn, Us, UG);
+      const ClosureState<ND> cg = closure<ND>(UG[0], UG + 1, sc.c, sc.p1);
+      double lmaxL, lminL;
+      wave_speeds<ND>(cg, d, sc.c, sc.p1, lmaxL, lminL);
+      load_rad<ND>(Un, N, p.cell, UnS);
+      ghost_state<ND>(g.bc[face], d, bd.plane[face], bd.mask[face], l.pidx, pn, UnS, UnG);
+      const double fL = closure<ND>(UnG[0], UnG + 1, sc.c, sc.p1).f;
+      const FaceCoef fl = face_coef(lmaxL, lminL, lmax, lmin, sig, 0.5 * (fL + fself), sc);
+      cf.lowface[cf.lowoff[d] + 0 * pn + l.pidx] = fl.a;
+      cf.lowface[cf.lowoff[d] + 1 * pn + l.pidx] = fl.dd;
+      cf.lowface[cf.lowoff[d] + 2 * pn + l.pidx] = fl.alpha;
+      double J[D::njac];
+      pressure_jacobian<ND>(cg, sc.c, sc.c2, sc.p1, sc.newton, J);
+#pragma unroll
+      for (int q = 0; q < D::njac; ++q) cf.gjac[cf.gjoff[face] + q * pn + l.pidx] = J[q];
+    }
+  }
+  if (CPL) {
+    const double T = Uk[(1 + ND) * N + p.cell];
+    cf.kap[p.cell] = 4.0 * sc.a_r * T * T * T;
+  }
+}
+
+void launch_setup(int nd, bool cpl, const Geom& g, const Scheme& sc, const Coefs<double>& cf, const Bdry& bd,
+                  const double* Uk, const double* Un, const double* fn, hipStream_t s) {
+  dim3 blk(TX, TY), grd((g.n[0] + TX - 1) / TX, (g.rows + TY - 1) / TY);
+  if (nd == 2) {
+    if (cpl) k_setup<2, true><<<grd, blk, 0, s>>>(g, sc, cf, bd, Uk, Un, fn);
+    else k_setup<2, false><<<grd, blk, 0, s>>>(g, sc, cf, bd, Uk, Un, fn);
+  } else {
+    if (cpl) k_setup<3, true><<<grd, blk, 0, s>>>(g, sc, cf, bd, Uk, Un, fn);
+    else k_setup<3, false><<<grd, blk, 0, s>>>(g, sc, cf, bd, Uk, Un, fn);
+  }
+}
+
+// Coefficients of the -face of a cell (the +face of its left neighbour, or the
+// boundary plane).
+template <typename R>
+__device__ __forceinline__ void minus_face(const Geom& g, const Coefs<R>& cf, const Nb& l, int d, R& a, R& dd,
+                                           R& al) {
+  if (l.kind == 0) {
+    a = cf.face[(3 * d + 0) * g.N + l.nb];
+    dd = cf.face[(3 * d + 1) * g.N + l.nb];
+    al = cf.face[(3 * d + 2) * g.N + l.nb];
+  } else {
+    const int64_t pn = g.plane_n[d];
+    a = cf.lowface[cf.lowoff[d] + 0 * pn + l.pidx];
+    dd = cf.lowface[cf.lowoff[d] + 1 * pn + l.pidx];
+    al = cf.lowface[cf.lowoff[d] + 2 * pn + l.pidx];
+  }
+}
+
+// ----------------------------------------------------------------------------
+// Block-Jacobi: assemble the exact diagonal block of A and invert it
+// ----------------------------------------------------------------------------
+template <int NU>
+__device__ __forceinline__ bool invert_block(double (&A)[NU][NU], double (&Ai)[NU][NU]) {
+#pragma unroll
+  for (int r = 0; r < NU; ++r)
+#pragma unroll
+    for (int c = 0; c < NU; ++c) Ai[r][c] = r == c ? 1.0 : 0.0;
+  bool ok = true;
+#pragma unroll
+  for (int col = 0; col < NU; ++col) {
+    // partial pivoting (rows col..NU-1)
+    int piv = col;
+    double best = fabs(A[col][col]);
+#pragma unroll
+    for (int r = col + 1; r < NU; ++r) {
+      const double v = fabs(A[r][col]);
+      if (v > best) { best = v; piv = r; }
+    }
+    ok = ok && best > 0.0;
+#pragma unroll
+    for (int r = col + 1; r < NU; ++r) {
+      if (r == piv) {
+#pragma unroll
+        for (int c = 0; c < NU; ++c) {
+          double t = A[col][c]; A[col][c] = A[r][c]; A[r][c] = t;
+          t = Ai[col][c]; Ai[col][c] = Ai[r][c]; Ai[r][c] = t;
+        }
+      }
+    }
+    const double inv = 1.0 / A[col][col];
+#pragma unroll
+    for (int c = 0; c < NU; ++c) { A[col][c] *= inv; Ai[col][c] *= inv; }
+#pragma unroll
+    for (int r = 0; r < NU; ++r) {
+      if (r == col) continue;
+      const double f = A[r][col];
+#pragma unroll
+      for (int c = 0; c < NU; ++c) { A[r][c] -= f * A[col][c]; Ai[r][c] -= f * Ai[col][c]; }
+    }
+  }
+  return ok;
+}
+
+template <int ND, bool CPL>
+__global__ __launch_bounds__(256) void k_setup_bj(Geom g, Scheme sc, Coefs<double> cf, Bdry bd) {
+  using Dm = Dims<ND>;
+  constexpr int NR = 1 + ND;
+  constexpr int NU = NR + (CPL ? 1 : 0);
+  CellPos p;
+  if (!cell_pos(g, p)) return;
+  const int64_t N = g.N;
+  double B[NU][NU];
+#pragma unroll
+  for (int r = 0; r < NU; ++r)
+#pragma unroll
+    for (int c = 0; c < NU; ++c) B[r][c] = (r == c && r < NR) ? 1.0 : 0.0;
+  const double sig = cf.sigma[p.cell];
+  const double s = sc.s;
+#pragma unroll
+  for (int d = 0; d < ND; ++d) {
+    // Jacobian rows (d, m) of this cell
+    double Js[ND][NR];
+#pragma unroll
+    for (int m = 0; m < ND; ++m)
+#pragma unroll
+      for (int k = 0; k < NR; ++k) Js[m][k] = cf.jac[(pair_index<ND>(d, m) * NR + k) * N + p.cell];
+    // ---- + face ----
+    const double a = cf.face[(3 * d + 0) * N + p.cell];
+    const double dd = cf.face[(3 * d + 1) * N + p.cell];
+    const double al = cf.face[(3 * d + 2) * N + p.cell];
+    const double b = 1.0 - a;
+    const Nb r = neighbour(g, p, d, 1);
+    double gR[NR];
+    double JR[ND][NR];
+    double sigR;
+    if (r.kind == 1) {
+      const int face = 2 * d + 1;
+      const int64_t pn = g.plane_n[d];
+#pragma unroll
+      for (int k = 0; k < NR; ++k) gR[k] = ghost_weight(g.bc[face], d, k, bd.mask[face], r.pidx);
+#pragma unroll
+      for (int m = 0; m < ND; ++m)
+#pragma unroll
+        for (int k = 0; k < NR; ++k) JR[m][k] = cf.gjac[cf.gjoff[face] + (pair_index<ND>(d, m) * NR + k) * pn + r.pidx];
+      sigR = sig;
+    } else {
+      const double self = (r.nb == p.cell) ? 1.0 : 0.0;  // periodic with one cell
+#pragma unroll
+      for (int k = 0; k < NR; ++k) gR[k] = self;
+#pragma unroll
+      for (int m = 0; m < ND; ++m)
+#pragma unroll
+        for (int k = 0; k < NR; ++k) JR[m][k] = Js[m][k];
+      sigR = cf.sigma[r.nb];
+    }
+    B[0][0] += s * al * dd * (gR[0] - 1.0);
+    B[0][1 + d] += s * al * (a + b * gR[1 + d]);
+#pragma unroll
+    for (int m = 0; m < ND; ++m) {
+#pragma unroll
+      for (int k = 0; k < NR; ++k) B[1 + m][k] += s * (a * Js[m][k] + b * JR[m][k] * gR[k]);
+      B[1 + m][1 + m] += s * dd * (gR[1 + m] - 1.0);
+    }
+    // ---- - face ----
+    const Nb l = neighbour(g, p, d, 0);
+    double am, ddm, alm;
+    minus_face(g, cf, l, d, am, ddm, alm);
+    const double bm = 1.0 - am;
+    double gL[NR];
+    double JL[ND][NR];
+    double sigL;
+    if (l.kind == 1) {
+      const int face = 2 * d;
+      const int64_t pn = g.plane_n[d];
+#pragma unroll
+      for (int k = 0; k < NR; ++k) gL[k] = ghost_weight(g.bc[face], d, k, bd.mask[face], l.pidx);
+#pragma unroll
+      for (int m = 0; m < ND; ++m)
+#pragma unroll
+        for (int k = 0; k < NR; ++k) JL[m][k] = cf.gjac[cf.gjoff[face] + (pair_index<ND>(d, m) * NR + k) * pn + l.pidx];
+      sigL = sig;
+    } else {
+      const double self = (l.nb == p.cell) ? 1.0 : 0.0;
+#pragma unroll
+      for (int k = 0; k < NR; ++k) gL[k] = self;
+#pragma unroll
+      for (int m = 0; m < ND; ++m)
+#pragma unroll
+        for (int k = 0; k < NR; ++k) JL[m][k] = Js[m][k];
+      sigL = cf.sigma[l.nb];
+    }
+    B[0][1 + d] -= s * alm * (am * gL[1 + d] + bm);
+    B[0][0] -= s * alm * ddm * (1.0 - gL[0]);
+#pragma unroll
+    for (int m = 0; m < ND; ++m) {
+#pragma unroll
+      for (int k = 0; k < NR; ++k) B[1 + m][k] -= s * (am * JL[m][k] * gL[k] + bm * Js[m][k]);
+      B[1 + m][1 + m] -= s * ddm * (1.0 - gL[1 + m]);
+    }
+    if (sc.wb) {
+      B[1 + d][1 + d] += 0.25 * sc.cdt * (0.5 * (sig + sigR) * (1.0 + gR[1 + d]) + 0.5 * (sig + sigL) * (gL[1 + d] + 1.0));
+    }
+  }
+  if (!sc.wb) {
+#pragma unroll
+    for (int m = 0; m < ND; ++m) B[1 + m][1 + m] += sc.cdt * sig;
+  }
+  if (sc.src == SRC_ABS) B[0][0] += sc.cdt * sig;
+  if (CPL) {
+    const double kap = cf.kap[p.cell];
+    const double rcv = cf.rcv[p.cell];
+    const double k = sc.cdt * sig;
+    B[0][0] += k;
+    B[0][NU - 1] -= k * kap;
+    B[NU - 1][0] -= k;
+    B[NU - 1][NU - 1] += rcv + k * kap;
+  }
+  double Bi[NU][NU];
+  invert_block<NU>(B, Bi);
+#pragma unroll
+  for (int rr = 0; rr < NU; ++rr)
+#pragma unroll
+    for (int c = 0; c < NU; ++c) cf.bjinv[(rr * NU + c) * N + p.cell] = Bi[rr][c];
+}
+
+void launch_setup_bj(int nd, bool cpl, const Geom& g, const Scheme& sc, const Coefs<double>& cf, const Bdry& bd,
+                     hipStream_t s) {
+  dim3 blk(TX, TY), grd((g.n[0] + TX - 1) / TX, (g.rows + TY - 1) / TY);
+  if (nd == 2) {
+    if (cpl) k_setup_bj<2, true><<<grd, blk, 0, s>>>(g, sc, cf, bd);
+    else k_setup_bj<2, false><<<grd, blk, 0, s>>>(g, sc, cf, bd);
+  } else {
+    if (cpl) k_setup_bj<3, true><<<grd, blk, 0, s>>>(g, sc, cf, bd);
+    else k_setup_bj<3, false><<<grd, blk, 0, s>>>(g, sc, cf, bd);
+  }
+}
+
+// ----------------------------------------------------------------------------
+// a2 / a3: stencil kernel.  MODE 0: y = A x; 1: y = b - A x; 2: y = -R(U), x = U^k
+// ----------------------------------------------------------------------------
+template <int ND, bool CPL, int MODE, typename R, typename VI, typename VO>
+__global__ __launch_bounds__(256) void k_stencil(Geom g, Scheme sc, Coefs<R> cf, Bdry bd, const VI* __restrict__ x,
+                                                 const double* __restrict__ b, const double* __restrict__ Un,
+                                                 VO* __restrict__ y) {
+  constexpr int NR = 1 + ND;
+  constexpr int NU = NR + (CPL ? 1 : 0);
+  CellPos p;
+  if (!cell_pos(g, p)) return;
+  const int64_t N = g.N;
+  const R s = (R)sc.s;
+  const R cdt = (R)sc.cdt;
+  R xs[NU];
+#pragma unroll
+  for (int c = 0; c < NU; ++c) xs[c] = (R)x[c * N + p.cell];
+  R ys[NU];
+#pragma unroll
+  for (int c = 0; c < NR; ++c) ys[c] = (MODE == 2) ? xs[c] - (R)Un[c * N + p.cell] : xs[c];
+  if (CPL) ys[NU - 1] = (R)0;
+  const R sig = cf.sigma[p.cell];
+
+  // c^2 P_{dm} (residual: from the state) or its linearisation J x (apply) of a cell
+  auto pressure_cell = [&](int d, int64_t cell, const R* xc, R* q) {
+    if (MODE == 2) {
+      double Fd[ND];
+#pragma unroll
+      for (int m = 0; m < ND; ++m) Fd[m] = (double)xc[1 + m];
+      const ClosureState<ND> cs = closure<ND>((double)xc[0], Fd, sc.c, sc.p1);
+#pragma unroll
+      for (int m = 0; m < ND; ++m) q[m] = (R)(c2D<ND>(cs, d, m, sc.c2) * (double)xc[0]);
+    } else {
+#pragma unroll
+      for (int m = 0; m < ND; ++m) {
+        R acc = (R)0;
+#pragma unroll
+        for (int k = 0; k < NR; ++k) acc += cf.jac[(pair_index<ND>(d, m) * NR + k) * N + cell] * xc[k];
+        q[m] = acc;
+      }
+    }
+  };
+  auto pressure_ghost = [&](int d, int face, int64_t pidx, const R* xg, R* q) {
+    if (MODE == 2) {
+      double Fd[ND];
+#pragma unroll
+      for (int m = 0; m < ND; ++m) Fd[m] = (double)xg[1 + m];
+      const ClosureState<ND> cs = closure<ND>((double)xg[0], Fd, sc.c, sc.p1);
+#pragma unroll
+      for (int m = 0; m < ND; ++m) q[m] = (R)(c2D<ND>(cs, d, m, sc.c2) * (double)xg[0]);
+    } else {
+      const int64_t pn = g.plane_n[d];
+#pragma unroll
+      for (int m = 0; m < ND; ++m) {
+        R acc = (R)0;
+#pragma unroll
+        for (int k = 0; k < NR; ++k) acc += cf.gjac[cf.gjoff[face] + (pair_index<ND>(d, m) * NR + k) * pn + pidx] * xg[k];
+        q[m] = acc;
+      }
+    }
+  };
+  // state or perturbation of the ghost beside this cell
+  auto ghost_value = [&](int d, int face, int64_t pidx, R* xg) {
+    if (MODE == 2) {
+      double Us[NR], Ug[NR];
+#pragma unroll
+      for (int c = 0; c < NR; ++c) Us[c] = (double)xs[c];
+      ghost_state<ND>(g.bc[face], d, bd.plane[face], bd.mask[face], pidx, g.plane_n[d], Us, Ug);
+#pragma unroll
+      for (int c = 0; c < NR; ++c) xg[c] = (R)Ug[c];
+    } else {
+#pragma unroll
+      for (int c = 0; c < NR; ++c) xg[c] = (R)ghost_weight(g.bc[face], d, c, bd.mask[face], pidx) * xs[c];
+    }
+  };
+
+#pragma unroll
+  for (int d = 0; d < ND; ++d) {
+    R qs[ND];
+    pressure_cell(d, p.cell, xs, qs);
+    // right neighbour
+    const Nb r = neighbour(g, p, d, 1);
+    R xr[NR], qr[ND], sigR;
+    if (r.kind == 0) {
+#pragma unroll
+      for (int c = 0; c < NR; ++c) xr[c] = (R)x[c * N + r.nb];
+      pressure_cell(d, r.nb, xr, qr);
+      sigR = cf.sigma[r.nb];
+    } else {
+      ghost_value(d, 2 * d + 1, r.pidx, xr);
+      pressure_ghost(d, 2 * d + 1, r.pidx, xr, qr);
+      sigR = sig;
+    }
+    // left neighbour
+    const Nb l = neighbour(g, p, d, 0);
+    R xl[NR], ql[ND], sigL;
+    if (l.kind == 0) {
+#pragma unroll
+      for (int c = 0; c < NR; ++c) xl[c] = (R)x[c * N + l.nb];
+      pressure_cell(d, l.nb, xl, ql);
+      sigL = cf.sigma[l.nb];
+    } else {
+      ghost_value(d, 2 * d, l.pidx, xl);
+      pressure_ghost(d, 2 * d, l.pidx, xl, ql);
+      sigL = sig;
+    }
+    const R ap = cf.face[(3 * d + 0) * N + p.cell];
+    const R ddp = cf.face[(3 * d + 1) * N + p.cell];
+    const R alp = cf.face[(3 * d + 2) * N + p.cell];
+    const R bp = (R)1 - ap;
+    R am, ddm, alm;
+    minus_face(g, cf, l, d, am, ddm, alm);
+    const R bm = (R)1 - am;
+    // energy flux (HLL with the asymptotic correction alpha)
+    const R FEp = alp * (ap * xs[1 + d] + bp * xr[1 + d] + ddp * (xr[0] - xs[0]));
+    const R FEm = alm * (am * xl[1 + d] + bm * xs[1 + d] + ddm * (xs[0] - xl[0]));
+    ys[0] += s * (FEp - FEm);
+    // radiative-flux fluxes
+#pragma unroll
+    for (int m = 0; m < ND; ++m) {
+      const R FPp = ap * qs[m] + bp * qr[m] + ddp * (xr[1 + m] - xs[1 + m]);
+      const R FPm = am * ql[m] + bm * qs[m] + ddm * (xs[1 + m] - xl[1 + m]);
+      ys[1 + m] += s * (FPp - FPm);
+    }
+    if (sc.wb) {
+      // {sigma F_d}: trapezoidal face average over the two faces normal to d
+      ys[1 + d] += (R)0.25 * cdt *
+                   ((R)0.5 * (sig + sigR) * (xs[1 + d] + xr[1 + d]) + (R)0.5 * (sig + sigL) * (xl[1 + d] + xs[1 + d]));
+    }
+  }
+  if (!sc.wb) {
+#pragma unroll
+    for (int m = 0; m < ND; ++m) ys[1 + m] += cdt * sig * xs[1 + m];
+  }
+  if (sc.src == SRC_ABS) ys[0] += cdt * sig * xs[0];
+  if (CPL) {
+    const R T = xs[NU - 1];
+    R exch;
+    if (MODE == 2) {
+      const double Td = (double)T;
+      exch = (R)(sc.cdt * (double)sig * (sc.a_r * Td * Td * Td * Td - (double)xs[0]));
+      ys[NU - 1] = cf.rcv[p.cell] * (T - (R)Un[(NU - 1) * N + p.cell]) + exch;
+    } else {
+      exch = cdt * sig * (cf.kap[p.cell] * T - xs[0]);
+      ys[NU - 1] = cf.rcv[p.cell] * T + exch;
+    }
+    ys[0] -= exch;
+  }
+#pragma unroll
+  for (int c = 0; c < NU; ++c) {
+    R v = ys[c];
+    if (MODE == 1) v = (R)b[c * N + p.cell] - v;
+    if (MODE == 2) v = -v;
+    y[c * N + p.cell] = (VO)v;
+  }
+}
+
+template <typename R, typename VI, typename VO>
+void launch_apply(int nd, bool cpl, int mode, const Geom& g, const Scheme& sc, const Coefs<R>& cf, const Bdry& bd,
+                  const VI* x, const double* b, VO* y, hipStream_t s) {
+  dim3 blk(TX, TY), grd((g.n[0] + TX - 1) / TX, (g.rows + TY - 1) / TY);
+#define M1_ST(ND_, CPL_, MODE_) k_stencil<ND_, CPL_, MODE_, R, VI, VO><<<grd, blk, 0, s>>>(g, sc, cf, bd, x, b, nullptr, y)
+  if (nd == 2) {
+    if (cpl) { if (mode == 0) M1_ST(2, true, 0); else M1_ST(2, true, 1); }
+    else { if (mode == 0) M1_ST(2, false, 0); else M1_ST(2, false, 1); }
+  } else {
+    if (cpl) { if (mode == 0) M1_ST(3, true, 0); else M1_ST(3, true, 1); }
+    else { if (mode == 0) M1_ST(3, false, 0); else M1_ST(3, false, 1); }
+  }
+#undef M1_ST
+}
+
+void launch_residual(int nd, bool cpl, const Geom& g, const Scheme& sc, const Coefs<double>& cf, const Bdry& bd,
+                     const double* Uk, const double* Un, double* out, hipStream_t s) {
+  dim3 blk(TX, TY), grd((g.n[0] + TX - 1) / TX, (g.rows + TY - 1) / TY);
+  if (nd == 2) {
+    if (cpl) k_stencil<2, true, 2, double, double, double><<<grd, blk, 0, s>>>(g, sc, cf, bd, Uk, nullptr, Un, out);
+    else k_stencil<2, false, 2, double, double, double><<<grd, blk, 0, s>>>(g, sc, cf, bd, Uk, nullptr, Un, out);
+  } else {
+    if (cpl) k_stencil<3, true, 2, double, double, double><<<grd, blk, 0, s>>>(g, sc, cf, bd, Uk, nullptr, Un, out);
+    else k_stencil<3, false, 2, double, double, double><<<grd, blk, 0, s>>>(g, sc, cf, bd, Uk, nullptr, Un, out);
+  }
+}
+
+// ----------------------------------------------------------------------------
+// a4: z = M^{-1} r with the stored block inverses
+// ----------------------------------------------------------------------------
+template <int NU, typename R, typename VI, typename VO>
+__global__ __launch_bounds__(256) void k_bj(int64_t N, const R* __restrict__ inv, const VI* __restrict__ r,
+                                            VO* __restrict__ z) {
+  const int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (cell >= N) return;
+  R rv[NU];
+#pragma unroll
+  for (int c = 0; c < NU; ++c) rv[c] = (R)r[c * N + cell];
+#pragma unroll
+  for (int rr = 0; rr < NU; ++rr) {
+    R acc = (R)0;
+#pragma unroll
+    for (int c = 0; c < NU; ++c) acc += inv[(rr * NU + c) * N + cell] * rv[c];
+    z[rr * N + cell] = (VO)acc;
+  }
+}
+
+template <typename R, typename VI, typename VO>
+void launch_bj(int nd, bool cpl, const Geom& g, const Coefs<R>& cf, const VI* r, VO* z, hipStream_t s) {
+  const int nu = 1 + nd + (cpl ? 1 : 0);
+  const int blk = 256;
+  const int64_t grd = (g.N + blk - 1) / blk;
+  switch (nu) {
+    case 3: k_bj<3, R, VI, VO><<<grd, blk, 0, s>>>(g.N, cf.bjinv, r, z); break;
+    case 4: k_bj<4, R, VI, VO><<<grd, blk, 0, s>>>(g.N, cf.bjinv, r, z); break;
+    case 5: k_bj<5, R, VI, VO><<<grd, blk, 0, s>>>(g.N, cf.bjinv, r, z); break;
+  }
+}
+
+__global__ void k_convert(const double* __restrict__ src, float* __restrict__ dst, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = (float)src[i];
+}
+
+void launch_convert(const double* src, float* dst, int64_t n, hipStream_t s) {
+  const int64_t grd = std::min<int64_t>((n + 255) / 256, 4096);
+  k_convert<<<grd, 256, 0, s>>>(src, dst, n);
+}
+
+// explicit instantiations
+template void launch_apply<double, double, double>(int, bool, int, const Geom&, const Scheme&, const Coefs<double>&,
+                                                   const Bdry&, const double*, const double*, double*, hipStream_t);
+template void launch_apply<float, float, double>(int, bool, int, const Geom&, const Scheme&, const Coefs<float>&,
+                                                 const Bdry&, const float*, const double*, double*, hipStream_t);
+template void launch_apply<float, float, float>(int, bool, int, const Geom&, const Scheme&, const Coefs<float>&,
+                                                const Bdry&, const float*, const double*, float*, hipStream_t);
+template void launch_apply<float, double, double>(int, bool, int, const Geom&, const Scheme&, const Coefs<float>&,
+                                                  const Bdry&, const double*, const double*, double*, hipStream_t);
+template void launch_apply<double, double, float>(int, bool, int, const Geom&, const Scheme&, const Coefs<double>&,
+                                                  const Bdry&, const double*, const double*, float*, hipStream_t);
+template void launch_bj<double, double, double>(int, bool, const Geom&, const Coefs<double>&, const double*, double*,
+                                                hipStream_t);
+template void launch_bj<float, double, float>(int, bool, const Geom&, const Coefs<float>&, const double*, float*,
+                                              hipStream_t);
+template void launch_bj<float, float, float>(int, bool, const Geom&, const Coefs<float>&, const float*, float*,
+                                             hipStream_t);
+
+}  // namespace m1

@@ -1,0 +1,436 @@
+// Krylov kernels for gfx950: restarted GMRES with a one-reduction Arnoldi that
+// delays the second Gram-Schmidt pass by one iteration.
+//
+// Iteration j (Q_j = [q_0..q_{j-1}] orthonormal, u_j the once-projected candidate
+// for q_j, p = B u_j with B = A M^{-1}):
+//   one fused pass     s = Q_j^T u_j, t = Q_j^T p, alpha = u_j.u_j, gamma = u_j.p
+//   one workgroup      nu = sqrt(alpha - |s|^2); column j-1 of H = h'_{j-1} + s, H[j,j-1] = nu;
+//                      Givens update; cc = (gamma - s.t)/nu^2;
+//                      h'_j = ([t; (gamma - s.t)/nu] - H s) / nu
+//   one fused pass     q_j = (u_j - Q_j s)/nu,  u_{j+1} = (p - Q_j (t - cc s) - cc u_j)/nu
+// which follows from q_j = (u_j - Q_j s)/nu, B q_j = (p - Q_{j+1} H s)/nu and the
+// orthonormality of Q_{j+1}.  The vector passes read the basis twice per iteration
+// instead of four times for classical Gram-Schmidt with reorthogonalisation.
+// All sums accumulate in FP64 whatever the basis storage type; reductions are
+// two-stage (per-block partials, then one workgroup) in a fixed order, so results
+// repeat bit for bit run to run.
+#include <algorithm>
+
+#include "m1_internal.h"
+
+namespace m1 {
+
+constexpr int kDotThreads = 256;
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+int dot_blocks(int64_t n) {
+  const int64_t per = (int64_t)kDotThreads * 4;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(1024, (n + per - 1) / per));
+}
+
+// partial layout: value v of block b at part[v * nb + b];
+// values: s_i (i < J), then t_i (i < J) if HASP, then alpha, then gamma if HASP
+template <int J, bool HASP, typename TV>
+__global__ __launch_bounds__(kDotThreads) void k_dot(const TV* __restrict__ V, int64_t vs, const TV* __restrict__ u,
+                                                     const TV* __restrict__ p, int64_t n, double* __restrict__ part,
+                                                     int nb, const GmresState* __restrict__ gs) {
+  if (gs && gs->done) return;
+  constexpr int NV = HASP ? 2 * J + 2 : J + 1;
+  double acc[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+  for (int64_t e = (int64_t)blockIdx.x * kDotThreads + threadIdx.x; e < n; e += (int64_t)nb * kDotThreads) {
+    const double uv = (double)u[e];
+    const double pv = HASP ? (double)p[e] : 0.0;
+#pragma unroll
+    for (int i = 0; i < J; ++i) {
+      const double q = (double)V[i * vs + e];
+      acc[i] += q * uv;
+      if (HASP) acc[J + i] += q * pv;
+    }
+    if (HASP) {
+      acc[2 * J] += uv * uv;
+      acc[2 * J + 1] += uv * pv;
+    } else {
+      acc[J] += uv * uv;
+    }
+  }
+  __shared__ double red[kDotThreads / 64][NV > 0 ? NV : 1];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    const double t = wave_sum(acc[v]);
+    if (lane == 0) red[w][v] = t;
+  }
+  __syncthreads();
+  for (int v = threadIdx.x; v < NV; v += kDotThreads) {
+    double t = 0.0;
+#pragma unroll
+    for (int ww = 0; ww < kDotThreads / 64; ++ww) t += red[ww][v];
+    part[(int64_t)v * nb + blockIdx.x] = t;
+  }
+}
+
+template <int J, bool HASP, typename TV>
+static void dot_one(const TV* V, int64_t vs, const TV* u, const TV* p, int64_t n, double* part, int nb,
+                    const GmresState* gs, hipStream_t s) {
+  k_dot<J, HASP, TV><<<nb, kDotThreads, 0, s>>>(V, vs, u, p, n, part, nb, gs);
+}
+
+template <typename TV, int... Js>
+static void dot_dispatch(std::integer_sequence<int, Js...>, int j, bool hasp, const TV* V, int64_t vs, const TV* u,
+                         const TV* p, int64_t n, double* part, int nb, const GmresState* gs, hipStream_t s) {
+  using Fn = void (*)(const TV*, int64_t, const TV*, const TV*, int64_t, double*, int, const GmresState*, hipStream_t);
+  static const Fn with_p[] = {&dot_one<Js, true, TV>...};
+  static const Fn without_p[] = {&dot_one<Js, false, TV>...};
+  (hasp ? with_p : without_p)[j](V, vs, u, p, n, part, nb, gs, s);
+}
+
+template <typename TV>
+void launch_dot(int j, const TV* V, int64_t vs, const TV* u, const TV* p, int64_t n, double* partials, int nb,
+                const GmresState* gs, hipStream_t s) {
+  dot_dispatch<TV>(std::make_integer_sequence<int, kMaxRestart + 1>{}, j, p != nullptr, V, vs, u, p, n, partials,
+                   nb, gs, s);
+}
+
+// ----------------------------------------------------------------------------
+// a6: one workgroup: reduce the partials, finalise Hessenberg column j-1,
+// Givens rotation, residual estimate, coefficients of the next update pass.
+// ----------------------------------------------------------------------------
+constexpr int kScalarThreads = 256;
+
+__global__ __launch_bounds__(kScalarThreads) void k_scalar(int j, int final_step, const double* __restrict__ part,
+                                                           int nb, GmresState* gs) {
+  if (gs->done) return;
+  const int hasp = !final_step;
+  const int nv = hasp ? 2 * j + 2 : j + 1;
+  __shared__ double red[2 * kMaxRestart + 2];
+  __shared__ double Hs[kMaxRestart + 1];
+  __shared__ double sh_nu;
+  __shared__ int sh_done;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int v = w; v < nv; v += kScalarThreads / 64) {
+    double t = 0.0;
+    for (int b = lane; b < nb; b += 64) t += part[(int64_t)v * nb + b];
+    t = wave_sum(t);
+    if (lane == 0) red[v] = t;
+  }
+  __syncthreads();
+  const double* s = red;
+  const double* t = red + j;
+  const double alpha = hasp ? red[2 * j] : red[j];
+  const double gamma = hasp ? red[2 * j + 1] : 0.0;
+  constexpr int ld = kMaxRestart + 1;
+  if (threadIdx.x == 0) {
+    double ss = 0.0;
+    for (int i = 0; i < j; ++i) ss += s[i] * s[i];
+    const double nu2 = alpha - ss;
+    int done = 0;
+    double nu = 0.0;
+    if (j == 0) {
+      nu = sqrt(fmax(alpha, 0.0));
+      gs->beta = nu;
+      gs->g[0] = nu;
+      gs->est = nu;
+      if (!(nu > 0.0)) {  // zero right-hand side (or NaN)
+        done = 1;
+        gs->k = 0;
+        if (nu != nu) gs->nonfinite = 1;
+      }
+    } else {
+      double col2 = nu2 > 0.0 ? nu2 : 0.0;
+      for (int i = 0; i < j; ++i) {
+        const double h = gs->hprev[i] + s[i];
+        col2 += h * h;
+      }
+      nu = (nu2 > 1e-28 * col2) ? sqrt(nu2) : 0.0;
+      if (nu == 0.0) gs->breakdown = 1;
+      const int c = j - 1;
+      double h[kMaxRestart + 1];
+      for (int i = 0; i < j; ++i) {
+        h[i] = gs->hprev[i] + s[i];
+        gs->Hraw[c * ld + i] = h[i];
+      }
+      h[j] = nu;
+      gs->Hraw[c * ld + j] = nu;
+      for (int i = 0; i < c; ++i) {
+        const double a = gs->cs[i] * h[i] + gs->sn[i] * h[i + 1];
+        h[i + 1] = -gs->sn[i] * h[i] + gs->cs[i] * h[i + 1];
+        h[i] = a;
+      }
+      const double den = sqrt(h[c] * h[c] + h[j] * h[j]);
+      const double cs = den > 0.0 ? h[c] / den : 1.0;
+      const double sn = den > 0.0 ? h[j] / den : 0.0;
+      gs->cs[c] = cs;
+      gs->sn[c] = sn;
+      h[c] = den;
+      h[j] = 0.0;
+      for (int i = 0; i <= j; ++i) gs->Rm[c * ld + i] = h[i];
+      gs->g[j] = -sn * gs->g[c];
+      gs->g[c] = cs * gs->g[c];
+      gs->est = fabs(gs->g[j]);
+      if (!(gs->est == gs->est) || !(den == den)) gs->nonfinite = 1;
+      if (gs->est <= gs->tol || nu == 0.0 || final_step || gs->nonfinite) {
+        done = 1;
+        gs->k = j;
+        // back substitution R y = g
+        for (int i = j - 1; i >= 0; --i) {
+          double acc = gs->g[i];
+          for (int l = i + 1; l < j; ++l) acc -= gs->Rm[l * ld + i] * gs->y[l];
+          gs->y[i] = acc / gs->Rm[i * ld + i];
+        }
+      }
+    }
+    sh_nu = nu;
+    sh_done = done;
+    if (done) gs->done = 1;
+  }
+  __syncthreads();
+  if (sh_done) return;
+  const double nu = sh_nu;
+  // (H s)[r] for r = 0..j with the unrotated Hessenberg (columns 0..j-1)
+  for (int r = threadIdx.x; r <= j; r += kScalarThreads) {
+    double acc = 0.0;
+    for (int i = 0; i < j; ++i) acc += gs->Hraw[i * ld + r] * s[i];
+    Hs[r] = acc;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double st = 0.0;
+    for (int i = 0; i < j; ++i) st += s[i] * t[i];
+    const double qp = (gamma - st) / nu;        // q_j . p
+    const double cc = qp / nu;
+    gs->cc = cc;
+    gs->inv_nu = 1.0 / nu;
+    for (int i = 0; i < j; ++i) {
+      gs->coef_s[i] = s[i];
+      gs->coef_t[i] = t[i] - cc * s[i];
+      gs->hprev[i] = (t[i] - Hs[i]) / nu;
+    }
+    gs->hprev[j] = (qp - Hs[j]) / nu;
+  }
+}
+
+void launch_scalar(int j, int final_step, const double* partials, int nb, GmresState* gs, hipStream_t s) {
+  k_scalar<<<1, kScalarThreads, 0, s>>>(j, final_step, partials, nb, gs);
+}
+
+// ----------------------------------------------------------------------------
+// update pass: q_j and u_{j+1}
+// ----------------------------------------------------------------------------
+template <int J, typename TV>
+__global__ __launch_bounds__(kDotThreads) void k_update(TV* __restrict__ V, int64_t vs, const TV* __restrict__ u,
+                                                        const TV* __restrict__ p, TV* __restrict__ unext, int64_t n,
+                                                        const GmresState* __restrict__ gs) {
+  if (gs->done) return;
+  double cs_[J > 0 ? J : 1], ct_[J > 0 ? J : 1];
+#pragma unroll
+  for (int i = 0; i < J; ++i) {
+    cs_[i] = gs->coef_s[i];
+    ct_[i] = gs->coef_t[i];
+  }
+  const double cc = gs->cc, inv = gs->inv_nu;
+  TV* __restrict__ qj = V + (int64_t)J * vs;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    const double uv = (double)u[e];
+    double a1 = uv;
+    double a2 = (double)p[e] - cc * uv;
+#pragma unroll
+    for (int i = 0; i < J; ++i) {
+      const double q = (double)V[i * vs + e];
+      a1 -= cs_[i] * q;
+      a2 -= ct_[i] * q;
+    }
+    qj[e] = (TV)(a1 * inv);
+    unext[e] = (TV)(a2 * inv);
+  }
+}
+
+template <int J, typename TV>
+static void upd_one(TV* V, int64_t vs, const TV* u, const TV* p, TV* un, int64_t n, const GmresState* gs,
+                    hipStream_t s) {
+  const int nb = dot_blocks(n);
+  k_update<J, TV><<<nb, kDotThreads, 0, s>>>(V, vs, u, p, un, n, gs);
+}
+
+template <typename TV, int... Js>
+static void upd_dispatch(std::integer_sequence<int, Js...>, int j, TV* V, int64_t vs, const TV* u, const TV* p,
+                         TV* un, int64_t n, const GmresState* gs, hipStream_t s) {
+  using Fn = void (*)(TV*, int64_t, const TV*, const TV*, TV*, int64_t, const GmresState*, hipStream_t);
+  static const Fn tab[] = {&upd_one<Js, TV>...};
+  tab[j](V, vs, u, p, un, n, gs, s);
+}
+
+template <typename TV>
+void launch_update(int j, TV* V, int64_t vs, const TV* u, const TV* p, TV* unext, int64_t n, const GmresState* gs,
+                   hipStream_t s) {
+  upd_dispatch<TV>(std::make_integer_sequence<int, kMaxRestart>{}, j, V, vs, u, p, unext, n, gs, s);
+}
+
+// ----------------------------------------------------------------------------
+// a7: x += M^{-1} (Q_k y)
+// ----------------------------------------------------------------------------
+template <int NU, typename R, typename TV>
+__global__ __launch_bounds__(256) void k_xupdate(int64_t N, const R* __restrict__ inv, const TV* __restrict__ V,
+                                                 int64_t vs, const GmresState* __restrict__ gs, double* __restrict__ x,
+                                                 int use_pc) {
+  const int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (cell >= N) return;
+  const int k = gs->k;
+  double v[NU];
+#pragma unroll
+  for (int c = 0; c < NU; ++c) v[c] = 0.0;
+  for (int i = 0; i < k; ++i) {
+    const double yi = gs->y[i];
+#pragma unroll
+    for (int c = 0; c < NU; ++c) v[c] += yi * (double)V[i * vs + c * N + cell];
+  }
+#pragma unroll
+  for (int r = 0; r < NU; ++r) {
+    double z = v[r];
+    if (use_pc) {
+      z = 0.0;
+#pragma unroll
+      for (int c = 0; c < NU; ++c) z += (double)inv[(r * NU + c) * N + cell] * v[c];
+    }
+    x[r * N + cell] += z;
+  }
+}
+
+template <typename R, typename TV>
+void launch_xupdate(int nd, bool cpl, const Geom& g, const Coefs<R>& cf, const TV* V, int64_t vs,
+                    const GmresState* gs, double* x, int use_pc, hipStream_t s) {
+  const int nu = 1 + nd + (cpl ? 1 : 0);
+  const int64_t grd = (g.N + 255) / 256;
+  switch (nu) {
+    case 3: k_xupdate<3, R, TV><<<grd, 256, 0, s>>>(g.N, cf.bjinv, V, vs, gs, x, use_pc); break;
+    case 4: k_xupdate<4, R, TV><<<grd, 256, 0, s>>>(g.N, cf.bjinv, V, vs, gs, x, use_pc); break;
+    case 5: k_xupdate<5, R, TV><<<grd, 256, 0, s>>>(g.N, cf.bjinv, V, vs, gs, x, use_pc); break;
+  }
+}
+
+// ----------------------------------------------------------------------------
+// small helpers
+// ----------------------------------------------------------------------------
+__global__ void k_reduce(const double* __restrict__ part, int nv, int nb, double* __restrict__ out) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int v = w; v < nv; v += blockDim.x / 64) {
+    double t = 0.0;
+    for (int b = lane; b < nb; b += 64) t += part[(int64_t)v * nb + b];
+    t = wave_sum(t);
+    if (lane == 0) out[v] = t;
+  }
+}
+
+void launch_reduce(const double* partials, int nv, int nb, double* out, hipStream_t s) {
+  k_reduce<<<1, 256, 0, s>>>(partials, nv, nb, out);
+}
+
+__global__ void k_cycle_init(GmresState* gs, const double* beta2, double tol_abs, double tol_rel) {
+  if (threadIdx.x == 0) {
+    gs->done = 0;
+    gs->k = 0;
+    gs->breakdown = 0;
+    gs->nonfinite = 0;
+    const double beta = sqrt(fmax(beta2[0], 0.0));
+    gs->tol = fmax(tol_abs, tol_rel * beta);
+  }
+}
+
+void launch_cycle_init(GmresState* gs, const double* beta2, double tol_abs, double tol_rel, hipStream_t s) {
+  k_cycle_init<<<1, 64, 0, s>>>(gs, beta2, tol_abs, tol_rel);
+}
+
+template <int ND>
+__device__ __forceinline__ bool f_gt_1(const double* U, int64_t N, int64_t cell, double c) {
+  double F2 = 0.0;
+#pragma unroll
+  for (int m = 0; m < ND; ++m) {
+    const double f = U[(1 + m) * N + cell];
+    F2 += f * f;
+  }
+  return sqrt(F2) > kFgt1 * c * U[cell];
+}
+
+template <int ND>
+__global__ __launch_bounds__(256) void k_newton_update(int64_t N, int nu, double* __restrict__ U,
+                                                       const double* __restrict__ dx, double c,
+                                                       unsigned long long* fcount) {
+  const int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  bool gt = false;
+  if (cell < N) {
+    for (int q = 0; q < nu; ++q) U[q * N + cell] += dx[q * N + cell];
+    gt = f_gt_1<ND>(U, N, cell, c);
+  }
+  const unsigned long long ballot = __ballot(gt);
+  if ((threadIdx.x & 63) == 0 && ballot) atomicAdd(fcount, (unsigned long long)__popcll(ballot));
+}
+
+void launch_newton_update(int nd, const Geom& g, double* Uk, const double* dx, int nu, double c,
+                          unsigned long long* fcount, hipStream_t s) {
+  const int64_t grd = (g.N + 255) / 256;
+  if (nd == 2) k_newton_update<2><<<grd, 256, 0, s>>>(g.N, nu, Uk, dx, c, fcount);
+  else k_newton_update<3><<<grd, 256, 0, s>>>(g.N, nu, Uk, dx, c, fcount);
+}
+
+template <int ND>
+__global__ __launch_bounds__(256) void k_count_f(int64_t N, const double* __restrict__ U, double c,
+                                                 unsigned long long* fcount) {
+  const int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool gt = cell < N && f_gt_1<ND>(U, N, cell, c);
+  const unsigned long long ballot = __ballot(gt);
+  if ((threadIdx.x & 63) == 0 && ballot) atomicAdd(fcount, (unsigned long long)__popcll(ballot));
+}
+
+void launch_count_f(int nd, const Geom& g, const double* U, double c, unsigned long long* fcount, hipStream_t s) {
+  const int64_t grd = (g.N + 255) / 256;
+  if (nd == 2) k_count_f<2><<<grd, 256, 0, s>>>(g.N, U, c, fcount);
+  else k_count_f<3><<<grd, 256, 0, s>>>(g.N, U, c, fcount);
+}
+
+template <typename TS, typename TD>
+__global__ void k_copy_cast(const TS* __restrict__ src, TD* __restrict__ dst, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = (TD)src[i];
+}
+
+template <typename TS, typename TD>
+void launch_copy_cast(const TS* src, TD* dst, int64_t n, hipStream_t s) {
+  const int64_t grd = std::min<int64_t>((n + 255) / 256, 4096);
+  k_copy_cast<TS, TD><<<grd, 256, 0, s>>>(src, dst, n);
+}
+
+__global__ void k_scale(double* __restrict__ v, double a, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    v[i] *= a;
+}
+
+void launch_scale(double* v, double a, int64_t n, hipStream_t s) {
+  const int64_t grd = std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 4096));
+  k_scale<<<grd, 256, 0, s>>>(v, a, n);
+}
+
+// explicit instantiations
+template void launch_dot<double>(int, const double*, int64_t, const double*, const double*, int64_t, double*, int,
+                                 const GmresState*, hipStream_t);
+template void launch_dot<float>(int, const float*, int64_t, const float*, const float*, int64_t, double*, int,
+                                const GmresState*, hipStream_t);
+template void launch_update<double>(int, double*, int64_t, const double*, const double*, double*, int64_t,
+                                    const GmresState*, hipStream_t);
+template void launch_update<float>(int, float*, int64_t, const float*, const float*, float*, int64_t,
+                                   const GmresState*, hipStream_t);
+template void launch_xupdate<double, double>(int, bool, const Geom&, const Coefs<double>&, const double*, int64_t,
+                                             const GmresState*, double*, int, hipStream_t);
+template void launch_xupdate<float, double>(int, bool, const Geom&, const Coefs<float>&, const double*, int64_t,
+                                            const GmresState*, double*, int, hipStream_t);
+template void launch_xupdate<float, float>(int, bool, const Geom&, const Coefs<float>&, const float*, int64_t,
+                                           const GmresState*, double*, int, hipStream_t);
+template void launch_copy_cast<double, float>(const double*, float*, int64_t, hipStream_t);
+template void launch_copy_cast<double, double>(const double*, double*, int64_t, hipStream_t);
+
+}  // namespace m1

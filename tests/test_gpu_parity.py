@@ -1,0 +1,208 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle on the same
+seeded inputs.  Kernel-level parity (residual, operator, block-Jacobi) at 1e-13
+relative; step parity at 1e-10 (fixed-iteration and converged protocols)."""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import m1_oracle as O
+
+pytestmark = pytest.mark.gpu
+
+BC2 = {
+    "periodic": ("periodic",) * 4,
+    "mixed": ("outflow", "reflect", "dirichlet", "outflow"),
+    "walls": ("dirichlet", "dirichlet", "reflect", "reflect"),
+}
+BC3 = {
+    "periodic": ("periodic",) * 6,
+    "mixed": ("outflow", "dirichlet", "reflect", "outflow", "periodic", "periodic"),
+    "open": ("outflow", "outflow", "reflect", "reflect", "dirichlet", "outflow"),
+}
+
+KERNEL_CASES = []
+for bcn, bc in BC2.items():
+    for src in ["none", "absorption", "coupled_t"]:
+        KERNEL_CASES.append(((131, 37), bc, src, "wb", "newton"))
+KERNEL_CASES += [((70, 9), BC2["mixed"], "none", "centered", "newton"),
+                 ((70, 9), BC2["mixed"], "none", "wb", "picard"),
+                 ((64, 1), ("outflow", "outflow", "periodic", "periodic"), "none", "wb", "newton"),
+                 ((1, 5), ("periodic", "periodic", "reflect", "dirichlet"), "coupled_t", "centered", "newton")]
+for bcn, bc in BC3.items():
+    for src in ["none", "absorption", "coupled_t"]:
+        KERNEL_CASES.append(((23, 19, 11), bc, src, "wb", "newton"))
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _problem(n, bc, src, fs, lz, seed=7, **kw):
+    p = W.random_problem(n, seed, source=src, flux_source=fs, bc=bc, **kw)
+    p["linearization"] = lz
+    return p
+
+
+def _rel(a, b):
+    a = np.asarray(a, float).ravel()
+    b = np.asarray(b, float).ravel()
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+@pytest.mark.parametrize("n,bc,src,fs,lz", KERNEL_CASES)
+def test_kernel_parity(n, bc, src, fs, lz):
+    import paper_2011_13926_amd as P
+    _say("kernel parity", n, bc, src, fs, lz)
+    p = _problem(n, bc, src, fs, lz)
+    sch = O.Scheme.from_problem(p)
+    U = O.state_from_problem(p, "U")
+    Un = O.state_from_problem(p, "n")
+    lin = O.linearize(sch, p["sigma"], p.get("rho_cv"), U, Un, p["dt"])
+    s = P.Solver(p, U_lin=U, U_n=Un, dt=p["dt"])
+    try:
+        R_gpu = s.residual().cpu().numpy()
+        R_ref = O.residual(lin)
+        assert _rel(R_gpu, R_ref) <= 1e-13
+        x = W.random_vector(U.size, 3).reshape(U.shape)
+        y_gpu = s.apply_operator(x).cpu().numpy()
+        y_ref = O.apply_operator(lin, x)
+        assert _rel(y_gpu, y_ref) <= 1e-13
+        z_gpu = s.precondition(x).cpu().numpy()
+        z_ref = O.BlockJacobi(lin)(x)
+        assert _rel(z_gpu, z_ref) <= 1e-12
+    finally:
+        s.close()
+
+
+STEP_CASES = [
+    ((40, 33), BC2["mixed"], "none", "wb"),
+    ((40, 33), BC2["walls"], "coupled_t", "centered"),
+    ((24, 20), BC2["periodic"], "absorption", "wb"),
+    ((12, 10, 9), BC3["open"], "coupled_t", "wb"),
+]
+
+
+@pytest.mark.parametrize("n,bc,src,fs", STEP_CASES)
+def test_step_fixed_iterations(n, bc, src, fs):
+    """Exactly 2 Newton x 20 GMRES iterations on both sides: same Krylov spaces."""
+    import torch
+    import paper_2011_13926_amd as P
+    _say("fixed-iteration step", n, bc, src, fs)
+    p = _problem(n, bc, src, fs, "newton", seed=11, dt=2.0, fmax=0.6)
+    sch = O.Scheme.from_problem(p)
+    Un = O.state_from_problem(p, "n")
+    ref = O.implicit_step(sch, p["sigma"], p.get("rho_cv"), Un, p["dt"], restart=30, newton_max=2, fixed_iters=20)
+    s = P.Solver(p, restart=30, newton_max=2, fixed_iters=20)
+    try:
+        U = s.to_device(Un)
+        st, stats = s.implicit_step(U)
+        assert stats["newton_iters"] == 2 and stats["krylov_iters"] == 40
+        got = U.cpu().numpy()
+        for c in range(got.shape[0]):
+            assert _rel(got[c] - Un[c], ref.U[c] - Un[c]) <= 1e-10, c
+    finally:
+        s.close()
+
+
+@pytest.mark.parametrize("n,bc,src,fs", STEP_CASES)
+def test_step_converged(n, bc, src, fs):
+    """Both sides converge to 1e-12; the new states agree to 1e-10 per component."""
+    import paper_2011_13926_amd as P
+    _say("converged step", n, bc, src, fs)
+    p = _problem(n, bc, src, fs, "newton", seed=12, dt=2.0, fmax=0.6)
+    sch = O.Scheme.from_problem(p)
+    Un = O.state_from_problem(p, "n")
+    ref = O.implicit_step(sch, p["sigma"], p.get("rho_cv"), Un, p["dt"], rtol=1e-12, newton_rtol=1e-12)
+    assert ref.converged
+    s = P.Solver(p, rtol=1e-12, newton_rtol=1e-12)
+    try:
+        U = s.to_device(Un)
+        st, stats = s.implicit_step(U)
+        got = U.cpu().numpy()
+        for c in range(got.shape[0]):
+            assert _rel(got[c], ref.U[c]) <= 1e-10, c
+        assert stats["nonlinear_residual"] <= 1e-12
+    finally:
+        s.close()
+
+
+def test_diffusive_gaussian_64_parity_and_checks():
+    """The 64x64 diffusive Gaussian workload at dt = 100, rtol 1e-10: parity with the
+    oracle, realisability and mirror symmetry on the GPU result."""
+    import paper_2011_13926_amd as P
+    _say("diffusive gaussian 64")
+    p = W.diffusive_gaussian()
+    sch = O.Scheme.from_problem(p)
+    Un = O.state_from_problem(p, "U")
+    ref = O.implicit_step(sch, p["sigma"], None, Un, p["dt"], rtol=1e-12, newton_rtol=1e-12)
+    s = P.Solver(p, rtol=1e-12, newton_rtol=1e-12)
+    try:
+        U = s.to_device(Un)
+        st, stats = s.implicit_step(U)
+        got = U.cpu().numpy()
+        assert _rel(got[0], ref.U[0]) <= 1e-10
+        assert _rel(got[0] - Un[0], ref.U[0] - Un[0]) <= 1e-8
+        f = np.sqrt(got[1] ** 2 + got[2] ** 2) / got[0]
+        assert f.max() <= 1 + 1e-12
+        assert np.allclose(got[0], got[0].T, rtol=1e-9)
+        assert stats["cells_f_gt_1"] == 0
+    finally:
+        s.close()
+
+
+def test_determinism_bitwise():
+    import torch
+    import paper_2011_13926_amd as P
+    _say("determinism")
+    p = _problem((96, 50), BC2["mixed"], "none", "wb", "newton", seed=5, dt=3.0, fmax=0.5)
+    Un = O.state_from_problem(p, "n")
+    outs = []
+    for _ in range(2):
+        s = P.Solver(p, rtol=1e-10)
+        U = s.to_device(Un)
+        s.implicit_step(U)
+        outs.append(U.cpu().numpy())
+        s.close()
+    assert np.array_equal(outs[0], outs[1])
+
+
+def test_error_paths_on_gpu():
+    import torch
+    import paper_2011_13926_amd as P
+    _say("error paths")
+    p = _problem((16, 12), BC2["mixed"], "none", "wb", "newton", seed=3)
+    # NaN opacity is rejected at setup
+    q = dict(p)
+    sig = p["sigma"].copy()
+    sig[3, 4] = np.nan
+    q["sigma"] = sig
+    with pytest.raises(P.M1Error) as e:
+        P.Solver(q)
+    assert e.value.status == P.M1_ERR_NONFINITE
+    # apply before any linearisation
+    s = P.Solver(p)
+    x = s.vector()
+    with pytest.raises(P.M1Error) as e:
+        s.apply_operator(x)
+    assert e.value.status == P.M1_ERR_STATE
+    s.close()
+    # forced non-convergence leaves the state unchanged
+    s = P.Solver(p, max_iters=1, newton_max=1, rtol=1e-14)
+    Un = O.state_from_problem(p, "n")
+    U = s.to_device(Un)
+    before = U.clone()
+    st, stats = s.implicit_step(U, raise_on_fail=False)
+    assert st == P.M1_NOT_CONVERGED
+    assert torch.equal(U, before)
+    s.close()
+    # E <= 0 in the input state is rejected
+    s = P.Solver(p)
+    bad = Un.copy()
+    bad[0, 0, 0] = -1.0
+    U = s.to_device(bad)
+    st, _ = s.implicit_step(U, raise_on_fail=False)
+    assert st == P.M1_ERR_INVALID_ARG
+    s.close()
