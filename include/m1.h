@@ -28,9 +28,9 @@
  * Ownership: the caller owns every buffer it passes; buffers are borrowed for the
  * duration of the call.  The context copies sigma, rho_cv and the boundary planes
  * at m1_setup and owns all workspace (coefficients, Krylov basis, scratch).
- * Everything is enqueued on the HIP stream given to m1_setup; m1_apply_operator
- * and m1_precondition return once the work is enqueued, m1_implicit_step and
- * m1_residual_norm block until their result is known.  A context is bound to one
+ * Everything is enqueued on the HIP stream given to m1_setup; m1_apply_operator,
+ * m1_precondition and m1_residual return once the work is enqueued;
+ * m1_setup, m1_linearize and m1_implicit_step block until their result is known.  A context is bound to one
  * stream and one device and is not thread safe.
  *
  * Errors: every call returns an m1_status; nothing aborts or throws across the
@@ -190,11 +190,57 @@ void m1_destroy(m1_ctx* ctx);
 const char* m1_last_error(const m1_ctx* ctx);
 
 /* Per-kernel-class timing with HIP events on the context's stream (for
- * measurement; off by default).  class ids: see m1_kernel_class_name. */
+ * measurement; off by default; enabling resets the counters).  For each class:
+ * launches, summed event time (ms) and summed algorithmic bytes (each array
+ * element a launch must read or write, counted once).  total_bytes may be NULL.
+ * Class ids 0..m1_kernel_class_count()-1, names from m1_kernel_class_name. */
 m1_status m1_profile_enable(m1_ctx* ctx, int32_t on);
-m1_status m1_profile_query(m1_ctx* ctx, int32_t kclass, int64_t* launches, double* total_ms);
+m1_status m1_profile_query(m1_ctx* ctx, int32_t kclass, int64_t* launches, double* total_ms, double* total_bytes);
 const char* m1_kernel_class_name(int32_t kclass);
 int32_t m1_kernel_class_count(void);
+
+/* ---------------------------------------------------------------------------
+ * Learned preconditioner (not in the paper).  A small U-Net on 2D fields, NHWC:
+ * per level l two 3x3 convolutions (ReLU) with channels[l], 2x2 average pooling
+ * between levels, nearest upsampling + skip concatenation on the way up, and a
+ * 1x1 head with cout channels.  BF16 MFMA kernels, FP32 accumulation, FP32
+ * master weights with Adam.  x, y, target: device FP32 arrays H x W x channels.
+ * Used inside flexible GMRES as z = M^{-1} r + (|r|/s) NN(features(r)),
+ * s = sqrt(3N), with block-Jacobi as fallback (m1_stats.fell_back).
+ * ------------------------------------------------------------------------- */
+typedef struct m1nn m1nn;
+
+m1_status m1nn_create(int32_t cin, int32_t cout, int32_t levels, const int32_t* channels, int32_t Hmax,
+                      int32_t Wmax, void* hip_stream, m1nn** out);
+int64_t m1nn_param_count(const m1nn* net);
+/* host arrays in definition order: each 3x3 weight as [dy][dx][ci][co], its bias,
+ * then the head weight [ci][co] and bias */
+m1_status m1nn_set_params(m1nn* net, const float* host, int64_t count);
+m1_status m1nn_get_params(m1nn* net, float* host, int64_t count);
+m1_status m1nn_get_grads(m1nn* net, float* host, int64_t count);
+m1_status m1nn_forward(m1nn* net, const float* x, int32_t H, int32_t W, float* y);
+/* forward + relative loss |y - t|^2/|t|^2 + backward (gradients kept for get_grads / adam_step) */
+m1_status m1nn_backward(m1nn* net, const float* x, const float* target, int32_t H, int32_t W, double* loss);
+m1_status m1nn_adam_step(m1nn* net, float lr);
+m1_status m1nn_train_step(m1nn* net, const float* x, const float* target, int32_t H, int32_t W, float lr,
+                          double* loss);
+m1_status m1nn_save(m1nn* net, const char* path);   /* host path */
+m1_status m1nn_load(m1nn* net, const char* path);
+void m1nn_destroy(m1nn* net);
+const char* m1nn_last_error(const m1nn* net);
+
+/* Attach a network (borrowed; must outlive its use) as the context's learned
+ * preconditioner; the context must be 2D radiation-only (n_u = 3) with
+ * pc = M1_PC_LEARNED, nx and ny multiples of 2^(levels-1). */
+m1_status m1_set_network(m1_ctx* ctx, m1nn* net);
+/* Network input features (H x W x 9 FP32) of a residual vector r at the current
+ * linearisation: s r/|r| (3), s M^{-1} r/|r| (3), log10(1 + c sigma dt)/4, f_x, f_y. */
+m1_status m1_nn_features(m1_ctx* ctx, const double* r, float* features);
+/* Training target s (e - M^{-1} r)/|r| (H x W x 3 FP32) for a residual r with error e. */
+m1_status m1_nn_target(m1_ctx* ctx, const double* r, const double* e, float* target);
+/* Solve A x = b at the current linearisation with the configured GMRES and
+ * preconditioner (x0 = 0).  stats may be NULL.  Blocks. */
+m1_status m1_solve_linear(m1_ctx* ctx, const double* b, double* x, m1_stats* stats);
 
 #ifdef __cplusplus
 }

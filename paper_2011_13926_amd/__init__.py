@@ -86,9 +86,29 @@ _sig = {
     "m1_destroy": (None, [_vp]),
     "m1_last_error": (ctypes.c_char_p, [_vp]),
     "m1_profile_enable": (ctypes.c_int32, [_vp, ctypes.c_int32]),
-    "m1_profile_query": (ctypes.c_int32, [_vp, ctypes.c_int32, _P(ctypes.c_int64), _P(ctypes.c_double)]),
+    "m1_profile_query": (ctypes.c_int32, [_vp, ctypes.c_int32, _P(ctypes.c_int64), _P(ctypes.c_double),
+                                          _P(ctypes.c_double)]),
     "m1_kernel_class_name": (ctypes.c_char_p, [ctypes.c_int32]),
     "m1_kernel_class_count": (ctypes.c_int32, []),
+    "m1_set_network": (ctypes.c_int32, [_vp, _vp]),
+    "m1_nn_features": (ctypes.c_int32, [_vp, _vp, _vp]),
+    "m1_nn_target": (ctypes.c_int32, [_vp, _vp, _vp, _vp]),
+    "m1_solve_linear": (ctypes.c_int32, [_vp, _vp, _vp, _P(M1Stats)]),
+    "m1nn_create": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P(ctypes.c_int32),
+                                     ctypes.c_int32, ctypes.c_int32, _vp, _P(_vp)]),
+    "m1nn_param_count": (ctypes.c_int64, [_vp]),
+    "m1nn_set_params": (ctypes.c_int32, [_vp, _vp, ctypes.c_int64]),
+    "m1nn_get_params": (ctypes.c_int32, [_vp, _vp, ctypes.c_int64]),
+    "m1nn_get_grads": (ctypes.c_int32, [_vp, _vp, ctypes.c_int64]),
+    "m1nn_forward": (ctypes.c_int32, [_vp, _vp, ctypes.c_int32, ctypes.c_int32, _vp]),
+    "m1nn_backward": (ctypes.c_int32, [_vp, _vp, _vp, ctypes.c_int32, ctypes.c_int32, _P(ctypes.c_double)]),
+    "m1nn_adam_step": (ctypes.c_int32, [_vp, ctypes.c_float]),
+    "m1nn_train_step": (ctypes.c_int32, [_vp, _vp, _vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_float,
+                                         _P(ctypes.c_double)]),
+    "m1nn_save": (ctypes.c_int32, [_vp, ctypes.c_char_p]),
+    "m1nn_load": (ctypes.c_int32, [_vp, ctypes.c_char_p]),
+    "m1nn_destroy": (None, [_vp]),
+    "m1nn_last_error": (ctypes.c_char_p, [_vp]),
 }
 EXPORTED = tuple(_sig)
 for _name, (_res, _args) in _sig.items():
@@ -113,6 +133,23 @@ m1_profile_query = _lib.m1_profile_query
 m1_kernel_class_name = _lib.m1_kernel_class_name
 m1_kernel_class_count = _lib.m1_kernel_class_count
 m1_status_string = _lib.m1_status_string
+m1_set_network = _lib.m1_set_network
+m1_nn_features = _lib.m1_nn_features
+m1_nn_target = _lib.m1_nn_target
+m1_solve_linear = _lib.m1_solve_linear
+m1nn_create = _lib.m1nn_create
+m1nn_param_count = _lib.m1nn_param_count
+m1nn_set_params = _lib.m1nn_set_params
+m1nn_get_params = _lib.m1nn_get_params
+m1nn_get_grads = _lib.m1nn_get_grads
+m1nn_forward = _lib.m1nn_forward
+m1nn_backward = _lib.m1nn_backward
+m1nn_adam_step = _lib.m1nn_adam_step
+m1nn_train_step = _lib.m1nn_train_step
+m1nn_save = _lib.m1nn_save
+m1nn_load = _lib.m1nn_load
+m1nn_destroy = _lib.m1nn_destroy
+m1nn_last_error = _lib.m1nn_last_error
 
 
 class M1Error(RuntimeError):
@@ -280,9 +317,10 @@ class Solver:
         for k, name in enumerate(kernel_classes()):
             n = ctypes.c_int64()
             ms = ctypes.c_double()
-            self._check(_lib.m1_profile_query(self.ctx, k, ctypes.byref(n), ctypes.byref(ms)))
+            nbytes = ctypes.c_double()
+            self._check(_lib.m1_profile_query(self.ctx, k, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(nbytes)))
             if n.value:
-                out[name] = (n.value, ms.value)
+                out[name] = {"launches": n.value, "ms": ms.value, "bytes": nbytes.value}
         return out
 
     def close(self):

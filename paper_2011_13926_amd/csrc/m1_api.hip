@@ -13,6 +13,7 @@
 
 #include "../../include/m1.h"
 #include "m1_internal.h"
+#include "m1_nn.h"
 
 using namespace m1;
 
@@ -20,16 +21,20 @@ namespace {
 
 const char* kClassNames[KC_COUNT] = {"setup",   "setup_bj", "residual",   "apply",         "block_jacobi",
                                      "arnoldi_dot", "arnoldi_scalar", "arnoldi_update", "x_update",
-                                     "true_residual", "newton_update", "norm", "convert"};
+                                     "true_residual", "newton_update", "norm", "convert", "learned_pc"};
 
 struct Profiler {
   bool on = false;
   std::vector<hipEvent_t> pool;
   size_t used = 0;
-  struct Rec { int kc; hipEvent_t a, b; };
+  // iter >= 0: a launch inside a GMRES cycle that may have returned at once after
+  // the cycle converged; resolved against the cycle's column count (prof_resolve).
+  // phase 0: before the Hessenberg step of iteration `iter`, 1: after it, 2: final step.
+  struct Rec { int kc; hipEvent_t a, b; double bytes; int iter; int phase; bool valid; };
   std::vector<Rec> pending;
   int64_t launches[KC_COUNT] = {};
   double ms[KC_COUNT] = {};
+  double bytes[KC_COUNT] = {};
 };
 
 }  // namespace
@@ -70,6 +75,11 @@ struct m1_ctx {
   GmresState* gs = nullptr;
   double* dscal = nullptr;
   unsigned long long* dcount = nullptr;
+  // flexible GMRES (learned preconditioner)
+  m1nn* net = nullptr;
+  void* Z = nullptr;
+  void* zt = nullptr;
+  int use_learned = 0;   // 1 while the current solve uses the network
   // pinned host read-back
   double* hscal = nullptr;
   Profiler prof;
@@ -98,8 +108,10 @@ hipEvent_t prof_event(m1_ctx* c) {
   return p.pool[p.used++];
 }
 
+// Launch with optional HIP-event timing; `bytes` is the launch's algorithmic
+// HBM traffic (each array element the kernel must read or write, once).
 template <typename F>
-void timed(m1_ctx* c, int kc, F&& launch) {
+void timed(m1_ctx* c, int kc, double bytes, F&& launch, int iter = -1, int phase = 0) {
   if (!c->prof.on) {
     launch();
     return;
@@ -108,7 +120,17 @@ void timed(m1_ctx* c, int kc, F&& launch) {
   if (a) hipEventRecord(a, c->stream);
   launch();
   if (b) hipEventRecord(b, c->stream);
-  if (a && b) c->prof.pending.push_back({kc, a, b});
+  if (a && b) c->prof.pending.push_back({kc, a, b, bytes, iter, phase, true});
+}
+
+// Drop the records of launches that returned at once because the cycle had
+// already finished: k columns were used out of `steps`.
+void prof_resolve(m1_ctx* c, int k, int steps) {
+  for (auto& r : c->prof.pending) {
+    if (r.iter < 0) continue;
+    r.valid = r.phase == 0 ? r.iter <= k : (r.phase == 1 ? r.iter < k : k == steps);
+    r.iter = -1;
+  }
 }
 
 void prof_collect(m1_ctx* c) {
@@ -117,9 +139,10 @@ void prof_collect(m1_ctx* c) {
   hipEventSynchronize(p.pending.back().b);
   for (auto& r : p.pending) {
     float ms = 0.f;
-    if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+    if (r.valid && hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
       p.launches[r.kc] += 1;
       p.ms[r.kc] += ms;
+      p.bytes[r.kc] += r.bytes;
     }
   }
   p.pending.clear();
@@ -149,7 +172,10 @@ m1_status validate_config(const m1_config* c, std::string& err) {
     err = "enum value out of range";
     return M1_ERR_INVALID_ARG;
   }
-  if (c->pc == M1_PC_LEARNED) { err = "learned preconditioner is not available in this build"; return M1_ERR_INVALID_ARG; }
+  if (c->pc == M1_PC_LEARNED && (c->ndim != 2 || c->source == M1_SRC_COUPLED_T)) {
+    err = "the learned preconditioner is for 2D radiation-only problems";
+    return M1_ERR_INVALID_ARG;
+  }
   if (!(finite(c->lambda_floor) && c->lambda_floor >= 0)) { err = "lambda_floor must be >= 0"; return M1_ERR_INVALID_ARG; }
   for (int f = 0; f < 2 * c->ndim; ++f) {
     if (c->bc[f] < 0 || c->bc[f] > 3) { err = "bc value out of range"; return M1_ERR_INVALID_ARG; }
@@ -223,7 +249,7 @@ void free_all(m1_ctx* c) {
     if (c->mask[f]) hipFree(c->mask[f]);
   }
   void* bufs[] = {c->Uk, c->Un, c->fn, c->coef64, c->coef32, c->V, c->b, c->x, c->u[0], c->u[1],
-                  c->p, c->z, c->part, c->gs, c->dscal, c->dcount};
+                  c->p, c->z, c->part, c->gs, c->dscal, c->dcount, c->Z, c->zt};
   for (void* b : bufs)
     if (b) hipFree(b);
   if (c->hscal) hipHostFree(c->hscal);
@@ -250,6 +276,26 @@ template <typename R> void layout(m1_ctx* c, R* base, Coefs<R>& cf) {
   cf.rcv = base + off; off += c->cpl ? N : 0;
   cf.bjinv = base + off; off += (int64_t)c->nu * c->nu * N;
   c->coef_len = off;
+}
+
+// ---- algorithmic bytes per launch (per cell: every array element touched once) ----
+double cells(const m1_ctx* c) { return (double)c->g.N; }
+double bytes_apply(const m1_ctx* c, size_t rs, size_t vin, size_t vout, bool with_b) {
+  const double per = c->nu * (double)(vin + vout) + (c->njac + 3.0 * c->nd + 1.0 + (c->cpl ? 2.0 : 0.0)) * rs +
+                     (with_b ? c->nu * 8.0 : 0.0);
+  return per * cells(c);
+}
+double bytes_bj(const m1_ctx* c, size_t rs, size_t vin, size_t vout) {
+  return (c->nu * (double)(vin + vout) + (double)c->nu * c->nu * rs) * cells(c);
+}
+double bytes_setup(const m1_ctx* c) {
+  return ((c->nrad + 2.0 + (c->cpl ? 1.0 : 0.0)) + (c->njac + 3.0 * c->nd + (c->cpl ? 1.0 : 0.0))) * 8.0 * cells(c);
+}
+double bytes_setup_bj(const m1_ctx* c) {
+  return ((c->njac + 3.0 * c->nd + 1.0 + (c->cpl ? 2.0 : 0.0)) + (double)c->nu * c->nu) * 8.0 * cells(c);
+}
+double bytes_residual(const m1_ctx* c) {
+  return (3.0 * c->nu + 3.0 * c->nd + 1.0 + (c->cpl ? 1.0 : 0.0)) * 8.0 * cells(c);
 }
 
 Bdry bdry(const m1_ctx* c) {
@@ -292,9 +338,9 @@ m1_status copy_state_out(m1_ctx* c, const double* src, m1_state* U) {
 // Linearise at c->Uk with time-level state c->Un (|f^n| already in c->fn).
 m1_status linearize_internal(m1_ctx* c) {
   const Bdry bd = bdry(c);
-  timed(c, KC_SETUP, [&] { launch_setup(c->nd, c->cpl, c->g, c->sc, c->cf64, bd, c->Uk, c->Un, c->fn, c->stream); });
-  timed(c, KC_SETUP_BJ, [&] { launch_setup_bj(c->nd, c->cpl, c->g, c->sc, c->cf64, bd, c->stream); });
-  if (mixed(c)) timed(c, KC_CONVERT, [&] { launch_convert(c->coef64, c->coef32, c->coef_len, c->stream); });
+  timed(c, KC_SETUP, bytes_setup(c), [&] { launch_setup(c->nd, c->cpl, c->g, c->sc, c->cf64, bd, c->Uk, c->Un, c->fn, c->stream); });
+  timed(c, KC_SETUP_BJ, bytes_setup_bj(c), [&] { launch_setup_bj(c->nd, c->cpl, c->g, c->sc, c->cf64, bd, c->stream); });
+  if (mixed(c)) timed(c, KC_CONVERT, 12.0 * c->coef_len, [&] { launch_convert(c->coef64, c->coef32, c->coef_len, c->stream); });
   HIPCHK(c, hipGetLastError());
   c->linearized = true;
   return M1_OK;
@@ -302,7 +348,7 @@ m1_status linearize_internal(m1_ctx* c) {
 
 // ||v||^2 of an FP64 vector into c->dscal[slot] (device)
 void norm2_into(m1_ctx* c, const double* v, int slot) {
-  timed(c, KC_NORM, [&] {
+  timed(c, KC_NORM, 8.0 * c->n, [&] {
     launch_dot<double>(0, nullptr, 0, v, nullptr, c->n, c->part, c->nb, nullptr, c->stream);
     launch_reduce(c->part, 1, c->nb, c->dscal + slot, c->stream);
   });
@@ -330,7 +376,10 @@ m1_status gmres(m1_ctx* c, double bnorm, SolveResult& res, const Coefs<R>& cfi) 
   const int budget = fixed ? c->cfg.fixed_iters : c->cfg.max_iters;
   const double rtol = c->cfg.rtol;
   const double tol_rel = (mixed(c) && !fixed) ? c->cfg.inner_rtol : 0.0;
-  const int use_pc = c->cfg.pc == M1_PC_BLOCK_JACOBI;
+  const bool learned = c->use_learned && c->net;
+  const int use_pc = !learned && c->cfg.pc != M1_PC_NONE;
+  R* Z = (R*)c->Z;
+  R* zt = (R*)c->zt;
   HIPCHK(c, hipMemsetAsync(c->x, 0, sizeof(double) * n, c->stream));
   // r = b
   launch_copy_cast<double, TV>(c->b, u[0], n, c->stream);
@@ -348,24 +397,40 @@ m1_status gmres(m1_ctx* c, double bnorm, SolveResult& res, const Coefs<R>& cfi) 
     for (int j = 0; j < steps; ++j) {
       TV* uj = u[j & 1];
       TV* un = u[(j + 1) & 1];
-      if (use_pc) {
-        timed(c, KC_BJ, [&] { launch_bj<R, TV, R>(c->nd, c->cpl, c->g, cfi, uj, z, c->stream); });
-        timed(c, KC_APPLY, [&] { launch_apply<R, R, TV>(c->nd, c->cpl, 0, c->g, c->sc, cfi, bd, z, nullptr, p, c->stream); });
+      if (learned) {
+        timed(c, KC_NN, 0.0, [&] {
+          launch_dot<TV>(0, nullptr, 0, uj, nullptr, n, c->part, c->nb, c->gs, c->stream);
+          launch_reduce(c->part, 1, c->nb, c->dscal + 2, c->stream);
+          launch_nn_features<TV>(c->g.N, uj, c->dscal + 2, c->cf64.bjinv, c->Uk, c->cf64.sigma, c->cfg.c, c->sc.cdt,
+                                 nn_cin_pad(c->net), nn_input(c->net), nullptr, c->stream, &c->gs->done);
+          nn_run(c->net, c->g.n[1], c->g.n[0], c->stream, &c->gs->done);
+          launch_nn_combine<TV, R>(c->g.N, uj, c->dscal + 2, c->cf64.bjinv, nn_output(c->net), zt, c->stream,
+                                   &c->gs->done);
+        }, j, 0);
+        timed(c, KC_APPLY, bytes_apply(c, sizeof(R), sizeof(R), sizeof(TV), false), [&] { launch_apply<R, R, TV>(c->nd, c->cpl, 0, c->g, c->sc, cfi, bd, zt, nullptr, p, c->stream, &c->gs->done); }, j, 0);
+      } else if (use_pc) {
+        timed(c, KC_BJ, bytes_bj(c, sizeof(R), sizeof(TV), sizeof(R)), [&] { launch_bj<R, TV, R>(c->nd, c->cpl, c->g, cfi, uj, z, c->stream, &c->gs->done); }, j, 0);
+        timed(c, KC_APPLY, bytes_apply(c, sizeof(R), sizeof(R), sizeof(TV), false), [&] { launch_apply<R, R, TV>(c->nd, c->cpl, 0, c->g, c->sc, cfi, bd, z, nullptr, p, c->stream, &c->gs->done); }, j, 0);
       } else {
-        timed(c, KC_APPLY, [&] { launch_apply<R, TV, TV>(c->nd, c->cpl, 0, c->g, c->sc, cfi, bd, uj, nullptr, p, c->stream); });
+        timed(c, KC_APPLY, bytes_apply(c, sizeof(R), sizeof(TV), sizeof(TV), false), [&] { launch_apply<R, TV, TV>(c->nd, c->cpl, 0, c->g, c->sc, cfi, bd, uj, nullptr, p, c->stream, &c->gs->done); }, j, 0);
       }
-      timed(c, KC_DOT, [&] { launch_dot<TV>(j, V, vs, uj, p, n, c->part, c->nb, c->gs, c->stream); });
-      timed(c, KC_SCALAR, [&] { launch_scalar(j, 0, c->part, c->nb, c->gs, c->stream); });
-      timed(c, KC_UPDATE, [&] { launch_update<TV>(j, V, vs, uj, p, un, n, c->gs, c->stream); });
+      timed(c, KC_DOT, (j + 2.0) * n * sizeof(TV), [&] { launch_dot<TV>(j, V, vs, uj, p, n, c->part, c->nb, c->gs, c->stream); }, j, 0);
+      timed(c, KC_SCALAR, (2.0 * j + 2.0) * c->nb * 8.0, [&] { launch_scalar(j, 0, c->part, c->nb, c->gs, c->stream); }, j, 0);
+      timed(c, KC_UPDATE, (j + 4.0) * n * sizeof(TV), [&] { launch_update<TV>(j, V, vs, uj, p, un, n, c->gs, c->stream); }, j, 1);
+      if (learned) timed(c, KC_UPDATE, (j + 2.0) * n * sizeof(R), [&] { launch_zupdate<R>(j, Z, vs, zt, n, c->gs, c->stream); }, j, 1);
     }
-    timed(c, KC_DOT, [&] { launch_dot<TV>(steps, V, vs, u[steps & 1], nullptr, n, c->part, c->nb, c->gs, c->stream); });
-    timed(c, KC_SCALAR, [&] { launch_scalar(steps, 1, c->part, c->nb, c->gs, c->stream); });
-    timed(c, KC_XUPDATE, [&] { launch_xupdate<R, TV>(c->nd, c->cpl, c->g, cfi, V, vs, c->gs, c->x, use_pc, c->stream); });
+    timed(c, KC_DOT, (steps + 1.0) * n * sizeof(TV), [&] { launch_dot<TV>(steps, V, vs, u[steps & 1], nullptr, n, c->part, c->nb, c->gs, c->stream); }, steps, 2);
+    timed(c, KC_SCALAR, (steps + 1.0) * c->nb * 8.0, [&] { launch_scalar(steps, 1, c->part, c->nb, c->gs, c->stream); }, steps, 2);
+    if (learned) {
+      timed(c, KC_XUPDATE, (double)steps * n * sizeof(R) + 16.0 * n, [&] { launch_xupdate<R, R>(c->nd, c->cpl, c->g, cfi, Z, vs, c->gs, c->x, 0, c->stream); });
+    } else {
+      timed(c, KC_XUPDATE, (double)steps * n * sizeof(TV) + 16.0 * n + (use_pc ? (double)c->nu * c->nu * sizeof(R) * cells(c) : 0.0), [&] { launch_xupdate<R, TV>(c->nd, c->cpl, c->g, cfi, V, vs, c->gs, c->x, use_pc, c->stream); });
+    }
     // true residual in FP64: r = b - A x, stored as the next cycle's u_0
-    timed(c, KC_TRUE_RESID, [&] {
+    timed(c, KC_TRUE_RESID, bytes_apply(c, 8, 8, sizeof(TV), true), [&] {
       launch_apply<double, double, TV>(c->nd, c->cpl, 1, c->g, c->sc, c->cf64, bd, c->x, c->b, u[0], c->stream);
     });
-    timed(c, KC_NORM, [&] {
+    timed(c, KC_NORM, (double)n * sizeof(TV), [&] {
       launch_dot<TV>(0, nullptr, 0, u[0], nullptr, n, c->part, c->nb, nullptr, c->stream);
       launch_reduce(c->part, 1, c->nb, c->dscal + 1, c->stream);
     });
@@ -374,8 +439,9 @@ m1_status gmres(m1_ctx* c, double bnorm, SolveResult& res, const Coefs<R>& cfi) 
     int hk[4];
     HIPCHK(c, hipMemcpyAsync(hk, c->gs, sizeof(int) * 4, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    prof_collect(c);
     const int k = hk[1];
+    prof_resolve(c, k, steps);
+    prof_collect(c);
     total += fixed ? steps : std::max(k, 1);
     beta = std::sqrt(std::max(c->hscal[0], 0.0));
     if (!std::isfinite(beta) || hk[3]) { res.nonfinite = true; break; }
@@ -386,10 +452,27 @@ m1_status gmres(m1_ctx* c, double bnorm, SolveResult& res, const Coefs<R>& cfi) 
   return M1_OK;
 }
 
-m1_status solve(m1_ctx* c, double bnorm, SolveResult& res) {
+m1_status solve_once(m1_ctx* c, double bnorm, SolveResult& res) {
   if (!mixed(c)) return gmres<double, double>(c, bnorm, res, c->cf64);
   if (basis32(c)) return gmres<float, float>(c, bnorm, res, c->cf32);
   return gmres<double, float>(c, bnorm, res, c->cf32);
+}
+
+// The learned preconditioner runs first when attached; if its solve fails
+// (iteration cap or non-finite values) block-Jacobi redoes the solve.
+m1_status solve(m1_ctx* c, double bnorm, SolveResult& res, int& fell_back) {
+  c->use_learned = (c->cfg.pc == M1_PC_LEARNED && c->net) ? 1 : 0;
+  m1_status st = solve_once(c, bnorm, res);
+  if (st != M1_OK) return st;
+  if (c->use_learned && (!res.converged || res.nonfinite)) {
+    const int it = res.iters;
+    c->use_learned = 0;
+    st = solve_once(c, bnorm, res);
+    res.iters += it;
+    fell_back = 1;
+  }
+  c->use_learned = 0;
+  return st;
 }
 
 }  // namespace
@@ -509,6 +592,13 @@ m1_status m1_setup(const m1_config* cfg, const m1_fields* fields, const m1_state
     if ((st = dalloc(c, &a, c->n * (int64_t)rs)) != M1_OK) return fail(st);
     c->z = a;
   }
+  if (cfg->pc == M1_PC_LEARNED) {
+    char* a = nullptr;
+    if ((st = dalloc(c, &a, (int64_t)(c->m + 1) * c->n * (int64_t)rs)) != M1_OK) return fail(st);
+    c->Z = a;
+    if ((st = dalloc(c, &a, c->n * (int64_t)rs)) != M1_OK) return fail(st);
+    c->zt = a;
+  }
   if ((st = dalloc(c, &c->part, (int64_t)(2 * kMaxRestart + 2) * c->nb)) != M1_OK) return fail(st);
   if ((st = dalloc(c, &c->gs, 1)) != M1_OK) return fail(st);
   if ((st = dalloc(c, &c->dscal, 8)) != M1_OK) return fail(st);
@@ -579,7 +669,7 @@ m1_status m1_apply_operator(m1_ctx* c, const double* x, double* y) {
   if (!x || !y) { c->err = "x or y is NULL"; return M1_ERR_INVALID_ARG; }
   if (x == y) { c->err = "x and y must not overlap"; return M1_ERR_INVALID_ARG; }
   if (!c->linearized) { c->err = "no linearisation yet"; return M1_ERR_STATE; }
-  timed(c, KC_APPLY, [&] {
+  timed(c, KC_APPLY, bytes_apply(c, 8, 8, 8, false), [&] {
     launch_apply<double, double, double>(c->nd, c->cpl, 0, c->g, c->sc, c->cf64, bdry(c), x, nullptr, y, c->stream);
   });
   HIPCHK(c, hipGetLastError());
@@ -594,7 +684,7 @@ m1_status m1_precondition(m1_ctx* c, const double* r, double* z) {
     if (r != z) HIPCHK(c, hipMemcpyAsync(z, r, sizeof(double) * c->n, hipMemcpyDeviceToDevice, c->stream));
     return M1_OK;
   }
-  timed(c, KC_BJ, [&] { launch_bj<double, double, double>(c->nd, c->cpl, c->g, c->cf64, r, z, c->stream); });
+  timed(c, KC_BJ, bytes_bj(c, 8, 8, 8), [&] { launch_bj<double, double, double>(c->nd, c->cpl, c->g, c->cf64, r, z, c->stream); });
   HIPCHK(c, hipGetLastError());
   return M1_OK;
 }
@@ -603,7 +693,7 @@ m1_status m1_residual(m1_ctx* c, double* R) {
   if (!c) return M1_ERR_INVALID_ARG;
   if (!R) { c->err = "R is NULL"; return M1_ERR_INVALID_ARG; }
   if (!c->linearized) { c->err = "no linearisation yet"; return M1_ERR_STATE; }
-  timed(c, KC_RESIDUAL, [&] { launch_residual(c->nd, c->cpl, c->g, c->sc, c->cf64, bdry(c), c->Uk, c->Un, R, c->stream); });
+  timed(c, KC_RESIDUAL, bytes_residual(c), [&] { launch_residual(c->nd, c->cpl, c->g, c->sc, c->cf64, bdry(c), c->Uk, c->Un, R, c->stream); });
   // the residual kernel writes -R (the Newton right-hand side); flip the sign
   launch_scale(R, -1.0, c->n, c->stream);
   HIPCHK(c, hipGetLastError());
@@ -623,12 +713,12 @@ m1_status m1_implicit_step(m1_ctx* c, m1_state* U, double dt, m1_stats* stats) {
   launch_fn(c->nd, c->g, c->sc, c->Un, c->fn, c->stream);
   const bool fixed = c->cfg.fixed_iters > 0;
   double r0 = -1.0, rel = 1.0;
-  int it = 0, kry = 0, rst = 0;
+  int it = 0, kry = 0, rst = 0, fell_back = 0;
   bool converged = false, nonfinite = false;
   double lin_rel = 0.0;
   while (true) {
     if ((st = linearize_internal(c)) != M1_OK) return st;
-    timed(c, KC_RESIDUAL, [&] { launch_residual(c->nd, c->cpl, c->g, c->sc, c->cf64, bdry(c), c->Uk, c->Un, c->b, c->stream); });
+    timed(c, KC_RESIDUAL, bytes_residual(c), [&] { launch_residual(c->nd, c->cpl, c->g, c->sc, c->cf64, bdry(c), c->Uk, c->Un, c->b, c->stream); });
     norm2_into(c, c->b, 0);
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipMemcpyAsync(c->hscal, c->dscal, sizeof(double), hipMemcpyDeviceToHost, c->stream));
@@ -647,12 +737,12 @@ m1_status m1_implicit_step(m1_ctx* c, m1_state* U, double dt, m1_stats* stats) {
       break;
     }
     SolveResult sr;
-    if ((st = solve(c, rn, sr)) != M1_OK) return st;
+    if ((st = solve(c, rn, sr, fell_back)) != M1_OK) return st;
     kry += sr.iters;
     rst += sr.restarts;
     lin_rel = sr.rel;
     if (sr.nonfinite) { nonfinite = true; break; }
-    timed(c, KC_NEWTON_UPDATE, [&] {
+    timed(c, KC_NEWTON_UPDATE, 24.0 * c->n, [&] {
       k_zero_u64<<<1, 64, 0, c->stream>>>(c->dcount);
       launch_newton_update(c->nd, c->g, c->Uk, c->x, c->nu, c->cfg.c, c->dcount, c->stream);
     });
@@ -672,7 +762,7 @@ m1_status m1_implicit_step(m1_ctx* c, m1_state* U, double dt, m1_stats* stats) {
     stats->newton_iters = it;
     stats->krylov_iters = kry;
     stats->restarts = rst;
-    stats->fell_back = 0;
+    stats->fell_back = fell_back;
     stats->rel_residual = lin_rel;
     stats->nonlinear_residual = rel;
     stats->cells_f_gt_1 = (int64_t)nf;
@@ -680,6 +770,72 @@ m1_status m1_implicit_step(m1_ctx* c, m1_state* U, double dt, m1_stats* stats) {
   }
   if (nonfinite) { c->err = "non-finite value in the Newton/GMRES iteration"; return M1_ERR_NONFINITE; }
   if (!converged) { c->err = "Newton iteration did not converge"; return M1_NOT_CONVERGED; }
+  return M1_OK;
+}
+
+m1_status m1_set_network(m1_ctx* c, m1nn* net) {
+  if (!c) return M1_ERR_INVALID_ARG;
+  if (net == nullptr) { c->net = nullptr; return M1_OK; }
+  if (c->cfg.pc != M1_PC_LEARNED || c->nd != 2 || c->nu != 3) {
+    c->err = "the context must be 2D radiation-only with pc = M1_PC_LEARNED";
+    return M1_ERR_INVALID_ARG;
+  }
+  if (nn_cin(net) != 9 || nn_cout(net) != 3) { c->err = "the network must map 9 input channels to 3"; return M1_ERR_INVALID_ARG; }
+  const int q = 1 << (nn_levels(net) - 1);
+  if (c->g.n[0] % q || c->g.n[1] % q) { c->err = "nx and ny must be multiples of 2^(levels-1)"; return M1_ERR_INVALID_ARG; }
+  c->net = net;
+  return M1_OK;
+}
+
+m1_status m1_nn_features(m1_ctx* c, const double* r, float* features) {
+  if (!c || !r || !features) return M1_ERR_INVALID_ARG;
+  if (!c->linearized) { c->err = "no linearisation yet"; return M1_ERR_STATE; }
+  if (c->nd != 2 || c->nu != 3) { c->err = "features are defined for 2D radiation-only problems"; return M1_ERR_INVALID_ARG; }
+  launch_dot<double>(0, nullptr, 0, r, nullptr, c->n, c->part, c->nb, nullptr, c->stream);
+  launch_reduce(c->part, 1, c->nb, c->dscal + 3, c->stream);
+  launch_nn_features<double>(c->g.N, r, c->dscal + 3, c->cf64.bjinv, c->Uk, c->cf64.sigma, c->cfg.c, c->sc.cdt, 0,
+                             nullptr, features, c->stream);
+  HIPCHK(c, hipGetLastError());
+  return M1_OK;
+}
+
+m1_status m1_nn_target(m1_ctx* c, const double* r, const double* e, float* target) {
+  if (!c || !r || !e || !target) return M1_ERR_INVALID_ARG;
+  if (!c->linearized) { c->err = "no linearisation yet"; return M1_ERR_STATE; }
+  if (c->nd != 2 || c->nu != 3) { c->err = "targets are defined for 2D radiation-only problems"; return M1_ERR_INVALID_ARG; }
+  launch_dot<double>(0, nullptr, 0, r, nullptr, c->n, c->part, c->nb, nullptr, c->stream);
+  launch_reduce(c->part, 1, c->nb, c->dscal + 3, c->stream);
+  launch_nn_target(c->g.N, r, e, c->dscal + 3, c->cf64.bjinv, target, c->stream);
+  HIPCHK(c, hipGetLastError());
+  return M1_OK;
+}
+
+m1_status m1_solve_linear(m1_ctx* c, const double* b, double* x, m1_stats* stats) {
+  if (!c || !b || !x) return M1_ERR_INVALID_ARG;
+  if (!c->linearized) { c->err = "no linearisation yet"; return M1_ERR_STATE; }
+  const auto t0 = std::chrono::steady_clock::now();
+  HIPCHK(c, hipMemcpyAsync(c->b, b, sizeof(double) * c->n, hipMemcpyDeviceToDevice, c->stream));
+  norm2_into(c, c->b, 0);
+  HIPCHK(c, hipMemcpyAsync(c->hscal, c->dscal, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  const double bn = std::sqrt(std::max(c->hscal[0], 0.0));
+  SolveResult sr;
+  int fell_back = 0;
+  m1_status st = solve(c, bn, sr, fell_back);
+  if (st != M1_OK) return st;
+  HIPCHK(c, hipMemcpyAsync(x, c->x, sizeof(double) * c->n, hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  prof_collect(c);
+  if (stats) {
+    std::memset(stats, 0, sizeof(*stats));
+    stats->krylov_iters = sr.iters;
+    stats->restarts = sr.restarts;
+    stats->fell_back = fell_back;
+    stats->rel_residual = sr.rel;
+    stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+  if (sr.nonfinite) { c->err = "non-finite value in GMRES"; return M1_ERR_NONFINITE; }
+  if (!sr.converged) { c->err = "GMRES did not converge"; return M1_NOT_CONVERGED; }
   return M1_OK;
 }
 
@@ -699,15 +855,17 @@ m1_status m1_profile_enable(m1_ctx* c, int32_t on) {
   for (int k = 0; k < KC_COUNT; ++k) {
     c->prof.launches[k] = 0;
     c->prof.ms[k] = 0.0;
+    c->prof.bytes[k] = 0.0;
   }
   return M1_OK;
 }
 
-m1_status m1_profile_query(m1_ctx* c, int32_t kc, int64_t* launches, double* total_ms) {
+m1_status m1_profile_query(m1_ctx* c, int32_t kc, int64_t* launches, double* total_ms, double* total_bytes) {
   if (!c || kc < 0 || kc >= KC_COUNT || !launches || !total_ms) return M1_ERR_INVALID_ARG;
   prof_collect(c);
   *launches = c->prof.launches[kc];
   *total_ms = c->prof.ms[kc];
+  if (total_bytes) *total_bytes = c->prof.bytes[kc];
   return M1_OK;
 }
 

@@ -50,7 +50,7 @@ struct GmresState {
 
 enum KernelClass {
   KC_SETUP = 0, KC_SETUP_BJ, KC_RESIDUAL, KC_APPLY, KC_BJ, KC_DOT, KC_SCALAR, KC_UPDATE, KC_XUPDATE,
-  KC_TRUE_RESID, KC_NEWTON_UPDATE, KC_NORM, KC_CONVERT, KC_COUNT
+  KC_TRUE_RESID, KC_NEWTON_UPDATE, KC_NORM, KC_CONVERT, KC_NN, KC_COUNT
 };
 
 // ---- launchers (defined in m1_kernels.hip / m1_krylov.hip) ----
@@ -62,11 +62,12 @@ void launch_setup_bj(int nd, bool cpl, const Geom& g, const Scheme& sc, const Co
 // mode: 0 y = A x, 1 y = b - A x
 template <typename R, typename VI, typename VO>
 void launch_apply(int nd, bool cpl, int mode, const Geom& g, const Scheme& sc, const Coefs<R>& cf, const Bdry& bd,
-                  const VI* x, const double* b, VO* y, hipStream_t s);
+                  const VI* x, const double* b, VO* y, hipStream_t s, const int* skip = nullptr);
 void launch_residual(int nd, bool cpl, const Geom& g, const Scheme& sc, const Coefs<double>& cf, const Bdry& bd,
                      const double* Uk, const double* Un, double* out_negR, hipStream_t s);
 template <typename R, typename VI, typename VO>
-void launch_bj(int nd, bool cpl, const Geom& g, const Coefs<R>& cf, const VI* r, VO* z, hipStream_t s);
+void launch_bj(int nd, bool cpl, const Geom& g, const Coefs<R>& cf, const VI* r, VO* z, hipStream_t s,
+               const int* skip = nullptr);
 void launch_convert(const double* src, float* dst, int64_t n, hipStream_t s);
 
 // Krylov pieces
@@ -78,6 +79,8 @@ void launch_scalar(int j, int final_step, const double* partials, int nb, GmresS
 template <typename TV>
 void launch_update(int j, TV* V, int64_t vstride, const TV* u, const TV* p, TV* unext, int64_t n,
                    const GmresState* gs, hipStream_t s);
+template <typename TZ>
+void launch_zupdate(int j, TZ* Z, int64_t vs, const TZ* zt, int64_t n, const GmresState* gs, hipStream_t s);
 template <typename R, typename TV>
 void launch_xupdate(int nd, bool cpl, const Geom& g, const Coefs<R>& cf, const TV* V, int64_t vstride,
                     const GmresState* gs, double* x, int use_pc, hipStream_t s);

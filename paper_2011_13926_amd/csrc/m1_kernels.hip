@@ -380,9 +380,10 @@ void launch_setup_bj(int nd, bool cpl, const Geom& g, const Scheme& sc, const Co
 template <int ND, bool CPL, int MODE, typename R, typename VI, typename VO>
 __global__ __launch_bounds__(256) void k_stencil(Geom g, Scheme sc, Coefs<R> cf, Bdry bd, const VI* __restrict__ x,
                                                  const double* __restrict__ b, const double* __restrict__ Un,
-                                                 VO* __restrict__ y) {
+                                                 VO* __restrict__ y, const int* __restrict__ skip) {
   constexpr int NR = 1 + ND;
   constexpr int NU = NR + (CPL ? 1 : 0);
+  if (skip && *skip) return;
   CellPos p;
   if (!cell_pos(g, p)) return;
   const int64_t N = g.N;
@@ -533,9 +534,9 @@ __global__ __launch_bounds__(256) void k_stencil(Geom g, Scheme sc, Coefs<R> cf,
 
 template <typename R, typename VI, typename VO>
 void launch_apply(int nd, bool cpl, int mode, const Geom& g, const Scheme& sc, const Coefs<R>& cf, const Bdry& bd,
-                  const VI* x, const double* b, VO* y, hipStream_t s) {
+                  const VI* x, const double* b, VO* y, hipStream_t s, const int* skip) {
   dim3 blk(TX, TY), grd((g.n[0] + TX - 1) / TX, (g.rows + TY - 1) / TY);
-#define M1_ST(ND_, CPL_, MODE_) k_stencil<ND_, CPL_, MODE_, R, VI, VO><<<grd, blk, 0, s>>>(g, sc, cf, bd, x, b, nullptr, y)
+#define M1_ST(ND_, CPL_, MODE_) k_stencil<ND_, CPL_, MODE_, R, VI, VO><<<grd, blk, 0, s>>>(g, sc, cf, bd, x, b, nullptr, y, skip)
   if (nd == 2) {
     if (cpl) { if (mode == 0) M1_ST(2, true, 0); else M1_ST(2, true, 1); }
     else { if (mode == 0) M1_ST(2, false, 0); else M1_ST(2, false, 1); }
@@ -550,11 +551,11 @@ void launch_residual(int nd, bool cpl, const Geom& g, const Scheme& sc, const Co
                      const double* Uk, const double* Un, double* out, hipStream_t s) {
   dim3 blk(TX, TY), grd((g.n[0] + TX - 1) / TX, (g.rows + TY - 1) / TY);
   if (nd == 2) {
-    if (cpl) k_stencil<2, true, 2, double, double, double><<<grd, blk, 0, s>>>(g, sc, cf, bd, Uk, nullptr, Un, out);
-    else k_stencil<2, false, 2, double, double, double><<<grd, blk, 0, s>>>(g, sc, cf, bd, Uk, nullptr, Un, out);
+    if (cpl) k_stencil<2, true, 2, double, double, double><<<grd, blk, 0, s>>>(g, sc, cf, bd, Uk, nullptr, Un, out, nullptr);
+    else k_stencil<2, false, 2, double, double, double><<<grd, blk, 0, s>>>(g, sc, cf, bd, Uk, nullptr, Un, out, nullptr);
   } else {
-    if (cpl) k_stencil<3, true, 2, double, double, double><<<grd, blk, 0, s>>>(g, sc, cf, bd, Uk, nullptr, Un, out);
-    else k_stencil<3, false, 2, double, double, double><<<grd, blk, 0, s>>>(g, sc, cf, bd, Uk, nullptr, Un, out);
+    if (cpl) k_stencil<3, true, 2, double, double, double><<<grd, blk, 0, s>>>(g, sc, cf, bd, Uk, nullptr, Un, out, nullptr);
+    else k_stencil<3, false, 2, double, double, double><<<grd, blk, 0, s>>>(g, sc, cf, bd, Uk, nullptr, Un, out, nullptr);
   }
 }
 
@@ -563,7 +564,8 @@ void launch_residual(int nd, bool cpl, const Geom& g, const Scheme& sc, const Co
 // ----------------------------------------------------------------------------
 template <int NU, typename R, typename VI, typename VO>
 __global__ __launch_bounds__(256) void k_bj(int64_t N, const R* __restrict__ inv, const VI* __restrict__ r,
-                                            VO* __restrict__ z) {
+                                            VO* __restrict__ z, const int* __restrict__ skip) {
+  if (skip && *skip) return;
   const int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (cell >= N) return;
   R rv[NU];
@@ -579,14 +581,15 @@ __global__ __launch_bounds__(256) void k_bj(int64_t N, const R* __restrict__ inv
 }
 
 template <typename R, typename VI, typename VO>
-void launch_bj(int nd, bool cpl, const Geom& g, const Coefs<R>& cf, const VI* r, VO* z, hipStream_t s) {
+void launch_bj(int nd, bool cpl, const Geom& g, const Coefs<R>& cf, const VI* r, VO* z, hipStream_t s,
+               const int* skip) {
   const int nu = 1 + nd + (cpl ? 1 : 0);
   const int blk = 256;
   const int64_t grd = (g.N + blk - 1) / blk;
   switch (nu) {
-    case 3: k_bj<3, R, VI, VO><<<grd, blk, 0, s>>>(g.N, cf.bjinv, r, z); break;
-    case 4: k_bj<4, R, VI, VO><<<grd, blk, 0, s>>>(g.N, cf.bjinv, r, z); break;
-    case 5: k_bj<5, R, VI, VO><<<grd, blk, 0, s>>>(g.N, cf.bjinv, r, z); break;
+    case 3: k_bj<3, R, VI, VO><<<grd, blk, 0, s>>>(g.N, cf.bjinv, r, z, skip); break;
+    case 4: k_bj<4, R, VI, VO><<<grd, blk, 0, s>>>(g.N, cf.bjinv, r, z, skip); break;
+    case 5: k_bj<5, R, VI, VO><<<grd, blk, 0, s>>>(g.N, cf.bjinv, r, z, skip); break;
   }
 }
 
@@ -602,20 +605,20 @@ void launch_convert(const double* src, float* dst, int64_t n, hipStream_t s) {
 
 // explicit instantiations
 template void launch_apply<double, double, double>(int, bool, int, const Geom&, const Scheme&, const Coefs<double>&,
-                                                   const Bdry&, const double*, const double*, double*, hipStream_t);
+                                                   const Bdry&, const double*, const double*, double*, hipStream_t, const int*);
 template void launch_apply<float, float, double>(int, bool, int, const Geom&, const Scheme&, const Coefs<float>&,
-                                                 const Bdry&, const float*, const double*, double*, hipStream_t);
+                                                 const Bdry&, const float*, const double*, double*, hipStream_t, const int*);
 template void launch_apply<float, float, float>(int, bool, int, const Geom&, const Scheme&, const Coefs<float>&,
-                                                const Bdry&, const float*, const double*, float*, hipStream_t);
+                                                const Bdry&, const float*, const double*, float*, hipStream_t, const int*);
 template void launch_apply<float, double, double>(int, bool, int, const Geom&, const Scheme&, const Coefs<float>&,
-                                                  const Bdry&, const double*, const double*, double*, hipStream_t);
+                                                  const Bdry&, const double*, const double*, double*, hipStream_t, const int*);
 template void launch_apply<double, double, float>(int, bool, int, const Geom&, const Scheme&, const Coefs<double>&,
-                                                  const Bdry&, const double*, const double*, float*, hipStream_t);
+                                                  const Bdry&, const double*, const double*, float*, hipStream_t, const int*);
 template void launch_bj<double, double, double>(int, bool, const Geom&, const Coefs<double>&, const double*, double*,
-                                                hipStream_t);
+                                                hipStream_t, const int*);
 template void launch_bj<float, double, float>(int, bool, const Geom&, const Coefs<float>&, const double*, float*,
-                                              hipStream_t);
+                                              hipStream_t, const int*);
 template void launch_bj<float, float, float>(int, bool, const Geom&, const Coefs<float>&, const float*, float*,
-                                             hipStream_t);
+                                             hipStream_t, const int*);
 
 }  // namespace m1

@@ -1,0 +1,1009 @@
+// Learned preconditioner network for gfx950: a small U-Net (3x3 convolutions,
+// 2x2 average pooling, nearest upsampling with skip concatenation, 1x1 head)
+// with BF16 MFMA (v_mfma_f32_16x16x16_bf16, FP32 accumulate) forward, input-
+// gradient and weight-gradient kernels, and Adam on FP32 master weights.
+//
+// Activations are NHWC.  A 3x3 convolution is an implicit GEMM: M = pixels,
+// N = output channels, K = 9 taps x input channels (in chunks of 16).  The input
+// gradient is the same kernel run on the output gradient with the weights flipped
+// in both spatial directions and transposed in channels.  The weight gradient is a
+// GEMM over pixels (K = pixels) on channel-major copies, split over pixel chunks
+// and reduced in a fixed order.
+//
+// MFMA 16x16x16 operand layout (lane l, element r = 0..3):
+//   A[i][k]: i = l % 16, k = 4 (l / 16) + r;  B[k][j]: j = l % 16, k = 4 (l / 16) + r;
+//   D[i][j]: j = l % 16, i = 4 (l / 16) + r.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/m1.h"
+#include "m1_internal.h"
+#include "m1_nn.h"
+
+namespace m1 {
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint16_t f2bf(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+__device__ __forceinline__ bf16x4 load4(const uint16_t* p) {
+  const uint2 v = *reinterpret_cast<const uint2*>(p);
+  bf16x4 r;
+  r[0] = (short)(v.x & 0xFFFF);
+  r[1] = (short)(v.x >> 16);
+  r[2] = (short)(v.y & 0xFFFF);
+  r[3] = (short)(v.y >> 16);
+  return r;
+}
+__device__ __forceinline__ bf16x4 load4(const float* p) {
+  const float4 v = *reinterpret_cast<const float4*>(p);
+  bf16x4 r;
+  r[0] = (short)f2bf(v.x);
+  r[1] = (short)f2bf(v.y);
+  r[2] = (short)f2bf(v.z);
+  r[3] = (short)f2bf(v.w);
+  return r;
+}
+__device__ __forceinline__ void store1(uint16_t* p, float v) { *p = f2bf(v); }
+__device__ __forceinline__ void store1(float* p, float v) { *p = v; }
+
+// ---------------------------------------------------------------------------
+// 3x3 convolution (forward, or input gradient with transformed weights)
+// Input channels: [0, C0) from x0 (optionally at half resolution, nearest
+// upsampled), [C0, C0 + C1) from x1.  w: [9][Cout][C0 + C1] bf16.
+// Block: 4 wavefronts x 16 pixels of one row; each wave covers 64 output channels.
+// ---------------------------------------------------------------------------
+template <typename TIN, typename TOUT>
+__global__ __launch_bounds__(256) void k_conv3(int H, int W, const TIN* __restrict__ x0, int C0, int up0,
+                                               const TIN* __restrict__ x1, int C1, const uint16_t* __restrict__ w,
+                                               const float* __restrict__ bias, int Cout, TOUT* __restrict__ y,
+                                               int relu, const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int h = blockIdx.y;
+  const int pbase = blockIdx.x * 64 + wv * 16;
+  if (pbase >= W) return;  // whole wavefront idle
+  const int co_base = blockIdx.z * 64;
+  const int pA = pbase + (lane & 15);
+  const int kq = (lane >> 4) * 4;
+  const int Cin = C0 + C1;
+  const int W0 = up0 ? (W >> 1) : W;
+  f32x4 acc[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const bf16x4 zero = {0, 0, 0, 0};
+  for (int tap = 0; tap < 9; ++tap) {
+    const int hh = h + tap / 3 - 1, ww = pA + tap % 3 - 1;
+    const bool inb = hh >= 0 && hh < H && ww >= 0 && ww < W;
+    for (int c0 = 0; c0 < Cin; c0 += 16) {
+      bf16x4 A = zero;
+      if (inb) {
+        if (c0 < C0) {
+          const int sh = up0 ? (hh >> 1) : hh, sw = up0 ? (ww >> 1) : ww;
+          A = load4(x0 + ((int64_t)sh * W0 + sw) * C0 + c0 + kq);
+        } else {
+          A = load4(x1 + ((int64_t)hh * W + ww) * C1 + (c0 - C0) + kq);
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int co = co_base + t * 16 + (lane & 15);
+        const bf16x4 B = co < Cout ? load4(w + ((int64_t)tap * Cout + co) * Cin + c0 + kq) : zero;
+        acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A, B, acc[t], 0, 0, 0);
+      }
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int co = co_base + t * 16 + (lane & 15);
+    if (co >= Cout) continue;
+    const float b = bias ? bias[co] : 0.f;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int px = pbase + (lane >> 4) * 4 + r;
+      if (px >= W) continue;
+      float v = acc[t][r] + b;
+      if (relu) v = fmaxf(v, 0.f);
+      store1(y + ((int64_t)h * W + px) * Cout + co, v);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// weight gradient: part[chunk][tap][co][ci] = sum_{p in chunk} gT[co][p] * xs_tap[p][ci]
+// xT: channel-major input (Cin x HW), gT: channel-major output gradient (Cout x HW).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_wgrad3(int H, int W, const uint16_t* __restrict__ xT, int Cin,
+                                                const uint16_t* __restrict__ gT, int Cout, int chunk,
+                                                float* __restrict__ part) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int tap = blockIdx.y;
+  const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+  const int nco = (Cout + 63) / 64;
+  const int co_blk = blockIdx.x % nco, ci_blk = blockIdx.x / nco;
+  const int HW = H * W;
+  const int p0 = blockIdx.z * chunk;
+  const int p1 = min(p0 + chunk, HW);
+  const int co_row = co_blk * 64 + wv * 16 + (lane & 15);
+  const int kq = (lane >> 4) * 4;
+  f32x4 acc[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int pk = p0; pk < p1; pk += 16) {
+    bf16x4 A = {0, 0, 0, 0};
+    int hs[4], ws[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int p = pk + kq + r;
+      hs[r] = -1;
+      if (p < p1) {
+        if (co_row < Cout) A[r] = (short)gT[(int64_t)co_row * HW + p];
+        const int hh = p / W + dy, ww = p % W + dx;
+        if (hh >= 0 && hh < H && ww >= 0 && ww < W) {
+          hs[r] = hh;
+          ws[r] = ww;
+        }
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int ci = ci_blk * 64 + t * 16 + (lane & 15);
+      bf16x4 B = {0, 0, 0, 0};
+      if (ci < Cin) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          if (hs[r] >= 0) B[r] = (short)xT[(int64_t)ci * HW + hs[r] * W + ws[r]];
+      }
+      acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A, B, acc[t], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int ci = ci_blk * 64 + t * 16 + (lane & 15);
+    if (ci >= Cin) continue;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int co = co_blk * 64 + wv * 16 + (lane >> 4) * 4 + r;
+      if (co < Cout) part[(((int64_t)blockIdx.z * 9 + tap) * Cout + co) * Cin + ci] = acc[t][r];
+    }
+  }
+}
+
+// sum over chunks in a fixed order: out[i] = sum_c part[c * n + i]
+__global__ void k_sum_chunks(const float* __restrict__ part, int nchunks, int64_t n, float* __restrict__ out) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    float s = 0.f;
+    for (int c = 0; c < nchunks; ++c) s += part[(int64_t)c * n + i];
+    out[i] = s;
+  }
+}
+
+// row sums of a channel-major tensor: out[c] = sum_p g[c][p]  (bias gradient)
+__global__ void k_rowsum(const uint16_t* __restrict__ gT, int HW, float* __restrict__ out) {
+  const int c = blockIdx.x;
+  float s = 0.f;
+  for (int p = threadIdx.x; p < HW; p += blockDim.x) s += bf2f(gT[(int64_t)c * HW + p]);
+  __shared__ float red[256];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[c] = red[0];
+}
+
+// ---------------------------------------------------------------------------
+// elementwise / layout helpers
+// ---------------------------------------------------------------------------
+// pack an (HW x cin) FP32 tensor into (HW x cpad) bf16 with zero channels
+__global__ void k_pack(int64_t npix, const float* __restrict__ x, int cin, int cpad, uint16_t* __restrict__ out) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < npix * cpad; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t p = i / cpad;
+    const int c = (int)(i % cpad);
+    out[i] = c < cin ? f2bf(x[p * cin + c]) : (uint16_t)0;
+  }
+}
+
+__global__ void k_pool2(int Ho, int Wo, int C, const uint16_t* __restrict__ in, uint16_t* __restrict__ out,
+                        const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  const int64_t n = (int64_t)Ho * Wo * C;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int c = (int)(i % C);
+    const int64_t p = i / C;
+    const int wo = (int)(p % Wo), ho = (int)(p / Wo);
+    const int Wi = 2 * Wo;
+    float s = 0.f;
+    for (int a = 0; a < 2; ++a)
+      for (int b = 0; b < 2; ++b) s += bf2f(in[((int64_t)(2 * ho + a) * Wi + 2 * wo + b) * C + c]);
+    out[i] = f2bf(0.25f * s);
+  }
+}
+
+// channel-major bf16 copy of the (optionally concatenated / upsampled) conv input
+__global__ void k_to_chw(int H, int W, const uint16_t* __restrict__ x0, int C0, int up0,
+                         const uint16_t* __restrict__ x1, int C1, uint16_t* __restrict__ out) {
+  const int64_t HW = (int64_t)H * W;
+  const int C = C0 + C1;
+  const int W0 = up0 ? W / 2 : W;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < HW * C; i += (int64_t)gridDim.x * blockDim.x) {
+    const int c = (int)(i / HW);
+    const int64_t p = i % HW;
+    const int h = (int)(p / W), w = (int)(p % W);
+    uint16_t v;
+    if (c < C0) v = up0 ? x0[((int64_t)(h / 2) * W0 + w / 2) * C0 + c] : x0[p * C0 + c];
+    else v = x1[p * C1 + (c - C0)];
+    out[i] = v;
+  }
+}
+
+// gradient through ReLU: gpre = g * (out > 0); NHWC FP32 copy and channel-major bf16 copy
+__global__ void k_relu_grad(int64_t HW, int C, const float* __restrict__ g, const uint16_t* __restrict__ outv,
+                            float* __restrict__ gpre, uint16_t* __restrict__ gT) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < HW * C; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t p = i / C;
+    const int c = (int)(i % C);
+    const float v = bf2f(outv[i]) > 0.f ? g[i] : 0.f;
+    gpre[i] = v;
+    gT[(int64_t)c * HW + p] = f2bf(v);
+  }
+}
+
+// split the gradient of concat(up2(d), skip): gd[hh][ww][c] = sum of the 2x2 block
+// (c < Cu); gskip[h][w][c] = gcat[h][w][Cu + c]
+__global__ void k_split_cat(int H, int W, int Cu, int Cs, const float* __restrict__ gcat, float* __restrict__ gd,
+                            float* __restrict__ gskip) {
+  const int C = Cu + Cs;
+  const int64_t nhalf = (int64_t)(H / 2) * (W / 2) * Cu;
+  const int64_t nfull = (int64_t)H * W * Cs;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nhalf + nfull; i += (int64_t)gridDim.x * blockDim.x) {
+    if (i < nhalf) {
+      const int c = (int)(i % Cu);
+      const int64_t q = i / Cu;
+      const int wo = (int)(q % (W / 2)), ho = (int)(q / (W / 2));
+      float s = 0.f;
+      for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) s += gcat[((int64_t)(2 * ho + a) * W + 2 * wo + b) * C + c];
+      gd[i] = s;
+    } else {
+      const int64_t j = i - nhalf;
+      const int c = (int)(j % Cs);
+      const int64_t p = j / Cs;
+      gskip[j] = gcat[p * C + Cu + c];
+    }
+  }
+}
+
+// ge[h][w][c] += 0.25 * ga[h/2][w/2][c]  (average-pool backward), optionally ge = gadd + ...
+__global__ void k_pool_back_add(int H, int W, int C, const float* __restrict__ ga, const float* __restrict__ gadd,
+                                float* __restrict__ ge) {
+  const int64_t n = (int64_t)H * W * C;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int c = (int)(i % C);
+    const int64_t p = i / C;
+    const int w = (int)(p % W), h = (int)(p / W);
+    ge[i] = gadd[i] + 0.25f * ga[((int64_t)(h / 2) * (W / 2) + w / 2) * C + c];
+  }
+}
+
+// 1x1 head (FP32): y[p][co] = b[co] + sum_ci x[p][ci] * w[co][ci]
+__global__ void k_head_fwd(int64_t npix, const uint16_t* __restrict__ x, int Cin, const float* __restrict__ w,
+                           const float* __restrict__ b, int Cout, float* __restrict__ y,
+                           const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < npix; p += (int64_t)gridDim.x * blockDim.x) {
+    for (int co = 0; co < Cout; ++co) {
+      float s = b[co];
+      for (int ci = 0; ci < Cin; ++ci) s += bf2f(x[p * Cin + ci]) * w[co * Cin + ci];
+      y[p * Cout + co] = s;
+    }
+  }
+}
+
+__global__ void k_head_dx(int64_t npix, const float* __restrict__ gy, int Cout, const float* __restrict__ w, int Cin,
+                          float* __restrict__ gx) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < npix * Cin; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t p = i / Cin;
+    const int ci = (int)(i % Cin);
+    float s = 0.f;
+    for (int co = 0; co < Cout; ++co) s += gy[p * Cout + co] * w[co * Cin + ci];
+    gx[i] = s;
+  }
+}
+
+// head weight/bias gradient: one block per (co, ci) pair (ci = Cin means the bias)
+__global__ void k_head_dw(int64_t npix, const float* __restrict__ gy, int Cout, const uint16_t* __restrict__ x,
+                          int Cin, float* __restrict__ gw, float* __restrict__ gb) {
+  const int co = blockIdx.x / (Cin + 1), ci = blockIdx.x % (Cin + 1);
+  float s = 0.f;
+  for (int64_t p = threadIdx.x; p < npix; p += blockDim.x)
+    s += gy[p * Cout + co] * (ci < Cin ? bf2f(x[p * Cin + ci]) : 1.f);
+  __shared__ float red[256];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    if (ci < Cin) gw[co * Cin + ci] = red[0];
+    else gb[co] = red[0];
+  }
+}
+
+// relative loss: sums of (y - t)^2 and t^2 per block, then the gradient 2 (y - t) / sum t^2
+__global__ void k_loss_part(int64_t n, const float* __restrict__ y, const float* __restrict__ t,
+                            double* __restrict__ part) {
+  double a = 0.0, b = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const double d = (double)y[i] - (double)t[i];
+    a += d * d;
+    b += (double)t[i] * (double)t[i];
+  }
+  __shared__ double ra[256], rb[256];
+  ra[threadIdx.x] = a;
+  rb[threadIdx.x] = b;
+  __syncthreads();
+  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      ra[threadIdx.x] += ra[threadIdx.x + o];
+      rb[threadIdx.x] += rb[threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = ra[0];
+    part[2 * blockIdx.x + 1] = rb[0];
+  }
+}
+
+__global__ void k_loss_final(const double* __restrict__ part, int nb, double* __restrict__ out) {
+  if (threadIdx.x == 0) {
+    double a = 0.0, b = 0.0;
+    for (int i = 0; i < nb; ++i) {
+      a += part[2 * i];
+      b += part[2 * i + 1];
+    }
+    out[0] = b > 0 ? a / b : 0.0;
+    out[1] = b;
+  }
+}
+
+__global__ void k_loss_grad(int64_t n, const float* __restrict__ y, const float* __restrict__ t,
+                            const double* __restrict__ sums, float* __restrict__ gy) {
+  const float sc = sums[1] > 0 ? (float)(2.0 / sums[1]) : 0.f;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    gy[i] = sc * (y[i] - t[i]);
+}
+
+__global__ void k_adam(int64_t n, float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
+                       float* __restrict__ v, float lr, float b1, float b2, float eps, float c1, float c2) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+  }
+}
+
+// bf16 forward weights (same layout as the master) and input-gradient weights
+// wt[tap][ci][co] = w[8 - tap][co][ci]
+__global__ void k_weights_bf16(int Cout, int Cin, const float* __restrict__ wm, uint16_t* __restrict__ wf,
+                               uint16_t* __restrict__ wt) {
+  const int64_t n = (int64_t)9 * Cout * Cin;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int ci = (int)(i % Cin);
+    const int co = (int)((i / Cin) % Cout);
+    const int tap = (int)(i / ((int64_t)Cin * Cout));
+    const uint16_t v = f2bf(wm[i]);
+    wf[i] = v;
+    wt[((int64_t)(8 - tap) * Cin + ci) * Cout + co] = v;
+  }
+}
+
+static int64_t grid_for(int64_t n) { return std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 8192)); }
+
+}  // namespace m1
+
+using namespace m1;
+
+// ============================================================================
+// Host-side network object
+// ============================================================================
+namespace {
+
+struct ConvLayer {
+  int cin, cout;        // cin padded to a multiple of 16 (conv3)
+  int cin_true;         // channels of the unpadded definition
+  int64_t woff, boff;   // offsets in the parameter slab (FP32)
+  int64_t wsize;
+  uint16_t* wf = nullptr;   // bf16 forward weights
+  uint16_t* wt = nullptr;   // bf16 input-gradient weights
+};
+
+}  // namespace
+
+struct m1nn {
+  int cin = 0, cin_pad = 0, cout = 0, L = 0;
+  int ch[8] = {};
+  int Hmax = 0, Wmax = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  std::vector<ConvLayer> conv;   // enc0a, enc0b, ..., dec(L-2)a, dec(L-2)b, ..., dec0a, dec0b
+  int64_t nparam = 0;            // FP32 slab length (padded layout)
+  float* P = nullptr;            // master parameters
+  float* G = nullptr;            // gradients
+  float* Mo = nullptr;           // Adam first moment
+  float* Vo = nullptr;           // Adam second moment
+  int adam_t = 0;
+  int64_t head_w = 0, head_b = 0;
+  // activations (bf16 NHWC) per level
+  uint16_t* in = nullptr;
+  std::vector<uint16_t*> ha, e, a, hd, d;   // ha_l, e_l, a_{l} (pooled input of level l, l>=1), hd_l, d_l
+  float* y = nullptr;
+  // backward buffers
+  float* gy = nullptr;
+  float* gbuf0 = nullptr;   // FP32 scratch sized for the largest tensor
+  float* gbuf1 = nullptr;
+  float* gbuf2 = nullptr;
+  float* gpre = nullptr;
+  std::vector<float*> genc; // gradient w.r.t. e_l (FP32)
+  uint16_t* xT = nullptr;   // channel-major input copy for wgrad
+  uint16_t* gT = nullptr;   // channel-major gradient copy for wgrad
+  float* wpart = nullptr;
+  int64_t wpart_len = 0;
+  double* loss_part = nullptr;
+  double* loss_out = nullptr;
+  const int* skip = nullptr;  // device flag: forward kernels return at once when it is set
+};
+
+namespace {
+
+int conv_index(const m1nn* n, const char kind, int level, int ab) {
+  // kind 'e' encoder, 'd' decoder; ab 0 = first conv, 1 = second
+  if (kind == 'e') return 2 * level + ab;
+  // decoder levels are stored L-2 down to 0
+  return 2 * n->L + 2 * (n->L - 2 - level) + ab;
+}
+
+bool ok(m1nn* n, hipError_t e, const char* what) {
+  if (e == hipSuccess) return true;
+  n->err = std::string(what) + ": " + hipGetErrorString(e);
+  return false;
+}
+
+template <typename T> bool alloc(m1nn* n, T** p, int64_t count) {
+  *p = nullptr;
+  if (count <= 0) return true;
+  return ok(n, hipMalloc((void**)p, sizeof(T) * (size_t)count), "hipMalloc");
+}
+
+void nn_free(m1nn* n) {
+  auto f = [](void* p) { if (p) hipFree(p); };
+  for (auto& c : n->conv) { f(c.wf); f(c.wt); }
+  f(n->P); f(n->G); f(n->Mo); f(n->Vo); f(n->in); f(n->y); f(n->gy); f(n->gbuf0); f(n->gbuf1); f(n->gbuf2);
+  f(n->gpre); f(n->xT); f(n->gT); f(n->wpart); f(n->loss_part); f(n->loss_out);
+  for (auto* p : n->ha) f(p);
+  for (auto* p : n->e) f(p);
+  for (auto* p : n->a) f(p);
+  for (auto* p : n->hd) f(p);
+  for (auto* p : n->d) f(p);
+  for (auto* p : n->genc) f(p);
+}
+
+void refresh_weights(m1nn* n) {
+  for (auto& c : n->conv) {
+    const int64_t cnt = (int64_t)9 * c.cout * c.cin;
+    k_weights_bf16<<<grid_for(cnt), 256, 0, n->stream>>>(c.cout, c.cin, n->P + c.woff, c.wf, c.wt);
+  }
+}
+
+void conv3(m1nn* n, int H, int W, const uint16_t* x0, int C0, int up0, const uint16_t* x1, int C1, const ConvLayer& c,
+           uint16_t* y, int relu) {
+  dim3 grd((W + 63) / 64, H, (c.cout + 63) / 64);
+  k_conv3<uint16_t, uint16_t><<<grd, 256, 0, n->stream>>>(H, W, x0, C0, up0, x1, C1, c.wf, n->P + c.boff, c.cout, y,
+                                                          relu, n->skip);
+}
+
+// input gradient of a conv3 layer: gx (H, W, cin) FP32 from gpre (H, W, cout) FP32
+void conv3_dgrad(m1nn* n, int H, int W, const float* gpre, const ConvLayer& c, float* gx) {
+  dim3 grd((W + 63) / 64, H, (c.cin + 63) / 64);
+  k_conv3<float, float><<<grd, 256, 0, n->stream>>>(H, W, gpre, c.cout, 0, nullptr, 0, c.wt, nullptr, c.cin, gx, 0,
+                                                    nullptr);
+}
+
+// weight and bias gradient of a conv3 layer from xT (cin x HW) and gT (cout x HW)
+void conv3_wgrad(m1nn* n, int H, int W, const ConvLayer& c) {
+  const int HW = H * W;
+  const int chunk = 4096;
+  const int nch = (HW + chunk - 1) / chunk;
+  const int blocks = ((c.cout + 63) / 64) * ((c.cin + 63) / 64);
+  dim3 grd(blocks, 9, nch);
+  k_wgrad3<<<grd, 256, 0, n->stream>>>(H, W, n->xT, c.cin, n->gT, c.cout, chunk, n->wpart);
+  const int64_t nw = (int64_t)9 * c.cout * c.cin;
+  k_sum_chunks<<<grid_for(nw), 256, 0, n->stream>>>(n->wpart, nch, nw, n->G + c.woff);
+  k_rowsum<<<c.cout, 256, 0, n->stream>>>(n->gT, HW, n->G + c.boff);
+}
+
+void forward_impl(m1nn* n, int H, int W) {
+  const int L = n->L;
+  const uint16_t* a = n->in;
+  int cprev = n->cin_pad;
+  for (int l = 0; l < L; ++l) {
+    const int Hl = H >> l, Wl = W >> l;
+    const ConvLayer& ca = n->conv[conv_index(n, 'e', l, 0)];
+    const ConvLayer& cb = n->conv[conv_index(n, 'e', l, 1)];
+    conv3(n, Hl, Wl, a, cprev, 0, nullptr, 0, ca, n->ha[l], 1);
+    conv3(n, Hl, Wl, n->ha[l], n->ch[l], 0, nullptr, 0, cb, n->e[l], 1);
+    if (l < L - 1) {
+      const int64_t cnt = (int64_t)(Hl / 2) * (Wl / 2) * n->ch[l];
+      k_pool2<<<grid_for(cnt), 256, 0, n->stream>>>(Hl / 2, Wl / 2, n->ch[l], n->e[l], n->a[l + 1], n->skip);
+      a = n->a[l + 1];
+      cprev = n->ch[l];
+    }
+  }
+  const uint16_t* dnext = n->e[L - 1];
+  for (int l = L - 2; l >= 0; --l) {
+    const int Hl = H >> l, Wl = W >> l;
+    const ConvLayer& ca = n->conv[conv_index(n, 'd', l, 0)];
+    const ConvLayer& cb = n->conv[conv_index(n, 'd', l, 1)];
+    conv3(n, Hl, Wl, dnext, n->ch[l + 1], 1, n->e[l], n->ch[l], ca, n->hd[l], 1);
+    conv3(n, Hl, Wl, n->hd[l], n->ch[l], 0, nullptr, 0, cb, n->d[l], 1);
+    dnext = n->d[l];
+  }
+  const int64_t npix = (int64_t)H * W;
+  k_head_fwd<<<grid_for(npix), 256, 0, n->stream>>>(npix, n->d[0], n->ch[0], n->P + n->head_w, n->P + n->head_b,
+                                                    n->cout, n->y, n->skip);
+}
+
+// backward of o = relu(conv3(x)) given g = dL/do (FP32, H x W x cout):
+// weight/bias gradients into G, input gradient (before any ReLU of x) into gx
+void conv_layer_backward(m1nn* n, int H, int W, const float* g, const uint16_t* o, const uint16_t* x0, int C0,
+                         int up0, const uint16_t* x1, int C1, const ConvLayer& c, float* gx) {
+  const int64_t HW = (int64_t)H * W;
+  k_relu_grad<<<grid_for(HW * c.cout), 256, 0, n->stream>>>(HW, c.cout, g, o, n->gpre, n->gT);
+  k_to_chw<<<grid_for(HW * (C0 + C1)), 256, 0, n->stream>>>(H, W, x0, C0, up0, x1, C1, n->xT);
+  conv3_wgrad(n, H, W, c);
+  if (gx) conv3_dgrad(n, H, W, n->gpre, c, gx);
+}
+
+void backward_impl(m1nn* n, int H, int W) {
+  const int L = n->L;
+  const int64_t npix = (int64_t)H * W;
+  // head
+  k_head_dw<<<n->cout * (n->ch[0] + 1), 256, 0, n->stream>>>(npix, n->gy, n->cout, n->d[0], n->ch[0],
+                                                              n->G + n->head_w, n->G + n->head_b);
+  float* gd = n->gbuf0;  // gradient w.r.t. d_l (FP32)
+  k_head_dx<<<grid_for(npix * n->ch[0]), 256, 0, n->stream>>>(npix, n->gy, n->cout, n->P + n->head_w, n->ch[0], gd);
+  // decoder, level 0 upward
+  for (int l = 0; l < L - 1; ++l) {
+    const int Hl = H >> l, Wl = W >> l;
+    const ConvLayer& ca = n->conv[conv_index(n, 'd', l, 0)];
+    const ConvLayer& cb = n->conv[conv_index(n, 'd', l, 1)];
+    float* gh = n->gbuf1;
+    conv_layer_backward(n, Hl, Wl, gd, n->d[l], n->hd[l], n->ch[l], 0, nullptr, 0, cb, gh);
+    const uint16_t* dnext = (l + 1 == L - 1) ? n->e[L - 1] : n->d[l + 1];
+    float* gcat = n->gbuf2;
+    conv_layer_backward(n, Hl, Wl, gh, n->hd[l], dnext, n->ch[l + 1], 1, n->e[l], n->ch[l], ca, gcat);
+    // split: gradient of d_{l+1} (half resolution) and of the skip e_l
+    float* gdn = n->gbuf0;
+    const int64_t cnt = (int64_t)(Hl / 2) * (Wl / 2) * n->ch[l + 1] + (int64_t)Hl * Wl * n->ch[l];
+    k_split_cat<<<grid_for(cnt), 256, 0, n->stream>>>(Hl, Wl, n->ch[l + 1], n->ch[l], gcat, gdn, n->genc[l]);
+    gd = gdn;
+  }
+  // bottom: d_{L-1} = e_{L-1}
+  float* ge = n->gbuf1;
+  hipMemcpyAsync(ge, gd, sizeof(float) * (size_t)((H >> (L - 1)) * (W >> (L - 1)) * n->ch[L - 1]),
+                 hipMemcpyDeviceToDevice, n->stream);
+  for (int l = L - 1; l >= 0; --l) {
+    const int Hl = H >> l, Wl = W >> l;
+    const ConvLayer& ca = n->conv[conv_index(n, 'e', l, 0)];
+    const ConvLayer& cb = n->conv[conv_index(n, 'e', l, 1)];
+    float* gh = n->gbuf2;
+    conv_layer_backward(n, Hl, Wl, ge, n->e[l], n->ha[l], n->ch[l], 0, nullptr, 0, cb, gh);
+    const uint16_t* xin = l == 0 ? n->in : n->a[l];
+    const int cin = l == 0 ? n->cin_pad : n->ch[l - 1];
+    float* ga = l == 0 ? nullptr : n->gbuf0;
+    conv_layer_backward(n, Hl, Wl, gh, n->ha[l], xin, cin, 0, nullptr, 0, ca, ga);
+    if (l > 0) {
+      // gradient of e_{l-1} = skip gradient + average-pool backward of ga
+      const int Hp = H >> (l - 1), Wp = W >> (l - 1);
+      float* gen = n->gbuf1;
+      const int64_t cnt = (int64_t)Hp * Wp * n->ch[l - 1];
+      k_pool_back_add<<<grid_for(cnt), 256, 0, n->stream>>>(Hp, Wp, n->ch[l - 1], ga, n->genc[l - 1], gen);
+      ge = gen;
+    }
+  }
+}
+
+m1_status check_size(m1nn* n, int H, int W) {
+  const int q = 1 << (n->L - 1);
+  if (H < q || W < q || H % q || W % q || H > n->Hmax || W > n->Wmax) {
+    n->err = "H and W must be multiples of 2^(levels-1) and not exceed the sizes given at creation";
+    return M1_ERR_INVALID_ARG;
+  }
+  return M1_OK;
+}
+
+}  // namespace
+
+// ============================================================================
+// C ABI (network)
+// ============================================================================
+extern "C" {
+
+m1_status m1nn_create(int32_t cin, int32_t cout, int32_t levels, const int32_t* channels, int32_t Hmax, int32_t Wmax,
+                      void* hip_stream, m1nn** out) {
+  if (!out) return M1_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (cin < 1 || cin > 64 || cout < 1 || cout > 16 || levels < 1 || levels > 6 || !channels || Hmax < 1 || Wmax < 1)
+    return M1_ERR_INVALID_ARG;
+  for (int l = 0; l < levels; ++l)
+    if (channels[l] < 16 || channels[l] > 256 || channels[l] % 16) return M1_ERR_INVALID_ARG;
+  const int q = 1 << (levels - 1);
+  if (Hmax % q || Wmax % q) return M1_ERR_INVALID_ARG;
+  m1nn* n = new m1nn();
+  n->cin = cin;
+  n->cin_pad = (cin + 15) / 16 * 16;
+  n->cout = cout;
+  n->L = levels;
+  for (int l = 0; l < levels; ++l) n->ch[l] = channels[l];
+  n->Hmax = Hmax;
+  n->Wmax = Wmax;
+  n->stream = (hipStream_t)hip_stream;
+  // layer table and parameter slab (padded layout)
+  int64_t off = 0;
+  auto add = [&](int ci_pad, int ci_true, int co) {
+    ConvLayer c;
+    c.cin = ci_pad;
+    c.cin_true = ci_true;
+    c.cout = co;
+    c.woff = off;
+    c.wsize = (int64_t)9 * co * ci_pad;
+    off += c.wsize;
+    c.boff = off;
+    off += co;
+    n->conv.push_back(c);
+  };
+  int prev = n->cin_pad, prev_true = cin;
+  for (int l = 0; l < levels; ++l) {
+    add(prev, prev_true, channels[l]);
+    add(channels[l], channels[l], channels[l]);
+    prev = prev_true = channels[l];
+  }
+  for (int l = levels - 2; l >= 0; --l) {
+    add(channels[l + 1] + channels[l], channels[l + 1] + channels[l], channels[l]);
+    add(channels[l], channels[l], channels[l]);
+  }
+  n->head_w = off;
+  off += (int64_t)cout * channels[0];
+  n->head_b = off;
+  off += cout;
+  n->nparam = off;
+  bool good = alloc(n, &n->P, off) && alloc(n, &n->G, off) && alloc(n, &n->Mo, off) && alloc(n, &n->Vo, off);
+  for (auto& c : n->conv) good = good && alloc(n, &c.wf, c.wsize) && alloc(n, &c.wt, c.wsize);
+  const int64_t HW = (int64_t)Hmax * Wmax;
+  int cmax = n->cin_pad;
+  for (int l = 0; l < levels; ++l) cmax = std::max(cmax, channels[l] + (l + 1 < levels ? channels[l + 1] : 0));
+  good = good && alloc(n, &n->in, HW * n->cin_pad) && alloc(n, &n->y, HW * cout) && alloc(n, &n->gy, HW * cout);
+  n->ha.assign(levels, nullptr);
+  n->e.assign(levels, nullptr);
+  n->a.assign(levels, nullptr);
+  n->hd.assign(levels, nullptr);
+  n->d.assign(levels, nullptr);
+  n->genc.assign(levels, nullptr);
+  for (int l = 0; l < levels && good; ++l) {
+    const int64_t hw = HW >> (2 * l);
+    good = alloc(n, &n->ha[l], hw * channels[l]) && alloc(n, &n->e[l], hw * channels[l]) &&
+           alloc(n, &n->genc[l], hw * channels[l]);
+    if (good && l > 0) good = alloc(n, &n->a[l], hw * channels[l - 1]);
+    if (good && l < levels - 1) good = alloc(n, &n->hd[l], hw * channels[l]) && alloc(n, &n->d[l], hw * channels[l]);
+  }
+  good = good && alloc(n, &n->gbuf0, HW * cmax) && alloc(n, &n->gbuf1, HW * cmax) && alloc(n, &n->gbuf2, HW * cmax) &&
+         alloc(n, &n->gpre, HW * cmax) && alloc(n, &n->xT, HW * cmax) && alloc(n, &n->gT, HW * cmax);
+  int64_t wmax = 0;
+  for (auto& c : n->conv) wmax = std::max(wmax, c.wsize);
+  n->wpart_len = ((HW + 4095) / 4096) * wmax;
+  good = good && alloc(n, &n->wpart, n->wpart_len) && alloc(n, &n->loss_part, 2 * 1024) && alloc(n, &n->loss_out, 2);
+  if (!good) {
+    nn_free(n);
+    delete n;
+    return M1_ERR_OUT_OF_MEMORY;
+  }
+  hipMemsetAsync(n->P, 0, sizeof(float) * off, n->stream);
+  hipMemsetAsync(n->G, 0, sizeof(float) * off, n->stream);
+  hipMemsetAsync(n->Mo, 0, sizeof(float) * off, n->stream);
+  hipMemsetAsync(n->Vo, 0, sizeof(float) * off, n->stream);
+  refresh_weights(n);
+  if (hipStreamSynchronize(n->stream) != hipSuccess) {
+    nn_free(n);
+    delete n;
+    return M1_ERR_HIP;
+  }
+  *out = n;
+  return M1_OK;
+}
+
+int64_t m1nn_param_count(const m1nn* n) {
+  if (!n) return 0;
+  int64_t cnt = 0;
+  for (auto& c : n->conv) cnt += (int64_t)9 * c.cin_true * c.cout + c.cout;
+  return cnt + (int64_t)n->cout * n->ch[0] + n->cout;
+}
+
+// Host copy of the parameters in definition order, each conv3 weight as
+// [dy][dx][ci][co] (unpadded) then its bias; the head as [ci][co] then bias.
+static m1_status copy_params(m1nn* n, float* host, int64_t count, bool to_device, bool grads) {
+  if (!n || !host) return M1_ERR_INVALID_ARG;
+  if (count != m1nn_param_count(n)) { n->err = "parameter count mismatch"; return M1_ERR_INVALID_ARG; }
+  std::vector<float> slab(n->nparam, 0.f);
+  const float* src = grads ? n->G : n->P;
+  if (!ok(n, hipMemcpyAsync(slab.data(), src, sizeof(float) * n->nparam, hipMemcpyDeviceToHost, n->stream), "copy") ||
+      !ok(n, hipStreamSynchronize(n->stream), "sync"))
+    return M1_ERR_HIP;
+  int64_t k = 0;
+  for (auto& c : n->conv) {
+    for (int tap = 0; tap < 9; ++tap)
+      for (int ci = 0; ci < c.cin_true; ++ci)
+        for (int co = 0; co < c.cout; ++co) {
+          float& s = slab[c.woff + ((int64_t)tap * c.cout + co) * c.cin + ci];
+          if (to_device) s = host[k++]; else host[k++] = s;
+        }
+    for (int co = 0; co < c.cout; ++co) {
+      float& s = slab[c.boff + co];
+      if (to_device) s = host[k++]; else host[k++] = s;
+    }
+  }
+  for (int ci = 0; ci < n->ch[0]; ++ci)
+    for (int co = 0; co < n->cout; ++co) {
+      float& s = slab[n->head_w + (int64_t)co * n->ch[0] + ci];
+      if (to_device) s = host[k++]; else host[k++] = s;
+    }
+  for (int co = 0; co < n->cout; ++co) {
+    float& s = slab[n->head_b + co];
+    if (to_device) s = host[k++]; else host[k++] = s;
+  }
+  if (to_device) {
+    if (!ok(n, hipMemcpyAsync(n->P, slab.data(), sizeof(float) * n->nparam, hipMemcpyHostToDevice, n->stream), "copy"))
+      return M1_ERR_HIP;
+    refresh_weights(n);
+    if (!ok(n, hipStreamSynchronize(n->stream), "sync")) return M1_ERR_HIP;
+  }
+  return M1_OK;
+}
+
+m1_status m1nn_set_params(m1nn* n, const float* host, int64_t count) {
+  return copy_params(n, const_cast<float*>(host), count, true, false);
+}
+m1_status m1nn_get_params(m1nn* n, float* host, int64_t count) { return copy_params(n, host, count, false, false); }
+m1_status m1nn_get_grads(m1nn* n, float* host, int64_t count) { return copy_params(n, host, count, false, true); }
+
+m1_status m1nn_forward(m1nn* n, const float* x, int32_t H, int32_t W, float* y) {
+  if (!n || !x || !y) return M1_ERR_INVALID_ARG;
+  m1_status st = check_size(n, H, W);
+  if (st != M1_OK) return st;
+  const int64_t npix = (int64_t)H * W;
+  k_pack<<<grid_for(npix * n->cin_pad), 256, 0, n->stream>>>(npix, x, n->cin, n->cin_pad, n->in);
+  forward_impl(n, H, W);
+  if (!ok(n, hipMemcpyAsync(y, n->y, sizeof(float) * npix * n->cout, hipMemcpyDeviceToDevice, n->stream), "copy"))
+    return M1_ERR_HIP;
+  return ok(n, hipGetLastError(), "launch") ? M1_OK : M1_ERR_HIP;
+}
+
+m1_status m1nn_backward(m1nn* n, const float* x, const float* target, int32_t H, int32_t W, double* loss) {
+  if (!n || !x || !target) return M1_ERR_INVALID_ARG;
+  m1_status st = check_size(n, H, W);
+  if (st != M1_OK) return st;
+  const int64_t npix = (int64_t)H * W;
+  const int64_t ny = npix * n->cout;
+  k_pack<<<grid_for(npix * n->cin_pad), 256, 0, n->stream>>>(npix, x, n->cin, n->cin_pad, n->in);
+  forward_impl(n, H, W);
+  const int nb = (int)std::min<int64_t>(1024, (ny + 255) / 256);
+  k_loss_part<<<nb, 256, 0, n->stream>>>(ny, n->y, target, n->loss_part);
+  k_loss_final<<<1, 64, 0, n->stream>>>(n->loss_part, nb, n->loss_out);
+  k_loss_grad<<<grid_for(ny), 256, 0, n->stream>>>(ny, n->y, target, n->loss_out, n->gy);
+  backward_impl(n, H, W);
+  double lh[2] = {0, 0};
+  if (!ok(n, hipMemcpyAsync(lh, n->loss_out, sizeof(lh), hipMemcpyDeviceToHost, n->stream), "copy") ||
+      !ok(n, hipStreamSynchronize(n->stream), "sync"))
+    return M1_ERR_HIP;
+  if (loss) *loss = lh[0];
+  return std::isfinite(lh[0]) ? M1_OK : M1_ERR_NONFINITE;
+}
+
+m1_status m1nn_adam_step(m1nn* n, float lr) {
+  if (!n || !(lr > 0)) return M1_ERR_INVALID_ARG;
+  n->adam_t += 1;
+  const float b1 = 0.9f, b2 = 0.999f;
+  const float c1 = 1.f - std::pow(b1, (float)n->adam_t), c2 = 1.f - std::pow(b2, (float)n->adam_t);
+  k_adam<<<grid_for(n->nparam), 256, 0, n->stream>>>(n->nparam, n->P, n->G, n->Mo, n->Vo, lr, b1, b2, 1e-8f, c1, c2);
+  refresh_weights(n);
+  return ok(n, hipGetLastError(), "launch") ? M1_OK : M1_ERR_HIP;
+}
+
+m1_status m1nn_train_step(m1nn* n, const float* x, const float* target, int32_t H, int32_t W, float lr, double* loss) {
+  m1_status st = m1nn_backward(n, x, target, H, W, loss);
+  if (st != M1_OK) return st;
+  return m1nn_adam_step(n, lr);
+}
+
+m1_status m1nn_save(m1nn* n, const char* path) {
+  if (!n || !path) return M1_ERR_INVALID_ARG;
+  const int64_t cnt = m1nn_param_count(n);
+  std::vector<float> h(cnt);
+  m1_status st = m1nn_get_params(n, h.data(), cnt);
+  if (st != M1_OK) return st;
+  FILE* f = std::fopen(path, "wb");
+  if (!f) { n->err = "cannot open file"; return M1_ERR_INVALID_ARG; }
+  const int32_t head[4 + 8] = {0x4D314E4E, n->cin, n->cout, n->L, n->ch[0], n->ch[1], n->ch[2], n->ch[3],
+                               n->ch[4], n->ch[5], n->ch[6], n->ch[7]};
+  bool good = std::fwrite(head, sizeof(head), 1, f) == 1 && std::fwrite(h.data(), sizeof(float), cnt, f) == (size_t)cnt;
+  std::fclose(f);
+  return good ? M1_OK : M1_ERR_INVALID_ARG;
+}
+
+m1_status m1nn_load(m1nn* n, const char* path) {
+  if (!n || !path) return M1_ERR_INVALID_ARG;
+  FILE* f = std::fopen(path, "rb");
+  if (!f) { n->err = "cannot open file"; return M1_ERR_INVALID_ARG; }
+  int32_t head[12];
+  bool good = std::fread(head, sizeof(head), 1, f) == 1 && head[0] == 0x4D314E4E && head[1] == n->cin &&
+              head[2] == n->cout && head[3] == n->L;
+  for (int l = 0; l < n->L && good; ++l) good = head[4 + l] == n->ch[l];
+  const int64_t cnt = m1nn_param_count(n);
+  std::vector<float> h(cnt);
+  good = good && std::fread(h.data(), sizeof(float), cnt, f) == (size_t)cnt;
+  std::fclose(f);
+  if (!good) { n->err = "weight file does not match this network"; return M1_ERR_INVALID_ARG; }
+  return m1nn_set_params(n, h.data(), cnt);
+}
+
+void m1nn_destroy(m1nn* n) {
+  if (!n) return;
+  if (n->stream) hipStreamSynchronize(n->stream);
+  nn_free(n);
+  delete n;
+}
+
+const char* m1nn_last_error(const m1nn* n) { return n ? n->err.c_str() : ""; }
+
+}  // extern "C"
+
+namespace m1 {
+// device pointers used by the learned preconditioner inside GMRES
+uint16_t* nn_input(m1nn* n) { return n->in; }
+const float* nn_output(m1nn* n) { return n->y; }
+int nn_cin_pad(const m1nn* n) { return n->cin_pad; }
+int nn_cin(const m1nn* n) { return n->cin; }
+int nn_cout(const m1nn* n) { return n->cout; }
+m1_status nn_run(m1nn* n, int H, int W, hipStream_t s, const int* skip) {
+  m1_status st = check_size(n, H, W);
+  if (st != M1_OK) return st;
+  hipStream_t keep = n->stream;
+  n->stream = s;
+  n->skip = skip;
+  forward_impl(n, H, W);
+  n->stream = keep;
+  n->skip = nullptr;
+  return M1_OK;
+}
+int nn_levels(const m1nn* n) { return n->L; }
+}  // namespace m1
+
+namespace m1 {
+
+constexpr int kNnCin = 9;
+
+template <typename TV>
+__global__ void k_nn_features(int64_t N, const TV* __restrict__ r, const double* __restrict__ rnorm2,
+                              const double* __restrict__ bjinv, const double* __restrict__ Uk,
+                              const double* __restrict__ sigma, double c, double cdt, int cpad,
+                              uint16_t* __restrict__ in_bf16, float* __restrict__ out_f32,
+                              const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  const double rn = sqrt(fmax(rnorm2[0], 0.0));
+  const double sc = rn > 0 ? sqrt(3.0 * (double)N) / rn : 0.0;
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < N; p += (int64_t)gridDim.x * blockDim.x) {
+    double rv[3], f[kNnCin];
+    for (int k = 0; k < 3; ++k) rv[k] = (double)r[k * N + p];
+    for (int k = 0; k < 3; ++k) {
+      f[k] = sc * rv[k];
+      double z = 0.0;
+      for (int q = 0; q < 3; ++q) z += bjinv[(k * 3 + q) * N + p] * rv[q];
+      f[3 + k] = sc * z;
+    }
+    f[6] = log10(1.0 + sigma[p] * cdt) * 0.25;
+    const double E = Uk[p], Fx = Uk[N + p], Fy = Uk[2 * N + p];
+    const double Fm = sqrt(Fx * Fx + Fy * Fy);
+    const double fr = Fm / (c * fmax(E, 1e-300));
+    const double scale = fr > 1.0 ? 1.0 / fr : 1.0;
+    f[7] = Fx / (c * fmax(E, 1e-300)) * scale;
+    f[8] = Fy / (c * fmax(E, 1e-300)) * scale;
+    if (in_bf16) {
+      for (int k = 0; k < cpad; ++k) in_bf16[p * cpad + k] = k < kNnCin ? f2bf((float)f[k]) : (uint16_t)0;
+    }
+    if (out_f32) {
+      for (int k = 0; k < kNnCin; ++k) out_f32[p * kNnCin + k] = (float)f[k];
+    }
+  }
+}
+
+template <typename TV>
+void launch_nn_features(int64_t N, const TV* r, const double* rnorm2, const double* bjinv, const double* Uk,
+                        const double* sigma, double c, double cdt, int cpad, uint16_t* in_bf16, float* out_f32,
+                        hipStream_t s, const int* skip) {
+  k_nn_features<TV><<<grid_for(N), 256, 0, s>>>(N, r, rnorm2, bjinv, Uk, sigma, c, cdt, cpad, in_bf16, out_f32,
+                                                skip);
+}
+
+template <typename TV, typename TZ>
+__global__ void k_nn_combine(int64_t N, const TV* __restrict__ r, const double* __restrict__ rnorm2,
+                             const double* __restrict__ bjinv, const float* __restrict__ y, TZ* __restrict__ z,
+                             const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  const double rn = sqrt(fmax(rnorm2[0], 0.0));
+  const double back = rn / sqrt(3.0 * (double)N);
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < N; p += (int64_t)gridDim.x * blockDim.x) {
+    double rv[3];
+    for (int k = 0; k < 3; ++k) rv[k] = (double)r[k * N + p];
+    for (int k = 0; k < 3; ++k) {
+      double acc = 0.0;
+      for (int q = 0; q < 3; ++q) acc += bjinv[(k * 3 + q) * N + p] * rv[q];
+      z[k * N + p] = (TZ)(acc + back * (double)y[p * 3 + k]);
+    }
+  }
+}
+
+template <typename TV, typename TZ>
+void launch_nn_combine(int64_t N, const TV* r, const double* rnorm2, const double* bjinv, const float* y, TZ* z,
+                       hipStream_t s, const int* skip) {
+  k_nn_combine<TV, TZ><<<grid_for(N), 256, 0, s>>>(N, r, rnorm2, bjinv, y, z, skip);
+}
+
+__global__ void k_nn_target(int64_t N, const double* __restrict__ r, const double* __restrict__ e,
+                            const double* __restrict__ rnorm2, const double* __restrict__ bjinv,
+                            float* __restrict__ t) {
+  const double rn = sqrt(fmax(rnorm2[0], 0.0));
+  const double sc = rn > 0 ? sqrt(3.0 * (double)N) / rn : 0.0;
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < N; p += (int64_t)gridDim.x * blockDim.x) {
+    for (int k = 0; k < 3; ++k) {
+      double acc = 0.0;
+      for (int q = 0; q < 3; ++q) acc += bjinv[(k * 3 + q) * N + p] * r[q * N + p];
+      t[p * 3 + k] = (float)(sc * (e[k * N + p] - acc));
+    }
+  }
+}
+
+void launch_nn_target(int64_t N, const double* r, const double* e, const double* rnorm2, const double* bjinv,
+                      float* t, hipStream_t s) {
+  k_nn_target<<<grid_for(N), 256, 0, s>>>(N, r, e, rnorm2, bjinv, t);
+}
+
+template void launch_nn_features<double>(int64_t, const double*, const double*, const double*, const double*,
+                                         const double*, double, double, int, uint16_t*, float*, hipStream_t,
+                                         const int*);
+template void launch_nn_features<float>(int64_t, const float*, const double*, const double*, const double*,
+                                        const double*, double, double, int, uint16_t*, float*, hipStream_t,
+                                         const int*);
+template void launch_nn_combine<double, double>(int64_t, const double*, const double*, const double*, const float*,
+                                                double*, hipStream_t, const int*);
+template void launch_nn_combine<float, float>(int64_t, const float*, const double*, const double*, const float*,
+                                              float*, hipStream_t, const int*);
+template void launch_nn_combine<double, float>(int64_t, const double*, const double*, const double*, const float*,
+                                               float*, hipStream_t, const int*);
+
+}  // namespace m1

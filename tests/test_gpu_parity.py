@@ -206,3 +206,26 @@ def test_error_paths_on_gpu():
     st, _ = s.implicit_step(U, raise_on_fail=False)
     assert st == P.M1_ERR_INVALID_ARG
     s.close()
+
+
+@pytest.mark.parametrize("basis32", [False, True])
+@pytest.mark.parametrize("n,bc,src,fs", STEP_CASES[:3])
+def test_mixed_precision_step_matches_fp64_oracle(n, bc, src, fs, basis32):
+    """FP32 operator/preconditioner (and optionally FP32 basis) inside FP64-residual GMRES
+    (iterative refinement): solved to 1e-10, the state is within 1e-8 of the FP64 oracle."""
+    import paper_2011_13926_amd as P
+    _say("mixed step", n, bc, src, fs, "basis32" if basis32 else "basis64")
+    p = _problem(n, bc, src, fs, "newton", seed=13, dt=2.0, fmax=0.6)
+    sch = O.Scheme.from_problem(p)
+    Un = O.state_from_problem(p, "n")
+    ref = O.implicit_step(sch, p["sigma"], p.get("rho_cv"), Un, p["dt"], rtol=1e-12, newton_rtol=1e-12)
+    s = P.Solver(p, precision="mixed", basis_fp32=basis32, rtol=1e-10, newton_rtol=1e-10)
+    try:
+        U = s.to_device(Un)
+        st, stats = s.implicit_step(U)
+        got = U.cpu().numpy()
+        err = _rel(got, ref.U)
+        _say(f"  mixed error vs FP64 oracle: {err:.2e}  krylov={stats['krylov_iters']}")
+        assert err <= 1e-8
+    finally:
+        s.close()
