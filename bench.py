@@ -40,7 +40,26 @@ def parse():
     ap.add_argument("--max-iters", type=int, default=60000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-events", action="store_true", help="do not time kernels with HIP events")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy (reference for hardware byte counters)")
     return ap.parse_args()
+
+
+def copy_calibration():
+    """A plain device-to-device copy of 1 GiB, 5 times: 1 GiB read + 1 GiB written per launch.
+    Its FETCH_SIZE / WRITE_SIZE counter readings calibrate the counters' units."""
+    import torch
+    n = (1 << 30) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / 5
+    print(json.dumps({"copy_bytes_read": 1 << 30, "copy_bytes_written": 1 << 30, "seconds_per_copy": dt,
+                      "GBps_read_plus_write": 2 * (1 << 30) / dt / 1e9}), flush=True)
 
 
 VARIANTS = {
@@ -139,6 +158,9 @@ def cpu_baseline(p, U0, fp64_result, budget_s=25.0):
 
 def main():
     args = parse()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
                           "n_gpus": args.gpus}), flush=True)

@@ -121,28 +121,32 @@ def init_params(c_in, channels, c_out, seed=0, head_scale=0.1):
     return params
 
 
-def forward(params, x, channels, keep=False):
-    """Network output y (H, W, C_out); with keep=True also the activations for backward."""
+def forward(params, x, channels, keep=False, act_round=None):
+    """Network output y (H, W, C_out); with keep=True also the activations for backward.
+
+    act_round (optional) is applied to the input and to every stored activation
+    (conv and pooling outputs), e.g. to emulate reduced-precision storage."""
+    rnd = act_round if act_round is not None else (lambda v: v)
     L = len(channels)
     acts = {}
-    a = x
+    a = rnd(x)
     enc = []
     for l in range(L):
         acts[f"enc{l}a.in"] = a
-        h = np.maximum(conv3_forward(a, params[f"enc{l}a.w"], params[f"enc{l}a.b"]), 0.0)
+        h = rnd(np.maximum(conv3_forward(a, params[f"enc{l}a.w"], params[f"enc{l}a.b"]), 0.0))
         acts[f"enc{l}b.in"] = h
-        e = np.maximum(conv3_forward(h, params[f"enc{l}b.w"], params[f"enc{l}b.b"]), 0.0)
+        e = rnd(np.maximum(conv3_forward(h, params[f"enc{l}b.w"], params[f"enc{l}b.b"]), 0.0))
         enc.append(e)
         acts[f"enc{l}.out"] = e
         if l < L - 1:
-            a = avgpool2(e)
+            a = rnd(avgpool2(e))
     d = enc[L - 1]
     for l in range(L - 2, -1, -1):
         cat = np.concatenate([up2(d), enc[l]], axis=2)
         acts[f"dec{l}a.in"] = cat
-        h = np.maximum(conv3_forward(cat, params[f"dec{l}a.w"], params[f"dec{l}a.b"]), 0.0)
+        h = rnd(np.maximum(conv3_forward(cat, params[f"dec{l}a.w"], params[f"dec{l}a.b"]), 0.0))
         acts[f"dec{l}b.in"] = h
-        d = np.maximum(conv3_forward(h, params[f"dec{l}b.w"], params[f"dec{l}b.b"]), 0.0)
+        d = rnd(np.maximum(conv3_forward(h, params[f"dec{l}b.w"], params[f"dec{l}b.b"]), 0.0))
         acts[f"dec{l}.out"] = d
     acts["head.in"] = d
     y = conv1_forward(d, params["head.w"], params["head.b"])
@@ -181,6 +185,27 @@ def backward(params, acts, gy, channels):
         ga_next = ga
     g["input"] = ga_next
     return g
+
+
+def flatten_params(params, c_in, channels, c_out):
+    """Parameters in definition order: each weight (C order) then its bias."""
+    out = []
+    for name, kind, ci, co in layer_specs(c_in, channels, c_out):
+        out.append(params[name + ".w"].ravel())
+        out.append(params[name + ".b"].ravel())
+    return np.concatenate(out)
+
+
+def unflatten_params(flat, c_in, channels, c_out):
+    params, k = {}, 0
+    for name, kind, ci, co in layer_specs(c_in, channels, c_out):
+        shape = (3, 3, ci, co) if kind == "conv3" else (ci, co)
+        n = int(np.prod(shape))
+        params[name + ".w"] = np.asarray(flat[k:k + n], float).reshape(shape)
+        k += n
+        params[name + ".b"] = np.asarray(flat[k:k + co], float)
+        k += co
+    return params
 
 
 def relative_loss(y, target):

@@ -309,6 +309,32 @@ class Solver:
             raise M1Error(st, _lib.m1_last_error(self.ctx).decode())
         return st, stats.as_dict()
 
+    def set_network(self, net):
+        self._net = net
+        self._check(_lib.m1_set_network(self.ctx, net.handle if net is not None else None))
+
+    def nn_features(self, r):
+        r = self.to_device(r)
+        f = self.torch.zeros(self.shape + (9,), dtype=self.torch.float32, device=self.device)
+        self._check(_lib.m1_nn_features(self.ctx, r.data_ptr(), f.data_ptr()))
+        return f
+
+    def nn_target(self, r, e):
+        r = self.to_device(r)
+        e = self.to_device(e)
+        t = self.torch.zeros(self.shape + (3,), dtype=self.torch.float32, device=self.device)
+        self._check(_lib.m1_nn_target(self.ctx, r.data_ptr(), e.data_ptr(), t.data_ptr()))
+        return t
+
+    def solve_linear(self, b, *, raise_on_fail=True):
+        b = self.to_device(b)
+        x = self.vector()
+        stats = M1Stats()
+        st = _lib.m1_solve_linear(self.ctx, b.data_ptr(), x.data_ptr(), ctypes.byref(stats))
+        if raise_on_fail and st != M1_OK:
+            raise M1Error(st, _lib.m1_last_error(self.ctx).decode())
+        return x, st, stats.as_dict()
+
     def profile_enable(self, on=True):
         self._check(_lib.m1_profile_enable(self.ctx, 1 if on else 0))
 
@@ -327,6 +353,97 @@ class Solver:
         if getattr(self, "ctx", None):
             _lib.m1_destroy(self.ctx)
             self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Net:
+    """The learned preconditioner's network (m1nn handle) with torch-tensor I/O."""
+
+    def __init__(self, cin=9, cout=3, channels=(32, 48, 64, 64), Hmax=512, Wmax=512, device="cuda"):
+        torch = _torch()
+        self.torch = torch
+        self.cin, self.cout, self.channels = cin, cout, tuple(channels)
+        self.device = torch.device(device)
+        self.stream = torch.cuda.current_stream(self.device)
+        ch = (ctypes.c_int32 * len(channels))(*channels)
+        h = ctypes.c_void_p()
+        st = _lib.m1nn_create(cin, cout, len(channels), ch, Hmax, Wmax, ctypes.c_void_p(self.stream.cuda_stream),
+                              ctypes.byref(h))
+        if st != M1_OK:
+            raise M1Error(st, "m1nn_create failed")
+        self.handle = h
+
+    def _check(self, st):
+        if st != M1_OK:
+            raise M1Error(st, _lib.m1nn_last_error(self.handle).decode())
+
+    @property
+    def param_count(self):
+        return int(_lib.m1nn_param_count(self.handle))
+
+    def set_params(self, flat):
+        import numpy as np
+        a = np.ascontiguousarray(flat, dtype=np.float32)
+        self._check(_lib.m1nn_set_params(self.handle, a.ctypes.data, a.size))
+
+    def get_params(self):
+        import numpy as np
+        a = np.zeros(self.param_count, dtype=np.float32)
+        self._check(_lib.m1nn_get_params(self.handle, a.ctypes.data, a.size))
+        return a
+
+    def get_grads(self):
+        import numpy as np
+        a = np.zeros(self.param_count, dtype=np.float32)
+        self._check(_lib.m1nn_get_grads(self.handle, a.ctypes.data, a.size))
+        return a
+
+    def _t(self, a, C):
+        t = self.torch.as_tensor(a, dtype=self.torch.float32).to(self.device).contiguous()
+        assert t.dim() == 3 and t.shape[2] == C
+        return t
+
+    def forward(self, x):
+        x = self._t(x, self.cin)
+        H, W = x.shape[0], x.shape[1]
+        y = self.torch.zeros((H, W, self.cout), dtype=self.torch.float32, device=self.device)
+        self._check(_lib.m1nn_forward(self.handle, x.data_ptr(), H, W, y.data_ptr()))
+        return y
+
+    def backward(self, x, target):
+        x = self._t(x, self.cin)
+        t = self._t(target, self.cout)
+        loss = ctypes.c_double()
+        self._check(_lib.m1nn_backward(self.handle, x.data_ptr(), t.data_ptr(), x.shape[0], x.shape[1],
+                                       ctypes.byref(loss)))
+        return loss.value
+
+    def adam_step(self, lr):
+        self._check(_lib.m1nn_adam_step(self.handle, float(lr)))
+
+    def train_step(self, x, target, lr):
+        x = self._t(x, self.cin)
+        t = self._t(target, self.cout)
+        loss = ctypes.c_double()
+        self._check(_lib.m1nn_train_step(self.handle, x.data_ptr(), t.data_ptr(), x.shape[0], x.shape[1],
+                                         float(lr), ctypes.byref(loss)))
+        return loss.value
+
+    def save(self, path):
+        self._check(_lib.m1nn_save(self.handle, str(path).encode()))
+
+    def load(self, path):
+        self._check(_lib.m1nn_load(self.handle, str(path).encode()))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib.m1nn_destroy(self.handle)
+            self.handle = None
 
     def __del__(self):
         try:

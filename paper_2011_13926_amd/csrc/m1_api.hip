@@ -783,6 +783,10 @@ m1_status m1_set_network(m1_ctx* c, m1nn* net) {
   if (nn_cin(net) != 9 || nn_cout(net) != 3) { c->err = "the network must map 9 input channels to 3"; return M1_ERR_INVALID_ARG; }
   const int q = 1 << (nn_levels(net) - 1);
   if (c->g.n[0] % q || c->g.n[1] % q) { c->err = "nx and ny must be multiples of 2^(levels-1)"; return M1_ERR_INVALID_ARG; }
+  if (c->g.n[0] > nn_wmax(net) || c->g.n[1] > nn_hmax(net)) {
+    c->err = "the grid is larger than the network's Hmax x Wmax";
+    return M1_ERR_INVALID_ARG;
+  }
   c->net = net;
   return M1_OK;
 }

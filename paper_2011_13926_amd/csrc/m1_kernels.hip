@@ -6,6 +6,8 @@
 // cells (one wavefront per grid row, coalesced SoA loads) on 4 rows; blockIdx.y
 // walks rows (j + ny*k).
 #include <algorithm>
+#include <cstdlib>
+#include <string>
 
 #include "m1_internal.h"
 
@@ -532,9 +534,185 @@ __global__ __launch_bounds__(256) void k_stencil(Geom g, Scheme sc, Coefs<R> cf,
   }
 }
 
+// ----------------------------------------------------------------------------
+// a3, 2D, LDS-staged: a block owns a 64 x 8 tile; its (66 x 10) halo tile of the
+// input vector x and of the linearised pressure q = (J x) for the three
+// independent pairs (xx, xy, yy) is computed once into LDS (ghosts included),
+// then every cell assembles its fluxes from LDS.  Each input element and each
+// Jacobian entry is read from memory once per tile instead of once per use.
+// ----------------------------------------------------------------------------
+constexpr int LX = 64, LY = 8, LHX = LX + 2, LHY = LY + 2;
+
+template <bool CPL, int MODE, typename R, typename VI, typename VO>
+__global__ __launch_bounds__(256) void k_apply2d_lds(Geom g, Scheme sc, Coefs<R> cf, Bdry bd, const VI* __restrict__ x,
+                                                     const double* __restrict__ b, VO* __restrict__ y,
+                                                     const int* __restrict__ skip) {
+  constexpr int NR = 3;
+  constexpr int NU = NR + (CPL ? 1 : 0);
+  if (skip && *skip) return;
+  __shared__ R sx[NR][LHY][LHX];
+  __shared__ R sq[3][LHY][LHX];
+  __shared__ R ss[LHY][LHX];
+  const int64_t N = g.N;
+  const int nx = g.n[0], ny = g.n[1];
+  const int i0 = blockIdx.x * LX - 1, j0 = blockIdx.y * LY - 1;
+  // ---- stage the halo tile ----
+  for (int t = threadIdx.x; t < LHX * LHY; t += 256) {
+    const int li = t % LHX, lj = t / LHX;
+    int gi = i0 + li, gj = j0 + lj;
+    const bool outx = gi < 0 || gi >= nx, outy = gj < 0 || gj >= ny;
+    R xv[NR] = {(R)0, (R)0, (R)0}, qv[3] = {(R)0, (R)0, (R)0}, sv = (R)0;
+    if (!(outx && outy)) {
+      int face = -1, d = 0;
+      if (outx) {
+        d = 0;
+        if (g.bc[0] == BC_PERIODIC) gi = (gi + nx) % nx;
+        else { face = gi < 0 ? 0 : 1; gi = gi < 0 ? 0 : nx - 1; }
+      } else if (outy) {
+        d = 1;
+        if (g.bc[2] == BC_PERIODIC) gj = (gj + ny) % ny;
+        else { face = gj < 0 ? 2 : 3; gj = gj < 0 ? 0 : ny - 1; }
+      }
+      const int64_t cell = (int64_t)gj * nx + gi;
+#pragma unroll
+      for (int c = 0; c < NR; ++c) xv[c] = (R)x[c * N + cell];
+      sv = cf.sigma[cell];
+      if (face < 0) {
+#pragma unroll
+        for (int pq = 0; pq < 3; ++pq) {
+          R acc = (R)0;
+#pragma unroll
+          for (int k = 0; k < NR; ++k) acc += cf.jac[(pq * NR + k) * N + cell] * xv[k];
+          qv[pq] = acc;
+        }
+      } else {
+        const int64_t pidx = d == 0 ? (int64_t)gj : (int64_t)gi;
+        const int64_t pn = g.plane_n[d];
+#pragma unroll
+        for (int c = 0; c < NR; ++c) xv[c] *= (R)ghost_weight(g.bc[face], d, c, bd.mask[face], pidx);
+#pragma unroll
+        for (int pq = 0; pq < 3; ++pq) {
+          R acc = (R)0;
+#pragma unroll
+          for (int k = 0; k < NR; ++k) acc += cf.gjac[cf.gjoff[face] + (pq * NR + k) * pn + pidx] * xv[k];
+          qv[pq] = acc;
+        }
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < NR; ++c) sx[c][lj][li] = xv[c];
+#pragma unroll
+    for (int pq = 0; pq < 3; ++pq) sq[pq][lj][li] = qv[pq];
+    ss[lj][li] = sv;
+  }
+  __syncthreads();
+  // ---- fluxes: each thread handles the cells (tx, ty) and (tx, ty + 4) ----
+  const int tx = threadIdx.x % LX;
+  const R s = (R)sc.s;
+  const R cdt = (R)sc.cdt;
+  for (int ty = threadIdx.x / LX; ty < LY; ty += 256 / LX) {
+    const int i = blockIdx.x * LX + tx, j = blockIdx.y * LY + ty;
+    if (i >= nx || j >= ny) continue;
+    const int64_t cell = (int64_t)j * nx + i;
+    const int li = tx + 1, lj = ty + 1;
+    R xs[NU], ys[NU];
+#pragma unroll
+    for (int c = 0; c < NR; ++c) { xs[c] = sx[c][lj][li]; ys[c] = xs[c]; }
+    if (CPL) { xs[NU - 1] = (R)x[(NU - 1) * N + cell]; ys[NU - 1] = (R)0; }
+    const R sig = ss[lj][li];
+#pragma unroll
+    for (int d = 0; d < 2; ++d) {
+      // neighbours in LDS; pressure pair index of (d, m) in 2D: (0,0)=0 (0,1)=1 (1,1)=2
+      const int ri = d == 0 ? li + 1 : li, rj = d == 0 ? lj : lj + 1;
+      const int mi = d == 0 ? li - 1 : li, mj = d == 0 ? lj : lj - 1;
+      R xr[NR], xl[NR], qs[2], qr[2], ql[2];
+#pragma unroll
+      for (int c = 0; c < NR; ++c) { xr[c] = sx[c][rj][ri]; xl[c] = sx[c][mj][mi]; }
+#pragma unroll
+      for (int m = 0; m < 2; ++m) {
+        const int pq = d + m;
+        qs[m] = sq[pq][lj][li];
+        qr[m] = sq[pq][rj][ri];
+        ql[m] = sq[pq][mj][mi];
+      }
+      const R sigR = ss[rj][ri], sigL = ss[mj][mi];
+      const R ap = cf.face[(3 * d + 0) * N + cell];
+      const R ddp = cf.face[(3 * d + 1) * N + cell];
+      const R alp = cf.face[(3 * d + 2) * N + cell];
+      const R bp = (R)1 - ap;
+      R am, ddm, alm;
+      {
+        const int id = d == 0 ? i : j, n = d == 0 ? nx : ny;
+        const int64_t stride = d == 0 ? 1 : nx;
+        if (id > 0) {
+          const int64_t nb = cell - stride;
+          am = cf.face[(3 * d + 0) * N + nb]; ddm = cf.face[(3 * d + 1) * N + nb]; alm = cf.face[(3 * d + 2) * N + nb];
+        } else if (g.bc[2 * d] == BC_PERIODIC) {
+          const int64_t nb = cell + (int64_t)(n - 1) * stride;
+          am = cf.face[(3 * d + 0) * N + nb]; ddm = cf.face[(3 * d + 1) * N + nb]; alm = cf.face[(3 * d + 2) * N + nb];
+        } else {
+          const int64_t pidx = d == 0 ? (int64_t)j : (int64_t)i;
+          const int64_t pn = g.plane_n[d];
+          am = cf.lowface[cf.lowoff[d] + pidx]; ddm = cf.lowface[cf.lowoff[d] + pn + pidx];
+          alm = cf.lowface[cf.lowoff[d] + 2 * pn + pidx];
+        }
+      }
+      const R bm = (R)1 - am;
+      const R FEp = alp * (ap * xs[1 + d] + bp * xr[1 + d] + ddp * (xr[0] - xs[0]));
+      const R FEm = alm * (am * xl[1 + d] + bm * xs[1 + d] + ddm * (xs[0] - xl[0]));
+      ys[0] += s * (FEp - FEm);
+#pragma unroll
+      for (int m = 0; m < 2; ++m) {
+        const R FPp = ap * qs[m] + bp * qr[m] + ddp * (xr[1 + m] - xs[1 + m]);
+        const R FPm = am * ql[m] + bm * qs[m] + ddm * (xs[1 + m] - xl[1 + m]);
+        ys[1 + m] += s * (FPp - FPm);
+      }
+      if (sc.wb) {
+        ys[1 + d] += (R)0.25 * cdt *
+                     ((R)0.5 * (sig + sigR) * (xs[1 + d] + xr[1 + d]) + (R)0.5 * (sig + sigL) * (xl[1 + d] + xs[1 + d]));
+      }
+    }
+    if (!sc.wb) {
+#pragma unroll
+      for (int m = 0; m < 2; ++m) ys[1 + m] += cdt * sig * xs[1 + m];
+    }
+    if (sc.src == SRC_ABS) ys[0] += cdt * sig * xs[0];
+    if (CPL) {
+      const R T = xs[NU - 1];
+      const R exch = cdt * sig * (cf.kap[cell] * T - xs[0]);
+      ys[NU - 1] = cf.rcv[cell] * T + exch;
+      ys[0] -= exch;
+    }
+#pragma unroll
+    for (int c = 0; c < NU; ++c) {
+      R v = ys[c];
+      if (MODE == 1) v = (R)b[c * N + cell] - v;
+      y[c * N + cell] = (VO)v;
+    }
+  }
+}
+
+static int g_apply_variant = -1;  // -1: read M1_APPLY_KERNEL once ("lds" default in 2D, "direct")
+
+static bool use_lds_2d() {
+  if (g_apply_variant < 0) {
+    const char* e = getenv("M1_APPLY_KERNEL");
+    g_apply_variant = (e && std::string(e) == "direct") ? 0 : 1;
+  }
+  return g_apply_variant == 1;
+}
+
 template <typename R, typename VI, typename VO>
 void launch_apply(int nd, bool cpl, int mode, const Geom& g, const Scheme& sc, const Coefs<R>& cf, const Bdry& bd,
                   const VI* x, const double* b, VO* y, hipStream_t s, const int* skip) {
+  if (nd == 2 && use_lds_2d()) {
+    dim3 grd2((g.n[0] + LX - 1) / LX, (g.n[1] + LY - 1) / LY);
+#define M1_LDS(CPL_, MODE_) k_apply2d_lds<CPL_, MODE_, R, VI, VO><<<grd2, 256, 0, s>>>(g, sc, cf, bd, x, b, y, skip)
+    if (cpl) { if (mode == 0) M1_LDS(true, 0); else M1_LDS(true, 1); }
+    else { if (mode == 0) M1_LDS(false, 0); else M1_LDS(false, 1); }
+#undef M1_LDS
+    return;
+  }
   dim3 blk(TX, TY), grd((g.n[0] + TX - 1) / TX, (g.rows + TY - 1) / TY);
 #define M1_ST(ND_, CPL_, MODE_) k_stencil<ND_, CPL_, MODE_, R, VI, VO><<<grd, blk, 0, s>>>(g, sc, cf, bd, x, b, nullptr, y, skip)
   if (nd == 2) {

@@ -14,6 +14,8 @@ int nn_cin_pad(const m1nn* n);
 int nn_cin(const m1nn* n);
 int nn_cout(const m1nn* n);
 int nn_levels(const m1nn* n);
+int nn_hmax(const m1nn* n);
+int nn_wmax(const m1nn* n);
 m1_status nn_run(m1nn* n, int H, int W, hipStream_t s, const int* skip);
 
 // Learned-preconditioner features of a residual r (2D, n_u = 3), written as the

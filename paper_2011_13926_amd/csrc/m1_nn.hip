@@ -902,6 +902,8 @@ m1_status nn_run(m1nn* n, int H, int W, hipStream_t s, const int* skip) {
   return M1_OK;
 }
 int nn_levels(const m1nn* n) { return n->L; }
+int nn_hmax(const m1nn* n) { return n->Hmax; }
+int nn_wmax(const m1nn* n) { return n->Wmax; }
 }  // namespace m1
 
 namespace m1 {

@@ -1,0 +1,169 @@
+"""GPU tests of the learned preconditioner: the BF16-MFMA network forward and
+gradients against the FP64 oracle (with BF16 rounding emulated at the same
+points), training progress, and flexible GMRES with the network inside."""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import m1_oracle as O
+from oracle import nn_oracle as N
+
+pytestmark = pytest.mark.gpu
+CH = [32, 48, 64, 64]
+CIN, COUT = 9, 3
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _rel(a, b):
+    a = np.asarray(a, float).ravel()
+    b = np.asarray(b, float).ravel()
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def _random_net_params(seed):
+    rng = np.random.default_rng(seed)
+    params = N.init_params(CIN, CH, COUT, seed=seed, head_scale=1.0)
+    for k in params:
+        if k.endswith(".b"):
+            params[k] = rng.standard_normal(params[k].shape) * 0.05
+    # the GPU stores 3x3 weights in BF16 and everything else in FP32
+    for name, kind, ci, co in N.layer_specs(CIN, CH, COUT):
+        if kind == "conv3":
+            params[name + ".w"] = N.bf16_round(params[name + ".w"])
+    flat = N.flatten_params(params, CIN, CH, COUT).astype(np.float32)
+    return N.unflatten_params(flat.astype(np.float64), CIN, CH, COUT), flat
+
+
+def test_mfma_network_forward_matches_oracle():
+    import paper_2011_13926_amd as P
+    _say("nn forward 32x40")
+    params, flat = _random_net_params(1)
+    rng = np.random.default_rng(2)
+    x = rng.standard_normal((32, 40, CIN)).astype(np.float32)
+    net = P.Net(CIN, COUT, CH, Hmax=32, Wmax=40)
+    try:
+        net.set_params(flat)
+        assert np.array_equal(net.get_params(), flat)
+        y = net.forward(x).cpu().numpy()
+    finally:
+        net.close()
+    ref = N.forward(params, x.astype(np.float64), CH, act_round=N.bf16_round)
+    err = _rel(y, ref)
+    _say(f"  forward relative L2 vs oracle (BF16 emulated): {err:.2e}")
+    assert err <= 1e-2
+
+
+def test_mfma_network_gradients_match_oracle():
+    import paper_2011_13926_amd as P
+    _say("nn gradients 32x32")
+    params, flat = _random_net_params(3)
+    rng = np.random.default_rng(4)
+    x = rng.standard_normal((32, 32, CIN)).astype(np.float32)
+    t = rng.standard_normal((32, 32, COUT)).astype(np.float32)
+    net = P.Net(CIN, COUT, CH, Hmax=32, Wmax=32)
+    try:
+        net.set_params(flat)
+        loss = net.backward(x, t)
+        g = net.get_grads()
+    finally:
+        net.close()
+    y, acts = N.forward(params, x.astype(np.float64), CH, keep=True, act_round=N.bf16_round)
+    lref, gy = N.relative_loss(y, t.astype(np.float64))
+    assert loss == pytest.approx(lref, rel=1e-3)
+    gref = N.backward(params, acts, gy, CH)
+    k = 0
+    worst = 0.0
+    for name, kind, ci, co in N.layer_specs(CIN, CH, COUT):
+        for part in ("w", "b"):
+            ref = gref[f"{name}.{part}"].ravel()
+            got = g[k:k + ref.size]
+            k += ref.size
+            err = _rel(got, ref)
+            worst = max(worst, err)
+            assert err <= 5e-2, (name, part, err)
+    _say(f"  worst per-tensor gradient relative L2: {worst:.2e}")
+
+
+def test_training_reduces_the_loss():
+    import paper_2011_13926_amd as P
+    _say("nn training")
+    rng = np.random.default_rng(5)
+    x = rng.standard_normal((32, 32, CIN)).astype(np.float32)
+    t = (0.5 * x[:, :, :3] + 0.1).astype(np.float32)
+    net = P.Net(CIN, COUT, CH, Hmax=32, Wmax=32)
+    try:
+        params = N.init_params(CIN, CH, COUT, seed=6)
+        net.set_params(N.flatten_params(params, CIN, CH, COUT).astype(np.float32))
+        losses = [net.train_step(x, t, 3e-3) for _ in range(40)]
+    finally:
+        net.close()
+    _say(f"  loss {losses[0]:.3e} -> {losses[-1]:.3e}")
+    assert losses[-1] < 0.5 * losses[0]
+
+
+def test_learned_fgmres_converges_and_matches_block_jacobi():
+    import paper_2011_13926_amd as P
+    _say("learned FGMRES 64x64")
+    p = W.random_problem((64, 64), 21, bc=("outflow", "reflect", "dirichlet", "outflow"), dt=5.0, fmax=0.5)
+    U = O.state_from_problem(p, "U")
+    Un = O.state_from_problem(p, "n")
+    net = P.Net(CIN, COUT, CH, Hmax=64, Wmax=64)
+    params = N.init_params(CIN, CH, COUT, seed=7, head_scale=0.05)
+    net.set_params(N.flatten_params(params, CIN, CH, COUT).astype(np.float32))
+    s_bj = P.Solver(p, U_lin=U, U_n=Un, rtol=1e-11)
+    s_nn = P.Solver(p, U_lin=U, U_n=Un, rtol=1e-11, pc="learned")
+    try:
+        s_nn.set_network(net)
+        b = s_bj.residual()
+        x_bj, st1, stats_bj = s_bj.solve_linear(b)
+        x_nn, st2, stats_nn = s_nn.solve_linear(b)
+        _say(f"  BJ {stats_bj['krylov_iters']} it, learned {stats_nn['krylov_iters']} it, fell_back={stats_nn['fell_back']}")
+        assert _rel(x_nn.cpu().numpy(), x_bj.cpu().numpy()) <= 1e-8
+        # an implicit step with the learned preconditioner agrees with the oracle
+        s_nn2 = P.Solver(p, rtol=1e-11, newton_rtol=1e-11, pc="learned")
+        s_nn2.set_network(net)
+        Ud = s_nn2.to_device(Un)
+        st, stats = s_nn2.implicit_step(Ud)
+        ref = O.implicit_step(O.Scheme.from_problem(p), p["sigma"], None, Un, p["dt"], rtol=1e-12, newton_rtol=1e-12)
+        assert _rel(Ud.cpu().numpy(), ref.U) <= 1e-8
+        s_nn2.close()
+    finally:
+        s_bj.close()
+        s_nn.close()
+        net.close()
+
+
+def test_features_and_target_layout():
+    """Features and targets computed on the GPU agree with their definitions
+    evaluated with the oracle's block-Jacobi."""
+    import paper_2011_13926_amd as P
+    _say("features/target")
+    p = W.random_problem((16, 24), 8, dt=3.0, fmax=0.5)
+    U = O.state_from_problem(p, "U")
+    Un = O.state_from_problem(p, "n")
+    lin = O.linearize(O.Scheme.from_problem(p), p["sigma"], None, U, Un, p["dt"])
+    M = O.BlockJacobi(lin)
+    r = W.random_vector(U.size, 1).reshape(U.shape)
+    e = W.random_vector(U.size, 2).reshape(U.shape)
+    s = P.Solver(p, U_lin=U, U_n=Un)
+    try:
+        f = s.nn_features(r).cpu().numpy()
+        t = s.nn_target(r, e).cpu().numpy()
+    finally:
+        s.close()
+    N_ = 16 * 24
+    sc = np.sqrt(3 * N_) / np.linalg.norm(r)
+    z = M(r)
+    for k in range(3):
+        assert np.allclose(f[:, :, k], sc * r[k], rtol=1e-6, atol=1e-6)
+        assert np.allclose(f[:, :, 3 + k], sc * z[k], rtol=1e-5, atol=1e-5)
+        assert np.allclose(t[:, :, k], sc * (e[k] - z[k]), rtol=1e-5, atol=1e-5)
+    assert np.allclose(f[:, :, 6], np.log10(1 + p["sigma"] * p["dt"]) / 4, rtol=1e-6)
+    fx = U[1] / U[0]
+    assert np.allclose(f[:, :, 7], fx, rtol=1e-6, atol=1e-7)
