@@ -7,6 +7,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -152,6 +153,16 @@ void prof_collect(m1_ctx* c) {
 int nu_of(const m1_config& c) { return 1 + c.ndim + (c.source == M1_SRC_COUPLED_T ? 1 : 0); }
 
 bool finite(double v) { return std::isfinite(v); }
+
+// M1_VERBOSE=1 in the environment prints one line per Newton iteration to stderr.
+bool verbose() {
+  static int v = -1;
+  if (v < 0) {
+    const char* e = std::getenv("M1_VERBOSE");
+    v = (e && e[0] && e[0] != '0') ? 1 : 0;
+  }
+  return v == 1;
+}
 
 m1_status validate_config(const m1_config* c, std::string& err) {
   if (!c) { err = "cfg is NULL"; return M1_ERR_INVALID_ARG; }
@@ -741,6 +752,9 @@ m1_status m1_implicit_step(m1_ctx* c, m1_state* U, double dt, m1_stats* stats) {
     kry += sr.iters;
     rst += sr.restarts;
     lin_rel = sr.rel;
+    if (verbose())
+      std::fprintf(stderr, "[m1] newton %d |R|=%.3e rel=%.3e gmres_iters=%d restarts=%d lin_rel=%.2e%s\n", it, rn, rel,
+                   sr.iters, sr.restarts, sr.rel, sr.converged ? "" : " (not converged)");
     if (sr.nonfinite) { nonfinite = true; break; }
     timed(c, KC_NEWTON_UPDATE, 24.0 * c->n, [&] {
       k_zero_u64<<<1, 64, 0, c->stream>>>(c->dcount);

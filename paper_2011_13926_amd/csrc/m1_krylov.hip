@@ -102,117 +102,164 @@ void launch_dot(int j, const TV* V, int64_t vs, const TV* u, const TV* p, int64_
 // a6: one workgroup: reduce the partials, finalise Hessenberg column j-1,
 // Givens rotation, residual estimate, coefficients of the next update pass.
 // ----------------------------------------------------------------------------
-constexpr int kScalarThreads = 256;
+constexpr int kScalarThreads = 1024;
+constexpr int kLd = kMaxRestart + 1;
 
 __global__ __launch_bounds__(kScalarThreads) void k_scalar(int j, int final_step, const double* __restrict__ part,
                                                            int nb, GmresState* gs) {
   if (gs->done) return;
   const int hasp = !final_step;
   const int nv = hasp ? 2 * j + 2 : j + 1;
+  const int tid = threadIdx.x;
+  __shared__ double psum[kScalarThreads];
   __shared__ double red[2 * kMaxRestart + 2];
-  __shared__ double Hs[kMaxRestart + 1];
+  __shared__ double sH[kLd * kMaxRestart];   // unrotated Hessenberg, columns 0..j-1
+  __shared__ double sR[kLd * kMaxRestart];   // rotated Hessenberg
+  __shared__ double sHp[kLd], sCs[kMaxRestart], sSn[kMaxRestart], sG[kLd], sHs[kLd], sY[kMaxRestart];
   __shared__ double sh_nu;
-  __shared__ int sh_done;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  for (int v = w; v < nv; v += kScalarThreads / 64) {
-    double t = 0.0;
-    for (int b = lane; b < nb; b += 64) t += part[(int64_t)v * nb + b];
-    t = wave_sum(t);
-    if (lane == 0) red[v] = t;
+  __shared__ int sh_done, sh_k;
+  // (1) reduce the per-block partials: Q threads per value, fixed order
+  const int Q = max(1, kScalarThreads / nv);
+  {
+    const int v = tid / Q, q = tid % Q;
+    double acc = 0.0;
+    if (v < nv)
+      for (int b = q; b < nb; b += Q) acc += part[(int64_t)v * nb + b];
+    psum[tid] = acc;
+  }
+  // (2) stage the small GMRES state in LDS
+  for (int t = tid; t < j * kLd; t += kScalarThreads) {
+    sH[t] = gs->Hraw[t];
+    sR[t] = gs->Rm[t];
+  }
+  for (int t = tid; t <= j; t += kScalarThreads) {
+    sHp[t] = gs->hprev[t];
+    sG[t] = gs->g[t];
+  }
+  for (int t = tid; t < j; t += kScalarThreads) {
+    sCs[t] = gs->cs[t];
+    sSn[t] = gs->sn[t];
+  }
+  __syncthreads();
+  if (tid < nv) {
+    double sacc = 0.0;
+    for (int q = 0; q < Q; ++q) sacc += psum[tid * Q + q];
+    red[tid] = sacc;
   }
   __syncthreads();
   const double* s = red;
   const double* t = red + j;
   const double alpha = hasp ? red[2 * j] : red[j];
   const double gamma = hasp ? red[2 * j + 1] : 0.0;
-  constexpr int ld = kMaxRestart + 1;
-  if (threadIdx.x == 0) {
+  // (3) serial part on LDS
+  if (tid == 0) {
     double ss = 0.0;
     for (int i = 0; i < j; ++i) ss += s[i] * s[i];
     const double nu2 = alpha - ss;
-    int done = 0;
+    int done = 0, k = 0;
     double nu = 0.0;
     if (j == 0) {
       nu = sqrt(fmax(alpha, 0.0));
       gs->beta = nu;
-      gs->g[0] = nu;
+      sG[0] = nu;
       gs->est = nu;
       if (!(nu > 0.0)) {  // zero right-hand side (or NaN)
         done = 1;
-        gs->k = 0;
         if (nu != nu) gs->nonfinite = 1;
       }
     } else {
       double col2 = nu2 > 0.0 ? nu2 : 0.0;
       for (int i = 0; i < j; ++i) {
-        const double h = gs->hprev[i] + s[i];
+        const double h = sHp[i] + s[i];
         col2 += h * h;
       }
       nu = (nu2 > 1e-28 * col2) ? sqrt(nu2) : 0.0;
       if (nu == 0.0) gs->breakdown = 1;
       const int c = j - 1;
-      double h[kMaxRestart + 1];
+      double* hc = sH + c * kLd;
+      double* rc = sR + c * kLd;
       for (int i = 0; i < j; ++i) {
-        h[i] = gs->hprev[i] + s[i];
-        gs->Hraw[c * ld + i] = h[i];
+        hc[i] = sHp[i] + s[i];
+        rc[i] = hc[i];
       }
-      h[j] = nu;
-      gs->Hraw[c * ld + j] = nu;
+      hc[j] = nu;
+      rc[j] = nu;
       for (int i = 0; i < c; ++i) {
-        const double a = gs->cs[i] * h[i] + gs->sn[i] * h[i + 1];
-        h[i + 1] = -gs->sn[i] * h[i] + gs->cs[i] * h[i + 1];
-        h[i] = a;
+        const double a = sCs[i] * rc[i] + sSn[i] * rc[i + 1];
+        rc[i + 1] = -sSn[i] * rc[i] + sCs[i] * rc[i + 1];
+        rc[i] = a;
       }
-      const double den = sqrt(h[c] * h[c] + h[j] * h[j]);
-      const double cs = den > 0.0 ? h[c] / den : 1.0;
-      const double sn = den > 0.0 ? h[j] / den : 0.0;
-      gs->cs[c] = cs;
-      gs->sn[c] = sn;
-      h[c] = den;
-      h[j] = 0.0;
-      for (int i = 0; i <= j; ++i) gs->Rm[c * ld + i] = h[i];
-      gs->g[j] = -sn * gs->g[c];
-      gs->g[c] = cs * gs->g[c];
-      gs->est = fabs(gs->g[j]);
-      if (!(gs->est == gs->est) || !(den == den)) gs->nonfinite = 1;
-      if (gs->est <= gs->tol || nu == 0.0 || final_step || gs->nonfinite) {
+      const double den = sqrt(rc[c] * rc[c] + rc[j] * rc[j]);
+      const double cs = den > 0.0 ? rc[c] / den : 1.0;
+      const double sn = den > 0.0 ? rc[j] / den : 0.0;
+      sCs[c] = cs;
+      sSn[c] = sn;
+      rc[c] = den;
+      rc[j] = 0.0;
+      sG[j] = -sn * sG[c];
+      sG[c] = cs * sG[c];
+      const double est = fabs(sG[j]);
+      gs->est = est;
+      if (!(est == est) || !(den == den)) gs->nonfinite = 1;
+      if (est <= gs->tol || nu == 0.0 || final_step || gs->nonfinite) {
         done = 1;
-        gs->k = j;
+        k = j;
         // back substitution R y = g
         for (int i = j - 1; i >= 0; --i) {
-          double acc = gs->g[i];
-          for (int l = i + 1; l < j; ++l) acc -= gs->Rm[l * ld + i] * gs->y[l];
-          gs->y[i] = acc / gs->Rm[i * ld + i];
+          double acc = sG[i];
+          for (int l = i + 1; l < j; ++l) acc -= sR[l * kLd + i] * sY[l];
+          sY[i] = acc / sR[i * kLd + i];
         }
       }
     }
     sh_nu = nu;
     sh_done = done;
-    if (done) gs->done = 1;
+    sh_k = k;
   }
   __syncthreads();
-  if (sh_done) return;
+  // (4) write back: new column, rotation, g, y
+  if (j > 0) {
+    const int c = j - 1;
+    for (int t2 = tid; t2 <= j; t2 += kScalarThreads) {
+      gs->Hraw[c * kLd + t2] = sH[c * kLd + t2];
+      gs->Rm[c * kLd + t2] = sR[c * kLd + t2];
+    }
+    if (tid == 0) {
+      gs->cs[c] = sCs[c];
+      gs->sn[c] = sSn[c];
+    }
+  }
+  for (int t2 = tid; t2 <= j; t2 += kScalarThreads) gs->g[t2] = sG[t2];
+  if (sh_done) {
+    for (int t2 = tid; t2 < sh_k; t2 += kScalarThreads) gs->y[t2] = sY[t2];
+    __syncthreads();
+    if (tid == 0) {
+      gs->k = sh_k;
+      gs->done = 1;
+    }
+    return;
+  }
   const double nu = sh_nu;
-  // (H s)[r] for r = 0..j with the unrotated Hessenberg (columns 0..j-1)
-  for (int r = threadIdx.x; r <= j; r += kScalarThreads) {
+  // (5) (H s)[r], r = 0..j, with the unrotated Hessenberg (columns 0..j-1)
+  for (int r = tid; r <= j; r += kScalarThreads) {
     double acc = 0.0;
-    for (int i = 0; i < j; ++i) acc += gs->Hraw[i * ld + r] * s[i];
-    Hs[r] = acc;
+    for (int i = 0; i < j; ++i) acc += sH[i * kLd + r] * s[i];
+    sHs[r] = acc;
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    double st = 0.0;
-    for (int i = 0; i < j; ++i) st += s[i] * t[i];
-    const double qp = (gamma - st) / nu;        // q_j . p
-    const double cc = qp / nu;
+  double st = 0.0;
+  for (int i = 0; i < j; ++i) st += s[i] * t[i];
+  const double qp = (gamma - st) / nu;  // q_j . p
+  const double cc = qp / nu;
+  for (int i = tid; i < j; i += kScalarThreads) {
+    gs->coef_s[i] = s[i];
+    gs->coef_t[i] = t[i] - cc * s[i];
+    gs->hprev[i] = (t[i] - sHs[i]) / nu;
+  }
+  if (tid == 0) {
+    gs->hprev[j] = (qp - sHs[j]) / nu;
     gs->cc = cc;
     gs->inv_nu = 1.0 / nu;
-    for (int i = 0; i < j; ++i) {
-      gs->coef_s[i] = s[i];
-      gs->coef_t[i] = t[i] - cc * s[i];
-      gs->hprev[i] = (t[i] - Hs[i]) / nu;
-    }
-    gs->hprev[j] = (qp - Hs[j]) / nu;
   }
 }
 
