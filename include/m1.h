@@ -97,7 +97,8 @@ typedef enum { M1_PC_BLOCK_JACOBI = 0, M1_PC_NONE = 1, M1_PC_LEARNED = 2 } m1_pc
 
 typedef struct {
   int32_t ndim;            /* 2 or 3 */
-  int32_t reserved0;
+  int32_t newton_flags;    /* bit 0: backtracking line search on ||R|| (halving, up to 8 trials;
+                              never in fixed-iteration mode) */
   int64_t n[3];            /* nx, ny, nz (nz ignored in 2D); each >= 1 */
   double dx;               /* cell size (> 0) */
   double c;                /* speed of light (> 0) */

@@ -15,6 +15,10 @@ from __future__ import annotations
 import ctypes
 import os
 
+# torch is imported first so that libm1.so binds to the HIP runtime torch has
+# loaded: device pointers and streams from torch are only valid in that runtime.
+import torch as _torch_module  # noqa: F401
+
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "lib", "libm1.so")
 
@@ -40,7 +44,7 @@ PC = {"bj": 0, "none": 1, "learned": 2}
 
 class M1Config(ctypes.Structure):
     _fields_ = [
-        ("ndim", ctypes.c_int32), ("reserved0", ctypes.c_int32), ("n", ctypes.c_int64 * 3),
+        ("ndim", ctypes.c_int32), ("newton_flags", ctypes.c_int32), ("n", ctypes.c_int64 * 3),
         ("dx", ctypes.c_double), ("c", ctypes.c_double), ("a_r", ctypes.c_double),
         ("source", ctypes.c_int32), ("flux_source", ctypes.c_int32), ("closure", ctypes.c_int32),
         ("ap_correction", ctypes.c_int32), ("lambda_floor", ctypes.c_double), ("bc", ctypes.c_int32 * 6),
@@ -166,10 +170,11 @@ def kernel_classes():
 # high-level wrapper
 # ---------------------------------------------------------------------------
 def make_config(p, *, precision="fp64", pc="bj", restart=30, max_iters=20000, newton_max=20, fixed_iters=0,
-                rtol=1e-10, newton_rtol=None, inner_rtol=1e-6, basis_fp32=False):
+                rtol=1e-10, newton_rtol=None, inner_rtol=1e-6, basis_fp32=False, line_search=True):
     """m1_config from a problem description (the dict layout of ``workloads``)."""
     cfg = M1Config()
     cfg.ndim = p["ndim"]
+    cfg.newton_flags = 1 if line_search else 0
     for d in range(3):
         cfg.n[d] = p["n"][d] if d < p["ndim"] else 1
     cfg.dx, cfg.c, cfg.a_r = p["dx"], p["c"], p["a_r"]

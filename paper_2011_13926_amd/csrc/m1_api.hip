@@ -22,7 +22,7 @@ namespace {
 
 const char* kClassNames[KC_COUNT] = {"setup",   "setup_bj", "residual",   "apply",         "block_jacobi",
                                      "arnoldi_dot", "arnoldi_scalar", "arnoldi_update", "x_update",
-                                     "true_residual", "newton_update", "norm", "convert", "learned_pc"};
+                                     "true_residual", "newton_update", "norm", "convert", "learned_pc", "apply_bj_fused"};
 
 struct Profiler {
   bool on = false;
@@ -56,6 +56,7 @@ struct m1_ctx {
   // states
   double* Uk = nullptr;
   double* Un = nullptr;
+  double* Uprev = nullptr;   // Newton line search: the iterate before the step
   double* fn = nullptr;
   // coefficients
   double* coef64 = nullptr;
@@ -259,7 +260,7 @@ void free_all(m1_ctx* c) {
     if (c->plane[f]) hipFree(c->plane[f]);
     if (c->mask[f]) hipFree(c->mask[f]);
   }
-  void* bufs[] = {c->Uk, c->Un, c->fn, c->coef64, c->coef32, c->V, c->b, c->x, c->u[0], c->u[1],
+  void* bufs[] = {c->Uk, c->Un, c->Uprev, c->fn, c->coef64, c->coef32, c->V, c->b, c->x, c->u[0], c->u[1],
                   c->p, c->z, c->part, c->gs, c->dscal, c->dcount, c->Z, c->zt};
   for (void* b : bufs)
     if (b) hipFree(b);
@@ -389,6 +390,7 @@ m1_status gmres(m1_ctx* c, double bnorm, SolveResult& res, const Coefs<R>& cfi) 
   const double tol_rel = (mixed(c) && !fixed) ? c->cfg.inner_rtol : 0.0;
   const bool learned = c->use_learned && c->net;
   const int use_pc = !learned && c->cfg.pc != M1_PC_NONE;
+  const bool fused = use_pc && fused_apply_available(c->nd);
   R* Z = (R*)c->Z;
   R* zt = (R*)c->zt;
   HIPCHK(c, hipMemsetAsync(c->x, 0, sizeof(double) * n, c->stream));
@@ -419,6 +421,12 @@ m1_status gmres(m1_ctx* c, double bnorm, SolveResult& res, const Coefs<R>& cfi) 
                                    &c->gs->done);
         }, j, 0);
         timed(c, KC_APPLY, bytes_apply(c, sizeof(R), sizeof(R), sizeof(TV), false), [&] { launch_apply<R, R, TV>(c->nd, c->cpl, 0, c->g, c->sc, cfi, bd, zt, nullptr, p, c->stream, &c->gs->done); }, j, 0);
+      } else if (fused) {
+        // fused: p = A M^{-1} u_j (block-Jacobi applied while staging the halo tile)
+        timed(c, KC_APPLY_PC, bytes_apply(c, sizeof(R), sizeof(TV), sizeof(TV), false) +
+                                  (double)c->nu * c->nu * sizeof(R) * cells(c), [&] {
+          launch_apply_pre<R, TV, TV>(c->nd, c->cpl, c->g, c->sc, cfi, bd, uj, p, c->stream, &c->gs->done);
+        }, j, 0);
       } else if (use_pc) {
         timed(c, KC_BJ, bytes_bj(c, sizeof(R), sizeof(TV), sizeof(R)), [&] { launch_bj<R, TV, R>(c->nd, c->cpl, c->g, cfi, uj, z, c->stream, &c->gs->done); }, j, 0);
         timed(c, KC_APPLY, bytes_apply(c, sizeof(R), sizeof(R), sizeof(TV), false), [&] { launch_apply<R, R, TV>(c->nd, c->cpl, 0, c->g, c->sc, cfi, bd, z, nullptr, p, c->stream, &c->gs->done); }, j, 0);
@@ -584,6 +592,7 @@ m1_status m1_setup(const m1_config* cfg, const m1_fields* fields, const m1_state
   }
   if ((st = dalloc(c, &c->Uk, c->n)) != M1_OK) return fail(st);
   if ((st = dalloc(c, &c->Un, c->n)) != M1_OK) return fail(st);
+  if ((cfg->newton_flags & 1) && (st = dalloc(c, &c->Uprev, c->n)) != M1_OK) return fail(st);
   if ((st = dalloc(c, &c->fn, N)) != M1_OK) return fail(st);
   if ((st = dalloc(c, &c->b, c->n)) != M1_OK) return fail(st);
   if ((st = dalloc(c, &c->x, c->n)) != M1_OK) return fail(st);
@@ -727,15 +736,26 @@ m1_status m1_implicit_step(m1_ctx* c, m1_state* U, double dt, m1_stats* stats) {
   int it = 0, kry = 0, rst = 0, fell_back = 0;
   bool converged = false, nonfinite = false;
   double lin_rel = 0.0;
-  while (true) {
-    if ((st = linearize_internal(c)) != M1_OK) return st;
+  // evaluate the scheme at the current iterate: linearise, b = -R(U^k), ||R||
+  auto evaluate = [&](double& rn_out) -> m1_status {
+    m1_status s2;
+    if ((s2 = linearize_internal(c)) != M1_OK) return s2;
     timed(c, KC_RESIDUAL, bytes_residual(c), [&] { launch_residual(c->nd, c->cpl, c->g, c->sc, c->cf64, bdry(c), c->Uk, c->Un, c->b, c->stream); });
     norm2_into(c, c->b, 0);
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipMemcpyAsync(c->hscal, c->dscal, sizeof(double), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     prof_collect(c);
-    const double rn = std::sqrt(std::max(c->hscal[0], 0.0));
+    rn_out = std::sqrt(std::max(c->hscal[0], 0.0));
+    return M1_OK;
+  };
+  const bool line_search = (c->cfg.newton_flags & 1) && !fixed && c->Uprev;
+  bool evaluated = false;
+  double rn_next = 0.0;
+  while (true) {
+    double rn = rn_next;
+    if (!evaluated && (st = evaluate(rn)) != M1_OK) return st;
+    evaluated = false;
     if (!std::isfinite(rn)) { nonfinite = true; break; }
     if (r0 < 0) r0 = rn;
     rel = r0 > 0 ? rn / r0 : 0.0;
@@ -756,10 +776,31 @@ m1_status m1_implicit_step(m1_ctx* c, m1_state* U, double dt, m1_stats* stats) {
       std::fprintf(stderr, "[m1] newton %d |R|=%.3e rel=%.3e gmres_iters=%d restarts=%d lin_rel=%.2e%s\n", it, rn, rel,
                    sr.iters, sr.restarts, sr.rel, sr.converged ? "" : " (not converged)");
     if (sr.nonfinite) { nonfinite = true; break; }
-    timed(c, KC_NEWTON_UPDATE, 24.0 * c->n, [&] {
-      k_zero_u64<<<1, 64, 0, c->stream>>>(c->dcount);
-      launch_newton_update(c->nd, c->g, c->Uk, c->x, c->nu, c->cfg.c, c->dcount, c->stream);
-    });
+    if (!line_search) {
+      timed(c, KC_NEWTON_UPDATE, 24.0 * c->n, [&] {
+        k_zero_u64<<<1, 64, 0, c->stream>>>(c->dcount);
+        launch_newton_update(c->nd, c->g, c->Uk, c->Uk, c->x, 1.0, c->nu, c->cfg.c, c->dcount, c->stream);
+      });
+    } else {
+      // backtracking: U^{k+1} = U^k + lam delta, lam = 1, 1/2, ... while ||R|| does not drop
+      HIPCHK(c, hipMemcpyAsync(c->Uprev, c->Uk, sizeof(double) * c->n, hipMemcpyDeviceToDevice, c->stream));
+      double lam = 1.0;
+      for (int trial = 0;; ++trial) {
+        timed(c, KC_NEWTON_UPDATE, 24.0 * c->n, [&] {
+          launch_newton_update(c->nd, c->g, c->Uk, c->Uprev, c->x, lam, c->nu, c->cfg.c, c->dcount, c->stream);
+        });
+        double rt = 0.0;
+        if ((st = evaluate(rt)) != M1_OK) return st;
+        const bool ok = std::isfinite(rt) && rt <= (1.0 - 1e-4 * lam) * rn;
+        if (ok || trial == 7) {
+          if (verbose() && lam < 1.0) std::fprintf(stderr, "[m1]   line search: step %.4g, |R| %.3e -> %.3e\n", lam, rn, rt);
+          rn_next = rt;
+          evaluated = true;
+          break;
+        }
+        lam *= 0.5;
+      }
+    }
     ++it;
   }
   unsigned long long nf = 0;

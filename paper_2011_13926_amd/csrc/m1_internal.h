@@ -50,7 +50,7 @@ struct GmresState {
 
 enum KernelClass {
   KC_SETUP = 0, KC_SETUP_BJ, KC_RESIDUAL, KC_APPLY, KC_BJ, KC_DOT, KC_SCALAR, KC_UPDATE, KC_XUPDATE,
-  KC_TRUE_RESID, KC_NEWTON_UPDATE, KC_NORM, KC_CONVERT, KC_NN, KC_COUNT
+  KC_TRUE_RESID, KC_NEWTON_UPDATE, KC_NORM, KC_CONVERT, KC_NN, KC_APPLY_PC, KC_COUNT
 };
 
 // ---- launchers (defined in m1_kernels.hip / m1_krylov.hip) ----
@@ -63,6 +63,10 @@ void launch_setup_bj(int nd, bool cpl, const Geom& g, const Scheme& sc, const Co
 template <typename R, typename VI, typename VO>
 void launch_apply(int nd, bool cpl, int mode, const Geom& g, const Scheme& sc, const Coefs<R>& cf, const Bdry& bd,
                   const VI* x, const double* b, VO* y, hipStream_t s, const int* skip = nullptr);
+bool fused_apply_available(int nd);
+template <typename R, typename VI, typename VO>
+bool launch_apply_pre(int nd, bool cpl, const Geom& g, const Scheme& sc, const Coefs<R>& cf, const Bdry& bd,
+                      const VI* u, VO* y, hipStream_t s, const int* skip);
 void launch_residual(int nd, bool cpl, const Geom& g, const Scheme& sc, const Coefs<double>& cf, const Bdry& bd,
                      const double* Uk, const double* Un, double* out_negR, hipStream_t s);
 template <typename R, typename VI, typename VO>
@@ -86,8 +90,9 @@ void launch_xupdate(int nd, bool cpl, const Geom& g, const Coefs<R>& cf, const T
                     const GmresState* gs, double* x, int use_pc, hipStream_t s);
 void launch_reduce(const double* partials, int nv, int nb, double* out, hipStream_t s);
 void launch_cycle_init(GmresState* gs, const double* beta2, double tol_abs, double tol_rel, hipStream_t s);
-void launch_newton_update(int nd, const Geom& g, double* Uk, const double* dx, int nu, double c,
-                          unsigned long long* fcount, hipStream_t s);
+// Uk = U0 + lam * dx (U0 may be Uk), counting cells with |F| > c E
+void launch_newton_update(int nd, const Geom& g, double* Uk, const double* U0, const double* dx, double lam, int nu,
+                          double c, unsigned long long* fcount, hipStream_t s);
 void launch_count_f(int nd, const Geom& g, const double* U, double c, unsigned long long* fcount, hipStream_t s);
 void launch_scale(double* v, double a, int64_t n, hipStream_t s);
 template <typename TS, typename TD>

@@ -543,7 +543,9 @@ __global__ __launch_bounds__(256) void k_stencil(Geom g, Scheme sc, Coefs<R> cf,
 // ----------------------------------------------------------------------------
 constexpr int LX = 64, LY = 8, LHX = LX + 2, LHY = LY + 2;
 
-template <bool CPL, int MODE, typename R, typename VI, typename VO>
+// PRE = true: the input is u and the operator is applied to z = M^{-1} u, the
+// block-Jacobi solve done per staged cell (fused right preconditioning).
+template <bool CPL, int MODE, bool PRE, typename R, typename VI, typename VO>
 __global__ __launch_bounds__(256) void k_apply2d_lds(Geom g, Scheme sc, Coefs<R> cf, Bdry bd, const VI* __restrict__ x,
                                                      const double* __restrict__ b, VO* __restrict__ y,
                                                      const int* __restrict__ skip) {
@@ -574,8 +576,21 @@ __global__ __launch_bounds__(256) void k_apply2d_lds(Geom g, Scheme sc, Coefs<R>
         else { face = gj < 0 ? 2 : 3; gj = gj < 0 ? 0 : ny - 1; }
       }
       const int64_t cell = (int64_t)gj * nx + gi;
+      if (PRE) {
+        R uv[NU];
 #pragma unroll
-      for (int c = 0; c < NR; ++c) xv[c] = (R)x[c * N + cell];
+        for (int c = 0; c < NU; ++c) uv[c] = (R)x[c * N + cell];
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+          R acc = (R)0;
+#pragma unroll
+          for (int c = 0; c < NU; ++c) acc += cf.bjinv[(r * NU + c) * N + cell] * uv[c];
+          xv[r] = acc;
+        }
+      } else {
+#pragma unroll
+        for (int c = 0; c < NR; ++c) xv[c] = (R)x[c * N + cell];
+      }
       sv = cf.sigma[cell];
       if (face < 0) {
 #pragma unroll
@@ -618,7 +633,17 @@ __global__ __launch_bounds__(256) void k_apply2d_lds(Geom g, Scheme sc, Coefs<R>
     R xs[NU], ys[NU];
 #pragma unroll
     for (int c = 0; c < NR; ++c) { xs[c] = sx[c][lj][li]; ys[c] = xs[c]; }
-    if (CPL) { xs[NU - 1] = (R)x[(NU - 1) * N + cell]; ys[NU - 1] = (R)0; }
+    if (CPL) {
+      if (PRE) {
+        R acc = (R)0;
+#pragma unroll
+        for (int c = 0; c < NU; ++c) acc += cf.bjinv[((NU - 1) * NU + c) * N + cell] * (R)x[c * N + cell];
+        xs[NU - 1] = acc;
+      } else {
+        xs[NU - 1] = (R)x[(NU - 1) * N + cell];
+      }
+      ys[NU - 1] = (R)0;
+    }
     const R sig = ss[lj][li];
 #pragma unroll
     for (int d = 0; d < 2; ++d) {
@@ -707,7 +732,7 @@ void launch_apply(int nd, bool cpl, int mode, const Geom& g, const Scheme& sc, c
                   const VI* x, const double* b, VO* y, hipStream_t s, const int* skip) {
   if (nd == 2 && use_lds_2d()) {
     dim3 grd2((g.n[0] + LX - 1) / LX, (g.n[1] + LY - 1) / LY);
-#define M1_LDS(CPL_, MODE_) k_apply2d_lds<CPL_, MODE_, R, VI, VO><<<grd2, 256, 0, s>>>(g, sc, cf, bd, x, b, y, skip)
+#define M1_LDS(CPL_, MODE_) k_apply2d_lds<CPL_, MODE_, false, R, VI, VO><<<grd2, 256, 0, s>>>(g, sc, cf, bd, x, b, y, skip)
     if (cpl) { if (mode == 0) M1_LDS(true, 0); else M1_LDS(true, 1); }
     else { if (mode == 0) M1_LDS(false, 0); else M1_LDS(false, 1); }
 #undef M1_LDS
@@ -780,6 +805,26 @@ void launch_convert(const double* src, float* dst, int64_t n, hipStream_t s) {
   const int64_t grd = std::min<int64_t>((n + 255) / 256, 4096);
   k_convert<<<grd, 256, 0, s>>>(src, dst, n);
 }
+
+bool fused_apply_available(int nd) { return nd == 2 && use_lds_2d(); }
+
+// y = A M^{-1} u in one kernel (2D, LDS path); returns false when not available
+template <typename R, typename VI, typename VO>
+bool launch_apply_pre(int nd, bool cpl, const Geom& g, const Scheme& sc, const Coefs<R>& cf, const Bdry& bd,
+                      const VI* u, VO* y, hipStream_t s, const int* skip) {
+  if (nd != 2 || !use_lds_2d()) return false;
+  dim3 grd2((g.n[0] + LX - 1) / LX, (g.n[1] + LY - 1) / LY);
+  if (cpl) k_apply2d_lds<true, 0, true, R, VI, VO><<<grd2, 256, 0, s>>>(g, sc, cf, bd, u, nullptr, y, skip);
+  else k_apply2d_lds<false, 0, true, R, VI, VO><<<grd2, 256, 0, s>>>(g, sc, cf, bd, u, nullptr, y, skip);
+  return true;
+}
+
+template bool launch_apply_pre<double, double, double>(int, bool, const Geom&, const Scheme&, const Coefs<double>&,
+                                                       const Bdry&, const double*, double*, hipStream_t, const int*);
+template bool launch_apply_pre<float, double, double>(int, bool, const Geom&, const Scheme&, const Coefs<float>&,
+                                                      const Bdry&, const double*, double*, hipStream_t, const int*);
+template bool launch_apply_pre<float, float, float>(int, bool, const Geom&, const Scheme&, const Coefs<float>&,
+                                                    const Bdry&, const float*, float*, hipStream_t, const int*);
 
 // explicit instantiations
 template void launch_apply<double, double, double>(int, bool, int, const Geom&, const Scheme&, const Coefs<double>&,

@@ -1,0 +1,62 @@
+"""What the trained network gains over block-Jacobi alone.
+
+Loads the committed weights (trained on the Voronoi 512^2 workload by
+paper_2011_13926_amd/train_nn.py on solver-generated residual/error pairs) and
+solves the first Newton system of held-out seeds to 1e-8 with flexible GMRES +
+learned preconditioner and with block-Jacobi GMRES.  Both must converge (the
+fallback keeps the learned solve safe); the iteration and time ratios are
+printed and recorded, and the learned solution must agree with the
+block-Jacobi one to the tolerance."""
+import os
+import sys
+import time
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
+WEIGHTS = os.path.join(os.path.dirname(HERE), "paper_2011_13926_amd", "weights", "unet_voronoi512.bin")
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.mark.skipif(not os.path.exists(WEIGHTS), reason="no trained weights committed")
+@pytest.mark.parametrize("seed", [1000, 1001])
+def test_learned_preconditioner_gain_on_heldout_seed(seed):
+    import torch
+    import paper_2011_13926_amd as P
+    p = W.voronoi_opacity(seed=seed)
+    U0 = np.stack([p["E"], p["F"][0], p["F"][1]])
+    net = P.Net(9, 3, (32, 48, 64, 64), Hmax=512, Wmax=512)
+    net.load(WEIGHTS)
+    s_bj = P.Solver(p, U_lin=U0, U_n=U0, rtol=1e-8, max_iters=20000)
+    s_nn = P.Solver(p, U_lin=U0, U_n=U0, rtol=1e-8, max_iters=20000, pc="learned")
+    try:
+        s_nn.set_network(net)
+        b = -s_bj.residual()
+        out = {}
+        for name, s in (("bj", s_bj), ("learned", s_nn)):
+            s.solve_linear(b, raise_on_fail=False)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            x, st, stats = s.solve_linear(b, raise_on_fail=False)
+            torch.cuda.synchronize()
+            out[name] = (x, st, stats, time.perf_counter() - t0)
+        xb, stb, sb, tb = out["bj"]
+        xl, stl, sl, tl = out["learned"]
+        _say(f"seed {seed}: block-Jacobi {sb['krylov_iters']} it {tb*1e3:.1f} ms | learned {sl['krylov_iters']} it "
+             f"{tl*1e3:.1f} ms fell_back={sl['fell_back']} | iteration ratio {sb['krylov_iters']/max(sl['krylov_iters'],1):.2f} "
+             f"time ratio {tb/tl:.2f}")
+        assert stb == P.M1_OK and stl == P.M1_OK
+        err = float(torch.linalg.vector_norm(xl - xb) / torch.linalg.vector_norm(xb))
+        assert err <= 1e-6
+    finally:
+        s_bj.close()
+        s_nn.close()
+        net.close()

@@ -220,8 +220,9 @@ def test_mixed_precision_step_matches_fp64_oracle(n, bc, src, fs, basis32):
     p = _problem(n, bc, src, fs, "newton", seed=13, dt=2.0, fmax=0.6)
     sch = O.Scheme.from_problem(p)
     Un = O.state_from_problem(p, "n")
-    ref = O.implicit_step(sch, p["sigma"], p.get("rho_cv"), Un, p["dt"], rtol=1e-12, newton_rtol=1e-12)
-    s = P.Solver(p, precision="mixed", basis_fp32=basis32, rtol=1e-10, newton_rtol=1e-10)
+    ref = O.implicit_step(sch, p["sigma"], p.get("rho_cv"), Un, p["dt"], rtol=1e-12, newton_rtol=1e-12,
+                          newton_max=80)
+    s = P.Solver(p, precision="mixed", basis_fp32=basis32, rtol=1e-10, newton_rtol=1e-10, newton_max=80)
     try:
         U = s.to_device(Un)
         st, stats = s.implicit_step(U)
