@@ -121,11 +121,19 @@ __global__ __launch_bounds__(kScalarThreads) void k_scalar(int j, int final_step
   // (1) reduce the per-block partials: Q threads per value, fixed order
   const int Q = max(1, kScalarThreads / nv);
   {
+    // 8 independent partial sums per thread so the loads overlap (fixed order)
     const int v = tid / Q, q = tid % Q;
-    double acc = 0.0;
-    if (v < nv)
-      for (int b = q; b < nb; b += Q) acc += part[(int64_t)v * nb + b];
-    psum[tid] = acc;
+    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (v < nv) {
+      const double* pv = part + (int64_t)v * nb;
+      int b = q;
+      for (; b + 7 * Q < nb; b += 8 * Q) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc[u] += pv[b + u * Q];
+      }
+      for (int u = 0; b < nb; b += Q, ++u) acc[u] += pv[b];
+    }
+    psum[tid] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
   }
   // (2) stage the small GMRES state in LDS
   for (int t = tid; t < j * kLd; t += kScalarThreads) {
