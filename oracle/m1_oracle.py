@@ -473,11 +473,17 @@ def diagonal_blocks(lin):
 
 
 class BlockJacobi:
-    """z = M^{-1} r with M the block diagonal of A (one dense solve per cell)."""
+    """z = M^{-1} r with M the block diagonal of A (one dense solve per cell).
 
-    def __init__(self, lin):
+    shift (optional, shape (n_u, N)) is added to the diagonal of every block:
+    the block diagonal of A + diag(shift), used by pseudo-transient continuation."""
+
+    def __init__(self, lin, shift=None):
         self.nu = lin.sch.nu
         self.blocks = diagonal_blocks(lin)
+        if shift is not None:
+            idx = np.arange(self.nu)
+            self.blocks[:, idx, idx] += np.asarray(shift, float).reshape(self.nu, -1).T
         self.inv = np.linalg.inv(self.blocks)
 
     def __call__(self, r):
@@ -575,28 +581,60 @@ class StepResult:
     history: list
 
 
+def mass_diagonal(sch, rho_cv):
+    """Coefficient of U^{n+1} in each row of the backward-Euler residual: 1 on
+    the E and F rows, rho c_v on the T row; shape (n_u, N)."""
+    N = int(np.prod(sch.shape))
+    m = np.ones((sch.nu, N))
+    if sch.source == "coupled_t":
+        m[sch.nrad] = np.asarray(rho_cv, float).reshape(-1)
+    return m
+
+
 def implicit_step(sch, sigma, rho_cv, Un, dt, *, restart=30, rtol=1e-10, max_iters=20000,
-                  newton_max=20, newton_rtol=None, fixed_iters=0, pc="bj"):
+                  newton_max=20, newton_rtol=None, fixed_iters=0, pc="bj",
+                  psi0=0.0, ptc_rtol=0.0, line_search=False, clip=0.0):
     """Advance Un by one backward-Euler step (Sect. 3.1, Sect. 3.3.1).
 
     Newton loop: linearise at U^k, b = -R(U^k); stop when
     ||R(U^k)|| <= newton_rtol ||R(U^0)||; else solve A^k delta = b by GMRES and
     set U^{k+1} = U^k + delta.  With fixed_iters > 0 exactly newton_max linear
     solves of exactly fixed_iters GMRES iterations are made (no early exit).
+
+    Three optional safeguards change the path to the root, never the root
+    itself (the residual R is untouched).  They are solver additions; the
+    paper's Newton iteration has none of them:
+
+    * psi0 > 0: pseudo-transient continuation (Kelley and Keyes, SIAM J. Numer.
+      Anal. 35, 1998).  Iteration k solves (A^k + psi_k M) delta = -R(U^k),
+      M = mass_diagonal (the coefficient of U^{n+1} in each row); block-Jacobi
+      takes the shifted diagonal blocks.  psi follows switched evolution
+      relaxation (Mulder and van Leer, 1985): psi_{k+1} = psi_k ||R_{k+1}||/||R_k||
+      when the residual fell, 2 psi_k when it did not, and 0 once below
+      1e-6 psi0.  While psi > 0 the linear tolerance is ptc_rtol (if > 0).
+    * clip in (0, 1): before the update, dE is raised to at least -clip E per
+      cell (the energy of a cell drops by at most that fraction in one update).
+    * line_search (not with fixed_iters): U^{k+1} = U^k + lam delta with the
+      first lam in 1, 1/2, ..., 1/128 whose residual satisfies
+      ||R|| <= (1 - 1e-4 lam) max(last 5 accepted ||R||) (non-monotone
+      Armijo test, Grippo, Lampariello and Lucidi 1986); if none does, the trial
+      with the smallest ||R|| is taken (the earliest on ties).
     """
     if newton_rtol is None:
         newton_rtol = rtol
     U = np.array(Un, dtype=float, copy=True)
+    mass = mass_diagonal(sch, rho_cv)
+    psi = float(psi0)
     r0 = None
     kry = rst = 0
     hist = []
     rel = 1.0
     converged = False
     it = 0
+    lin = linearize(sch, sigma, rho_cv, U, Un, dt)
+    R = residual(lin)
+    rn = float(np.linalg.norm(R))
     while True:
-        lin = linearize(sch, sigma, rho_cv, U, Un, dt)
-        R = residual(lin)
-        rn = float(np.linalg.norm(R))
         if r0 is None:
             r0 = rn
         rel = rn / r0 if r0 > 0 else 0.0
@@ -610,12 +648,48 @@ def implicit_step(sch, sigma, rho_cv, Un, dt, *, restart=30, rtol=1e-10, max_ite
             break
         elif it >= newton_max:
             break
-        M = BlockJacobi(lin) if pc == "bj" else (lambda v: v)
-        res = gmres(lambda v: apply_operator(lin, v), M, -R.reshape(-1), restart=restart,
-                    rtol=rtol, max_iters=max_iters, fixed_iters=fixed_iters)
+        if not np.isfinite(rn):
+            break
+        shift = psi * mass if psi > 0 else None
+        M = BlockJacobi(lin, shift) if pc == "bj" else (lambda v: v)
+        if shift is None:
+            op = lambda v: apply_operator(lin, v)
+        else:
+            op = lambda v, sh=shift.reshape(-1): apply_operator(lin, v) + sh * v
+        lin_tol = ptc_rtol if (psi > 0 and ptc_rtol > 0) else rtol
+        res = gmres(op, M, -R.reshape(-1), restart=restart, rtol=lin_tol, max_iters=max_iters,
+                    fixed_iters=fixed_iters)
         kry += res.iters
         rst += res.restarts
-        U = U + res.x.reshape(U.shape)
+        delta = res.x.reshape(U.shape)
+        if clip > 0:
+            delta = delta.copy()
+            delta[0] = np.maximum(delta[0], -clip * U[0])
+        if line_search and fixed_iters == 0:
+            ref = max(hist[-5:])
+            lam, best = 1.0, None
+            for _ in range(8):
+                lin_t = linearize(sch, sigma, rho_cv, U + lam * delta, Un, dt)
+                R_t = residual(lin_t)
+                r_t = float(np.linalg.norm(R_t))
+                if best is None or (np.isfinite(r_t) and not r_t >= best[0]):
+                    best = (r_t, lam, lin_t, R_t)
+                if np.isfinite(r_t) and r_t <= (1.0 - 1e-4 * lam) * ref:
+                    best = (r_t, lam, lin_t, R_t)
+                    break
+                lam *= 0.5
+            r_new, lam, lin, R = best
+            U = U + lam * delta
+        else:
+            U = U + delta
+            lin = linearize(sch, sigma, rho_cv, U, Un, dt)
+            R = residual(lin)
+            r_new = float(np.linalg.norm(R))
+        if psi > 0:
+            psi = psi * r_new / rn if r_new < rn else 2.0 * psi
+            if psi < 1e-6 * psi0:
+                psi = 0.0
+        rn = r_new
         it += 1
     Fmag = np.sqrt(sum(U[1 + m] ** 2 for m in range(sch.ndim)))
     nf = int(np.count_nonzero(Fmag > F_GT_1_REL * sch.c * U[0]))

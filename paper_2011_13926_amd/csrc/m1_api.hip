@@ -50,6 +50,9 @@ struct m1_ctx {
   int device = 0;
   std::string err;
   bool linearized = false;
+  bool bj_ready = false;     // block-Jacobi inverse (and FP32 shadow) match the coefficients and sc.psi
+  double bj_psi = 0.0;       // shift the block-Jacobi inverse was built with
+  double lin_rtol = -1.0;    // >= 0: linear tolerance of the current Newton solve (else cfg.rtol)
   // boundary copies
   double* plane[6] = {};
   double* mask[6] = {};
@@ -208,6 +211,11 @@ m1_status validate_config(const m1_config* c, std::string& err) {
     err = "tolerances must be finite, >= 0 (inner_rtol < 1)";
     return M1_ERR_INVALID_ARG;
   }
+  if (!(finite(c->ptc_psi0) && c->ptc_psi0 >= 0) || !(finite(c->ptc_rtol) && c->ptc_rtol >= 0 && c->ptc_rtol < 1) ||
+      !(finite(c->positivity_clip) && c->positivity_clip >= 0 && c->positivity_clip < 1)) {
+    err = "ptc_psi0 must be finite and >= 0; ptc_rtol and positivity_clip in [0, 1)";
+    return M1_ERR_INVALID_ARG;
+  }
   return M1_OK;
 }
 
@@ -348,13 +356,32 @@ m1_status copy_state_out(m1_ctx* c, const double* src, m1_state* U) {
 }
 
 // Linearise at c->Uk with time-level state c->Un (|f^n| already in c->fn).
-m1_status linearize_internal(m1_ctx* c) {
+// block-Jacobi inverses of the current coefficients with the current shift
+// sc.psi, then the FP32 shadow of the whole slab (mixed precision)
+m1_status build_bj(m1_ctx* c) {
   const Bdry bd = bdry(c);
-  timed(c, KC_SETUP, bytes_setup(c), [&] { launch_setup(c->nd, c->cpl, c->g, c->sc, c->cf64, bd, c->Uk, c->Un, c->fn, c->stream); });
   timed(c, KC_SETUP_BJ, bytes_setup_bj(c), [&] { launch_setup_bj(c->nd, c->cpl, c->g, c->sc, c->cf64, bd, c->stream); });
   if (mixed(c)) timed(c, KC_CONVERT, 12.0 * c->coef_len, [&] { launch_convert(c->coef64, c->coef32, c->coef_len, c->stream); });
   HIPCHK(c, hipGetLastError());
+  c->bj_ready = true;
+  c->bj_psi = c->sc.psi;
+  return M1_OK;
+}
+
+m1_status ensure_bj(m1_ctx* c) {
+  if (c->bj_ready && c->bj_psi == c->sc.psi) return M1_OK;
+  return build_bj(c);
+}
+
+// closure and face coefficients at c->Uk (a1); with_bj also builds the
+// block-Jacobi inverses (else they are built on first use)
+m1_status linearize_internal(m1_ctx* c, bool with_bj = true) {
+  const Bdry bd = bdry(c);
+  timed(c, KC_SETUP, bytes_setup(c), [&] { launch_setup(c->nd, c->cpl, c->g, c->sc, c->cf64, bd, c->Uk, c->Un, c->fn, c->stream); });
+  HIPCHK(c, hipGetLastError());
   c->linearized = true;
+  c->bj_ready = false;
+  if (with_bj) return build_bj(c);
   return M1_OK;
 }
 
@@ -386,7 +413,7 @@ m1_status gmres(m1_ctx* c, double bnorm, SolveResult& res, const Coefs<R>& cfi) 
   R* z = (R*)c->z;
   const bool fixed = c->cfg.fixed_iters > 0;
   const int budget = fixed ? c->cfg.fixed_iters : c->cfg.max_iters;
-  const double rtol = c->cfg.rtol;
+  const double rtol = c->lin_rtol >= 0 ? c->lin_rtol : c->cfg.rtol;
   const double tol_rel = (mixed(c) && !fixed) ? c->cfg.inner_rtol : 0.0;
   const bool learned = c->use_learned && c->net;
   const int use_pc = !learned && c->cfg.pc != M1_PC_NONE;
@@ -571,6 +598,7 @@ m1_status m1_setup(const m1_config* cfg, const m1_fields* fields, const m1_state
   sc.ap = cfg->ap_correction != 0;
   sc.p1 = cfg->closure == M1_CLOSURE_P1;
   sc.newton = cfg->linearization == M1_LIN_NEWTON;
+  sc.psi = 0.0;
   set_dt(c, U_lin ? dt : 1.0);
   c->n = (int64_t)c->nu * g.N;
   c->nb = dot_blocks(c->n);
@@ -704,6 +732,8 @@ m1_status m1_precondition(m1_ctx* c, const double* r, double* z) {
     if (r != z) HIPCHK(c, hipMemcpyAsync(z, r, sizeof(double) * c->n, hipMemcpyDeviceToDevice, c->stream));
     return M1_OK;
   }
+  m1_status st;
+  if ((st = ensure_bj(c)) != M1_OK) return st;
   timed(c, KC_BJ, bytes_bj(c, 8, 8, 8), [&] { launch_bj<double, double, double>(c->nd, c->cpl, c->g, c->cf64, r, z, c->stream); });
   HIPCHK(c, hipGetLastError());
   return M1_OK;
@@ -736,10 +766,12 @@ m1_status m1_implicit_step(m1_ctx* c, m1_state* U, double dt, m1_stats* stats) {
   int it = 0, kry = 0, rst = 0, fell_back = 0;
   bool converged = false, nonfinite = false;
   double lin_rel = 0.0;
-  // evaluate the scheme at the current iterate: linearise, b = -R(U^k), ||R||
+  const double psi0 = c->cfg.ptc_psi0, clip = c->cfg.positivity_clip;
+  double psi = psi0;
+  // evaluate the scheme at the current iterate: coefficients, b = -R(U^k), ||R||
   auto evaluate = [&](double& rn_out) -> m1_status {
     m1_status s2;
-    if ((s2 = linearize_internal(c)) != M1_OK) return s2;
+    if ((s2 = linearize_internal(c, false)) != M1_OK) return s2;
     timed(c, KC_RESIDUAL, bytes_residual(c), [&] { launch_residual(c->nd, c->cpl, c->g, c->sc, c->cf64, bdry(c), c->Uk, c->Un, c->b, c->stream); });
     norm2_into(c, c->b, 0);
     HIPCHK(c, hipGetLastError());
@@ -749,16 +781,24 @@ m1_status m1_implicit_step(m1_ctx* c, m1_state* U, double dt, m1_stats* stats) {
     rn_out = std::sqrt(std::max(c->hscal[0], 0.0));
     return M1_OK;
   };
+  // U^k <- base + lam * delta (delta = c->x, energy step clipped at -clip E)
+  auto update = [&](const double* base, double lam) {
+    timed(c, KC_NEWTON_UPDATE, 24.0 * c->n, [&] {
+      launch_newton_update(c->nd, c->g, c->Uk, base, c->x, lam, clip, c->nu, c->cfg.c, c->dcount, c->stream);
+    });
+  };
+  auto finish = [&]() {
+    c->sc.psi = 0.0;
+    c->lin_rtol = -1.0;
+  };
   const bool line_search = (c->cfg.newton_flags & 1) && !fixed && c->Uprev;
-  bool evaluated = false;
-  double rn_next = 0.0;
+  std::vector<double> hist;
+  double rn = 0.0;
+  if ((st = evaluate(rn)) != M1_OK) { finish(); return st; }
   while (true) {
-    double rn = rn_next;
-    if (!evaluated && (st = evaluate(rn)) != M1_OK) return st;
-    evaluated = false;
-    if (!std::isfinite(rn)) { nonfinite = true; break; }
     if (r0 < 0) r0 = rn;
     rel = r0 > 0 ? rn / r0 : 0.0;
+    hist.push_back(rn);
     if (fixed) {
       if (it >= c->cfg.newton_max) { converged = true; break; }
     } else if (rn == 0.0 || (it > 0 && rel <= c->cfg.newton_rtol)) {
@@ -767,42 +807,56 @@ m1_status m1_implicit_step(m1_ctx* c, m1_state* U, double dt, m1_stats* stats) {
     } else if (it >= c->cfg.newton_max) {
       break;
     }
+    if (!std::isfinite(rn)) { nonfinite = true; break; }
+    // pseudo-transient continuation: solve (A + psi M) delta = -R
+    c->sc.psi = psi;
+    c->lin_rtol = (psi > 0 && c->cfg.ptc_rtol > 0) ? c->cfg.ptc_rtol : -1.0;
+    if ((st = ensure_bj(c)) != M1_OK) { finish(); return st; }
     SolveResult sr;
-    if ((st = solve(c, rn, sr, fell_back)) != M1_OK) return st;
+    if ((st = solve(c, rn, sr, fell_back)) != M1_OK) { finish(); return st; }
     kry += sr.iters;
     rst += sr.restarts;
     lin_rel = sr.rel;
     if (verbose())
-      std::fprintf(stderr, "[m1] newton %d |R|=%.3e rel=%.3e gmres_iters=%d restarts=%d lin_rel=%.2e%s\n", it, rn, rel,
-                   sr.iters, sr.restarts, sr.rel, sr.converged ? "" : " (not converged)");
+      std::fprintf(stderr, "[m1] newton %d |R|=%.3e rel=%.3e psi=%.2e gmres_iters=%d restarts=%d lin_rel=%.2e%s\n", it, rn,
+                   rel, psi, sr.iters, sr.restarts, sr.rel, sr.converged ? "" : " (not converged)");
     if (sr.nonfinite) { nonfinite = true; break; }
+    double r_new = 0.0;
     if (!line_search) {
-      timed(c, KC_NEWTON_UPDATE, 24.0 * c->n, [&] {
-        k_zero_u64<<<1, 64, 0, c->stream>>>(c->dcount);
-        launch_newton_update(c->nd, c->g, c->Uk, c->Uk, c->x, 1.0, c->nu, c->cfg.c, c->dcount, c->stream);
-      });
+      update(c->Uk, 1.0);
+      if ((st = evaluate(r_new)) != M1_OK) { finish(); return st; }
     } else {
-      // backtracking: U^{k+1} = U^k + lam delta, lam = 1, 1/2, ... while ||R|| does not drop
+      // non-monotone backtracking: the first lam in 1, 1/2, ..., 1/128 with
+      // ||R|| <= (1 - 1e-4 lam) max(last 5 accepted ||R||); else the best trial
       HIPCHK(c, hipMemcpyAsync(c->Uprev, c->Uk, sizeof(double) * c->n, hipMemcpyDeviceToDevice, c->stream));
-      double lam = 1.0;
-      for (int trial = 0;; ++trial) {
-        timed(c, KC_NEWTON_UPDATE, 24.0 * c->n, [&] {
-          launch_newton_update(c->nd, c->g, c->Uk, c->Uprev, c->x, lam, c->nu, c->cfg.c, c->dcount, c->stream);
-        });
+      const size_t h0 = hist.size() > 5 ? hist.size() - 5 : 0;
+      const double ref = *std::max_element(hist.begin() + h0, hist.end());
+      double lam = 1.0, best_r = 0.0, best_lam = 1.0, last_lam = 0.0;
+      bool have_best = false;
+      for (int trial = 0; trial < 8; ++trial) {
+        update(c->Uprev, lam);
         double rt = 0.0;
-        if ((st = evaluate(rt)) != M1_OK) return st;
-        const bool ok = std::isfinite(rt) && rt <= (1.0 - 1e-4 * lam) * rn;
-        if (ok || trial == 7) {
-          if (verbose() && lam < 1.0) std::fprintf(stderr, "[m1]   line search: step %.4g, |R| %.3e -> %.3e\n", lam, rn, rt);
-          rn_next = rt;
-          evaluated = true;
-          break;
-        }
+        if ((st = evaluate(rt)) != M1_OK) { finish(); return st; }
+        last_lam = lam;
+        if (!have_best || (std::isfinite(rt) && !(rt >= best_r))) { best_r = rt; best_lam = lam; have_best = true; }
+        if (std::isfinite(rt) && rt <= (1.0 - 1e-4 * lam) * ref) { best_r = rt; best_lam = lam; break; }
         lam *= 0.5;
       }
+      if (best_lam != last_lam) {
+        update(c->Uprev, best_lam);
+        if ((st = evaluate(best_r)) != M1_OK) { finish(); return st; }
+      }
+      r_new = best_r;
+      if (verbose() && best_lam < 1.0) std::fprintf(stderr, "[m1]   line search: step %.4g, |R| %.3e -> %.3e\n", best_lam, rn, r_new);
     }
+    if (psi > 0) {
+      psi = r_new < rn ? psi * r_new / rn : 2.0 * psi;   // switched evolution relaxation
+      if (psi < 1e-6 * psi0) psi = 0.0;
+    }
+    rn = r_new;
     ++it;
   }
+  finish();
   unsigned long long nf = 0;
   k_zero_u64<<<1, 64, 0, c->stream>>>(c->dcount);
   launch_count_f(c->nd, c->g, c->Uk, c->cfg.c, c->dcount, c->stream);
@@ -849,6 +903,7 @@ m1_status m1_set_network(m1_ctx* c, m1nn* net) {
 m1_status m1_nn_features(m1_ctx* c, const double* r, float* features) {
   if (!c || !r || !features) return M1_ERR_INVALID_ARG;
   if (!c->linearized) { c->err = "no linearisation yet"; return M1_ERR_STATE; }
+  if (ensure_bj(c) != M1_OK) return M1_ERR_HIP;
   if (c->nd != 2 || c->nu != 3) { c->err = "features are defined for 2D radiation-only problems"; return M1_ERR_INVALID_ARG; }
   launch_dot<double>(0, nullptr, 0, r, nullptr, c->n, c->part, c->nb, nullptr, c->stream);
   launch_reduce(c->part, 1, c->nb, c->dscal + 3, c->stream);
@@ -861,6 +916,7 @@ m1_status m1_nn_features(m1_ctx* c, const double* r, float* features) {
 m1_status m1_nn_target(m1_ctx* c, const double* r, const double* e, float* target) {
   if (!c || !r || !e || !target) return M1_ERR_INVALID_ARG;
   if (!c->linearized) { c->err = "no linearisation yet"; return M1_ERR_STATE; }
+  if (ensure_bj(c) != M1_OK) return M1_ERR_HIP;
   if (c->nd != 2 || c->nu != 3) { c->err = "targets are defined for 2D radiation-only problems"; return M1_ERR_INVALID_ARG; }
   launch_dot<double>(0, nullptr, 0, r, nullptr, c->n, c->part, c->nb, nullptr, c->stream);
   launch_reduce(c->part, 1, c->nb, c->dscal + 3, c->stream);
@@ -872,6 +928,7 @@ m1_status m1_nn_target(m1_ctx* c, const double* r, const double* e, float* targe
 m1_status m1_solve_linear(m1_ctx* c, const double* b, double* x, m1_stats* stats) {
   if (!c || !b || !x) return M1_ERR_INVALID_ARG;
   if (!c->linearized) { c->err = "no linearisation yet"; return M1_ERR_STATE; }
+  if (ensure_bj(c) != M1_OK) return M1_ERR_HIP;
   const auto t0 = std::chrono::steady_clock::now();
   HIPCHK(c, hipMemcpyAsync(c->b, b, sizeof(double) * c->n, hipMemcpyDeviceToDevice, c->stream));
   norm2_into(c, c->b, 0);

@@ -52,6 +52,7 @@ struct Scheme {
   int ap;            // asymptotic correction on/off
   int p1;            // P1 closure
   int newton;        // differentiate the tensor (1) or freeze it (0)
+  double psi;        // pseudo-transient shift of the linear operator (0: none)
 };
 
 __device__ __forceinline__ int64_t plane_index(int d, int i, int j, int k, const Geom& g) {

@@ -91,8 +91,8 @@ void launch_xupdate(int nd, bool cpl, const Geom& g, const Coefs<R>& cf, const T
 void launch_reduce(const double* partials, int nv, int nb, double* out, hipStream_t s);
 void launch_cycle_init(GmresState* gs, const double* beta2, double tol_abs, double tol_rel, hipStream_t s);
 // Uk = U0 + lam * dx (U0 may be Uk), counting cells with |F| > c E
-void launch_newton_update(int nd, const Geom& g, double* Uk, const double* U0, const double* dx, double lam, int nu,
-                          double c, unsigned long long* fcount, hipStream_t s);
+void launch_newton_update(int nd, const Geom& g, double* Uk, const double* U0, const double* dx, double lam,
+                          double clip, int nu, double c, unsigned long long* fcount, hipStream_t s);
 void launch_count_f(int nd, const Geom& g, const double* U, double c, unsigned long long* fcount, hipStream_t s);
 void launch_scale(double* v, double a, int64_t n, hipStream_t s);
 template <typename TS, typename TD>

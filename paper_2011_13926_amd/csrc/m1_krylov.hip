@@ -454,22 +454,28 @@ __device__ __forceinline__ bool f_gt_1(const double* U, int64_t N, int64_t cell,
 template <int ND>
 __global__ __launch_bounds__(256) void k_newton_update(int64_t N, int nu, double* __restrict__ U,
                                                        const double* __restrict__ U0, const double* __restrict__ dx,
-                                                       double lam, double c, unsigned long long* fcount) {
+                                                       double lam, double clip, double c,
+                                                       unsigned long long* fcount) {
   const int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   bool gt = false;
   if (cell < N) {
-    for (int q = 0; q < nu; ++q) U[q * N + cell] = U0[q * N + cell] + lam * dx[q * N + cell];
+    // positivity clip: the energy step is at least -clip E^k (clip = 0: off)
+    const double E0 = U0[cell];
+    double dE = dx[cell];
+    if (clip > 0.0) dE = fmax(dE, -clip * E0);
+    U[cell] = E0 + lam * dE;
+    for (int q = 1; q < nu; ++q) U[q * N + cell] = U0[q * N + cell] + lam * dx[q * N + cell];
     gt = f_gt_1<ND>(U, N, cell, c);
   }
   const unsigned long long ballot = __ballot(gt);
   if ((threadIdx.x & 63) == 0 && ballot) atomicAdd(fcount, (unsigned long long)__popcll(ballot));
 }
 
-void launch_newton_update(int nd, const Geom& g, double* Uk, const double* U0, const double* dx, double lam, int nu,
-                          double c, unsigned long long* fcount, hipStream_t s) {
+void launch_newton_update(int nd, const Geom& g, double* Uk, const double* U0, const double* dx, double lam,
+                          double clip, int nu, double c, unsigned long long* fcount, hipStream_t s) {
   const int64_t grd = (g.N + 255) / 256;
-  if (nd == 2) k_newton_update<2><<<grd, 256, 0, s>>>(g.N, nu, Uk, U0, dx, lam, c, fcount);
-  else k_newton_update<3><<<grd, 256, 0, s>>>(g.N, nu, Uk, U0, dx, lam, c, fcount);
+  if (nd == 2) k_newton_update<2><<<grd, 256, 0, s>>>(g.N, nu, Uk, U0, dx, lam, clip, c, fcount);
+  else k_newton_update<3><<<grd, 256, 0, s>>>(g.N, nu, Uk, U0, dx, lam, clip, c, fcount);
 }
 
 template <int ND>

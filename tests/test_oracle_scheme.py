@@ -115,6 +115,82 @@ def test_picard_newton_reaches_the_root_of_the_full_nonlinear_residual():
     assert np.linalg.norm(u - step.U.reshape(-1)) <= 1e-10 * np.linalg.norm(u)
 
 
+def test_globalised_newton_reaches_the_same_root():
+    """Pseudo-transient continuation, the non-monotone line search and the
+    positivity clip change the path, not the root: the globalised iteration ends
+    at the root of the finite-difference dense Newton on the FULL residual."""
+    p = W.random_problem((6, 5), 22, source="absorption", bc=BC2[1], dt=3.0, fmax=0.5)
+    sch = O.Scheme.from_problem(p)
+    Un = O.state_from_problem(p, "n")
+    sig = p["sigma"]
+
+    def Rfull(u):
+        return O.residual(O.linearize(sch, sig, None, u.reshape(Un.shape), Un, p["dt"])).reshape(-1)
+
+    u = Un.reshape(-1).copy()
+    for _ in range(30):
+        r = Rfull(u)
+        if np.linalg.norm(r) < 1e-14:
+            break
+        J = np.zeros((u.size, u.size))
+        for k in range(u.size):
+            h = 1e-7 * max(1.0, abs(u[k]))
+            e = np.zeros(u.size)
+            e[k] = h
+            J[:, k] = (Rfull(u + e) - Rfull(u - e)) / (2 * h)
+        u = u - np.linalg.solve(J, r)
+    assert np.linalg.norm(Rfull(u)) < 1e-12
+    step = O.implicit_step(sch, sig, None, Un, p["dt"], rtol=1e-14, newton_rtol=1e-13, newton_max=150,
+                           psi0=1.0, ptc_rtol=1e-3, line_search=True, clip=0.5)
+    assert step.converged
+    assert np.linalg.norm(u - step.U.reshape(-1)) <= 1e-10 * np.linalg.norm(u)
+
+
+def test_ptc_step_solves_the_shifted_system_and_clip_bounds_the_energy_step():
+    """One Newton iteration with a full Krylov space (exact solve) and psi0 solves
+    (A + psi0 M) delta = -R with M = 1 on the radiation rows and rho c_v on the T
+    row (assembled densely here); with the clip, dE = max(delta_E, -clip E)."""
+    p = W.random_problem((4, 3), 23, source="coupled_t", bc=BC2[1], dt=2.0, fmax=0.5)
+    sch = O.Scheme.from_problem(p)
+    Un = O.state_from_problem(p, "n")
+    sig, rc = p["sigma"], p["rho_cv"]
+    lin = O.linearize(sch, sig, rc, Un, Un, p["dt"])
+    A = O.assemble_dense(lin)
+    m = np.concatenate([np.ones(3 * Un[0].size), np.asarray(rc, float).reshape(-1)])
+    psi0 = 0.7
+    delta = np.linalg.solve(A + psi0 * np.diag(m), -O.residual(lin).reshape(-1)).reshape(Un.shape)
+    nfull = Un.size
+    one = O.implicit_step(sch, sig, rc, Un, p["dt"], restart=nfull, newton_max=1, fixed_iters=nfull, psi0=psi0)
+    assert np.linalg.norm(one.U - (Un + delta)) <= 1e-10 * np.linalg.norm(delta)
+    clip = 0.01
+    dE = np.maximum(delta[0], -clip * Un[0])
+    assert np.any(delta[0] < -clip * Un[0])          # the clip is active in this case
+    cl = O.implicit_step(sch, sig, rc, Un, p["dt"], restart=nfull, newton_max=1, fixed_iters=nfull, psi0=psi0,
+                         clip=clip)
+    assert np.linalg.norm(cl.U[0] - (Un[0] + dE)) <= 1e-10 * np.linalg.norm(Un[0])
+    assert np.linalg.norm(cl.U[1:] - (Un[1:] + delta[1:])) <= 1e-10 * np.linalg.norm(delta[1:])
+
+
+def test_beam_shadow_roots_centred_source_positive_well_balanced_negative():
+    """Why the beam/shadow workload takes the centred flux source (as the paper's
+    shadow test does, Sect. 5.4): on a 24^2 beam with one sharp clump
+    (sigma dx = 1e3) at dt = 50, the scheme's root with the well-balanced source
+    has E < 0 in the clump, while the centred-source root keeps E > 0 and f <= 1."""
+    out = {}
+    for fs in ("wb", "centered"):
+        p = W.beam_shadow(n=(24, 24), nclumps=1, dt=50.0, flux_source=fs)
+        sch = O.Scheme.from_problem(p)
+        Un = O.state_from_problem(p)
+        st = O.implicit_step(sch, p["sigma"], None, Un, p["dt"], rtol=1e-12, newton_rtol=1e-12, newton_max=40,
+                             max_iters=5000, line_search=True)
+        assert st.converged, fs
+        out[fs] = st.U
+    assert out["wb"][0].min() < -1e-4
+    E, F = out["centered"][0], out["centered"][1:]
+    assert E.min() > 0
+    assert (np.sqrt(F[0] ** 2 + F[1] ** 2) <= (1 + 1e-9) * E).all()
+
+
 def test_conservation_of_total_energy_periodic():
     p = W.random_problem((7, 6), 5, source="coupled_t", dt=4.0)
     lin = _lin(p)
