@@ -167,6 +167,13 @@ def pressure_jacobian(E, F, c, kind="m1"):
     with chi'(f) = [8f(5+2xi) + 6f(3+4f^2)/xi] / (5+2xi)^2.  Where f is clamped to 1
     (|F| > cE, or E <= 0) the derivatives of f vanish; F = 0 gives dP/dF = 0.
     P1: P = E I/3, so dP/dE = I/3 and dP/dF = 0.
+
+    The factor (3chi-1)/2 (E/|F|) of the direction term is evaluated without
+    cancellation: from chi = (3+4f^2)/(5+2xi) and xi^2 = 4 - 3f^2 one gets
+    3chi - 1 = 6f^2/(2+xi) exactly, so (3chi-1)/2 (E/|F|) = 3f/(c(2+xi)) where f
+    is not clamped (bounded as F -> 0, where the literal product is rounding
+    noise times an unbounded E/|F|); where f is clamped, chi = 1 and the factor
+    is E/|F| <= 1/c.
     """
     ndim = len(F)
     f, nvec, chi, D = closure(E, F, c, kind)
@@ -180,6 +187,7 @@ def pressure_jacobian(E, F, c, kind="m1"):
     clamped = Fmag >= c * Epos
     dchi = np.where(clamped, 0.0, dchi)
     E_over_F = np.where(Fmag > 0.0, E / np.where(Fmag > 0.0, Fmag, 1.0), 0.0)
+    geo_factor = np.where(clamped, E_over_F, 3.0 * f / (c * (2.0 + xi)))
     J = []
     for d in range(ndim):
         row = []
@@ -191,7 +199,7 @@ def pressure_jacobian(E, F, c, kind="m1"):
                 t1 = dchi / c * nvec[l] * shape_dm
                 geo = ((nvec[m] if d == l else 0.0) + (nvec[d] if m == l else 0.0)
                        - 2.0 * nvec[d] * nvec[m] * nvec[l])
-                t2 = 0.5 * (3.0 * chi - 1.0) * E_over_F * geo
+                t2 = geo_factor * geo
                 dF.append(t1 + t2)
             row.append([dE] + dF)
         J.append(row)

@@ -159,13 +159,15 @@ int nu_of(const m1_config& c) { return 1 + c.ndim + (c.source == M1_SRC_COUPLED_
 bool finite(double v) { return std::isfinite(v); }
 
 // M1_VERBOSE=1 in the environment prints one line per Newton iteration to stderr.
-bool verbose() {
+// M1_VERBOSE=1: one line per Newton iteration on stderr; 2: also every GMRES
+// cycle and every line-search trial
+int verbose() {
   static int v = -1;
   if (v < 0) {
     const char* e = std::getenv("M1_VERBOSE");
-    v = (e && e[0] && e[0] != '0') ? 1 : 0;
+    v = (e && e[0] >= '1' && e[0] <= '9') ? e[0] - '0' : 0;
   }
-  return v == 1;
+  return v;
 }
 
 m1_status validate_config(const m1_config* c, std::string& err) {
@@ -490,6 +492,9 @@ m1_status gmres(m1_ctx* c, double bnorm, SolveResult& res, const Coefs<R>& cfi) 
     prof_collect(c);
     total += fixed ? steps : std::max(k, 1);
     beta = std::sqrt(std::max(c->hscal[0], 0.0));
+    if (verbose() > 1)
+      std::fprintf(stderr, "[m1]     cycle %d: k=%d true |r|/|b|=%.3e done=%d breakdown=%d nonfinite=%d\n", cycles, k,
+                   bnorm > 0 ? beta / bnorm : 0.0, hk[0], hk[2], hk[3]);
     if (!std::isfinite(beta) || hk[3]) { res.nonfinite = true; break; }
   }
   res.iters = total;
@@ -807,7 +812,11 @@ m1_status m1_implicit_step(m1_ctx* c, m1_state* U, double dt, m1_stats* stats) {
     } else if (it >= c->cfg.newton_max) {
       break;
     }
-    if (!std::isfinite(rn)) { nonfinite = true; break; }
+    if (!std::isfinite(rn)) {
+      if (verbose()) std::fprintf(stderr, "[m1] newton %d: non-finite residual norm\n", it);
+      nonfinite = true;
+      break;
+    }
     // pseudo-transient continuation: solve (A + psi M) delta = -R
     c->sc.psi = psi;
     c->lin_rtol = (psi > 0 && c->cfg.ptc_rtol > 0) ? c->cfg.ptc_rtol : -1.0;
@@ -838,6 +847,7 @@ m1_status m1_implicit_step(m1_ctx* c, m1_state* U, double dt, m1_stats* stats) {
         double rt = 0.0;
         if ((st = evaluate(rt)) != M1_OK) { finish(); return st; }
         last_lam = lam;
+        if (verbose() > 1) std::fprintf(stderr, "[m1]     trial lam=%.4g |R|=%.6e (ref %.6e)\n", lam, rt, ref);
         if (!have_best || (std::isfinite(rt) && !(rt >= best_r))) { best_r = rt; best_lam = lam; have_best = true; }
         if (std::isfinite(rt) && rt <= (1.0 - 1e-4 * lam) * ref) { best_r = rt; best_lam = lam; break; }
         lam *= 0.5;

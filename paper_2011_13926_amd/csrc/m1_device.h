@@ -65,7 +65,7 @@ template <int ND> struct ClosureState {
   double nv[ND];     // unit direction (0 if F = 0)
   double chi;
   bool clamped;      // |F| >= cE (or E <= 0 with F != 0): f fixed at 1
-  double E_over_F;   // E/|F| (0 if F = 0)
+  double geoE;       // (3chi-1)/2 * E/|F|: 3f/(c(2+xi)) unclamped, E/|F| clamped, 0 if F = 0
 };
 
 template <int ND>
@@ -79,14 +79,16 @@ __device__ __forceinline__ ClosureState<ND> closure(double E, const double* F, d
   const double fr = Fm / (c * Ep);
   s.clamped = !(fr < 1.0);
   s.f = s.clamped ? 1.0 : fr;
-  const double inv = Fm > 0.0 ? 1.0 / Fm : 0.0;
+  // divide (not multiply by 1/|F|): 1/|F| overflows for subnormal |F|
 #pragma unroll
-  for (int m = 0; m < ND; ++m) s.nv[m] = F[m] * inv;
-  s.E_over_F = E * inv;
+  for (int m = 0; m < ND; ++m) s.nv[m] = Fm > 0.0 ? F[m] / Fm : 0.0;
+  const double xi = sqrt(4.0 - 3.0 * s.f * s.f);
+  // 3chi - 1 = 6f^2/(2+xi) exactly, so (3chi-1)/2 E/|F| = 3f/(c(2+xi)) without the
+  // cancellation of the literal product at small f
+  s.geoE = s.clamped ? (Fm > 0.0 ? E / Fm : 0.0) : 3.0 * s.f / (c * (2.0 + xi));
   if (p1) {
     s.chi = 1.0 / 3.0;
   } else {
-    const double xi = sqrt(4.0 - 3.0 * s.f * s.f);
     s.chi = (3.0 + 4.0 * s.f * s.f) / (5.0 + 2.0 * xi);
   }
   return s;
@@ -117,7 +119,6 @@ __device__ __forceinline__ void pressure_jacobian(const ClosureState<ND>& s, dou
     const double den = 5.0 + 2.0 * xi;
     dchi = (8.0 * f * den + 6.0 * f * (3.0 + 4.0 * f * f) / xi) / (den * den);
   }
-  const double aniso = 0.5 * (3.0 * s.chi - 1.0);
 #pragma unroll
   for (int d = 0; d < ND; ++d) {
 #pragma unroll
@@ -135,7 +136,7 @@ __device__ __forceinline__ void pressure_jacobian(const ClosureState<ND>& s, dou
 #pragma unroll
       for (int l = 0; l < ND; ++l) {
         const double geo = (d == l ? s.nv[m] : 0.0) + (m == l ? s.nv[d] : 0.0) - 2.0 * s.nv[d] * s.nv[m] * s.nv[l];
-        row[1 + l] = c2 * (dchi / c * s.nv[l] * shape + aniso * s.E_over_F * geo);
+        row[1 + l] = c2 * (dchi / c * s.nv[l] * shape + s.geoE * geo);
       }
     }
   }

@@ -157,7 +157,14 @@ def test_step_fixed_iterations_ptc_clip(n, bc, src, fs):
         s.close()
 
 
-@pytest.mark.parametrize("n,bc,src,fs", STEP_CASES[:3])
+# The random absorption case with the well-balanced source has a root with f up
+# to 23 in a fifth of the cells; there the residual has several roots and two
+# paths can end on different ones (on the oracle alone, plain and globalised
+# Newton differ by 1.6e-3).  The same-root claim is tested on admissible roots.
+SAME_ROOT_CASES = STEP_CASES[:2] + [((24, 20), BC2["periodic"], "absorption", "centered")]
+
+
+@pytest.mark.parametrize("n,bc,src,fs", SAME_ROOT_CASES)
 def test_step_converged_with_globalization_same_root(n, bc, src, fs):
     """PTC (psi0 = 1, loose linear tolerance while psi > 0), non-monotone line
     search and the positivity clip change the path only: the GPU's root agrees

@@ -196,3 +196,85 @@ def test_wb_source_fourier_symbol():
         e[1, 0, k] = 1.0
         A[:, k] = O.operator(lin, e, "linear")[1, 0]
     assert np.linalg.norm(np.linalg.inv(A), 2) <= 1.0 + 1e-12
+
+
+def test_pressure_jacobian_small_flux_is_bounded_and_matches_the_limit():
+    """Near F = 0 the Jacobian of P = D(E, F) E with respect to F tends to 0:
+    chi'(f) ~ f and (3chi - 1)/2 E/|F| = 3f/(c(2+xi)) ~ 3f/(4c).  The literal product
+    (3chi-1)/2 * E/|F| is rounding noise times an unbounded E/|F| (a plausible
+    evaluation mistake); the Jacobian must stay finite and of order f."""
+    c = 1.0
+    for Fx in (1e-12, 1e-100, 1e-300):
+        E = np.array([1e-6])
+        F = [np.array([Fx]), np.array([0.5 * Fx])]
+        J = O.pressure_jacobian(E, F, c)
+        f = np.hypot(Fx, 0.5 * Fx) / (c * 1e-6)
+        for d in range(2):
+            for m in range(2):
+                for l in range(2):
+                    v = J[d][m][1 + l][0]
+                    assert np.isfinite(v)
+                    assert abs(v) <= 3.0 * f + 1e-300
+    # the identity behind it, at moderate f where the literal form is accurate
+    f = np.linspace(1e-3, 1.0, 200)
+    xi = np.sqrt(4.0 - 3.0 * f * f)
+    chi = (3.0 + 4.0 * f * f) / (5.0 + 2.0 * xi)
+    assert np.allclose(3.0 * chi - 1.0, 6.0 * f * f / (2.0 + xi), rtol=1e-10, atol=1e-15)
+
+
+def test_pressure_jacobian_matches_high_precision_derivative_at_small_f():
+    """At f = 1e-9 and 1e-12 the Jacobian dP/dF equals the central difference of
+    P = D(E, F) E evaluated in 60-digit decimal arithmetic from the closure's
+    definition (Sect. 2.2).  In double precision the literal (3chi - 1) is 0 or
+    rounding noise there, so an evaluation through it misses the direction term
+    (~3f/(4c)) entirely."""
+    from decimal import Decimal, getcontext
+    getcontext().prec = 60
+    c = 1.0
+
+    def P_dec(E, F):
+        Fm = (F[0] * F[0] + F[1] * F[1]).sqrt()
+        f = Fm / (Decimal(c) * E)
+        xi = (Decimal(4) - 3 * f * f).sqrt()
+        chi = (3 + 4 * f * f) / (5 + 2 * xi)
+        n = [F[0] / Fm, F[1] / Fm]
+        return [[((1 - chi) / 2 if d == m else Decimal(0)) * E + (3 * chi - 1) / 2 * n[d] * n[m] * E
+                 for m in range(2)] for d in range(2)]
+
+    for fmag in (1e-9, 1e-12):
+        E0 = 1.5
+        F0 = [0.6 * fmag * c * E0, -0.8 * fmag * c * E0]
+        J = O.pressure_jacobian(np.array([E0]), [np.array([F0[0]]), np.array([F0[1]])], c)
+        for l in range(2):
+            h = Decimal(fmag) * Decimal("1e-20")
+            Fp = [Decimal(F0[0]), Decimal(F0[1])]
+            Fq = list(Fp)
+            Fp[l] += h
+            Fq[l] -= h
+            Pp, Pq = P_dec(Decimal(E0), Fp), P_dec(Decimal(E0), Fq)
+            for d in range(2):
+                for m in range(2):
+                    ref = float((Pp[d][m] - Pq[d][m]) / (2 * h))
+                    got = J[d][m][1 + l][0]
+                    assert abs(got - ref) <= 1e-6 * abs(ref) + 1e-30 * fmag, (fmag, l, d, m, got, ref)
+
+
+def test_pressure_jacobian_matches_finite_difference_at_small_f():
+    """At f = 1e-4 (where a central difference is still accurate) the Jacobian
+    equals the finite difference of c^2-free P = D(E, F) E."""
+    c = 1.0
+    E0, F0 = 2.0, np.array([1.2e-4, -0.7e-4])
+
+    def P(E, Fv):
+        _, _, _, D = O.closure(np.array([E]), [np.array([Fv[0]]), np.array([Fv[1]])], c)
+        return np.array([[D[d][m][0] * E for m in range(2)] for d in range(2)])
+
+    J = O.pressure_jacobian(np.array([E0]), [np.array([F0[0]]), np.array([F0[1]])], c)
+    h = 1e-9
+    for l in range(2):
+        e = np.zeros(2)
+        e[l] = h
+        fd = (P(E0, F0 + e) - P(E0, F0 - e)) / (2 * h)
+        for d in range(2):
+            for m in range(2):
+                assert abs(J[d][m][1 + l][0] - fd[d, m]) <= 1e-6 * max(1.0, abs(fd[d, m])) + 1e-9
