@@ -1,15 +1,20 @@
 #!/usr/bin/env python3
 """Benchmark: implicit M1 cell-updates/s at 1e-8 residual, plain FP64 vs mixed precision.
 
-Workload: the 2D 1024x1024 beam/shadow problem (background sigma*dx = 1e-3, eight
-seeded elliptical clumps with sigma*dx = 1e3, a beam F = cE entering through the
--x face, outflow elsewhere; centred flux source and HLL speeds floored at
-+-0.1c as in the paper's shadow test, Sect. 5.4), implicit steps at dt = 50 dx/c
-starting from E = 1e-6, F = 0.  One "step" is one complete implicit step: Newton
-until ||R(U)|| <= 1e-8 ||R(U^n)||, each Newton iteration a block-Jacobi GMRES(30)
-solve (pseudo-transient continuation, positivity clip and non-monotone line
-search as globalisation; they leave the root unchanged).  Inputs are resident
-in HBM before timing starts.
+One "step" is one complete implicit step of the named workload: Newton until
+||R(U)|| <= 1e-8 ||R(U^n)||, each Newton iteration a block-Jacobi GMRES(30)
+solve.  Inputs are resident in HBM before timing starts.  Workloads (seeded,
+synthetic; recipes in ``workloads``):
+
+* voronoi_512 (default): 2D 512^2 periodic Voronoi opacity field (64 cells,
+  log-uniform sigma dx in 1e-3..1e4), dt = 100 dx/c, well-balanced source,
+  held-out seed 1000; each linear solve to 1e-8.
+* beam_shadow_1024: 2D 1024^2 beam/shadow at dt = 50 dx/c (centred source,
+  +-0.1c speed floor), with pseudo-transient continuation, positivity clip and
+  line search.  Block-Jacobi GMRES(30) does not converge on this workload once
+  the beam is established (free streaming at 50x CFL); the line then reports
+  converged = false and is not a valid throughput.
+* diffusive_gaussian_64, coupled_lognormal_256, ionization_front_192.
 
 Prints ONE JSON line.  `value` is the faster of the measured solver variants
 that converged on every step; every variant's own numbers are in `variants`.
@@ -32,24 +37,47 @@ if ROOT not in sys.path:
 
 METRIC = "implicit M1 cell-updates/s at 1e-8 residual: plain FP64 vs mixed+learned"
 HBM_PEAK_GBS = 8000.0
+PROFILES = os.path.join(ROOT, "profiles")
+CSRC = os.path.join(ROOT, "paper_2011_13926_amd", "csrc")
+
+# profiler kernel class -> prefix of the HIP kernel's demangled name
+CLASS_KERNEL = {
+    "apply_bj_fused": ("k_apply2d_lds<false, 0, true", "k_apply2d_lds<true, 0, true", "k_apply3d_25d<false, 0, true",
+                       "k_apply3d_25d<true, 0, true"),
+    "apply": ("k_apply2d_lds<false, 0, false", "k_apply2d_lds<true, 0, false", "k_apply3d_25d<false, 0, false",
+              "k_apply3d_25d<true, 0, false", "void k_stencil"),
+    "arnoldi_dot": ("void k_dot",), "arnoldi_update": ("void k_update",), "arnoldi_scalar": ("k_scalar",),
+    "x_update": ("void k_xupdate",), "block_jacobi": ("void k_bj",),
+}
+
+
+def source_hash():
+    """SHA-256 over the HIP sources: byte-counter readings are valid only for the
+    kernels they were taken on."""
+    import hashlib
+    h = hashlib.sha256()
+    for fn in sorted(os.listdir(CSRC)):
+        if fn.endswith((".hip", ".h")):
+            with open(os.path.join(CSRC, fn), "rb") as fh:
+                h.update(fn.encode() + b"\0" + fh.read())
+    return h.hexdigest()
 
 
 def parse():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--n", type=int, default=1024)
-    ap.add_argument("--dt", type=float, default=50.0)
-    ap.add_argument("--variants", default="fp64,mixed")
-    ap.add_argument("--max-iters", type=int, default=3000, help="GMRES iterations per linear solve")
-    ap.add_argument("--newton-max", type=int, default=60)
-    ap.add_argument("--lin-rtol", type=float, default=1e-3, help="linear tolerance per Newton iteration")
-    ap.add_argument("--psi0", type=float, default=1.0, help="pseudo-transient continuation start (0: off)")
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=0)
+    ap.add_argument("--workload", default="voronoi_512", choices=sorted(WORKLOADS))
+    ap.add_argument("--variants", default="fp64,mixed,mixed32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-events", action="store_true", help="do not time kernels with HIP events")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for hardware byte counters)")
+    ap.add_argument("--summarize-profiles", metavar="DIR", default=None,
+                    help="turn rocprofv3 CSV output under DIR/{trace,fetch,write,copy_fetch,copy_write} into "
+                         "profiles/<workload>_kernels.md and profiles/<workload>_traffic.json")
+    ap.add_argument("--profile-commands", default="", help="text recorded with --summarize-profiles")
     return ap.parse_args()
 
 
@@ -70,6 +98,19 @@ def copy_calibration():
                       "GBps_read_plus_write": 2 * (1 << 30) / dt / 1e9}), flush=True)
 
 
+GLOBALISED = dict(ptc_psi0=1.0, ptc_rtol=1e-3, positivity_clip=0.9, line_search=True)
+WORKLOADS = {
+    "voronoi_512": dict(make=lambda W: W.voronoi_opacity(seed=1000),
+                        solver=dict(rtol=1e-8, newton_rtol=1e-8, max_iters=20000, newton_max=40, line_search=True)),
+    "beam_shadow_1024": dict(make=lambda W: W.beam_shadow(),
+                             solver=dict(rtol=1e-3, newton_rtol=1e-8, max_iters=3000, newton_max=60, **GLOBALISED)),
+    "diffusive_gaussian_64": dict(make=lambda W: W.diffusive_gaussian(),
+                                  solver=dict(rtol=1e-10, newton_rtol=1e-10, max_iters=20000, newton_max=20)),
+    "coupled_lognormal_256": dict(make=lambda W: W.coupled_lognormal(),
+                                  solver=dict(rtol=1e-8, newton_rtol=1e-8, max_iters=1500, newton_max=25, **GLOBALISED)),
+    "ionization_front_192": dict(make=lambda W: W.ionization_front(),
+                                 solver=dict(rtol=1e-8, newton_rtol=1e-8, max_iters=1500, newton_max=15, **GLOBALISED)),
+}
 VARIANTS = {
     "fp64": dict(precision="fp64"),
     "mixed": dict(precision="mixed", basis_fp32=False, inner_rtol=1e-6),
@@ -78,9 +119,17 @@ VARIANTS = {
 DTYPES = {"fp64": "f64", "mixed": "f32 operator+preconditioner / f64 Krylov", "mixed32": "f32 storage / f64 accumulation"}
 
 
+def state0(p):
+    import numpy as np
+    comps = [p["E"]] + [p["F"][m] for m in range(p["ndim"])]
+    if p["source"] == "coupled_t":
+        comps.append(p["T"])
+    return np.stack(comps)
+
+
 def run_variant(P, torch, p, U0, name, args):
-    opts = dict(VARIANTS[name], rtol=args.lin_rtol, newton_rtol=1e-8, restart=30, max_iters=args.max_iters,
-                newton_max=args.newton_max, ptc_psi0=args.psi0, ptc_rtol=1e-3, positivity_clip=0.9, line_search=True)
+    import numpy as np
+    opts = dict(VARIANTS[name], restart=30, **WORKLOADS[args.workload]["solver"])
     s = P.Solver(p, **opts)
     try:
         U = s.to_device(U0)
@@ -103,7 +152,7 @@ def run_variant(P, torch, p, U0, name, args):
         s.profile_enable(False)
     finally:
         s.close()
-    N = p["n"][0] * p["n"][1]
+    N = int(np.prod(p["n"][:p["ndim"]]))
     ok = all(x["status"] == P.M1_OK for x in stats)
     return dict(
         cell_updates_per_s=N * args.steps / wall,
@@ -116,7 +165,95 @@ def run_variant(P, torch, p, U0, name, args):
     )
 
 
-def roofline(prof):
+def _csvs(d, suffix):
+    import glob
+    return sorted(glob.glob(os.path.join(d, "**", "*" + suffix), recursive=True))
+
+
+def _counter_means(d, counter):
+    """Mean counter value per dispatch, by kernel name (text before the argument list)."""
+    import csv
+    agg = {}
+    for path in _csvs(d, "counter_collection.csv"):
+        with open(path) as fh:
+            for r in csv.DictReader(fh):
+                if r.get("Counter_Name") != counter:
+                    continue
+                nm = r["Kernel_Name"].split("(")[0].strip()
+                a = agg.setdefault(nm, [0, 0.0])
+                a[0] += 1
+                a[1] += float(r["Counter_Value"])
+    return {k: (n, tot / n) for k, (n, tot) in agg.items()}
+
+
+def summarize_profiles(d, workload, commands):
+    """Write the committed summaries: the kernel-stats table and, per kernel, the HBM
+    bytes per dispatch from FETCH_SIZE / WRITE_SIZE (KiB) scaled by what the same
+    counters read for a plain device copy of known size."""
+    import csv
+    rows = []
+    for path in _csvs(os.path.join(d, "trace"), "kernel_stats.csv"):
+        with open(path) as fh:
+            rows += list(csv.DictReader(fh))
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    cf = _counter_means(os.path.join(d, "copy_fetch"), "FETCH_SIZE")
+    cw = _counter_means(os.path.join(d, "copy_write"), "WRITE_SIZE")
+    copy_bytes = float(1 << 30)
+    kf = max(cf.items(), key=lambda kv: kv[1][1])
+    kw = max(cw.items(), key=lambda kv: kv[1][1])
+    scale_f = copy_bytes / (kf[1][1] * 1024.0)
+    scale_w = copy_bytes / (kw[1][1] * 1024.0)
+    fetch = _counter_means(os.path.join(d, "fetch"), "FETCH_SIZE")
+    write = _counter_means(os.path.join(d, "write"), "WRITE_SIZE")
+    kernels = {}
+    for nm in sorted(set(fetch) | set(write)):
+        fn, fv = fetch.get(nm, (0, 0.0))
+        wn, wv = write.get(nm, (0, 0.0))
+        kernels[nm] = {"dispatches": max(fn, wn), "fetch_kib": fv, "write_kib": wv,
+                       "hbm_bytes_per_dispatch": fv * 1024.0 * scale_f + wv * 1024.0 * scale_w}
+    traffic = {"workload": workload, "source_sha256": source_hash(), "copy_kernel": kf[0],
+               "copy_fetch_kib": kf[1][1], "copy_write_kib": kw[1][1], "scale_fetch": scale_f,
+               "scale_write": scale_w, "kernels": kernels, "commands": commands}
+    os.makedirs(PROFILES, exist_ok=True)
+    with open(os.path.join(PROFILES, f"{workload}_traffic.json"), "w") as fh:
+        json.dump(traffic, fh, indent=1)
+    lines = [f"# rocprofv3 kernel statistics: {workload}", "", "Commands (run from the repository root):", "",
+             "```", commands.strip(), "```", "",
+             "| kernel | calls | total ms | avg us | % |", "|---|---|---|---|---|"]
+    for r in rows[:16]:
+        lines.append(f"| `{r['Name'].split('(')[0][:100]}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.2f} | "
+                     f"{float(r['AverageNs']) / 1e3:.2f} | {float(r['Percentage']):.1f} |")
+    lines += ["", f"Copy calibration (1 GiB read + 1 GiB written per launch, `{kf[0]}`): FETCH_SIZE "
+              f"{kf[1][1]:.0f} KiB, WRITE_SIZE {kw[1][1]:.0f} KiB per dispatch -> scale {scale_f:.4f} (fetch), "
+              f"{scale_w:.4f} (write).", "", "| kernel | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB | HBM MB/dispatch |",
+              "|---|---|---|---|---|"]
+    for nm, v in sorted(kernels.items(), key=lambda kv: -kv[1]["hbm_bytes_per_dispatch"] * kv[1]["dispatches"])[:12]:
+        lines.append(f"| `{nm[:100]}` | {v['dispatches']} | {v['fetch_kib']:.0f} | {v['write_kib']:.0f} | "
+                     f"{v['hbm_bytes_per_dispatch'] / 1e6:.2f} |")
+    with open(os.path.join(PROFILES, f"{workload}_kernels.md"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print(json.dumps({"wrote": [f"profiles/{workload}_kernels.md", f"profiles/{workload}_traffic.json"]}))
+
+
+def measured_traffic(workload, cls):
+    """HBM bytes per launch of kernel class cls from the committed counter summary,
+    or None when there is none or the kernels changed since it was taken."""
+    path = os.path.join(PROFILES, f"{workload}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        t = json.load(fh)
+    if t.get("source_sha256") != source_hash():
+        return None
+    pref = CLASS_KERNEL.get(cls, ())
+    hits = [v for nm, v in t["kernels"].items() if any(nm.startswith(pf) or nm.startswith("void " + pf) for pf in pref)]
+    if not hits:
+        return None
+    n = sum(v["dispatches"] for v in hits)
+    return sum(v["hbm_bytes_per_dispatch"] * v["dispatches"] for v in hits) / max(n, 1)
+
+
+def roofline(prof, workload):
     if not prof:
         return None, None
     top = max(prof.items(), key=lambda kv: kv[1]["ms"])
@@ -126,16 +263,18 @@ def roofline(prof):
         avg_s = e["ms"] / e["launches"] / 1e3
         per_launch = e["bytes"] / e["launches"]
         gbs = per_launch / avg_s / 1e9
+        tr = measured_traffic(workload, nm)
         return {"kernel": nm, "bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": tr,
                 "bytes_per_launch": per_launch, "avg_launch_us": round(avg_s * 1e6, 2),
                 "launches": e["launches"], "share_of_gpu_time": round(e["ms"] / sum(x["ms"] for x in prof.values()), 4)}
 
-    apply = entry("apply", prof["apply"]) if "apply" in prof else None
+    apply_name = "apply_bj_fused" if "apply_bj_fused" in prof else ("apply" if "apply" in prof else None)
+    apply = entry(apply_name, prof[apply_name]) if apply_name else None
     return entry(name, v), apply
 
 
-def cpu_baseline(p, U0, fp64_result, budget_s=25.0):
+def cpu_baseline(p, U0, fp64_result):
     """The oracle on a bounded sample of the same workload: one linearisation
     (closure, coefficients, residual, block-Jacobi blocks) and one 30-iteration
     GMRES cycle at full size, scaled by the GPU plain-FP64 iteration counts."""
@@ -144,10 +283,11 @@ def cpu_baseline(p, U0, fp64_result, budget_s=25.0):
     import numpy as np
     from oracle import m1_oracle as O
 
+    rho_cv = p.get("rho_cv")
     with threadpool_limits(limits=1):
         sch = O.Scheme.from_problem(p)
         t0 = time.perf_counter()
-        lin = O.linearize(sch, p["sigma"], None, U0, U0, p["dt"])
+        lin = O.linearize(sch, p["sigma"], rho_cv, U0, U0, p["dt"])
         R = O.residual(lin)
         M = O.BlockJacobi(lin)
         t_setup = time.perf_counter() - t0
@@ -158,7 +298,7 @@ def cpu_baseline(p, U0, fp64_result, budget_s=25.0):
     newton = float(np.mean(fp64_result["newton_iters"]))
     krylov = float(np.mean(fp64_result["krylov_iters"]))
     t_step = (newton + 1) * t_setup + krylov * t_iter
-    N = p["n"][0] * p["n"][1]
+    N = int(np.prod(p["n"][:p["ndim"]]))
     return {"value": N / t_step, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
             "sample": (f"oracle at full size: one linearisation+residual+block-Jacobi setup ({t_setup:.2f}s) and one "
                        f"30-iteration GMRES cycle ({t_iter:.3f}s/iteration), scaled by the GPU plain-FP64 counts "
@@ -170,6 +310,9 @@ def main():
     if args.copy_calibration:
         copy_calibration()
         return
+    if args.summarize_profiles:
+        summarize_profiles(args.summarize_profiles, args.workload, args.profile_commands)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
                           "n_gpus": args.gpus}), flush=True)
@@ -180,15 +323,18 @@ def main():
     import paper_2011_13926_amd as P
     import workloads as W
 
-    p = W.beam_shadow(n=(args.n, args.n), dt=args.dt)
-    U0 = np.stack([p["E"], p["F"][0], p["F"][1]])
+    workload = args.workload
+    p = WORKLOADS[workload]["make"](W)
+    U0 = state0(p)
     results = {}
     for name in [v for v in args.variants.split(",") if v]:
         results[name] = run_variant(P, torch, p, U0, name, args)
     valid = {k: v for k, v in results.items() if v["converged_all"]}
-    pick = max(valid or results, key=lambda k: (valid or results)[k]["cell_updates_per_s"])
+    pool = valid or results
+    pick = max(pool, key=lambda k: pool[k]["cell_updates_per_s"])
     head = results[pick]
-    roof, roof_apply = roofline(head["kernels"])
+    roof, roof_apply = roofline(head["kernels"], workload)
+    solver = dict(WORKLOADS[workload]["solver"], restart=30, preconditioner="block_jacobi")
     out = {
         "metric": METRIC,
         "value": head["cell_updates_per_s"],
@@ -202,11 +348,8 @@ def main():
         "vs_baseline": None,
         "dtype": DTYPES[pick],
         "data": "synthetic",
-        "config": {"workload": f"beam_shadow_{args.n}", "grid": [args.n, args.n], "dt_over_cfl": args.dt,
-                   "flux_source": "centered", "lambda_floor": 0.1, "newton_rtol": 1e-8,
-                   "linear_rtol": args.lin_rtol, "restart": 30, "preconditioner": "block_jacobi",
-                   "ptc_psi0": args.psi0, "ptc_rtol": 1e-3, "positivity_clip": 0.9, "line_search": True,
-                   "solver": pick, "seed": 2011},
+        "config": {"workload": workload, "grid": list(p["n"][:p["ndim"]]), "dt_over_cfl": p["dt"],
+                   "flux_source": p["flux_source"], "lambda_floor": p["lambda_floor"], "solver": pick, **solver},
         "converged": head["converged_all"],
         "variants": {k: {kk: vv for kk, vv in v.items() if kk != "kernels"} for k, v in results.items()},
         "roofline": roof,

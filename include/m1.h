@@ -97,10 +97,12 @@ typedef enum { M1_PC_BLOCK_JACOBI = 0, M1_PC_NONE = 1, M1_PC_LEARNED = 2 } m1_pc
 
 typedef struct {
   int32_t ndim;            /* 2 or 3 */
-  int32_t newton_flags;    /* bit 0: non-monotone backtracking line search on ||R||: the first
-                              lam in 1, 1/2, ..., 1/128 with ||R(U + lam delta)|| <=
-                              (1 - 1e-4 lam) max(last 5 accepted ||R||), else the trial with the
-                              smallest ||R|| (never in fixed-iteration mode) */
+  int32_t newton_flags;    /* bit 0: backtracking line search on ||R||: the first lam in 1, 1/2,
+                              ..., 1/128 with ||R(U + lam delta)|| <= (1 - 1e-4 lam) ||R(U)||
+                              (Armijo); if none passes, with
+                              ptc_psi0 > 0 the step is rejected (U kept, psi = max(10 psi,
+                              1e-3 ptc_psi0)), else the trial with the smallest ||R|| is taken
+                              (never in fixed-iteration mode) */
   int64_t n[3];            /* nx, ny, nz (nz ignored in 2D); each >= 1 */
   double dx;               /* cell size (> 0) */
   double c;                /* speed of light (> 0) */
@@ -129,9 +131,10 @@ typedef struct {
                               psi_0 = ptc_psi0, psi_{k+1} = psi_k ||R_{k+1}||/||R_k|| when the
                               residual fell, else 2 psi_k; 0 once below 1e-6 ptc_psi0.  The
                               residual, hence the converged root, is unchanged.  0: off */
-  double ptc_rtol;         /* linear tolerance while psi > 0 (0: rtol) */
-  double positivity_clip;  /* in [0, 1): each Newton update lowers a cell's E by at most this
-                              fraction (dE >= -clip E^k); 0: off */
+  double ptc_rtol;         /* > 0: linear tolerance max(rtol, min(ptc_rtol, psi/ptc_psi0)) while
+                              psi > 0 (0: rtol throughout) */
+  double positivity_clip;  /* in [0, 1): each Newton update lowers a cell's E (and T) by at most
+                              this fraction (dE >= -clip E^k, dT >= -clip T^k); 0: off */
   const char* nn_weights_path; /* host string or NULL (learned preconditioner) */
 } m1_config;
 

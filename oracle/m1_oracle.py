@@ -619,14 +619,18 @@ def implicit_step(sch, sigma, rho_cv, Un, dt, *, restart=30, rtol=1e-10, max_ite
       takes the shifted diagonal blocks.  psi follows switched evolution
       relaxation (Mulder and van Leer, 1985): psi_{k+1} = psi_k ||R_{k+1}||/||R_k||
       when the residual fell, 2 psi_k when it did not, and 0 once below
-      1e-6 psi0.  While psi > 0 the linear tolerance is ptc_rtol (if > 0).
-    * clip in (0, 1): before the update, dE is raised to at least -clip E per
-      cell (the energy of a cell drops by at most that fraction in one update).
+      1e-6 psi0.  While psi > 0 and ptc_rtol > 0 the linear tolerance is
+      max(rtol, min(ptc_rtol, psi/psi0)): loose while far from the root,
+      tightening with the residual.
+    * clip in (0, 1): before the update, dE (and dT with the T row) is raised to
+      at least -clip E (-clip T) per cell: the energy and temperature of a cell
+      drop by at most that fraction in one update.
     * line_search (not with fixed_iters): U^{k+1} = U^k + lam delta with the
       first lam in 1, 1/2, ..., 1/128 whose residual satisfies
-      ||R|| <= (1 - 1e-4 lam) max(last 5 accepted ||R||) (non-monotone
-      Armijo test, Grippo, Lampariello and Lucidi 1986); if none does, the trial
-      with the smallest ||R|| is taken (the earliest on ties).
+      ||R|| <= (1 - 1e-4 lam) ||R(U^k)|| (Armijo test).  If none does: with
+      psi0 > 0 the step is rejected (U^{k+1} = U^k) and psi becomes
+      max(10 psi, 1e-3 psi0); without, the trial with the smallest ||R|| is
+      taken (the earliest on ties).
     """
     if newton_rtol is None:
         newton_rtol = rtol
@@ -664,7 +668,7 @@ def implicit_step(sch, sigma, rho_cv, Un, dt, *, restart=30, rtol=1e-10, max_ite
             op = lambda v: apply_operator(lin, v)
         else:
             op = lambda v, sh=shift.reshape(-1): apply_operator(lin, v) + sh * v
-        lin_tol = ptc_rtol if (psi > 0 and ptc_rtol > 0) else rtol
+        lin_tol = max(rtol, min(ptc_rtol, psi / psi0)) if (psi > 0 and ptc_rtol > 0) else rtol
         res = gmres(op, M, -R.reshape(-1), restart=restart, rtol=lin_tol, max_iters=max_iters,
                     fixed_iters=fixed_iters)
         kry += res.iters
@@ -673,9 +677,12 @@ def implicit_step(sch, sigma, rho_cv, Un, dt, *, restart=30, rtol=1e-10, max_ite
         if clip > 0:
             delta = delta.copy()
             delta[0] = np.maximum(delta[0], -clip * U[0])
+            if sch.source == "coupled_t":
+                delta[sch.nrad] = np.maximum(delta[sch.nrad], -clip * U[sch.nrad])
+        rejected = False
         if line_search and fixed_iters == 0:
-            ref = max(hist[-5:])
-            lam, best = 1.0, None
+            ref = rn
+            lam, best, passed = 1.0, None, False
             for _ in range(8):
                 lin_t = linearize(sch, sigma, rho_cv, U + lam * delta, Un, dt)
                 R_t = residual(lin_t)
@@ -684,16 +691,23 @@ def implicit_step(sch, sigma, rho_cv, Un, dt, *, restart=30, rtol=1e-10, max_ite
                     best = (r_t, lam, lin_t, R_t)
                 if np.isfinite(r_t) and r_t <= (1.0 - 1e-4 * lam) * ref:
                     best = (r_t, lam, lin_t, R_t)
+                    passed = True
                     break
                 lam *= 0.5
-            r_new, lam, lin, R = best
-            U = U + lam * delta
+            if passed or psi0 <= 0:
+                r_new, lam, lin, R = best
+                U = U + lam * delta
+            else:
+                rejected = True          # keep U^k, lin and R; raise the shift
+                r_new = rn
         else:
             U = U + delta
             lin = linearize(sch, sigma, rho_cv, U, Un, dt)
             R = residual(lin)
             r_new = float(np.linalg.norm(R))
-        if psi > 0:
+        if rejected:
+            psi = max(10.0 * psi, 1e-3 * psi0)
+        elif psi > 0:
             psi = psi * r_new / rn if r_new < rn else 2.0 * psi
             if psi < 1e-6 * psi0:
                 psi = 0.0

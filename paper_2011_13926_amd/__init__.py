@@ -171,7 +171,7 @@ def kernel_classes():
 # high-level wrapper
 # ---------------------------------------------------------------------------
 def make_config(p, *, precision="fp64", pc="bj", restart=30, max_iters=20000, newton_max=20, fixed_iters=0,
-                rtol=1e-10, newton_rtol=None, inner_rtol=1e-6, basis_fp32=False, line_search=True,
+                rtol=1e-10, newton_rtol=None, inner_rtol=1e-6, basis_fp32=False, line_search=False,
                 ptc_psi0=0.0, ptc_rtol=0.0, positivity_clip=0.0):
     """m1_config from a problem description (the dict layout of ``workloads``)."""
     cfg = M1Config()

@@ -797,13 +797,11 @@ m1_status m1_implicit_step(m1_ctx* c, m1_state* U, double dt, m1_stats* stats) {
     c->lin_rtol = -1.0;
   };
   const bool line_search = (c->cfg.newton_flags & 1) && !fixed && c->Uprev;
-  std::vector<double> hist;
   double rn = 0.0;
   if ((st = evaluate(rn)) != M1_OK) { finish(); return st; }
   while (true) {
     if (r0 < 0) r0 = rn;
     rel = r0 > 0 ? rn / r0 : 0.0;
-    hist.push_back(rn);
     if (fixed) {
       if (it >= c->cfg.newton_max) { converged = true; break; }
     } else if (rn == 0.0 || (it > 0 && rel <= c->cfg.newton_rtol)) {
@@ -819,7 +817,7 @@ m1_status m1_implicit_step(m1_ctx* c, m1_state* U, double dt, m1_stats* stats) {
     }
     // pseudo-transient continuation: solve (A + psi M) delta = -R
     c->sc.psi = psi;
-    c->lin_rtol = (psi > 0 && c->cfg.ptc_rtol > 0) ? c->cfg.ptc_rtol : -1.0;
+    c->lin_rtol = (psi > 0 && c->cfg.ptc_rtol > 0) ? std::max(c->cfg.rtol, std::min(c->cfg.ptc_rtol, psi / psi0)) : -1.0;
     if ((st = ensure_bj(c)) != M1_OK) { finish(); return st; }
     SolveResult sr;
     if ((st = solve(c, rn, sr, fell_back)) != M1_OK) { finish(); return st; }
@@ -831,17 +829,17 @@ m1_status m1_implicit_step(m1_ctx* c, m1_state* U, double dt, m1_stats* stats) {
                    rel, psi, sr.iters, sr.restarts, sr.rel, sr.converged ? "" : " (not converged)");
     if (sr.nonfinite) { nonfinite = true; break; }
     double r_new = 0.0;
+    bool rejected = false;
     if (!line_search) {
       update(c->Uk, 1.0);
       if ((st = evaluate(r_new)) != M1_OK) { finish(); return st; }
     } else {
-      // non-monotone backtracking: the first lam in 1, 1/2, ..., 1/128 with
-      // ||R|| <= (1 - 1e-4 lam) max(last 5 accepted ||R||); else the best trial
+      // backtracking: the first lam in 1, 1/2, ..., 1/128 with ||R|| <= (1 - 1e-4 lam) ||R(U^k)||;
+      // if none passes the step is rejected (PTC) or the best trial is taken
       HIPCHK(c, hipMemcpyAsync(c->Uprev, c->Uk, sizeof(double) * c->n, hipMemcpyDeviceToDevice, c->stream));
-      const size_t h0 = hist.size() > 5 ? hist.size() - 5 : 0;
-      const double ref = *std::max_element(hist.begin() + h0, hist.end());
+      const double ref = rn;
       double lam = 1.0, best_r = 0.0, best_lam = 1.0, last_lam = 0.0;
-      bool have_best = false;
+      bool have_best = false, passed = false;
       for (int trial = 0; trial < 8; ++trial) {
         update(c->Uprev, lam);
         double rt = 0.0;
@@ -849,17 +847,29 @@ m1_status m1_implicit_step(m1_ctx* c, m1_state* U, double dt, m1_stats* stats) {
         last_lam = lam;
         if (verbose() > 1) std::fprintf(stderr, "[m1]     trial lam=%.4g |R|=%.6e (ref %.6e)\n", lam, rt, ref);
         if (!have_best || (std::isfinite(rt) && !(rt >= best_r))) { best_r = rt; best_lam = lam; have_best = true; }
-        if (std::isfinite(rt) && rt <= (1.0 - 1e-4 * lam) * ref) { best_r = rt; best_lam = lam; break; }
+        if (std::isfinite(rt) && rt <= (1.0 - 1e-4 * lam) * ref) { best_r = rt; best_lam = lam; passed = true; break; }
         lam *= 0.5;
       }
-      if (best_lam != last_lam) {
-        update(c->Uprev, best_lam);
-        if ((st = evaluate(best_r)) != M1_OK) { finish(); return st; }
+      if (!passed && psi0 > 0) {
+        // reject the step: back to U^k (re-evaluated), raise the shift and re-solve
+        rejected = true;
+        HIPCHK(c, hipMemcpyAsync(c->Uk, c->Uprev, sizeof(double) * c->n, hipMemcpyDeviceToDevice, c->stream));
+        double rk = 0.0;
+        if ((st = evaluate(rk)) != M1_OK) { finish(); return st; }
+        r_new = rn;
+        if (verbose()) std::fprintf(stderr, "[m1]   step rejected (best trial |R| %.3e vs %.3e)\n", best_r, rn);
+      } else {
+        if (best_lam != last_lam) {
+          update(c->Uprev, best_lam);
+          if ((st = evaluate(best_r)) != M1_OK) { finish(); return st; }
+        }
+        r_new = best_r;
+        if (verbose() && best_lam < 1.0) std::fprintf(stderr, "[m1]   line search: step %.4g, |R| %.3e -> %.3e\n", best_lam, rn, r_new);
       }
-      r_new = best_r;
-      if (verbose() && best_lam < 1.0) std::fprintf(stderr, "[m1]   line search: step %.4g, |R| %.3e -> %.3e\n", best_lam, rn, r_new);
     }
-    if (psi > 0) {
+    if (rejected) {
+      psi = std::max(10.0 * psi, 1e-3 * psi0);
+    } else if (psi > 0) {
       psi = r_new < rn ? psi * r_new / rn : 2.0 * psi;   // switched evolution relaxation
       if (psi < 1e-6 * psi0) psi = 0.0;
     }

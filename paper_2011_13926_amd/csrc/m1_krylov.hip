@@ -459,12 +459,15 @@ __global__ __launch_bounds__(256) void k_newton_update(int64_t N, int nu, double
   const int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   bool gt = false;
   if (cell < N) {
-    // positivity clip: the energy step is at least -clip E^k (clip = 0: off)
-    const double E0 = U0[cell];
-    double dE = dx[cell];
-    if (clip > 0.0) dE = fmax(dE, -clip * E0);
-    U[cell] = E0 + lam * dE;
-    for (int q = 1; q < nu; ++q) U[q * N + cell] = U0[q * N + cell] + lam * dx[q * N + cell];
+    // positivity clip: the energy (and temperature) step is at least -clip of the
+    // current value (clip = 0: off)
+    const int tq = (nu == ND + 2) ? nu - 1 : -1;   // T row index with the coupled source
+    for (int q = 0; q < nu; ++q) {
+      const double u0 = U0[q * N + cell];
+      double d = dx[q * N + cell];
+      if (clip > 0.0 && (q == 0 || q == tq)) d = fmax(d, -clip * u0);
+      U[q * N + cell] = u0 + lam * d;
+    }
     gt = f_gt_1<ND>(U, N, cell, c);
   }
   const unsigned long long ballot = __ballot(gt);

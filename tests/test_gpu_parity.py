@@ -166,7 +166,7 @@ SAME_ROOT_CASES = STEP_CASES[:2] + [((24, 20), BC2["periodic"], "absorption", "c
 
 @pytest.mark.parametrize("n,bc,src,fs", SAME_ROOT_CASES)
 def test_step_converged_with_globalization_same_root(n, bc, src, fs):
-    """PTC (psi0 = 1, loose linear tolerance while psi > 0), non-monotone line
+    """PTC (psi0 = 1, loose linear tolerance while psi > 0), line
     search and the positivity clip change the path only: the GPU's root agrees
     with the oracle's plain-Newton root to 1e-10 (both converged to 1e-13: the
     two paths differ, so each side's stopping error enters the comparison)."""

@@ -116,7 +116,7 @@ def test_picard_newton_reaches_the_root_of_the_full_nonlinear_residual():
 
 
 def test_globalised_newton_reaches_the_same_root():
-    """Pseudo-transient continuation, the non-monotone line search and the
+    """Pseudo-transient continuation, the line search and the
     positivity clip change the path, not the root: the globalised iteration ends
     at the root of the finite-difference dense Newton on the FULL residual."""
     p = W.random_problem((6, 5), 22, source="absorption", bc=BC2[1], dt=3.0, fmax=0.5)
@@ -149,7 +149,8 @@ def test_globalised_newton_reaches_the_same_root():
 def test_ptc_step_solves_the_shifted_system_and_clip_bounds_the_energy_step():
     """One Newton iteration with a full Krylov space (exact solve) and psi0 solves
     (A + psi0 M) delta = -R with M = 1 on the radiation rows and rho c_v on the T
-    row (assembled densely here); with the clip, dE = max(delta_E, -clip E)."""
+    row (assembled densely here); with the clip, dE = max(delta_E, -clip E) and
+    dT = max(delta_T, -clip T)."""
     p = W.random_problem((4, 3), 23, source="coupled_t", bc=BC2[1], dt=2.0, fmax=0.5)
     sch = O.Scheme.from_problem(p)
     Un = O.state_from_problem(p, "n")
@@ -164,11 +165,13 @@ def test_ptc_step_solves_the_shifted_system_and_clip_bounds_the_energy_step():
     assert np.linalg.norm(one.U - (Un + delta)) <= 1e-10 * np.linalg.norm(delta)
     clip = 0.01
     dE = np.maximum(delta[0], -clip * Un[0])
-    assert np.any(delta[0] < -clip * Un[0])          # the clip is active in this case
+    dT = np.maximum(delta[3], -clip * Un[3])
+    assert np.any(delta[0] < -clip * Un[0]) and np.any(delta[3] < -clip * Un[3])   # both clips act here
     cl = O.implicit_step(sch, sig, rc, Un, p["dt"], restart=nfull, newton_max=1, fixed_iters=nfull, psi0=psi0,
                          clip=clip)
     assert np.linalg.norm(cl.U[0] - (Un[0] + dE)) <= 1e-10 * np.linalg.norm(Un[0])
-    assert np.linalg.norm(cl.U[1:] - (Un[1:] + delta[1:])) <= 1e-10 * np.linalg.norm(delta[1:])
+    assert np.linalg.norm(cl.U[3] - (Un[3] + dT)) <= 1e-10 * np.linalg.norm(Un[3])
+    assert np.linalg.norm(cl.U[1:3] - (Un[1:3] + delta[1:3])) <= 1e-10 * np.linalg.norm(delta[1:3])
 
 
 def test_beam_shadow_roots_centred_source_positive_well_balanced_negative():
