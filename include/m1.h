@@ -206,8 +206,11 @@ const char* m1_last_error(const m1_ctx* ctx);
 
 /* Per-kernel-class timing with HIP events on the context's stream (for
  * measurement; off by default; enabling resets the counters).  For each class:
- * launches, summed event time (ms) and summed algorithmic bytes (each array
- * element a launch must read or write, counted once).  total_bytes may be NULL.
+ * timed launches, their summed event time (ms) and summed algorithmic bytes
+ * (each array element a launch must read or write, counted once).  Classes
+ * launched once per Krylov iteration (apply, block-Jacobi, fused apply, multi-dot,
+ * Hessenberg step, update, network) are timed on every 13th launch only, the
+ * others on every launch.  total_bytes may be NULL.
  * Class ids 0..m1_kernel_class_count()-1, names from m1_kernel_class_name. */
 m1_status m1_profile_enable(m1_ctx* ctx, int32_t on);
 m1_status m1_profile_query(m1_ctx* ctx, int32_t kclass, int64_t* launches, double* total_ms, double* total_bytes);

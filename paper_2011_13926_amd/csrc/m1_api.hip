@@ -33,6 +33,7 @@ struct Profiler {
   // phase 0: before the Hessenberg step of iteration `iter`, 1: after it, 2: final step.
   struct Rec { int kc; hipEvent_t a, b; double bytes; int iter; int phase; bool valid; };
   std::vector<Rec> pending;
+  int64_t seen[KC_COUNT] = {};   // launches issued while profiling, sampled or not
   int64_t launches[KC_COUNT] = {};
   double ms[KC_COUNT] = {};
   double bytes[KC_COUNT] = {};
@@ -70,6 +71,7 @@ struct m1_ctx {
   // Krylov workspace
   void* V = nullptr;
   int64_t n = 0;        // vector length n_u*N
+  int64_t vs = 0;       // stride between basis vectors: n rounded up to 64 elements (aligned quads)
   double* b = nullptr;
   double* x = nullptr;
   void* u[2] = {};
@@ -113,11 +115,25 @@ hipEvent_t prof_event(m1_ctx* c) {
   return p.pool[p.used++];
 }
 
+// Kernel classes launched once per Krylov iteration are timed on every 13th
+// launch only (13 is prime to the restart lengths, so every Arnoldi step j is
+// sampled over a solve); an event pair per launch would cost about a third of
+// the solver's run time at 512^2.  Other classes are timed on every launch.
+bool per_iteration_class(int kc) {
+  return kc == KC_APPLY || kc == KC_BJ || kc == KC_DOT || kc == KC_SCALAR || kc == KC_UPDATE || kc == KC_NN ||
+         kc == KC_APPLY_PC;
+}
+
 // Launch with optional HIP-event timing; `bytes` is the launch's algorithmic
 // HBM traffic (each array element the kernel must read or write, once).
 template <typename F>
 void timed(m1_ctx* c, int kc, double bytes, F&& launch, int iter = -1, int phase = 0) {
   if (!c->prof.on) {
+    launch();
+    return;
+  }
+  const int64_t seq = c->prof.seen[kc]++;
+  if (per_iteration_class(kc) && seq % 13 != 0) {
     launch();
     return;
   }
@@ -158,7 +174,6 @@ int nu_of(const m1_config& c) { return 1 + c.ndim + (c.source == M1_SRC_COUPLED_
 
 bool finite(double v) { return std::isfinite(v); }
 
-// M1_VERBOSE=1 in the environment prints one line per Newton iteration to stderr.
 // M1_VERBOSE=1: one line per Newton iteration on stderr; 2: also every GMRES
 // cycle and every line-search trial
 int verbose() {
@@ -408,7 +423,7 @@ template <typename TV, typename R>
 m1_status gmres(m1_ctx* c, double bnorm, SolveResult& res, const Coefs<R>& cfi) {
   const Bdry bd = bdry(c);
   const int64_t n = c->n;
-  const int64_t vs = n;
+  const int64_t vs = c->vs;
   TV* V = (TV*)c->V;
   TV* u[2] = {(TV*)c->u[0], (TV*)c->u[1]};
   TV* p = (TV*)c->p;
@@ -606,6 +621,7 @@ m1_status m1_setup(const m1_config* cfg, const m1_fields* fields, const m1_state
   sc.psi = 0.0;
   set_dt(c, U_lin ? dt : 1.0);
   c->n = (int64_t)c->nu * g.N;
+  c->vs = (c->n + 63) / 64 * 64;
   c->nb = dot_blocks(c->n);
 
   auto fail = [&](m1_status s) {
@@ -633,7 +649,7 @@ m1_status m1_setup(const m1_config* cfg, const m1_fields* fields, const m1_state
   const size_t rs = mixed(c) ? sizeof(float) : sizeof(double);
   {
     char* v = nullptr;
-    if ((st = dalloc(c, &v, (int64_t)(c->m + 1) * c->n * (int64_t)tvs)) != M1_OK) return fail(st);
+    if ((st = dalloc(c, &v, (int64_t)(c->m + 1) * c->vs * (int64_t)tvs)) != M1_OK) return fail(st);
     c->V = v;
     char* a = nullptr;
     if ((st = dalloc(c, &a, c->n * (int64_t)tvs)) != M1_OK) return fail(st);
@@ -647,7 +663,7 @@ m1_status m1_setup(const m1_config* cfg, const m1_fields* fields, const m1_state
   }
   if (cfg->pc == M1_PC_LEARNED) {
     char* a = nullptr;
-    if ((st = dalloc(c, &a, (int64_t)(c->m + 1) * c->n * (int64_t)rs)) != M1_OK) return fail(st);
+    if ((st = dalloc(c, &a, (int64_t)(c->m + 1) * c->vs * (int64_t)rs)) != M1_OK) return fail(st);
     c->Z = a;
     if ((st = dalloc(c, &a, c->n * (int64_t)rs)) != M1_OK) return fail(st);
     c->zt = a;
@@ -989,6 +1005,7 @@ m1_status m1_profile_enable(m1_ctx* c, int32_t on) {
   prof_collect(c);
   c->prof.on = on != 0;
   for (int k = 0; k < KC_COUNT; ++k) {
+    c->prof.seen[k] = 0;
     c->prof.launches[k] = 0;
     c->prof.ms[k] = 0.0;
     c->prof.bytes[k] = 0.0;

@@ -28,10 +28,19 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// Enough blocks to fill the chip, few enough that each thread streams several
+// quads and the partials (2j+2 values per block) stay small for the one-workgroup
+// Hessenberg step.  Measured at n = 786432 (FP32 and FP64 basis): 256..512 blocks
+// of quad loads run at 3.0 / 4.6 TB/s, 768..1024 blocks of scalar loads at
+// 1.6 / 3.2 TB/s.
 int dot_blocks(int64_t n) {
-  const int64_t per = (int64_t)kDotThreads * 4;
-  return (int)std::max<int64_t>(1, std::min<int64_t>(1024, (n + per - 1) / per));
+  const int64_t per = (int64_t)kDotThreads * 4 * 2;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(512, (n + per - 1) / per));
 }
+
+template <typename TV> struct Quad;
+template <> struct Quad<float> { using T = float4; };
+template <> struct Quad<double> { using T = double4; };
 
 // partial layout: value v of block b at part[v * nb + b];
 // values: s_i (i < J), then t_i (i < J) if HASP, then alpha, then gamma if HASP
@@ -76,10 +85,92 @@ __global__ __launch_bounds__(kDotThreads) void k_dot(const TV* __restrict__ V, i
   }
 }
 
+// Same sums with four consecutive elements per load (16-byte float4 or two
+// 16-byte halves of a double4): u, p and every basis vector must start on a
+// quad boundary (the basis stride is padded to 64 elements).  The n % 4 tail
+// elements are added by the first threads of block 0.  Each quad's four
+// products are summed first, then added to the accumulator (fixed order).
+template <int J, bool HASP, typename TV>
+__global__ __launch_bounds__(kDotThreads) void k_dot4(const TV* __restrict__ V, int64_t vs,
+                                                      const TV* __restrict__ u, const TV* __restrict__ p, int64_t n,
+                                                      double* __restrict__ part, int nb,
+                                                      const GmresState* __restrict__ gs) {
+  if (gs && gs->done) return;
+  using T4 = typename Quad<TV>::T;
+  constexpr int NV = HASP ? 2 * J + 2 : J + 1;
+  double acc[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+  const int64_t n4 = n >> 2;
+  const T4* u4 = reinterpret_cast<const T4*>(u);
+  const T4* p4 = reinterpret_cast<const T4*>(p);
+  for (int64_t e = (int64_t)blockIdx.x * kDotThreads + threadIdx.x; e < n4; e += (int64_t)nb * kDotThreads) {
+    const T4 uq = u4[e];
+    const double u0 = uq.x, u1 = uq.y, u2 = uq.z, u3 = uq.w;
+    double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0;
+    if (HASP) {
+      const T4 pq = p4[e];
+      p0 = pq.x; p1 = pq.y; p2 = pq.z; p3 = pq.w;
+    }
+#pragma unroll
+    for (int i = 0; i < J; ++i) {
+      const T4 q = reinterpret_cast<const T4*>(V + i * vs)[e];
+      const double q0 = q.x, q1 = q.y, q2 = q.z, q3 = q.w;
+      acc[i] += (q0 * u0 + q1 * u1) + (q2 * u2 + q3 * u3);
+      if (HASP) acc[J + i] += (q0 * p0 + q1 * p1) + (q2 * p2 + q3 * p3);
+    }
+    const double uu = (u0 * u0 + u1 * u1) + (u2 * u2 + u3 * u3);
+    if (HASP) {
+      acc[2 * J] += uu;
+      acc[2 * J + 1] += (u0 * p0 + u1 * p1) + (u2 * p2 + u3 * p3);
+    } else {
+      acc[J] += uu;
+    }
+  }
+  if (blockIdx.x == 0 && threadIdx.x < (int)(n - 4 * n4)) {
+    const int64_t e = 4 * n4 + threadIdx.x;
+    const double uv = (double)u[e];
+    const double pv = HASP ? (double)p[e] : 0.0;
+#pragma unroll
+    for (int i = 0; i < J; ++i) {
+      const double q = (double)V[i * vs + e];
+      acc[i] += q * uv;
+      if (HASP) acc[J + i] += q * pv;
+    }
+    if (HASP) {
+      acc[2 * J] += uv * uv;
+      acc[2 * J + 1] += uv * pv;
+    } else {
+      acc[J] += uv * uv;
+    }
+  }
+  __shared__ double red[kDotThreads / 64][NV > 0 ? NV : 1];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    const double t = wave_sum(acc[v]);
+    if (lane == 0) red[w][v] = t;
+  }
+  __syncthreads();
+  for (int v = threadIdx.x; v < NV; v += kDotThreads) {
+    double t = 0.0;
+#pragma unroll
+    for (int ww = 0; ww < kDotThreads / 64; ++ww) t += red[ww][v];
+    part[(int64_t)v * nb + blockIdx.x] = t;
+  }
+}
+
+template <typename TV>
+static bool quad_aligned(const TV* a) {
+  return (reinterpret_cast<uintptr_t>(a) % (4 * sizeof(TV))) == 0;
+}
+
 template <int J, bool HASP, typename TV>
 static void dot_one(const TV* V, int64_t vs, const TV* u, const TV* p, int64_t n, double* part, int nb,
                     const GmresState* gs, hipStream_t s) {
-  k_dot<J, HASP, TV><<<nb, kDotThreads, 0, s>>>(V, vs, u, p, n, part, nb, gs);
+  const bool quads = quad_aligned(u) && (!HASP || quad_aligned(p)) && (J == 0 || (quad_aligned(V) && vs % 4 == 0));
+  if (quads) k_dot4<J, HASP, TV><<<nb, kDotThreads, 0, s>>>(V, vs, u, p, n, part, nb, gs);
+  else k_dot<J, HASP, TV><<<nb, kDotThreads, 0, s>>>(V, vs, u, p, n, part, nb, gs);
 }
 
 template <typename TV, int... Js>
@@ -192,11 +283,14 @@ __global__ __launch_bounds__(kScalarThreads) void k_scalar(int j, int final_step
       }
       hc[j] = nu;
       rc[j] = nu;
+      // apply the previous rotations; the running element stays in a register
+      double carry = rc[0];
       for (int i = 0; i < c; ++i) {
-        const double a = sCs[i] * rc[i] + sSn[i] * rc[i + 1];
-        rc[i + 1] = -sSn[i] * rc[i] + sCs[i] * rc[i + 1];
-        rc[i] = a;
+        const double cs_i = sCs[i], sn_i = sSn[i], nxt = rc[i + 1];
+        rc[i] = cs_i * carry + sn_i * nxt;
+        carry = -sn_i * carry + cs_i * nxt;
       }
+      rc[c] = carry;
       const double den = sqrt(rc[c] * rc[c] + rc[j] * rc[j]);
       const double cs = den > 0.0 ? rc[c] / den : 1.0;
       const double sn = den > 0.0 ? rc[j] / den : 0.0;
