@@ -40,15 +40,31 @@ HBM_PEAK_GBS = 8000.0
 PROFILES = os.path.join(ROOT, "profiles")
 CSRC = os.path.join(ROOT, "paper_2011_13926_amd", "csrc")
 
-# profiler kernel class -> prefix of the HIP kernel's demangled name
+# profiler kernel class -> prefixes of the HIP kernels' names (without "void " and "m1::")
 CLASS_KERNEL = {
     "apply_bj_fused": ("k_apply2d_lds<false, 0, true", "k_apply2d_lds<true, 0, true", "k_apply3d_25d<false, 0, true",
                        "k_apply3d_25d<true, 0, true"),
     "apply": ("k_apply2d_lds<false, 0, false", "k_apply2d_lds<true, 0, false", "k_apply3d_25d<false, 0, false",
-              "k_apply3d_25d<true, 0, false", "void k_stencil"),
-    "arnoldi_dot": ("void k_dot",), "arnoldi_update": ("void k_update",), "arnoldi_scalar": ("k_scalar",),
-    "x_update": ("void k_xupdate",), "block_jacobi": ("void k_bj",),
+              "k_apply3d_25d<true, 0, false", "k_stencil<2, false, 0", "k_stencil<2, true, 0", "k_stencil<3, false, 0",
+              "k_stencil<3, true, 0"),
+    "arnoldi_dot": ("k_dot<", "k_dot4<"), "arnoldi_update": ("k_update<",), "arnoldi_scalar": ("k_scalar",),
+    "x_update": ("k_xupdate<",), "block_jacobi": ("k_bj<",),
+    "true_residual": ("k_apply2d_lds<false, 1", "k_apply2d_lds<true, 1", "k_apply3d_25d<false, 1",
+                      "k_apply3d_25d<true, 1", "k_stencil<2, false, 1", "k_stencil<2, true, 1", "k_stencil<3, false, 1",
+                      "k_stencil<3, true, 1"),
 }
+
+
+def _kname(nm):
+    return nm.split("(")[0].replace("void ", "").replace("m1::", "").strip()
+
+
+def kernel_class(nm):
+    k = _kname(nm)
+    for cls, prefs in CLASS_KERNEL.items():
+        if any(k.startswith(pf) for pf in prefs):
+            return cls
+    return k.split("<")[0]
 
 
 def source_hash():
@@ -187,48 +203,74 @@ def _counter_means(d, counter):
 
 
 def summarize_profiles(d, workload, commands):
-    """Write the committed summaries: the kernel-stats table and, per kernel, the HBM
-    bytes per dispatch from FETCH_SIZE / WRITE_SIZE (KiB) scaled by what the same
-    counters read for a plain device copy of known size."""
+    """Write the committed summaries: kernel statistics per kernel and per class
+    and, per kernel, the HBM bytes per dispatch from FETCH_SIZE / WRITE_SIZE (KiB)
+    scaled by what the same counters read for a plain device copy of known size.
+    Without counter CSVs under d the existing traffic summary is reused."""
     import csv
     rows = []
     for path in _csvs(os.path.join(d, "trace"), "kernel_stats.csv"):
         with open(path) as fh:
             rows += list(csv.DictReader(fh))
     rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
-    cf = _counter_means(os.path.join(d, "copy_fetch"), "FETCH_SIZE")
-    cw = _counter_means(os.path.join(d, "copy_write"), "WRITE_SIZE")
-    copy_bytes = float(1 << 30)
-    kf = max(cf.items(), key=lambda kv: kv[1][1])
-    kw = max(cw.items(), key=lambda kv: kv[1][1])
-    scale_f = copy_bytes / (kf[1][1] * 1024.0)
-    scale_w = copy_bytes / (kw[1][1] * 1024.0)
-    fetch = _counter_means(os.path.join(d, "fetch"), "FETCH_SIZE")
-    write = _counter_means(os.path.join(d, "write"), "WRITE_SIZE")
-    kernels = {}
-    for nm in sorted(set(fetch) | set(write)):
-        fn, fv = fetch.get(nm, (0, 0.0))
-        wn, wv = write.get(nm, (0, 0.0))
-        kernels[nm] = {"dispatches": max(fn, wn), "fetch_kib": fv, "write_kib": wv,
-                       "hbm_bytes_per_dispatch": fv * 1024.0 * scale_f + wv * 1024.0 * scale_w}
-    traffic = {"workload": workload, "source_sha256": source_hash(), "copy_kernel": kf[0],
-               "copy_fetch_kib": kf[1][1], "copy_write_kib": kw[1][1], "scale_fetch": scale_f,
-               "scale_write": scale_w, "kernels": kernels, "commands": commands}
-    os.makedirs(PROFILES, exist_ok=True)
-    with open(os.path.join(PROFILES, f"{workload}_traffic.json"), "w") as fh:
-        json.dump(traffic, fh, indent=1)
-    lines = [f"# rocprofv3 kernel statistics: {workload}", "", "Commands (run from the repository root):", "",
-             "```", commands.strip(), "```", "",
-             "| kernel | calls | total ms | avg us | % |", "|---|---|---|---|---|"]
+    tpath = os.path.join(PROFILES, f"{workload}_traffic.json")
+    if _csvs(os.path.join(d, "fetch"), "counter_collection.csv"):
+        cf = _counter_means(os.path.join(d, "copy_fetch"), "FETCH_SIZE")
+        cw = _counter_means(os.path.join(d, "copy_write"), "WRITE_SIZE")
+        copy_bytes = float(1 << 30)
+        kf = max(cf.items(), key=lambda kv: kv[1][1])
+        kw = max(cw.items(), key=lambda kv: kv[1][1])
+        scale_f = copy_bytes / (kf[1][1] * 1024.0)
+        scale_w = copy_bytes / (kw[1][1] * 1024.0)
+        fetch = _counter_means(os.path.join(d, "fetch"), "FETCH_SIZE")
+        write = _counter_means(os.path.join(d, "write"), "WRITE_SIZE")
+        kernels = {}
+        for nm in sorted(set(fetch) | set(write)):
+            fn, fv = fetch.get(nm, (0, 0.0))
+            wn, wv = write.get(nm, (0, 0.0))
+            kernels[nm] = {"dispatches": max(fn, wn), "fetch_kib": fv, "write_kib": wv,
+                           "hbm_bytes_per_dispatch": fv * 1024.0 * scale_f + wv * 1024.0 * scale_w}
+        traffic = {"workload": workload, "source_sha256": source_hash(), "copy_kernel": kf[0],
+                   "copy_fetch_kib": kf[1][1], "copy_write_kib": kw[1][1], "scale_fetch": scale_f,
+                   "scale_write": scale_w, "kernels": kernels, "commands": commands}
+        os.makedirs(PROFILES, exist_ok=True)
+        with open(tpath, "w") as fh:
+            json.dump(traffic, fh, indent=1)
+    with open(tpath) as fh:
+        traffic = json.load(fh)
+    kernels = traffic["kernels"]
+    fam = {}
+    for r in rows:
+        cls = kernel_class(r["Name"])
+        a = fam.setdefault(cls, [0, 0.0])
+        a[0] += int(r["Calls"])
+        a[1] += float(r["TotalDurationNs"])
+    tot = sum(v[1] for v in fam.values()) or 1.0
+    famb = {}
+    for nm, v in kernels.items():
+        b = famb.setdefault(kernel_class(nm), [0, 0.0])
+        b[0] += v["dispatches"]
+        b[1] += v["hbm_bytes_per_dispatch"] * v["dispatches"]
+    lines = [f"# rocprofv3 kernel statistics: {workload}", "", "Commands (run from the repository root; `<raw>` is a "
+             "scratch directory for rocprofv3's CSV output):", "", "```", commands.strip(), "```", "",
+             f"HIP sources SHA-256 when taken: `{traffic['source_sha256']}`", "",
+             "## By kernel class", "", "| class | calls | total ms | avg us | % of GPU time | HBM MB/dispatch |",
+             "|---|---|---|---|---|---|"]
+    for cls, (n, t) in sorted(fam.items(), key=lambda kv: -kv[1][1]):
+        hb = famb.get(cls)
+        hbs = f"{hb[1] / hb[0] / 1e6:.2f}" if hb and hb[0] else "-"
+        lines.append(f"| {cls} | {n} | {t / 1e6:.2f} | {t / n / 1e3:.2f} | {100 * t / tot:.1f} | {hbs} |")
+    lines += ["", "## By kernel (top 16 by time)", "", "| kernel | calls | total ms | avg us | % |", "|---|---|---|---|---|"]
     for r in rows[:16]:
-        lines.append(f"| `{r['Name'].split('(')[0][:100]}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.2f} | "
+        lines.append(f"| `{_kname(r['Name'])[:100]}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.2f} | "
                      f"{float(r['AverageNs']) / 1e3:.2f} | {float(r['Percentage']):.1f} |")
-    lines += ["", f"Copy calibration (1 GiB read + 1 GiB written per launch, `{kf[0]}`): FETCH_SIZE "
-              f"{kf[1][1]:.0f} KiB, WRITE_SIZE {kw[1][1]:.0f} KiB per dispatch -> scale {scale_f:.4f} (fetch), "
-              f"{scale_w:.4f} (write).", "", "| kernel | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB | HBM MB/dispatch |",
-              "|---|---|---|---|---|"]
+    lines += ["", f"## HBM traffic (FETCH_SIZE, WRITE_SIZE)", "",
+              f"Copy calibration (1 GiB read + 1 GiB written per launch, `{traffic['copy_kernel']}`): FETCH_SIZE "
+              f"{traffic['copy_fetch_kib']:.0f} KiB, WRITE_SIZE {traffic['copy_write_kib']:.0f} KiB per dispatch -> "
+              f"scale {traffic['scale_fetch']:.4f} (fetch), {traffic['scale_write']:.4f} (write).", "",
+              "| kernel | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB | HBM MB/dispatch |", "|---|---|---|---|---|"]
     for nm, v in sorted(kernels.items(), key=lambda kv: -kv[1]["hbm_bytes_per_dispatch"] * kv[1]["dispatches"])[:12]:
-        lines.append(f"| `{nm[:100]}` | {v['dispatches']} | {v['fetch_kib']:.0f} | {v['write_kib']:.0f} | "
+        lines.append(f"| `{_kname(nm)[:100]}` | {v['dispatches']} | {v['fetch_kib']:.0f} | {v['write_kib']:.0f} | "
                      f"{v['hbm_bytes_per_dispatch'] / 1e6:.2f} |")
     with open(os.path.join(PROFILES, f"{workload}_kernels.md"), "w") as fh:
         fh.write("\n".join(lines) + "\n")
@@ -245,8 +287,7 @@ def measured_traffic(workload, cls):
         t = json.load(fh)
     if t.get("source_sha256") != source_hash():
         return None
-    pref = CLASS_KERNEL.get(cls, ())
-    hits = [v for nm, v in t["kernels"].items() if any(nm.startswith(pf) or nm.startswith("void " + pf) for pf in pref)]
+    hits = [v for nm, v in t["kernels"].items() if kernel_class(nm) == cls]
     if not hits:
         return None
     n = sum(v["dispatches"] for v in hits)

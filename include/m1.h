@@ -135,6 +135,9 @@ typedef struct {
                               psi > 0 (0: rtol throughout) */
   double positivity_clip;  /* in [0, 1): each Newton update lowers a cell's E (and T) by at most
                               this fraction (dE >= -clip E^k, dT >= -clip T^k); 0: off */
+  double newton_forcing;   /* > 0: inexact Newton (Eisenstat & Walker 1996 in spirit): iteration k
+                              solves to max(rtol, min(0.1, newton_forcing ||R_k||/||R_0||)); the
+                              looser of this and the PTC tolerance applies; 0: rtol */
   const char* nn_weights_path; /* host string or NULL (learned preconditioner) */
 } m1_config;
 

@@ -601,7 +601,7 @@ def mass_diagonal(sch, rho_cv):
 
 def implicit_step(sch, sigma, rho_cv, Un, dt, *, restart=30, rtol=1e-10, max_iters=20000,
                   newton_max=20, newton_rtol=None, fixed_iters=0, pc="bj",
-                  psi0=0.0, ptc_rtol=0.0, line_search=False, clip=0.0):
+                  psi0=0.0, ptc_rtol=0.0, line_search=False, clip=0.0, forcing=0.0):
     """Advance Un by one backward-Euler step (Sect. 3.1, Sect. 3.3.1).
 
     Newton loop: linearise at U^k, b = -R(U^k); stop when
@@ -609,7 +609,7 @@ def implicit_step(sch, sigma, rho_cv, Un, dt, *, restart=30, rtol=1e-10, max_ite
     set U^{k+1} = U^k + delta.  With fixed_iters > 0 exactly newton_max linear
     solves of exactly fixed_iters GMRES iterations are made (no early exit).
 
-    Three optional safeguards change the path to the root, never the root
+    Four optional additions change the path to the root, never the root
     itself (the residual R is untouched).  They are solver additions; the
     paper's Newton iteration has none of them:
 
@@ -622,6 +622,8 @@ def implicit_step(sch, sigma, rho_cv, Un, dt, *, restart=30, rtol=1e-10, max_ite
       1e-6 psi0.  While psi > 0 and ptc_rtol > 0 the linear tolerance is
       max(rtol, min(ptc_rtol, psi/psi0)): loose while far from the root,
       tightening with the residual.
+    * forcing > 0: inexact Newton; iteration k solves to max(rtol, min(0.1,
+      forcing ||R_k||/||R_0||)) (with PTC the looser of the two tolerances).
     * clip in (0, 1): before the update, dE (and dT with the T row) is raised to
       at least -clip E (-clip T) per cell: the energy and temperature of a cell
       drop by at most that fraction in one update.
@@ -668,7 +670,11 @@ def implicit_step(sch, sigma, rho_cv, Un, dt, *, restart=30, rtol=1e-10, max_ite
             op = lambda v: apply_operator(lin, v)
         else:
             op = lambda v, sh=shift.reshape(-1): apply_operator(lin, v) + sh * v
-        lin_tol = max(rtol, min(ptc_rtol, psi / psi0)) if (psi > 0 and ptc_rtol > 0) else rtol
+        lin_tol = rtol
+        if forcing > 0:
+            lin_tol = max(lin_tol, min(0.1, forcing * rel))
+        if psi > 0 and ptc_rtol > 0:
+            lin_tol = max(lin_tol, min(ptc_rtol, psi / psi0))
         res = gmres(op, M, -R.reshape(-1), restart=restart, rtol=lin_tol, max_iters=max_iters,
                     fixed_iters=fixed_iters)
         kry += res.iters

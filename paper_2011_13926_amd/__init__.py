@@ -52,7 +52,8 @@ class M1Config(ctypes.Structure):
         ("restart", ctypes.c_int32), ("max_iters", ctypes.c_int32), ("newton_max", ctypes.c_int32),
         ("fixed_iters", ctypes.c_int32), ("basis_fp32", ctypes.c_int32), ("rtol", ctypes.c_double),
         ("newton_rtol", ctypes.c_double), ("inner_rtol", ctypes.c_double), ("ptc_psi0", ctypes.c_double),
-        ("ptc_rtol", ctypes.c_double), ("positivity_clip", ctypes.c_double), ("nn_weights_path", ctypes.c_char_p),
+        ("ptc_rtol", ctypes.c_double), ("positivity_clip", ctypes.c_double), ("newton_forcing", ctypes.c_double),
+        ("nn_weights_path", ctypes.c_char_p),
     ]
 
 
@@ -172,7 +173,7 @@ def kernel_classes():
 # ---------------------------------------------------------------------------
 def make_config(p, *, precision="fp64", pc="bj", restart=30, max_iters=20000, newton_max=20, fixed_iters=0,
                 rtol=1e-10, newton_rtol=None, inner_rtol=1e-6, basis_fp32=False, line_search=False,
-                ptc_psi0=0.0, ptc_rtol=0.0, positivity_clip=0.0):
+                ptc_psi0=0.0, ptc_rtol=0.0, positivity_clip=0.0, newton_forcing=0.0):
     """m1_config from a problem description (the dict layout of ``workloads``)."""
     cfg = M1Config()
     cfg.ndim = p["ndim"]
@@ -196,6 +197,7 @@ def make_config(p, *, precision="fp64", pc="bj", restart=30, max_iters=20000, ne
     cfg.newton_rtol = rtol if newton_rtol is None else newton_rtol
     cfg.inner_rtol = inner_rtol
     cfg.ptc_psi0, cfg.ptc_rtol, cfg.positivity_clip = ptc_psi0, ptc_rtol, positivity_clip
+    cfg.newton_forcing = newton_forcing
     cfg.nn_weights_path = None
     return cfg
 

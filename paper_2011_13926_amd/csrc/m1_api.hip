@@ -229,8 +229,9 @@ m1_status validate_config(const m1_config* c, std::string& err) {
     return M1_ERR_INVALID_ARG;
   }
   if (!(finite(c->ptc_psi0) && c->ptc_psi0 >= 0) || !(finite(c->ptc_rtol) && c->ptc_rtol >= 0 && c->ptc_rtol < 1) ||
-      !(finite(c->positivity_clip) && c->positivity_clip >= 0 && c->positivity_clip < 1)) {
-    err = "ptc_psi0 must be finite and >= 0; ptc_rtol and positivity_clip in [0, 1)";
+      !(finite(c->positivity_clip) && c->positivity_clip >= 0 && c->positivity_clip < 1) ||
+      !(finite(c->newton_forcing) && c->newton_forcing >= 0)) {
+    err = "ptc_psi0 and newton_forcing must be finite and >= 0; ptc_rtol and positivity_clip in [0, 1)";
     return M1_ERR_INVALID_ARG;
   }
   return M1_OK;
@@ -833,7 +834,11 @@ m1_status m1_implicit_step(m1_ctx* c, m1_state* U, double dt, m1_stats* stats) {
     }
     // pseudo-transient continuation: solve (A + psi M) delta = -R
     c->sc.psi = psi;
-    c->lin_rtol = (psi > 0 && c->cfg.ptc_rtol > 0) ? std::max(c->cfg.rtol, std::min(c->cfg.ptc_rtol, psi / psi0)) : -1.0;
+    // linear tolerance: rtol, loosened by the forcing term and by PTC (the looser applies)
+    double eta = c->cfg.rtol;
+    if (c->cfg.newton_forcing > 0) eta = std::max(eta, std::min(0.1, c->cfg.newton_forcing * rel));
+    if (psi > 0 && c->cfg.ptc_rtol > 0) eta = std::max(eta, std::min(c->cfg.ptc_rtol, psi / psi0));
+    c->lin_rtol = eta;
     if ((st = ensure_bj(c)) != M1_OK) { finish(); return st; }
     SolveResult sr;
     if ((st = solve(c, rn, sr, fell_back)) != M1_OK) { finish(); return st; }

@@ -547,13 +547,34 @@ __global__ __launch_bounds__(256) void k_stencil(Geom g, Scheme sc, Coefs<R> cf,
 }
 
 // ----------------------------------------------------------------------------
-// a3, 2D, LDS-staged: a block owns a 64 x 8 tile; its (66 x 10) halo tile of the
-// input vector x and of the linearised pressure q = (J x) for the three
+// a3, 2D, LDS-staged: a block owns a 64 x 16 tile; its (66 x 18) halo tile of
+// the input vector x and of the linearised pressure q = (J x) for the three
 // independent pairs (xx, xy, yy) is computed once into LDS (ghosts included),
 // then every cell assembles its fluxes from LDS.  Each input element and each
 // Jacobian entry is read from memory once per tile instead of once per use.
+//
+// Tile order: workgroups go to the 8 XCDs round-robin by launch index, and each
+// XCD has its own L2.  Launch index L takes tile (L % 8) * per + L / 8 of the
+// row-major tile order (per = tiles / 8, rounded up), so every XCD works on a
+// contiguous band of tiles and the halo lines that neighbouring tiles share
+// meet in the same L2 instead of being fetched once per XCD.
 // ----------------------------------------------------------------------------
-constexpr int LX = 64, LY = 8, LHX = LX + 2, LHY = LY + 2;
+constexpr int LX = 64, LY = 16, LHX = LX + 2, LHY = LY + 2;
+
+__host__ __device__ inline int tiles2d(int nx, int ny) { return ((nx + LX - 1) / LX) * ((ny + LY - 1) / LY); }
+inline dim3 grid2d_xcd(const Geom& g) { return dim3(8 * ((tiles2d(g.n[0], g.n[1]) + 7) / 8)); }
+
+// tile (tbx, tby) of this workgroup; false for the padding workgroups
+__device__ __forceinline__ bool xcd_tile(int nx, int ny, int& tbx, int& tby) {
+  const int gx = (nx + LX - 1) / LX;
+  const int gt = tiles2d(nx, ny);
+  const int per = (gt + 7) / 8;
+  const int T = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+  if (T >= gt) return false;
+  tbx = T % gx;
+  tby = T / gx;
+  return true;
+}
 
 // PRE = true: the input is u and the operator is applied to z = M^{-1} u, the
 // block-Jacobi solve done per staged cell (fused right preconditioning).
@@ -569,7 +590,9 @@ __global__ __launch_bounds__(256) void k_apply2d_lds(Geom g, Scheme sc, Coefs<R>
   __shared__ R ss[LHY][LHX];
   const int64_t N = g.N;
   const int nx = g.n[0], ny = g.n[1];
-  const int i0 = blockIdx.x * LX - 1, j0 = blockIdx.y * LY - 1;
+  int tbx, tby;
+  if (!xcd_tile(nx, ny, tbx, tby)) return;
+  const int i0 = tbx * LX - 1, j0 = tby * LY - 1;
   // ---- stage the halo tile ----
   for (int t = threadIdx.x; t < LHX * LHY; t += 256) {
     const int li = t % LHX, lj = t / LHX;
@@ -638,7 +661,7 @@ __global__ __launch_bounds__(256) void k_apply2d_lds(Geom g, Scheme sc, Coefs<R>
   const R s = (R)sc.s;
   const R cdt = (R)sc.cdt;
   for (int ty = threadIdx.x / LX; ty < LY; ty += 256 / LX) {
-    const int i = blockIdx.x * LX + tx, j = blockIdx.y * LY + ty;
+    const int i = tbx * LX + tx, j = tby * LY + ty;
     if (i >= nx || j >= ny) continue;
     const int64_t cell = (int64_t)j * nx + i;
     const int li = tx + 1, lj = ty + 1;
@@ -1019,7 +1042,7 @@ template <typename R, typename VI, typename VO>
 void launch_apply(int nd, bool cpl, int mode, const Geom& g, const Scheme& sc, const Coefs<R>& cf, const Bdry& bd,
                   const VI* x, const double* b, VO* y, hipStream_t s, const int* skip) {
   if (nd == 2 && use_lds_2d()) {
-    dim3 grd2((g.n[0] + LX - 1) / LX, (g.n[1] + LY - 1) / LY);
+    const dim3 grd2 = grid2d_xcd(g);
 #define M1_LDS(CPL_, MODE_) k_apply2d_lds<CPL_, MODE_, false, R, VI, VO><<<grd2, 256, 0, s>>>(g, sc, cf, bd, x, b, y, skip)
     if (cpl) { if (mode == 0) M1_LDS(true, 0); else M1_LDS(true, 1); }
     else { if (mode == 0) M1_LDS(false, 0); else M1_LDS(false, 1); }
@@ -1116,7 +1139,7 @@ bool launch_apply_pre(int nd, bool cpl, const Geom& g, const Scheme& sc, const C
     return true;
   }
   if (nd != 2) return false;
-  dim3 grd2((g.n[0] + LX - 1) / LX, (g.n[1] + LY - 1) / LY);
+  const dim3 grd2 = grid2d_xcd(g);
   if (cpl) k_apply2d_lds<true, 0, true, R, VI, VO><<<grd2, 256, 0, s>>>(g, sc, cf, bd, u, nullptr, y, skip);
   else k_apply2d_lds<false, 0, true, R, VI, VO><<<grd2, 256, 0, s>>>(g, sc, cf, bd, u, nullptr, y, skip);
   return true;

@@ -226,7 +226,9 @@ __global__ __launch_bounds__(kScalarThreads) void k_scalar(int j, int final_step
     }
     psum[tid] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
   }
-  // (2) stage the small GMRES state in LDS
+  // (2) stage the small GMRES state in LDS (the serial part below makes no
+  // global loads: each would stall the one thread for a memory round trip)
+  const double tol = gs->tol;
   for (int t = tid; t < j * kLd; t += kScalarThreads) {
     sH[t] = gs->Hraw[t];
     sR[t] = gs->Rm[t];
@@ -274,6 +276,7 @@ __global__ __launch_bounds__(kScalarThreads) void k_scalar(int j, int final_step
       }
       nu = (nu2 > 1e-28 * col2) ? sqrt(nu2) : 0.0;
       if (nu == 0.0) gs->breakdown = 1;
+      bool nonfinite = false;
       const int c = j - 1;
       double* hc = sH + c * kLd;
       double* rc = sR + c * kLd;
@@ -302,8 +305,11 @@ __global__ __launch_bounds__(kScalarThreads) void k_scalar(int j, int final_step
       sG[c] = cs * sG[c];
       const double est = fabs(sG[j]);
       gs->est = est;
-      if (!(est == est) || !(den == den)) gs->nonfinite = 1;
-      if (est <= gs->tol || nu == 0.0 || final_step || gs->nonfinite) {
+      if (!(est == est) || !(den == den)) {
+        gs->nonfinite = 1;
+        nonfinite = true;
+      }
+      if (est <= tol || nu == 0.0 || final_step || nonfinite) {
         done = 1;
         k = j;
         // back substitution R y = g
@@ -400,11 +406,73 @@ __global__ __launch_bounds__(kDotThreads) void k_update(TV* __restrict__ V, int6
   }
 }
 
+// Same update on quads (one 16-byte FP32 or two 16-byte FP64 accesses per
+// vector per thread); operands quad-aligned, the n % 4 tail done by block 0.
+template <int J, typename TV>
+__global__ __launch_bounds__(kDotThreads) void k_update4(TV* __restrict__ V, int64_t vs, const TV* __restrict__ u,
+                                                         const TV* __restrict__ p, TV* __restrict__ unext, int64_t n,
+                                                         const GmresState* __restrict__ gs) {
+  if (gs->done) return;
+  using T4 = typename Quad<TV>::T;
+  double cs_[J > 0 ? J : 1], ct_[J > 0 ? J : 1];
+#pragma unroll
+  for (int i = 0; i < J; ++i) {
+    cs_[i] = gs->coef_s[i];
+    ct_[i] = gs->coef_t[i];
+  }
+  const double cc = gs->cc, inv = gs->inv_nu;
+  TV* __restrict__ qj = V + (int64_t)J * vs;
+  const int64_t n4 = n >> 2;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n4; e += (int64_t)gridDim.x * blockDim.x) {
+    const T4 uq = reinterpret_cast<const T4*>(u)[e];
+    const T4 pq = reinterpret_cast<const T4*>(p)[e];
+    double a1[4] = {(double)uq.x, (double)uq.y, (double)uq.z, (double)uq.w};
+    double a2[4] = {(double)pq.x - cc * a1[0], (double)pq.y - cc * a1[1], (double)pq.z - cc * a1[2],
+                    (double)pq.w - cc * a1[3]};
+#pragma unroll
+    for (int i = 0; i < J; ++i) {
+      const T4 q = reinterpret_cast<const T4*>(V + i * vs)[e];
+      const double qv[4] = {(double)q.x, (double)q.y, (double)q.z, (double)q.w};
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        a1[k] -= cs_[i] * qv[k];
+        a2[k] -= ct_[i] * qv[k];
+      }
+    }
+    T4 o1, o2;
+    o1.x = (TV)(a1[0] * inv); o1.y = (TV)(a1[1] * inv); o1.z = (TV)(a1[2] * inv); o1.w = (TV)(a1[3] * inv);
+    o2.x = (TV)(a2[0] * inv); o2.y = (TV)(a2[1] * inv); o2.z = (TV)(a2[2] * inv); o2.w = (TV)(a2[3] * inv);
+    reinterpret_cast<T4*>(qj)[e] = o1;
+    reinterpret_cast<T4*>(unext)[e] = o2;
+  }
+  if (blockIdx.x == 0 && threadIdx.x < (int)(n - 4 * n4)) {
+    const int64_t e = 4 * n4 + threadIdx.x;
+    const double uv = (double)u[e];
+    double a1 = uv;
+    double a2 = (double)p[e] - cc * uv;
+#pragma unroll
+    for (int i = 0; i < J; ++i) {
+      const double q = (double)V[i * vs + e];
+      a1 -= cs_[i] * q;
+      a2 -= ct_[i] * q;
+    }
+    qj[e] = (TV)(a1 * inv);
+    unext[e] = (TV)(a2 * inv);
+  }
+}
+
 template <int J, typename TV>
 static void upd_one(TV* V, int64_t vs, const TV* u, const TV* p, TV* un, int64_t n, const GmresState* gs,
                     hipStream_t s) {
-  const int nb = dot_blocks(n);
-  k_update<J, TV><<<nb, kDotThreads, 0, s>>>(V, vs, u, p, un, n, gs);
+  const bool quads = quad_aligned(u) && quad_aligned(p) && quad_aligned(un) && quad_aligned(V) && vs % 4 == 0;
+  if (quads) {
+    const int64_t n4 = n >> 2;
+    const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(8192, (n4 + kDotThreads - 1) / kDotThreads));
+    k_update4<J, TV><<<nb, kDotThreads, 0, s>>>(V, vs, u, p, un, n, gs);
+  } else {
+    const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(8192, (n + kDotThreads - 1) / kDotThreads));
+    k_update<J, TV><<<nb, kDotThreads, 0, s>>>(V, vs, u, p, un, n, gs);
+  }
 }
 
 template <typename TV, int... Js>

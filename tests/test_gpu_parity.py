@@ -166,8 +166,8 @@ SAME_ROOT_CASES = STEP_CASES[:2] + [((24, 20), BC2["periodic"], "absorption", "c
 
 @pytest.mark.parametrize("n,bc,src,fs", SAME_ROOT_CASES)
 def test_step_converged_with_globalization_same_root(n, bc, src, fs):
-    """PTC (psi0 = 1, loose linear tolerance while psi > 0), line
-    search and the positivity clip change the path only: the GPU's root agrees
+    """PTC (psi0 = 1, loose linear tolerance while psi > 0), the inexact-Newton
+    forcing term, line search and the positivity clip change the path only: the GPU's root agrees
     with the oracle's plain-Newton root to 1e-10 (both converged to 1e-13: the
     two paths differ, so each side's stopping error enters the comparison)."""
     import paper_2011_13926_amd as P
@@ -179,7 +179,7 @@ def test_step_converged_with_globalization_same_root(n, bc, src, fs):
                           newton_max=120)
     assert ref.converged
     s = P.Solver(p, rtol=1e-13, newton_rtol=1e-13, newton_max=160, ptc_psi0=1.0, ptc_rtol=1e-3,
-                 positivity_clip=0.5, line_search=True)
+                 positivity_clip=0.5, line_search=True, newton_forcing=1.0)
     try:
         U = s.to_device(Un)
         st, stats = s.implicit_step(U)

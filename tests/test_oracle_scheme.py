@@ -144,6 +144,10 @@ def test_globalised_newton_reaches_the_same_root():
                            psi0=1.0, ptc_rtol=1e-3, line_search=True, clip=0.5)
     assert step.converged
     assert np.linalg.norm(u - step.U.reshape(-1)) <= 1e-10 * np.linalg.norm(u)
+    inexact = O.implicit_step(sch, sig, None, Un, p["dt"], rtol=1e-14, newton_rtol=1e-13, newton_max=150,
+                              forcing=1.0, line_search=True)
+    assert inexact.converged
+    assert np.linalg.norm(u - inexact.U.reshape(-1)) <= 1e-10 * np.linalg.norm(u)
 
 
 def test_ptc_step_solves_the_shifted_system_and_clip_bounds_the_energy_step():
