@@ -69,12 +69,12 @@ def generate_pairs(P, torch, p, steps, newton_max=6, rtol=1e-10, partial=(30, 90
     return pairs
 
 
-def train(P, torch, pairs, iters, lr=1e-3, seed=0, net=None, n=512, log_every=100):
+def train(P, torch, pairs, iters, lr=1e-3, seed=0, net=None, n=512, log_every=100, channels=CHANNELS):
     from oracle import nn_oracle as N  # initial weights only (He-normal draw)
     if net is None:
-        net = P.Net(9, 3, CHANNELS, Hmax=n, Wmax=n)
-        params = N.init_params(9, list(CHANNELS), 3, seed=seed, head_scale=0.1)
-        net.set_params(N.flatten_params(params, 9, list(CHANNELS), 3).astype(np.float32))
+        net = P.Net(9, 3, channels, Hmax=n, Wmax=n)
+        params = N.init_params(9, list(channels), 3, seed=seed, head_scale=0.1)
+        net.set_params(N.flatten_params(params, 9, list(channels), 3).astype(np.float32))
     rng = np.random.default_rng(seed)
     hist = []
     for it in range(iters):
@@ -85,6 +85,16 @@ def train(P, torch, pairs, iters, lr=1e-3, seed=0, net=None, n=512, log_every=10
         if log_every and (it % log_every == 0 or it == iters - 1):
             _log(f"iter {it} loss {np.mean(hist[-log_every:]):.4f}")
     return net, hist
+
+
+def heldout_loss(torch, net, pairs):
+    """Mean relative loss ||NN(x) - t||^2 / ||t||^2 on pairs not used for training."""
+    vals = []
+    for f, t in pairs:
+        y = net.forward(f)
+        tt = torch.as_tensor(t, dtype=torch.float32, device=y.device)
+        vals.append(float(((y - tt) ** 2).sum() / (tt ** 2).sum().clamp_min(1e-300)))
+    return float(np.mean(vals)) if vals else float("nan")
 
 
 def evaluate(P, torch, net, seeds, n=512, rtol=1e-8, dt=100.0):
@@ -129,7 +139,10 @@ def main():
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--n", type=int, default=512)
     ap.add_argument("--report", default=None)
+    ap.add_argument("--channels", default=",".join(str(c) for c in CHANNELS))
+    ap.add_argument("--no-solve-eval", action="store_true", help="skip the FGMRES comparison on held-out seeds")
     args = ap.parse_args()
+    channels = tuple(int(v) for v in args.channels.split(","))
     import torch
 
     import paper_2011_13926_amd as P
@@ -139,12 +152,18 @@ def main():
     for seed in _seeds(args.train):
         pairs += generate_pairs(P, torch, problem(seed, args.n), args.steps)
         _log(f"seed {seed}: {len(pairs)} pairs ({time.perf_counter() - t0:.1f}s)")
-    net, hist = train(P, torch, pairs, args.iters, lr=args.lr, n=args.n)
+    held = []
+    for seed in _seeds(args.heldout):
+        held += generate_pairs(P, torch, problem(seed, args.n), 1, newton_max=2)
+    net, hist = train(P, torch, pairs, args.iters, lr=args.lr, n=args.n, channels=channels)
     net.save(args.out)
     _log(f"saved {args.out} after {time.perf_counter() - t0:.1f}s")
-    ev = evaluate(P, torch, net, _seeds(args.heldout), args.n)
-    rep = {"pairs": len(pairs), "iters": args.iters, "loss_first100": float(np.mean(hist[:100])),
-           "loss_last100": float(np.mean(hist[-100:])), "heldout": ev}
+    hl = heldout_loss(torch, net, held)
+    _log(f"held-out loss {hl:.4f} on {len(held)} pairs")
+    ev = [] if args.no_solve_eval else evaluate(P, torch, net, _seeds(args.heldout), args.n)
+    rep = {"pairs": len(pairs), "iters": args.iters, "channels": list(channels),
+           "loss_first100": float(np.mean(hist[:100])), "loss_last100": float(np.mean(hist[-100:])),
+           "heldout_pairs": len(held), "heldout_loss": hl, "heldout": ev}
     if args.report:
         with open(args.report, "w") as fh:
             json.dump(rep, fh, indent=1)
