@@ -148,22 +148,29 @@ def run_variant(P, torch, p, U0, name, args):
     opts = dict(VARIANTS[name], restart=30, **WORKLOADS[args.workload]["solver"])
     s = P.Solver(p, **opts)
     try:
-        U = s.to_device(U0)
+        U0d = s.to_device(U0)
+        U = U0d.clone()
         for _ in range(args.warmup):
+            U.copy_(U0d)
             st, _ = s.implicit_step(U, raise_on_fail=False)
             print(f"[bench] {name} warmup step status={st}", file=sys.stderr, flush=True)
         torch.cuda.synchronize()
         s.profile_enable(not args.no_events)
         stats = []
-        t0 = time.perf_counter()
+        wall = 0.0
+        # every timed step is the same implicit step on the same input (restored
+        # from U^n outside the timed interval)
         for k in range(args.steps):
+            U.copy_(U0d)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
             st, sd = s.implicit_step(U, raise_on_fail=False)
+            torch.cuda.synchronize()
+            wall += time.perf_counter() - t0
             sd["status"] = st
             stats.append(sd)
             print(f"[bench] {name} step {k} status={st} newton={sd['newton_iters']} krylov={sd['krylov_iters']} "
-                  f"{sd['seconds']:.3f}s", file=sys.stderr, flush=True)
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
+                  f"{sd['seconds']:.3f}s min E of U^(n+1) {float(U[0].min()):.3e}", file=sys.stderr, flush=True)
         prof = s.profile() if not args.no_events else {}
         s.profile_enable(False)
     finally:
