@@ -30,11 +30,11 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 // Enough blocks to fill the chip, few enough that each thread streams several
 // quads and the partials (2j+2 values per block) stay small for the one-workgroup
-// Hessenberg step.  Measured at n = 786432 (FP32 and FP64 basis): 256..512 blocks
-// of quad loads run at 3.0 / 4.6 TB/s, 768..1024 blocks of scalar loads at
-// 1.6 / 3.2 TB/s.
+// Hessenberg step.  Measured at n = 786432 (FP32 and FP64 basis): 256 blocks of
+// quad loads with the LDS block reduction run at 4.8 / 5.9 TB/s; scalar loads
+// with 768..1024 blocks at 1.6 / 3.2 TB/s.
 int dot_blocks(int64_t n) {
-  const int64_t per = (int64_t)kDotThreads * 4 * 2;
+  const int64_t per = (int64_t)kDotThreads * 4 * 3;
   return (int)std::max<int64_t>(1, std::min<int64_t>(512, (n + per - 1) / per));
 }
 
@@ -144,19 +144,35 @@ __global__ __launch_bounds__(kDotThreads) void k_dot4(const TV* __restrict__ V, 
       acc[J] += uv * uv;
     }
   }
-  __shared__ double red[kDotThreads / 64][NV > 0 ? NV : 1];
+  // block reduction: fold each wavefront's lanes to 16 (two exchanges per
+  // value), park the 4 x 16 folded sums of every value in LDS, then four threads
+  // per value add 16 each and fold; a full six-step exchange per value cost as
+  // much as the loads themselves (measured 17.7 -> 11.2 us at n = 786432, FP32)
+  __shared__ double lds[NV > 0 ? NV : 1][65];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
-    const double t = wave_sum(acc[v]);
-    if (lane == 0) red[w][v] = t;
+    double a = acc[v];
+    a += __shfl_xor(a, 32, 64);
+    a += __shfl_xor(a, 16, 64);
+    acc[v] = a;
+  }
+  if (lane < 16) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) lds[v][w * 16 + lane] = acc[v];
   }
   __syncthreads();
-  for (int v = threadIdx.x; v < NV; v += kDotThreads) {
-    double t = 0.0;
+  for (int base = 0; base < NV * 4; base += kDotThreads) {
+    const int idx = base + threadIdx.x;
+    const int v = idx >> 2, q = idx & 3;
+    double a = 0.0;
+    if (v < NV) {
 #pragma unroll
-    for (int ww = 0; ww < kDotThreads / 64; ++ww) t += red[ww][v];
-    part[(int64_t)v * nb + blockIdx.x] = t;
+      for (int k = 0; k < 16; ++k) a += lds[v][q * 16 + k];
+    }
+    a += __shfl_xor(a, 1, 64);
+    a += __shfl_xor(a, 2, 64);
+    if (v < NV && q == 0) part[(int64_t)v * nb + blockIdx.x] = a;
   }
 }
 
@@ -252,10 +268,29 @@ __global__ __launch_bounds__(kScalarThreads) void k_scalar(int j, int final_step
   const double* t = red + j;
   const double alpha = hasp ? red[2 * j] : red[j];
   const double gamma = hasp ? red[2 * j + 1] : 0.0;
-  // (3) serial part on LDS
+  // (3a) one wavefront: |s|^2, |h'+s|^2 and the new Hessenberg column h = h' + s
+  // (unrotated and, before rotation, rotated copies) in parallel
+  __shared__ double sh_ss, sh_hh;
+  if (tid < 64) {
+    double a = 0.0, b = 0.0;
+    for (int i = tid; i < j; i += 64) {
+      const double h = sHp[i] + s[i];
+      a += s[i] * s[i];
+      b += h * h;
+      sH[(j - 1) * kLd + i] = h;
+      sR[(j - 1) * kLd + i] = h;
+    }
+    a = wave_sum(a);
+    b = wave_sum(b);
+    if (tid == 0) {
+      sh_ss = a;
+      sh_hh = b;
+    }
+  }
+  __syncthreads();
+  // (3b) serial part on LDS
   if (tid == 0) {
-    double ss = 0.0;
-    for (int i = 0; i < j; ++i) ss += s[i] * s[i];
+    const double ss = sh_ss;
     const double nu2 = alpha - ss;
     int done = 0, k = 0;
     double nu = 0.0;
@@ -269,21 +304,13 @@ __global__ __launch_bounds__(kScalarThreads) void k_scalar(int j, int final_step
         if (nu != nu) gs->nonfinite = 1;
       }
     } else {
-      double col2 = nu2 > 0.0 ? nu2 : 0.0;
-      for (int i = 0; i < j; ++i) {
-        const double h = sHp[i] + s[i];
-        col2 += h * h;
-      }
+      const double col2 = (nu2 > 0.0 ? nu2 : 0.0) + sh_hh;
       nu = (nu2 > 1e-28 * col2) ? sqrt(nu2) : 0.0;
       if (nu == 0.0) gs->breakdown = 1;
       bool nonfinite = false;
       const int c = j - 1;
       double* hc = sH + c * kLd;
       double* rc = sR + c * kLd;
-      for (int i = 0; i < j; ++i) {
-        hc[i] = sHp[i] + s[i];
-        rc[i] = hc[i];
-      }
       hc[j] = nu;
       rc[j] = nu;
       // apply the previous rotations; the running element stays in a register
