@@ -560,6 +560,7 @@ __global__ __launch_bounds__(256) void k_stencil(Geom g, Scheme sc, Coefs<R> cf,
 // meet in the same L2 instead of being fetched once per XCD.
 // ----------------------------------------------------------------------------
 constexpr int LX = 64, LY = 16, LHX = LX + 2, LHY = LY + 2;
+constexpr int kApply2dThreads = 512;   // two cells per thread: 16 waves per tile for latency hiding
 
 __host__ __device__ inline int tiles2d(int nx, int ny) { return ((nx + LX - 1) / LX) * ((ny + LY - 1) / LY); }
 inline dim3 grid2d_xcd(const Geom& g) { return dim3(8 * ((tiles2d(g.n[0], g.n[1]) + 7) / 8)); }
@@ -579,7 +580,7 @@ __device__ __forceinline__ bool xcd_tile(int nx, int ny, int& tbx, int& tby) {
 // PRE = true: the input is u and the operator is applied to z = M^{-1} u, the
 // block-Jacobi solve done per staged cell (fused right preconditioning).
 template <bool CPL, int MODE, bool PRE, typename R, typename VI, typename VO>
-__global__ __launch_bounds__(256) void k_apply2d_lds(Geom g, Scheme sc, Coefs<R> cf, Bdry bd, const VI* __restrict__ x,
+__global__ __launch_bounds__(kApply2dThreads) void k_apply2d_lds(Geom g, Scheme sc, Coefs<R> cf, Bdry bd, const VI* __restrict__ x,
                                                      const double* __restrict__ b, VO* __restrict__ y,
                                                      const int* __restrict__ skip) {
   constexpr int NR = 3;
@@ -594,7 +595,7 @@ __global__ __launch_bounds__(256) void k_apply2d_lds(Geom g, Scheme sc, Coefs<R>
   if (!xcd_tile(nx, ny, tbx, tby)) return;
   const int i0 = tbx * LX - 1, j0 = tby * LY - 1;
   // ---- stage the halo tile ----
-  for (int t = threadIdx.x; t < LHX * LHY; t += 256) {
+  for (int t = threadIdx.x; t < LHX * LHY; t += kApply2dThreads) {
     const int li = t % LHX, lj = t / LHX;
     int gi = i0 + li, gj = j0 + lj;
     const bool outx = gi < 0 || gi >= nx, outy = gj < 0 || gj >= ny;
@@ -660,7 +661,7 @@ __global__ __launch_bounds__(256) void k_apply2d_lds(Geom g, Scheme sc, Coefs<R>
   const int tx = threadIdx.x % LX;
   const R s = (R)sc.s;
   const R cdt = (R)sc.cdt;
-  for (int ty = threadIdx.x / LX; ty < LY; ty += 256 / LX) {
+  for (int ty = threadIdx.x / LX; ty < LY; ty += kApply2dThreads / LX) {
     const int i = tbx * LX + tx, j = tby * LY + ty;
     if (i >= nx || j >= ny) continue;
     const int64_t cell = (int64_t)j * nx + i;
@@ -1043,7 +1044,7 @@ void launch_apply(int nd, bool cpl, int mode, const Geom& g, const Scheme& sc, c
                   const VI* x, const double* b, VO* y, hipStream_t s, const int* skip) {
   if (nd == 2 && use_lds_2d()) {
     const dim3 grd2 = grid2d_xcd(g);
-#define M1_LDS(CPL_, MODE_) k_apply2d_lds<CPL_, MODE_, false, R, VI, VO><<<grd2, 256, 0, s>>>(g, sc, cf, bd, x, b, y, skip)
+#define M1_LDS(CPL_, MODE_) k_apply2d_lds<CPL_, MODE_, false, R, VI, VO><<<grd2, kApply2dThreads, 0, s>>>(g, sc, cf, bd, x, b, y, skip)
     if (cpl) { if (mode == 0) M1_LDS(true, 0); else M1_LDS(true, 1); }
     else { if (mode == 0) M1_LDS(false, 0); else M1_LDS(false, 1); }
 #undef M1_LDS
@@ -1140,8 +1141,8 @@ bool launch_apply_pre(int nd, bool cpl, const Geom& g, const Scheme& sc, const C
   }
   if (nd != 2) return false;
   const dim3 grd2 = grid2d_xcd(g);
-  if (cpl) k_apply2d_lds<true, 0, true, R, VI, VO><<<grd2, 256, 0, s>>>(g, sc, cf, bd, u, nullptr, y, skip);
-  else k_apply2d_lds<false, 0, true, R, VI, VO><<<grd2, 256, 0, s>>>(g, sc, cf, bd, u, nullptr, y, skip);
+  if (cpl) k_apply2d_lds<true, 0, true, R, VI, VO><<<grd2, kApply2dThreads, 0, s>>>(g, sc, cf, bd, u, nullptr, y, skip);
+  else k_apply2d_lds<false, 0, true, R, VI, VO><<<grd2, kApply2dThreads, 0, s>>>(g, sc, cf, bd, u, nullptr, y, skip);
   return true;
 }
 
