@@ -560,7 +560,7 @@ __global__ __launch_bounds__(256) void k_stencil(Geom g, Scheme sc, Coefs<R> cf,
 // meet in the same L2 instead of being fetched once per XCD.
 // ----------------------------------------------------------------------------
 constexpr int LX = 64, LY = 16, LHX = LX + 2, LHY = LY + 2;
-constexpr int kApply2dThreads = 512;   // two cells per thread: 16 waves per tile for latency hiding
+constexpr int kApply2dThreads = 1024;  // one cell per thread: 16 waves per tile hide the staging latency
 
 __host__ __device__ inline int tiles2d(int nx, int ny) { return ((nx + LX - 1) / LX) * ((ny + LY - 1) / LY); }
 inline dim3 grid2d_xcd(const Geom& g) { return dim3(8 * ((tiles2d(g.n[0], g.n[1]) + 7) / 8)); }
