@@ -42,16 +42,13 @@ CSRC = os.path.join(ROOT, "paper_2011_13926_amd", "csrc")
 
 # profiler kernel class -> prefixes of the HIP kernels' names (without "void " and "m1::")
 CLASS_KERNEL = {
-    "apply_bj_fused": ("k_apply2d_lds<false, 0, true", "k_apply2d_lds<true, 0, true", "k_apply3d_25d<false, 0, true",
-                       "k_apply3d_25d<true, 0, true"),
-    "apply": ("k_apply2d_lds<false, 0, false", "k_apply2d_lds<true, 0, false", "k_apply3d_25d<false, 0, false",
-              "k_apply3d_25d<true, 0, false", "k_stencil<2, false, 0", "k_stencil<2, true, 0", "k_stencil<3, false, 0",
-              "k_stencil<3, true, 0"),
+    "apply_bj_fused": ("k_apply2d_lds<false, 0, true", "k_apply2d_lds<true, 0, true"),
+    "apply": ("k_apply2d_lds<false, 0, false", "k_apply2d_lds<true, 0, false", "k_stencil<2, false, 0",
+              "k_stencil<2, true, 0", "k_stencil<3, false, 0", "k_stencil<3, true, 0"),
     "arnoldi_dot": ("k_dot<", "k_dot4<"), "arnoldi_update": ("k_update<", "k_update4<"), "arnoldi_scalar": ("k_scalar",),
     "x_update": ("k_xupdate<",), "block_jacobi": ("k_bj<",),
-    "true_residual": ("k_apply2d_lds<false, 1", "k_apply2d_lds<true, 1", "k_apply3d_25d<false, 1",
-                      "k_apply3d_25d<true, 1", "k_stencil<2, false, 1", "k_stencil<2, true, 1", "k_stencil<3, false, 1",
-                      "k_stencil<3, true, 1"),
+    "true_residual": ("k_apply2d_lds<false, 1", "k_apply2d_lds<true, 1", "k_stencil<2, false, 1",
+                      "k_stencil<2, true, 1", "k_stencil<3, false, 1", "k_stencil<3, true, 1"),
 }
 
 

@@ -759,276 +759,6 @@ __global__ __launch_bounds__(kApply2dThreads) void k_apply2d_lds(Geom g, Scheme 
   }
 }
 
-// ----------------------------------------------------------------------------
-// a3, 3D, 2.5-D blocking: a block owns a 64 x 4 (x, y) column of cells and walks
-// KZ planes in z.  Each plane's (66 x 6) halo tile of x and of the pressure pairs
-// needed by the x and y faces (xx, xy, xz, yy, yz) is staged in LDS; the z
-// neighbours of a thread's own cell stay in registers (the previous plane's own
-// values, and the next plane's loaded directly).  PRE: operate on z = M^{-1} u.
-// ----------------------------------------------------------------------------
-constexpr int ZX = 64, ZY = 4, ZHX = ZX + 2, ZHY = ZY + 2, KZ = 16;
-
-template <bool CPL, bool PRE, typename R, typename VI>
-struct Cell3 {
-  R x[4];
-  R q[6];   // pressure pairs xx, xy, xz, yy, yz, zz (pair_index<3>)
-  R sig;
-};
-
-// values of in-domain cell `cell` (all six pairs)
-template <bool CPL, bool PRE, typename R, typename VI>
-__device__ __forceinline__ void load_cell3(const Coefs<R>& cf, const VI* __restrict__ x, int64_t N, int64_t cell,
-                                           Cell3<CPL, PRE, R, VI>& v) {
-  constexpr int NR = 4, NU = NR + (CPL ? 1 : 0);
-  if (PRE) {
-    R u[NU];
-#pragma unroll
-    for (int c = 0; c < NU; ++c) u[c] = (R)x[c * N + cell];
-#pragma unroll
-    for (int r = 0; r < NR; ++r) {
-      R acc = (R)0;
-#pragma unroll
-      for (int c = 0; c < NU; ++c) acc += cf.bjinv[(r * NU + c) * N + cell] * u[c];
-      v.x[r] = acc;
-    }
-  } else {
-#pragma unroll
-    for (int c = 0; c < NR; ++c) v.x[c] = (R)x[c * N + cell];
-  }
-#pragma unroll
-  for (int pq = 0; pq < 6; ++pq) {
-    R acc = (R)0;
-#pragma unroll
-    for (int k = 0; k < NR; ++k) acc += cf.jac[(pq * NR + k) * N + cell] * v.x[k];
-    v.q[pq] = acc;
-  }
-  v.sig = cf.sigma[cell];
-}
-
-// ghost beside boundary cell values `in` on face `face` (plane index pidx)
-template <bool CPL, bool PRE, typename R, typename VI>
-__device__ __forceinline__ void ghost_cell3(const Geom& g, const Coefs<R>& cf, const Bdry& bd, int face, int64_t pidx,
-                                            const Cell3<CPL, PRE, R, VI>& in, Cell3<CPL, PRE, R, VI>& v) {
-  constexpr int NR = 4;
-  const int d = face / 2;
-  const int64_t pn = g.plane_n[d];
-#pragma unroll
-  for (int c = 0; c < NR; ++c) v.x[c] = (R)ghost_weight(g.bc[face], d, c, bd.mask[face], pidx) * in.x[c];
-#pragma unroll
-  for (int pq = 0; pq < 6; ++pq) {
-    R acc = (R)0;
-#pragma unroll
-    for (int k = 0; k < NR; ++k) acc += cf.gjac[cf.gjoff[face] + (pq * NR + k) * pn + pidx] * v.x[k];
-    v.q[pq] = acc;
-  }
-  v.sig = in.sig;
-}
-
-template <bool CPL, int MODE, bool PRE, typename R, typename VI, typename VO>
-__global__ __launch_bounds__(256) void k_apply3d_25d(Geom g, Scheme sc, Coefs<R> cf, Bdry bd, const VI* __restrict__ x,
-                                                     const double* __restrict__ b, VO* __restrict__ y,
-                                                     const int* __restrict__ skip) {
-  constexpr int NR = 4;
-  constexpr int NU = NR + (CPL ? 1 : 0);
-  using C3 = Cell3<CPL, PRE, R, VI>;
-  if (skip && *skip) return;
-  __shared__ R sx[NR][ZHY][ZHX];
-  __shared__ R sq[5][ZHY][ZHX];
-  __shared__ R ss[ZHY][ZHX];
-  const int64_t N = g.N;
-  const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
-  const int64_t plane = (int64_t)nx * ny;
-  const int tx = threadIdx.x % ZX, ty = threadIdx.x / ZX;
-  const int i = blockIdx.x * ZX + tx, j = blockIdx.y * ZY + ty;
-  const bool own = i < nx && j < ny;
-  const int kbeg = blockIdx.z * KZ, kend = min(kbeg + KZ, nz);
-  const R s = (R)sc.s;
-  const R cdt = (R)sc.cdt;
-  // halo cell handled by this thread (136 cells: top, bottom rows and left, right columns)
-  int hli = -1, hlj = -1;
-  {
-    const int t = threadIdx.x;
-    if (t < ZX) { hli = t + 1; hlj = 0; }
-    else if (t < 2 * ZX) { hli = t - ZX + 1; hlj = ZHY - 1; }
-    else if (t < 2 * ZX + ZY) { hli = 0; hlj = t - 2 * ZX + 1; }
-    else if (t < 2 * ZX + 2 * ZY) { hli = ZHX - 1; hlj = t - 2 * ZX - ZY + 1; }
-  }
-  C3 dn, me, up;
-  // value of the own column at plane kk (in-domain or periodic), or ghost of `face`
-  auto column_value = [&](int kk, int face, const C3& from, C3& out) {
-    if (kk >= 0 && kk < nz) {
-      load_cell3<CPL, PRE, R, VI>(cf, x, N, (int64_t)kk * plane + (int64_t)j * nx + i, out);
-    } else if (g.bc[4] == BC_PERIODIC) {
-      const int kw = (kk + nz) % nz;
-      load_cell3<CPL, PRE, R, VI>(cf, x, N, (int64_t)kw * plane + (int64_t)j * nx + i, out);
-    } else {
-      ghost_cell3<CPL, PRE, R, VI>(g, cf, bd, face, (int64_t)j * nx + i, from, out);
-    }
-  };
-  if (own) {
-    load_cell3<CPL, PRE, R, VI>(cf, x, N, (int64_t)kbeg * plane + (int64_t)j * nx + i, me);
-    column_value(kbeg - 1, 4, me, dn);
-  }
-  for (int k = kbeg; k < kend; ++k) {
-    // ---- stage plane k: every tile position and the halo, by global position ----
-    auto stage = [&](int li, int lj) {
-      int gi = blockIdx.x * ZX + li - 1, gj = blockIdx.y * ZY + lj - 1;
-      const bool outx = gi < 0 || gi >= nx, outy = gj < 0 || gj >= ny;
-      C3 hv;
-      bool valid = !(outx && outy);
-      if (valid) {
-        int face = -1;
-        if (outx) {
-          if (g.bc[0] == BC_PERIODIC) gi = (gi + nx) % nx;
-          else { face = gi < 0 ? 0 : 1; gi = gi < 0 ? 0 : nx - 1; }
-        } else if (outy) {
-          if (g.bc[2] == BC_PERIODIC) gj = (gj + ny) % ny;
-          else { face = gj < 0 ? 2 : 3; gj = gj < 0 ? 0 : ny - 1; }
-        }
-        const int64_t cell = (int64_t)k * plane + (int64_t)gj * nx + gi;
-        if (face < 0) {
-          load_cell3<CPL, PRE, R, VI>(cf, x, N, cell, hv);
-        } else {
-          C3 bv;
-          load_cell3<CPL, PRE, R, VI>(cf, x, N, cell, bv);
-          const int64_t pidx = face < 2 ? (int64_t)k * ny + gj : (int64_t)k * nx + gi;
-          ghost_cell3<CPL, PRE, R, VI>(g, cf, bd, face, pidx, bv, hv);
-        }
-      }
-#pragma unroll
-      for (int c = 0; c < NR; ++c) sx[c][lj][li] = valid ? hv.x[c] : (R)0;
-#pragma unroll
-      for (int pq = 0; pq < 5; ++pq) sq[pq][lj][li] = valid ? hv.q[pq] : (R)0;
-      ss[lj][li] = valid ? hv.sig : (R)0;
-    };
-    if (own) {
-      const int li = tx + 1, lj = ty + 1;
-#pragma unroll
-      for (int c = 0; c < NR; ++c) sx[c][lj][li] = me.x[c];
-#pragma unroll
-      for (int pq = 0; pq < 5; ++pq) sq[pq][lj][li] = me.q[pq];
-      ss[lj][li] = me.sig;
-    } else {
-      stage(tx + 1, ty + 1);
-    }
-    if (hli >= 0) stage(hli, hlj);
-    if (own) column_value(k + 1, 5, me, up);
-    __syncthreads();
-    if (own) {
-      const int64_t cell = (int64_t)k * plane + (int64_t)j * nx + i;
-      const int li = tx + 1, lj = ty + 1;
-      R xs[NU], ys[NU];
-#pragma unroll
-      for (int c = 0; c < NR; ++c) { xs[c] = me.x[c]; ys[c] = xs[c]; }
-      if (CPL) {
-        if (PRE) {
-          R acc = (R)0;
-#pragma unroll
-          for (int c = 0; c < NU; ++c) acc += cf.bjinv[((NU - 1) * NU + c) * N + cell] * (R)x[c * N + cell];
-          xs[NU - 1] = acc;
-        } else {
-          xs[NU - 1] = (R)x[(NU - 1) * N + cell];
-        }
-        ys[NU - 1] = (R)0;
-      }
-      const R sig = me.sig;
-      const int idx3[3] = {i, j, k};
-      const int nn[3] = {nx, ny, nz};
-      const int64_t stride[3] = {1, nx, plane};
-#pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        R xr[NR], xl[NR], qs[3], qr[3], ql[3], sigR, sigL;
-        if (d < 2) {
-          const int ri = d == 0 ? li + 1 : li, rj = d == 0 ? lj : lj + 1;
-          const int mi = d == 0 ? li - 1 : li, mj = d == 0 ? lj : lj - 1;
-#pragma unroll
-          for (int c = 0; c < NR; ++c) { xr[c] = sx[c][rj][ri]; xl[c] = sx[c][mj][mi]; }
-#pragma unroll
-          for (int m = 0; m < 3; ++m) {
-            const int pq = pair_index<3>(d, m);
-            qs[m] = me.q[pq];
-            qr[m] = sq[pq][rj][ri];
-            ql[m] = sq[pq][mj][mi];
-          }
-          sigR = ss[rj][ri];
-          sigL = ss[mj][mi];
-        } else {
-#pragma unroll
-          for (int c = 0; c < NR; ++c) { xr[c] = up.x[c]; xl[c] = dn.x[c]; }
-#pragma unroll
-          for (int m = 0; m < 3; ++m) {
-            const int pq = pair_index<3>(2, m);
-            qs[m] = me.q[pq];
-            qr[m] = up.q[pq];
-            ql[m] = dn.q[pq];
-          }
-          sigR = up.sig;
-          sigL = dn.sig;
-        }
-        const R ap = cf.face[(3 * d + 0) * N + cell];
-        const R ddp = cf.face[(3 * d + 1) * N + cell];
-        const R alp = cf.face[(3 * d + 2) * N + cell];
-        const R bp = (R)1 - ap;
-        R am, ddm, alm;
-        if (idx3[d] > 0) {
-          const int64_t nb = cell - stride[d];
-          am = cf.face[(3 * d + 0) * N + nb]; ddm = cf.face[(3 * d + 1) * N + nb]; alm = cf.face[(3 * d + 2) * N + nb];
-        } else if (g.bc[2 * d] == BC_PERIODIC) {
-          const int64_t nb = cell + (int64_t)(nn[d] - 1) * stride[d];
-          am = cf.face[(3 * d + 0) * N + nb]; ddm = cf.face[(3 * d + 1) * N + nb]; alm = cf.face[(3 * d + 2) * N + nb];
-        } else {
-          const int64_t pidx = d == 0 ? (int64_t)k * ny + j : (d == 1 ? (int64_t)k * nx + i : (int64_t)j * nx + i);
-          const int64_t pn = g.plane_n[d];
-          am = cf.lowface[cf.lowoff[d] + pidx]; ddm = cf.lowface[cf.lowoff[d] + pn + pidx];
-          alm = cf.lowface[cf.lowoff[d] + 2 * pn + pidx];
-        }
-        const R bm = (R)1 - am;
-        const R FEp = alp * (ap * xs[1 + d] + bp * xr[1 + d] + ddp * (xr[0] - xs[0]));
-        const R FEm = alm * (am * xl[1 + d] + bm * xs[1 + d] + ddm * (xs[0] - xl[0]));
-        ys[0] += s * (FEp - FEm);
-#pragma unroll
-        for (int m = 0; m < 3; ++m) {
-          const R FPp = ap * qs[m] + bp * qr[m] + ddp * (xr[1 + m] - xs[1 + m]);
-          const R FPm = am * ql[m] + bm * qs[m] + ddm * (xs[1 + m] - xl[1 + m]);
-          ys[1 + m] += s * (FPp - FPm);
-        }
-        if (sc.wb) {
-          ys[1 + d] += (R)0.25 * cdt *
-                       ((R)0.5 * (sig + sigR) * (xs[1 + d] + xr[1 + d]) + (R)0.5 * (sig + sigL) * (xl[1 + d] + xs[1 + d]));
-        }
-      }
-      if (!sc.wb) {
-#pragma unroll
-        for (int m = 0; m < 3; ++m) ys[1 + m] += cdt * sig * xs[1 + m];
-      }
-      if (sc.src == SRC_ABS) ys[0] += cdt * sig * xs[0];
-      if (CPL) {
-        const R T = xs[NU - 1];
-        const R exch = cdt * sig * (cf.kap[cell] * T - xs[0]);
-        ys[NU - 1] = cf.rcv[cell] * T + exch;
-        ys[0] -= exch;
-      }
-      if (sc.psi != 0.0) {
-        const R psi = (R)sc.psi;
-#pragma unroll
-        for (int c = 0; c < NR; ++c) ys[c] += psi * xs[c];
-        if (CPL) ys[NU - 1] += psi * cf.rcv[cell] * xs[NU - 1];
-      }
-#pragma unroll
-      for (int c = 0; c < NU; ++c) {
-        R v = ys[c];
-        if (MODE == 1) v = (R)b[c * N + cell] - v;
-        y[c * N + cell] = (VO)v;
-      }
-    }
-    __syncthreads();
-    if (own) {
-      dn = me;
-      me = up;
-    }
-  }
-}
-
 static int g_apply_variant = -1;  // -1: read M1_APPLY_KERNEL once ("lds" default in 2D, "direct")
 
 static bool use_lds_2d() {
@@ -1048,14 +778,6 @@ void launch_apply(int nd, bool cpl, int mode, const Geom& g, const Scheme& sc, c
     if (cpl) { if (mode == 0) M1_LDS(true, 0); else M1_LDS(true, 1); }
     else { if (mode == 0) M1_LDS(false, 0); else M1_LDS(false, 1); }
 #undef M1_LDS
-    return;
-  }
-  if (nd == 3 && use_lds_2d()) {
-    dim3 grd3((g.n[0] + ZX - 1) / ZX, (g.n[1] + ZY - 1) / ZY, (g.n[2] + KZ - 1) / KZ);
-#define M1_25D(CPL_, MODE_) k_apply3d_25d<CPL_, MODE_, false, R, VI, VO><<<grd3, 256, 0, s>>>(g, sc, cf, bd, x, b, y, skip)
-    if (cpl) { if (mode == 0) M1_25D(true, 0); else M1_25D(true, 1); }
-    else { if (mode == 0) M1_25D(false, 0); else M1_25D(false, 1); }
-#undef M1_25D
     return;
   }
   dim3 blk(TX, TY), grd((g.n[0] + TX - 1) / TX, (g.rows + TY - 1) / TY);
@@ -1126,19 +848,13 @@ void launch_convert(const double* src, float* dst, int64_t n, hipStream_t s) {
   k_convert<<<grd, 256, 0, s>>>(src, dst, n);
 }
 
-bool fused_apply_available(int nd) { return (nd == 2 || nd == 3) && use_lds_2d(); }
+bool fused_apply_available(int nd) { return nd == 2 && use_lds_2d(); }
 
 // y = A M^{-1} u in one kernel (2D, LDS path); returns false when not available
 template <typename R, typename VI, typename VO>
 bool launch_apply_pre(int nd, bool cpl, const Geom& g, const Scheme& sc, const Coefs<R>& cf, const Bdry& bd,
                       const VI* u, VO* y, hipStream_t s, const int* skip) {
   if (!use_lds_2d()) return false;
-  if (nd == 3) {
-    dim3 grd3((g.n[0] + ZX - 1) / ZX, (g.n[1] + ZY - 1) / ZY, (g.n[2] + KZ - 1) / KZ);
-    if (cpl) k_apply3d_25d<true, 0, true, R, VI, VO><<<grd3, 256, 0, s>>>(g, sc, cf, bd, u, nullptr, y, skip);
-    else k_apply3d_25d<false, 0, true, R, VI, VO><<<grd3, 256, 0, s>>>(g, sc, cf, bd, u, nullptr, y, skip);
-    return true;
-  }
   if (nd != 2) return false;
   const dim3 grd2 = grid2d_xcd(g);
   if (cpl) k_apply2d_lds<true, 0, true, R, VI, VO><<<grd2, kApply2dThreads, 0, s>>>(g, sc, cf, bd, u, nullptr, y, skip);
