@@ -734,6 +734,69 @@ def explicit_step(sch, sigma, rho_cv, Un, dt):
     return U
 
 
+def source_terms(sch, sigma, rho_cv, U, dt):
+    """The source part of the residual at state U, row by row (the terms the
+    semi-implicit step treats implicitly): c dt sigma F_m on the flux rows
+    (centred form, Eq. "wb_naive"); c dt sigma E on the energy row with
+    absorption; with the T row, -c dt sigma (a_r T^4 - E) on the energy row and
+    +c dt sigma (a_r T^4 - E) on the T row."""
+    if sch.flux_source != "centered":
+        raise ValueError("the source part is separable per cell only for the centred flux source")
+    S = np.zeros_like(U)
+    c, nrad = sch.c, sch.nrad
+    for m in range(sch.ndim):
+        S[1 + m] = c * dt * sigma * U[1 + m]
+    if sch.source == "absorption":
+        S[0] = c * dt * sigma * U[0]
+    elif sch.source == "coupled_t":
+        exch = c * dt * sigma * (sch.a_r * U[nrad] ** 4 - U[0])
+        S[0] = -exch
+        S[nrad] = exch
+    return S
+
+
+def semi_implicit_step(sch, sigma, rho_cv, Un, dt, t_newton=60):
+    """Semi-implicit step (Sect. 3.1: sources implicit, hyperbolic part explicit).
+
+    H = R(U^n) - S(U^n) is the flux divergence of the scheme at time n (closure,
+    speeds and alpha from U^n); the new state solves, cell by cell,
+        U - U^n + H + S(U) = 0,
+    i.e. F_m = (F_m^n - H_Fm)/(1 + c dt sigma); with absorption
+    E = (E^n - H_E)/(1 + c dt sigma), without a source E = E^n - H_E; with the T
+    row, E = (E* + k a_r T^4)/(1 + k) (k = c dt sigma, E* = E^n - H_E) and T the
+    root of rho c_v (T - T^n) + k (a_r T^4 - E) = 0, found by Newton from T^n
+    (t_newton iterations, stopping once the update is below 1e-15 T).  Only the
+    centred flux source (Eq. "wb_naive") keeps the sources local to a cell.
+    """
+    lin = linearize(sch, sigma, rho_cv, Un, Un, dt)
+    H = residual(lin) - source_terms(sch, sigma, rho_cv, Un, dt)
+    c, nrad, k = sch.c, sch.nrad, sch.c * dt * sigma
+    U = np.array(Un, dtype=float, copy=True)
+    for m in range(sch.ndim):
+        U[1 + m] = (Un[1 + m] - H[1 + m]) / (1.0 + k)
+    if sch.source == "absorption":
+        U[0] = (Un[0] - H[0]) / (1.0 + k)
+    elif sch.source == "coupled_t":
+        Es = Un[0] - H[0]
+        rc = np.asarray(rho_cv, float)
+        T = np.array(Un[nrad], dtype=float, copy=True)
+        # eliminate E: g(T) = rc (T - T^n) + k (a_r T^4 - (Es + k a_r T^4)/(1 + k))
+        #                  = rc (T - T^n) + k/(1+k) (a_r T^4 - Es)
+        w = k / (1.0 + k)
+        for _ in range(t_newton):
+            g = rc * (T - Un[nrad]) + w * (sch.a_r * T ** 4 - Es)
+            dg = rc + 4.0 * w * sch.a_r * T ** 3
+            dT = g / dg
+            T = T - dT
+            if np.all(np.abs(dT) <= 1e-15 * np.abs(T)):
+                break
+        U[nrad] = T
+        U[0] = (Es + k * sch.a_r * T ** 4) / (1.0 + k)
+    else:
+        U[0] = Un[0] - H[0]
+    return U
+
+
 def discrete_diffusion_step(sigma, E, dt, c=1.0, dx=1.0):
     """Backward-Euler step of the discrete diffusion limit (Eq. "discreteDiffusionEqua").
 
