@@ -5,7 +5,8 @@ libm1.so.  PyTorch provides device memory and the stream.  If the library has
 not been built this module raises on import -- there is no CPU fallback.
 
 Low level: ``m1_setup``, ``m1_linearize``, ``m1_apply_operator``,
-``m1_precondition``, ``m1_residual``, ``m1_implicit_step``, ``m1_destroy``,
+``m1_precondition``, ``m1_residual``, ``m1_implicit_step``, ``m1_explicit_step``,
+``m1_semi_implicit_step``, ``m1_destroy``,
 ``m1_last_error``, ``m1_profile_enable``, ``m1_profile_query`` mirror the C
 functions one to one (pointers are passed as Python ints / ctypes structs).
 High level: :class:`Solver` builds the structs from a problem description.
@@ -89,6 +90,8 @@ _sig = {
     "m1_precondition": (ctypes.c_int32, [_vp, _vp, _vp]),
     "m1_residual": (ctypes.c_int32, [_vp, _vp]),
     "m1_implicit_step": (ctypes.c_int32, [_vp, _P(M1State), ctypes.c_double, _P(M1Stats)]),
+    "m1_explicit_step": (ctypes.c_int32, [_vp, _P(M1State), ctypes.c_double, _P(M1Stats)]),
+    "m1_semi_implicit_step": (ctypes.c_int32, [_vp, _P(M1State), ctypes.c_double, _P(M1Stats)]),
     "m1_destroy": (None, [_vp]),
     "m1_last_error": (ctypes.c_char_p, [_vp]),
     "m1_profile_enable": (ctypes.c_int32, [_vp, ctypes.c_int32]),
@@ -132,6 +135,8 @@ m1_apply_operator = _lib.m1_apply_operator
 m1_precondition = _lib.m1_precondition
 m1_residual = _lib.m1_residual
 m1_implicit_step = _lib.m1_implicit_step
+m1_explicit_step = _lib.m1_explicit_step
+m1_semi_implicit_step = _lib.m1_semi_implicit_step
 m1_destroy = _lib.m1_destroy
 m1_last_error = _lib.m1_last_error
 m1_profile_enable = _lib.m1_profile_enable
@@ -318,6 +323,22 @@ class Solver:
         if raise_on_fail and st not in (M1_OK,):
             raise M1Error(st, _lib.m1_last_error(self.ctx).decode())
         return st, stats.as_dict()
+
+    def _time_step(self, fn, U, dt, raise_on_fail):
+        stats = M1Stats()
+        st = fn(self.ctx, ctypes.byref(state_struct(U, self.ndim, self.coupled)),
+                float(dt if dt is not None else self.p["dt"]), ctypes.byref(stats))
+        if raise_on_fail and st != M1_OK:
+            raise M1Error(st, _lib.m1_last_error(self.ctx).decode())
+        return st, stats.as_dict()
+
+    def explicit_step(self, U, dt=None, *, raise_on_fail=True):
+        """Forward-Euler step of the device tensor U in place; returns (status, stats dict)."""
+        return self._time_step(_lib.m1_explicit_step, U, dt, raise_on_fail)
+
+    def semi_implicit_step(self, U, dt=None, *, raise_on_fail=True):
+        """Semi-implicit step (sources implicit, fluxes explicit) of U in place (centred flux source)."""
+        return self._time_step(_lib.m1_semi_implicit_step, U, dt, raise_on_fail)
 
     def set_network(self, net):
         self._net = net

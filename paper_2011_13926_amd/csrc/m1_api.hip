@@ -22,7 +22,8 @@ namespace {
 
 const char* kClassNames[KC_COUNT] = {"setup",   "setup_bj", "residual",   "apply",         "block_jacobi",
                                      "arnoldi_dot", "arnoldi_scalar", "arnoldi_update", "x_update",
-                                     "true_residual", "newton_update", "norm", "convert", "learned_pc", "apply_bj_fused"};
+                                     "true_residual", "newton_update", "norm", "convert", "learned_pc", "apply_bj_fused",
+                                     "time_update"};
 
 struct Profiler {
   bool on = false;
@@ -544,6 +545,54 @@ m1_status solve(m1_ctx* c, double bnorm, SolveResult& res, int& fell_back) {
 
 }  // namespace
 
+// Explicit (semi = false) or semi-implicit step: one evaluation of the scheme at
+// U^n (a1, a2), then a per-cell update of the state (no linear solve).
+m1_status time_step(m1_ctx* c, m1_state* U, double dt, m1_stats* stats, bool semi) {
+  if (!c) return M1_ERR_INVALID_ARG;
+  const auto t0 = std::chrono::steady_clock::now();
+  if (!(std::isfinite(dt) && dt > 0)) { c->err = "dt must be finite and > 0"; return M1_ERR_INVALID_ARG; }
+  if (semi && c->cfg.flux_source != M1_FSRC_CENTERED) {
+    c->err = "the semi-implicit step needs the centred flux source (the well-balanced source couples cells)";
+    return M1_ERR_INVALID_ARG;
+  }
+  m1_status st;
+  if ((st = copy_state_in(c, U, c->Un)) != M1_OK) return st;
+  if ((st = check_array(c, c->Un, c->n, 0, "U", M1_ERR_NONFINITE)) != M1_OK) return st;
+  if ((st = check_array(c, c->Un, c->g.N, 1, "U.E", M1_ERR_INVALID_ARG)) != M1_OK) return st;
+  HIPCHK(c, hipMemcpyAsync(c->Uk, c->Un, sizeof(double) * c->n, hipMemcpyDeviceToDevice, c->stream));
+  set_dt(c, dt);
+  c->sc.psi = 0.0;
+  launch_fn(c->nd, c->g, c->sc, c->Un, c->fn, c->stream);
+  if ((st = linearize_internal(c, false)) != M1_OK) return st;
+  timed(c, KC_RESIDUAL, bytes_residual(c), [&] { launch_residual(c->nd, c->cpl, c->g, c->sc, c->cf64, bdry(c), c->Uk, c->Un, c->b, c->stream); });
+  const double per_cell = 8.0 * (2.0 * c->nu + 1.0 + (c->cpl ? 1.0 : 0.0));
+  timed(c, KC_TIME_UPDATE, per_cell * cells(c), [&] {
+    launch_time_update(c->nd, c->cpl, semi, c->g, c->sc, c->cf64, c->Un, c->b, c->Uk, c->stream);
+  });
+  unsigned long long nf = 0;
+  k_zero_u64<<<1, 64, 0, c->stream>>>(c->dcount);
+  launch_count_f(c->nd, c->g, c->Uk, c->cfg.c, c->dcount, c->stream);
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipMemcpyAsync(&nf, c->dcount, sizeof(nf), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  prof_collect(c);
+  // the linearisation held by the context is at U^n, not at the returned state
+  if ((st = check_array(c, c->Uk, c->n, 0, "U^(n+1)", M1_ERR_NONFINITE)) != M1_OK) return st;
+  if ((st = copy_state_out(c, c->Uk, U)) != M1_OK) return st;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (stats) {
+    stats->newton_iters = 0;
+    stats->krylov_iters = 0;
+    stats->restarts = 0;
+    stats->fell_back = 0;
+    stats->rel_residual = 0.0;
+    stats->nonlinear_residual = 0.0;
+    stats->cells_f_gt_1 = (int64_t)nf;
+    stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+  return M1_OK;
+}
+
 // ============================================================================
 // C ABI
 // ============================================================================
@@ -921,6 +970,14 @@ m1_status m1_implicit_step(m1_ctx* c, m1_state* U, double dt, m1_stats* stats) {
   if (nonfinite) { c->err = "non-finite value in the Newton/GMRES iteration"; return M1_ERR_NONFINITE; }
   if (!converged) { c->err = "Newton iteration did not converge"; return M1_NOT_CONVERGED; }
   return M1_OK;
+}
+
+m1_status m1_explicit_step(m1_ctx* c, m1_state* U, double dt, m1_stats* stats) {
+  return time_step(c, U, dt, stats, false);
+}
+
+m1_status m1_semi_implicit_step(m1_ctx* c, m1_state* U, double dt, m1_stats* stats) {
+  return time_step(c, U, dt, stats, true);
 }
 
 m1_status m1_set_network(m1_ctx* c, m1nn* net) {

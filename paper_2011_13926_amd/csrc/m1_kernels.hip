@@ -869,6 +869,74 @@ template bool launch_apply_pre<float, double, double>(int, bool, const Geom&, co
 template bool launch_apply_pre<float, float, float>(int, bool, const Geom&, const Scheme&, const Coefs<float>&,
                                                     const Bdry&, const float*, float*, hipStream_t, const int*);
 
+// ----------------------------------------------------------------------------
+// Explicit and semi-implicit time steps (Sect. 3.1): the new state from
+// b = -R(U^n), the Newton right-hand side evaluated at U^k = U^n.  There R(U^n)
+// is the flux divergence H plus the source part S(U^n), so U^n - H = U^n + b + S(U^n).
+//   explicit:      U = U^n + b on the radiation rows, T = T^n + b_T/(rho c_v)
+//   semi-implicit: sources at the new level, per cell (centred flux source):
+//     F_m = (F_m^n - H_Fm)/(1 + k), k = c dt sigma
+//     E   = (E^n - H_E)/(1 + k) with absorption, E^n - H_E without a source
+//     coupled: E* = E^n - H_E, T the root of rho c_v (T - T^n) + k/(1+k) (a_r T^4 - E*)
+//              (Newton from T^n), then E = (E* + k a_r T^4)/(1 + k)
+// ----------------------------------------------------------------------------
+constexpr int kTNewtonMax = 60;
+
+template <int NR, bool CPL, bool SEMI>
+__global__ __launch_bounds__(256) void k_time_update(int64_t N, Scheme sc, const double* __restrict__ sigma,
+                                                     const double* __restrict__ rcv, const double* __restrict__ Un,
+                                                     const double* __restrict__ b, double* __restrict__ U) {
+  const int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (cell >= N) return;
+  const double En = Un[cell], b0 = b[cell];
+  if (!SEMI) {
+#pragma unroll
+    for (int q = 0; q < NR; ++q) U[q * N + cell] = Un[q * N + cell] + b[q * N + cell];
+    if (CPL) U[NR * N + cell] = Un[NR * N + cell] + b[NR * N + cell] / rcv[cell];
+    return;
+  }
+  const double k = sc.cdt * sigma[cell];
+  const double inv = 1.0 / (1.0 + k);
+#pragma unroll
+  for (int q = 1; q < NR; ++q) {
+    const double Fn = Un[q * N + cell];
+    U[q * N + cell] = (Fn + b[q * N + cell] + k * Fn) * inv;
+  }
+  if (CPL) {
+    const double Tn = Un[NR * N + cell], rc = rcv[cell];
+    const double Es = En + b0 - k * (sc.a_r * Tn * Tn * Tn * Tn - En);
+    const double w = k * inv;
+    double T = Tn;
+    for (int it = 0; it < kTNewtonMax; ++it) {
+      const double T3 = T * T * T;
+      const double gT = rc * (T - Tn) + w * (sc.a_r * T3 * T - Es);
+      const double dT = gT / (rc + 4.0 * w * sc.a_r * T3);
+      T -= dT;
+      if (fabs(dT) <= 1e-15 * fabs(T)) break;
+    }
+    U[NR * N + cell] = T;
+    U[cell] = (Es + k * sc.a_r * T * T * T * T) * inv;
+  } else if (sc.src == SRC_ABS) {
+    U[cell] = (En + b0 + k * En) * inv;
+  } else {
+    U[cell] = En + b0;
+  }
+}
+
+void launch_time_update(int nd, bool cpl, bool semi, const Geom& g, const Scheme& sc, const Coefs<double>& cf,
+                        const double* Un, const double* b, double* U, hipStream_t s) {
+  const int64_t grd = (g.N + 255) / 256;
+#define M1_TU(NR_, CPL_, SEMI_) k_time_update<NR_, CPL_, SEMI_><<<grd, 256, 0, s>>>(g.N, sc, cf.sigma, cf.rcv, Un, b, U)
+  if (nd == 2) {
+    if (cpl) { if (semi) M1_TU(3, true, true); else M1_TU(3, true, false); }
+    else { if (semi) M1_TU(3, false, true); else M1_TU(3, false, false); }
+  } else {
+    if (cpl) { if (semi) M1_TU(4, true, true); else M1_TU(4, true, false); }
+    else { if (semi) M1_TU(4, false, true); else M1_TU(4, false, false); }
+  }
+#undef M1_TU
+}
+
 // explicit instantiations
 template void launch_apply<double, double, double>(int, bool, int, const Geom&, const Scheme&, const Coefs<double>&,
                                                    const Bdry&, const double*, const double*, double*, hipStream_t, const int*);

@@ -174,6 +174,38 @@ def beam_shadow(n=(1024, 1024), seed=2011, nclumps=8, sigma_bg=1e-3,
     return p
 
 
+def beam45(n=128, dt=0.5, lambda_floor=0.0, t_background=0.3, t_beam=1.0):
+    """2D beam at 45 degrees in vacuum (Sect. 5.3): no randomness.
+
+    The box [-1, 1]^2 on n x n cells (here in cell units, dx = 1), sigma = 0,
+    radiation only.  Initial state E = a_r t_background^4 (300 K against a 1000 K
+    beam: t_background = 0.3 in units of the beam temperature), F = 0.  The -x
+    face is Dirichlet: on the cells with y in [-0.875, -0.75] (rows n/16 .. n/8 - 1,
+    8 cells at n = 128) the ghost holds E = a_r t_beam^4 and F = c E (1, 1)/sqrt 2
+    (reduced flux 1 along the diagonal); on the rest of that face the ghost holds
+    the background state.  The other faces are outflow.  Centred flux source
+    (sigma = 0 makes the source choice immaterial).  lambda_floor = 1 gives the
+    fixed eigenvalues +-c of the paper's comparison.  dt = 0.5 is the explicit
+    CFL limit c dt = dx / 2 of the 2D scheme.
+    """
+    p = base_problem((n, n), dt=dt, flux_source="centered", lambda_floor=lambda_floor,
+                     bc=["dirichlet", "outflow", "outflow", "outflow"])
+    e_bg = p["a_r"] * t_background ** 4
+    e_beam = p["a_r"] * t_beam ** 4
+    rows = np.arange(n)
+    on = ((rows >= n // 16) & (rows < n // 8)).astype(float)
+    ghost = np.zeros((3, n))
+    ghost[0] = e_bg + (e_beam - e_bg) * on
+    ghost[1] = ghost[2] = p["c"] * e_beam * on / np.sqrt(2.0)
+    p["ghost"][0] = ghost
+    p["sigma"] = np.zeros((n, n))
+    p["rho_cv"] = None
+    p["E"] = np.full((n, n), e_bg)
+    p["F"] = np.zeros((2, n, n))
+    p["T"] = None
+    return p
+
+
 def gaussian_random_field(shape, seed, slope=-11.0 / 3.0):
     """Zero-mean, unit-variance periodic Gaussian random field.
 
