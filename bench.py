@@ -49,6 +49,7 @@ CLASS_KERNEL = {
     "x_update": ("k_xupdate<",), "block_jacobi": ("k_bj<",),
     "true_residual": ("k_apply2d_lds<false, 1", "k_apply2d_lds<true, 1", "k_stencil<2, false, 1",
                       "k_stencil<2, true, 1", "k_stencil<3, false, 1", "k_stencil<3, true, 1"),
+    "time_step": ("k_step2d_lds<", "k_step_direct<"),
 }
 
 
@@ -83,6 +84,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=0)
     ap.add_argument("--workload", default="voronoi_512", choices=sorted(WORKLOADS))
     ap.add_argument("--variants", default="fp64,mixed,mixed32")
+    ap.add_argument("--scheme", default="implicit", choices=["implicit", "semi_implicit", "explicit"],
+                    help="implicit (the default benchmark) or the explicit / semi-implicit step at the CFL "
+                         "time step, advancing the workload's dt per timed step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-events", action="store_true", help="do not time kernels with HIP events")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -350,6 +354,117 @@ def cpu_baseline(p, U0, fp64_result):
                        f"({newton:.1f} Newton, {krylov:.0f} Krylov iterations per step); BLAS limited to 1 thread")}
 
 
+TIME_STEP_METRIC = {
+    "semi_implicit": "semi-implicit M1 cell-updates/s at the CFL time step (sources implicit)",
+    "explicit": "explicit M1 cell-updates/s at the CFL time step",
+}
+
+
+def time_step_cpu_baseline(p, U0, scheme, dt):
+    """The oracle's explicit / semi-implicit step on the whole grid, one step, 1 thread."""
+    from threadpoolctl import threadpool_limits
+
+    import numpy as np
+    from oracle import m1_oracle as O
+
+    N = int(np.prod(p["n"][:p["ndim"]]))
+    what = "the whole grid"
+    if N > (1 << 21):
+        # a slab of whole planes along the slowest axis, outflow on its cut faces
+        nz = p["n"][-1]
+        k = max(1, (1 << 21) // (N // nz))
+        q = dict(p, n=tuple(p["n"][:-1]) + (k,), bc=list(p["bc"]))
+        q["bc"][2 * (p["ndim"] - 1)] = q["bc"][2 * (p["ndim"] - 1) + 1] = "outflow"
+        q["ghost"] = {f: v for f, v in p["ghost"].items() if f < 2 * (p["ndim"] - 1)}
+        q["ghost_mask"] = {f: v for f, v in p["ghost_mask"].items() if f < 2 * (p["ndim"] - 1)}
+        for key in ("sigma", "rho_cv", "E", "T"):
+            if q.get(key) is not None:
+                q[key] = p[key][:k]
+        q["F"] = p["F"][:, :k]
+        p, U0 = q, U0[:, :k]
+        what = f"a slab of {k} of the {nz} planes (outflow on the cut)"
+    with threadpool_limits(limits=1):
+        sch = O.Scheme.from_problem(p)
+        f = O.semi_implicit_step if scheme == "semi_implicit" else O.explicit_step
+        t0 = time.perf_counter()
+        f(sch, p["sigma"], p.get("rho_cv"), U0, dt)
+        t = time.perf_counter() - t0
+    n_sample = int(np.prod(p["n"][:p["ndim"]]))
+    return {"value": n_sample / t, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"one oracle {scheme} step of {what}, {n_sample} cells ({t:.2f}s); BLAS limited to 1 thread"}
+
+
+def time_step_bench(args):
+    """Explicit or semi-implicit steps at the CFL time step c dt = dx / ndim; one
+    timed step advances the workload's own dt (the interval one implicit step
+    covers) in ceil(dt / dt_CFL) sub-steps, from the same initial state each time."""
+    import math
+
+    import numpy as np
+    import torch
+
+    import paper_2011_13926_amd as P
+    import workloads as W
+
+    workload = args.workload
+    p = WORKLOADS[workload]["make"](W)
+    if args.scheme == "semi_implicit":
+        p["flux_source"] = "centered"
+    U0 = state0(p)
+    dt_cfl = p["dx"] / (p["c"] * p["ndim"])
+    nsub = int(math.ceil(p["dt"] / dt_cfl - 1e-12))
+    s = P.Solver(p, restart=1)
+    f = s.semi_implicit_step if args.scheme == "semi_implicit" else s.explicit_step
+    try:
+        U0d = s.to_device(U0)
+        U = U0d.clone()
+        for _ in range(args.warmup):
+            U.copy_(U0d)
+            f(U, dt=dt_cfl, nsteps=nsub, raise_on_fail=False)
+        torch.cuda.synchronize()
+        s.profile_enable(not args.no_events)
+        wall, statuses = 0.0, []
+        for k in range(args.steps):
+            U.copy_(U0d)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st, sd = f(U, dt=dt_cfl, nsteps=nsub, raise_on_fail=False)
+            torch.cuda.synchronize()
+            wall += time.perf_counter() - t0
+            statuses.append(st)
+            print(f"[bench] {args.scheme} step {k}: {nsub} sub-steps status={st} {sd['seconds'] * 1e3:.2f} ms "
+                  f"min E {float(U[0].min()):.3e}", file=sys.stderr, flush=True)
+        prof = s.profile() if not args.no_events else {}
+        s.profile_enable(False)
+    finally:
+        s.close()
+    N = int(np.prod(p["n"][:p["ndim"]]))
+    roof, _ = roofline(prof, workload + "_" + args.scheme)
+    out = {
+        "metric": TIME_STEP_METRIC[args.scheme],
+        "value": N * nsub * args.steps / wall,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * wall / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": workload, "grid": list(p["n"][:p["ndim"]]), "scheme": args.scheme,
+                   "dt_cfl": dt_cfl, "substeps_per_step": nsub, "advanced_per_step": nsub * dt_cfl,
+                   "flux_source": p["flux_source"], "lambda_floor": p["lambda_floor"]},
+        "status": statuses,
+        "roofline": roof,
+        "kernels": prof,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = time_step_cpu_baseline(p, U0, args.scheme, dt_cfl)
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.copy_calibration:
@@ -362,6 +477,9 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
                           "n_gpus": args.gpus}), flush=True)
         sys.exit(2)
+    if args.scheme != "implicit":
+        time_step_bench(args)
+        return
     import numpy as np
     import torch
 

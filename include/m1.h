@@ -204,30 +204,31 @@ m1_status m1_residual(m1_ctx* ctx, double* R);
  * stats may be NULL.  Blocks until the step's status is known. */
 m1_status m1_implicit_step(m1_ctx* ctx, m1_state* U, double dt, m1_stats* stats);
 
-/* Explicit (forward-Euler) step of the same spatial scheme: U^{n+1} = U^n - R(U^n),
- * the residual of Sect. 3.1.1 evaluated once at U^n (closure, HLL speeds and alpha
- * at time n); the T row is divided by rho c_v.  U holds U^n on entry and U^{n+1}
- * on return (device buffers, not retained).  dt > 0; U.E > 0 and finite
- * (M1_ERR_INVALID_ARG / M1_ERR_NONFINITE otherwise, U unchanged).  Positivity
- * of E needs the hyperbolic CFL bound c dt <= dx / ndim and, with sources,
- * c dt sigma < 1; neither is checked.  A non-finite result returns
- * M1_ERR_NONFINITE and leaves U unchanged.  stats (may be NULL): iteration
- * counts 0, cells_f_gt_1 of U^{n+1}, wall time.  Blocks until done.  The
- * context's linearisation afterwards is the one at U^n. */
-m1_status m1_explicit_step(m1_ctx* ctx, m1_state* U, double dt, m1_stats* stats);
+/* nsteps explicit (forward-Euler) steps of the same spatial scheme:
+ * U^{n+1} = U^n - R(U^n), the residual of Sect. 3.1.1 evaluated at U^n (closure,
+ * HLL speeds and alpha at time n); the T row is divided by rho c_v.  U holds
+ * U^n on entry and U^{n+nsteps} on return (device buffers, not retained).
+ * dt > 0, nsteps >= 1; U.E > 0 and finite on entry (M1_ERR_INVALID_ARG /
+ * M1_ERR_NONFINITE otherwise, U unchanged).  Positivity of E needs the
+ * hyperbolic CFL bound c dt <= dx / ndim and, with sources, c dt sigma < 1;
+ * neither is checked, and E is not checked between the steps.  A non-finite
+ * final state returns M1_ERR_NONFINITE and leaves U unchanged.  stats (may be
+ * NULL): iteration counts 0, cells_f_gt_1 of the final state, wall time.
+ * Blocks until done.  The context's linearisation (m1_linearize) is kept. */
+m1_status m1_explicit_step(m1_ctx* ctx, m1_state* U, double dt, int32_t nsteps, m1_stats* stats);
 
-/* Semi-implicit step (Sect. 3.1: sources implicit, hyperbolic part explicit):
- * with H = R(U^n) - S(U^n) the flux divergence at time n and S the source part
- * of the residual, U^{n+1} solves U - U^n + H + S(U) = 0 cell by cell:
- * F_m = (F_m^n - H_Fm)/(1 + k), k = c dt sigma; E = (E^n - H_E)/(1 + k) with
- * absorption, E^n - H_E without a source; with the T row, T is the root of
- * rho c_v (T - T^n) + k/(1+k) (a_r T^4 - E*) (E* = E^n - H_E; Newton from T^n,
- * at most 60 iterations, stopping once |dT| <= 1e-15 T) and
+/* nsteps semi-implicit steps (Sect. 3.1: sources implicit, hyperbolic part
+ * explicit): with H = R(U^n) - S(U^n) the flux divergence at time n and S the
+ * source part of the residual, U^{n+1} solves U - U^n + H + S(U) = 0 cell by
+ * cell: F_m = (F_m^n - H_Fm)/(1 + k), k = c dt sigma; E = (E^n - H_E)/(1 + k)
+ * with absorption, E^n - H_E without a source; with the T row, T is the root
+ * of rho c_v (T - T^n) + k/(1+k) (a_r T^4 - E*) (E* = E^n - H_E; Newton from
+ * T^n, at most 60 iterations, stopping once |dT| <= 1e-15 T) and
  * E = (E* + k a_r T^4)/(1 + k).  Requires the centred flux source (Eq.
  * "wb_naive"): the well-balanced source couples neighbouring cells, and the
  * call returns M1_ERR_INVALID_ARG.  Arguments, errors and stats as for
  * m1_explicit_step; the CFL bound still applies, for any sigma. */
-m1_status m1_semi_implicit_step(m1_ctx* ctx, m1_state* U, double dt, m1_stats* stats);
+m1_status m1_semi_implicit_step(m1_ctx* ctx, m1_state* U, double dt, int32_t nsteps, m1_stats* stats);
 
 void m1_destroy(m1_ctx* ctx);
 const char* m1_last_error(const m1_ctx* ctx);

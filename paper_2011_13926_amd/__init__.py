@@ -90,8 +90,8 @@ _sig = {
     "m1_precondition": (ctypes.c_int32, [_vp, _vp, _vp]),
     "m1_residual": (ctypes.c_int32, [_vp, _vp]),
     "m1_implicit_step": (ctypes.c_int32, [_vp, _P(M1State), ctypes.c_double, _P(M1Stats)]),
-    "m1_explicit_step": (ctypes.c_int32, [_vp, _P(M1State), ctypes.c_double, _P(M1Stats)]),
-    "m1_semi_implicit_step": (ctypes.c_int32, [_vp, _P(M1State), ctypes.c_double, _P(M1Stats)]),
+    "m1_explicit_step": (ctypes.c_int32, [_vp, _P(M1State), ctypes.c_double, ctypes.c_int32, _P(M1Stats)]),
+    "m1_semi_implicit_step": (ctypes.c_int32, [_vp, _P(M1State), ctypes.c_double, ctypes.c_int32, _P(M1Stats)]),
     "m1_destroy": (None, [_vp]),
     "m1_last_error": (ctypes.c_char_p, [_vp]),
     "m1_profile_enable": (ctypes.c_int32, [_vp, ctypes.c_int32]),
@@ -324,21 +324,21 @@ class Solver:
             raise M1Error(st, _lib.m1_last_error(self.ctx).decode())
         return st, stats.as_dict()
 
-    def _time_step(self, fn, U, dt, raise_on_fail):
+    def _time_step(self, fn, U, dt, nsteps, raise_on_fail):
         stats = M1Stats()
         st = fn(self.ctx, ctypes.byref(state_struct(U, self.ndim, self.coupled)),
-                float(dt if dt is not None else self.p["dt"]), ctypes.byref(stats))
+                float(dt if dt is not None else self.p["dt"]), int(nsteps), ctypes.byref(stats))
         if raise_on_fail and st != M1_OK:
             raise M1Error(st, _lib.m1_last_error(self.ctx).decode())
         return st, stats.as_dict()
 
-    def explicit_step(self, U, dt=None, *, raise_on_fail=True):
-        """Forward-Euler step of the device tensor U in place; returns (status, stats dict)."""
-        return self._time_step(_lib.m1_explicit_step, U, dt, raise_on_fail)
+    def explicit_step(self, U, dt=None, nsteps=1, *, raise_on_fail=True):
+        """nsteps forward-Euler steps of the device tensor U in place; returns (status, stats dict)."""
+        return self._time_step(_lib.m1_explicit_step, U, dt, nsteps, raise_on_fail)
 
-    def semi_implicit_step(self, U, dt=None, *, raise_on_fail=True):
-        """Semi-implicit step (sources implicit, fluxes explicit) of U in place (centred flux source)."""
-        return self._time_step(_lib.m1_semi_implicit_step, U, dt, raise_on_fail)
+    def semi_implicit_step(self, U, dt=None, nsteps=1, *, raise_on_fail=True):
+        """nsteps semi-implicit steps (sources implicit, fluxes explicit) of U in place (centred flux source)."""
+        return self._time_step(_lib.m1_semi_implicit_step, U, dt, nsteps, raise_on_fail)
 
     def set_network(self, net):
         self._net = net

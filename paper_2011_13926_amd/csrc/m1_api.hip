@@ -23,7 +23,7 @@ namespace {
 const char* kClassNames[KC_COUNT] = {"setup",   "setup_bj", "residual",   "apply",         "block_jacobi",
                                      "arnoldi_dot", "arnoldi_scalar", "arnoldi_update", "x_update",
                                      "true_residual", "newton_update", "norm", "convert", "learned_pc", "apply_bj_fused",
-                                     "time_update"};
+                                     "time_step"};
 
 struct Profiler {
   bool on = false;
@@ -545,40 +545,46 @@ m1_status solve(m1_ctx* c, double bnorm, SolveResult& res, int& fell_back) {
 
 }  // namespace
 
-// Explicit (semi = false) or semi-implicit step: one evaluation of the scheme at
-// U^n (a1, a2), then a per-cell update of the state (no linear solve).
-m1_status time_step(m1_ctx* c, m1_state* U, double dt, m1_stats* stats, bool semi) {
+// nsteps explicit (semi = false) or semi-implicit steps, one fused kernel each
+// (a1, a2 and the update), ping-ponging between the context's two work vectors
+// b and x, so the linearisation held in Uk, Un and the coefficient slab stays.
+m1_status time_steps(m1_ctx* c, m1_state* U, double dt, int32_t nsteps, m1_stats* stats, bool semi) {
   if (!c) return M1_ERR_INVALID_ARG;
   const auto t0 = std::chrono::steady_clock::now();
   if (!(std::isfinite(dt) && dt > 0)) { c->err = "dt must be finite and > 0"; return M1_ERR_INVALID_ARG; }
+  if (nsteps < 1) { c->err = "nsteps must be >= 1"; return M1_ERR_INVALID_ARG; }
   if (semi && c->cfg.flux_source != M1_FSRC_CENTERED) {
     c->err = "the semi-implicit step needs the centred flux source (the well-balanced source couples cells)";
     return M1_ERR_INVALID_ARG;
   }
   m1_status st;
-  if ((st = copy_state_in(c, U, c->Un)) != M1_OK) return st;
-  if ((st = check_array(c, c->Un, c->n, 0, "U", M1_ERR_NONFINITE)) != M1_OK) return st;
-  if ((st = check_array(c, c->Un, c->g.N, 1, "U.E", M1_ERR_INVALID_ARG)) != M1_OK) return st;
-  HIPCHK(c, hipMemcpyAsync(c->Uk, c->Un, sizeof(double) * c->n, hipMemcpyDeviceToDevice, c->stream));
-  set_dt(c, dt);
-  c->sc.psi = 0.0;
-  launch_fn(c->nd, c->g, c->sc, c->Un, c->fn, c->stream);
-  if ((st = linearize_internal(c, false)) != M1_OK) return st;
-  timed(c, KC_RESIDUAL, bytes_residual(c), [&] { launch_residual(c->nd, c->cpl, c->g, c->sc, c->cf64, bdry(c), c->Uk, c->Un, c->b, c->stream); });
-  const double per_cell = 8.0 * (2.0 * c->nu + 1.0 + (c->cpl ? 1.0 : 0.0));
-  timed(c, KC_TIME_UPDATE, per_cell * cells(c), [&] {
-    launch_time_update(c->nd, c->cpl, semi, c->g, c->sc, c->cf64, c->Un, c->b, c->Uk, c->stream);
-  });
+  double* src = c->b;
+  double* dst = c->x;
+  if ((st = copy_state_in(c, U, src)) != M1_OK) return st;
+  if ((st = check_array(c, src, c->n, 0, "U", M1_ERR_NONFINITE)) != M1_OK) return st;
+  if ((st = check_array(c, src, c->g.N, 1, "U.E", M1_ERR_INVALID_ARG)) != M1_OK) return st;
+  // the step kernels read only dt-derived scalars of the scheme; the context's own are kept
+  Scheme sc = c->sc;
+  sc.dt = dt;
+  sc.s = dt / c->cfg.dx;
+  sc.cdt = c->cfg.c * dt;
+  sc.psi = 0.0;
+  const Bdry bd = bdry(c);
+  const double bytes = 8.0 * (2.0 * c->nu + 1.0 + (c->cpl ? 1.0 : 0.0)) * cells(c);
+  for (int32_t k = 0; k < nsteps; ++k) {
+    timed(c, KC_TIME_STEP, bytes, [&] { launch_time_step(c->nd, c->cpl, semi, c->g, sc, c->cf64, bd, src, dst, c->stream); });
+    std::swap(src, dst);
+  }
+  HIPCHK(c, hipGetLastError());
   unsigned long long nf = 0;
   k_zero_u64<<<1, 64, 0, c->stream>>>(c->dcount);
-  launch_count_f(c->nd, c->g, c->Uk, c->cfg.c, c->dcount, c->stream);
+  launch_count_f(c->nd, c->g, src, c->cfg.c, c->dcount, c->stream);
   HIPCHK(c, hipGetLastError());
   HIPCHK(c, hipMemcpyAsync(&nf, c->dcount, sizeof(nf), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   prof_collect(c);
-  // the linearisation held by the context is at U^n, not at the returned state
-  if ((st = check_array(c, c->Uk, c->n, 0, "U^(n+1)", M1_ERR_NONFINITE)) != M1_OK) return st;
-  if ((st = copy_state_out(c, c->Uk, U)) != M1_OK) return st;
+  if ((st = check_array(c, src, c->n, 0, "U^(n+nsteps)", M1_ERR_NONFINITE)) != M1_OK) return st;
+  if ((st = copy_state_out(c, src, U)) != M1_OK) return st;
   HIPCHK(c, hipStreamSynchronize(c->stream));
   if (stats) {
     stats->newton_iters = 0;
@@ -662,6 +668,7 @@ m1_status m1_setup(const m1_config* cfg, const m1_fields* fields, const m1_state
   sc.c2 = cfg->c * cfg->c;
   sc.a_r = cfg->a_r;
   sc.dx = cfg->dx;
+  sc.dx_c = cfg->dx / cfg->c;
   sc.lambda_floor = cfg->lambda_floor;
   sc.src = cfg->source;
   sc.wb = cfg->flux_source == M1_FSRC_WELL_BALANCED;
@@ -972,12 +979,12 @@ m1_status m1_implicit_step(m1_ctx* c, m1_state* U, double dt, m1_stats* stats) {
   return M1_OK;
 }
 
-m1_status m1_explicit_step(m1_ctx* c, m1_state* U, double dt, m1_stats* stats) {
-  return time_step(c, U, dt, stats, false);
+m1_status m1_explicit_step(m1_ctx* c, m1_state* U, double dt, int32_t nsteps, m1_stats* stats) {
+  return time_steps(c, U, dt, nsteps, stats, false);
 }
 
-m1_status m1_semi_implicit_step(m1_ctx* c, m1_state* U, double dt, m1_stats* stats) {
-  return time_step(c, U, dt, stats, true);
+m1_status m1_semi_implicit_step(m1_ctx* c, m1_state* U, double dt, int32_t nsteps, m1_stats* stats) {
+  return time_steps(c, U, dt, nsteps, stats, true);
 }
 
 m1_status m1_set_network(m1_ctx* c, m1nn* net) {

@@ -53,6 +53,7 @@ struct Scheme {
   int p1;            // P1 closure
   int newton;        // differentiate the tensor (1) or freeze it (0)
   double psi;        // pseudo-transient shift of the linear operator (0: none)
+  double dx_c;       // dx / c (the asymptotic correction's scale)
 };
 
 __device__ __forceinline__ int64_t plane_index(int d, int i, int j, int k, const Geom& g) {
@@ -66,6 +67,8 @@ template <int ND> struct ClosureState {
   double chi;
   bool clamped;      // |F| >= cE (or E <= 0 with F != 0): f fixed at 1
   double geoE;       // (3chi-1)/2 * E/|F|: 3f/(c(2+xi)) unclamped, E/|F| clamped, 0 if F = 0
+  double xi;         // sqrt(4 - 3 f^2)
+  double rxi;        // 1 / (xi (xi + 2))
 };
 
 template <int ND>
@@ -79,10 +82,18 @@ __device__ __forceinline__ ClosureState<ND> closure(double E, const double* F, d
   const double fr = Fm / (c * Ep);
   s.clamped = !(fr < 1.0);
   s.f = s.clamped ? 1.0 : fr;
-  // divide (not multiply by 1/|F|): 1/|F| overflows for subnormal |F|
+  // one reciprocal for the direction; divide where 1/|F| would overflow (subnormal |F|)
+  if (Fm > 1e-300) {
+    const double inv = 1.0 / Fm;
 #pragma unroll
-  for (int m = 0; m < ND; ++m) s.nv[m] = Fm > 0.0 ? F[m] / Fm : 0.0;
+    for (int m = 0; m < ND; ++m) s.nv[m] = F[m] * inv;
+  } else {
+#pragma unroll
+    for (int m = 0; m < ND; ++m) s.nv[m] = Fm > 0.0 ? F[m] / Fm : 0.0;
+  }
   const double xi = sqrt(4.0 - 3.0 * s.f * s.f);
+  s.xi = xi;
+  s.rxi = 1.0 / (xi * (xi + 2.0));
   // 3chi - 1 = 6f^2/(2+xi) exactly, so (3chi-1)/2 E/|F| = 3f/(c(2+xi)) without the
   // cancellation of the literal product at small f
   s.geoE = s.clamped ? (Fm > 0.0 ? E / Fm : 0.0) : 3.0 * s.f / (c * (2.0 + xi));
@@ -115,7 +126,7 @@ __device__ __forceinline__ void pressure_jacobian(const ClosureState<ND>& s, dou
   double dchi = 0.0;
   if (!p1 && newton && !s.clamped) {
     const double f = s.f;
-    const double xi = sqrt(4.0 - 3.0 * f * f);
+    const double xi = s.xi;
     const double den = 5.0 + 2.0 * xi;
     dchi = (8.0 * f * den + 6.0 * f * (3.0 + 4.0 * f * f) / xi) / (den * den);
   }
@@ -154,12 +165,13 @@ __device__ __forceinline__ void wave_speeds(const ClosureState<ND>& s, int d, do
   const double f = s.f;
   const double fn = f * s.nv[d];
   const double fperp2 = fmax(f * f - fn * fn, 0.0);
-  const double xi = sqrt(4.0 - 3.0 * f * f);
+  const double xi = s.xi;
   const double q = (xi - 1.0) * (xi + 2.0);
-  // sqrt(2) sqrt(q (2q + 3 fperp^2)) / (sqrt(3) xi (xi+2))
-  const double root = 0.81649658092772603273 * sqrt(q * (2.0 * q + 3.0 * fperp2)) / (xi * (xi + 2.0));
-  lmax = c * (fn / xi + root);
-  lmin = c * (fn / xi - root);
+  // sqrt(2) sqrt(q (2q + 3 fperp^2)) / (sqrt(3) xi (xi+2)); fn / xi = fn (xi+2) / (xi (xi+2))
+  const double root = 0.81649658092772603273 * sqrt(q * (2.0 * q + 3.0 * fperp2)) * s.rxi;
+  const double adv = fn * (xi + 2.0) * s.rxi;
+  lmax = c * (adv + root);
+  lmin = c * (adv - root);
 }
 
 // HLL weights a = l+/(l+ - l-), dd = l+ l-/(l+ - l-) (b = 1 - a) and alpha.
@@ -181,10 +193,11 @@ __device__ __forceinline__ FaceCoef face_coef(double lmaxL, double lminL, double
     fc.a = 0.5;
     fc.dd = 0.0;
   } else {
-    fc.a = lp / den;
-    fc.dd = lp * lm / den;
+    const double inv = 1.0 / den;
+    fc.a = lp * inv;
+    fc.dd = lp * lm * inv;
   }
-  fc.alpha = sc.ap ? 1.0 / (1.0 - 3.0 * sigf * sc.dx * (1.0 - fbar * fbar) * fc.dd / sc.c) : 1.0;
+  fc.alpha = sc.ap ? 1.0 / (1.0 - 3.0 * sigf * sc.dx_c * (1.0 - fbar * fbar) * fc.dd) : 1.0;
   return fc;
 }
 

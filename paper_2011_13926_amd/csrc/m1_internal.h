@@ -50,7 +50,7 @@ struct GmresState {
 
 enum KernelClass {
   KC_SETUP = 0, KC_SETUP_BJ, KC_RESIDUAL, KC_APPLY, KC_BJ, KC_DOT, KC_SCALAR, KC_UPDATE, KC_XUPDATE,
-  KC_TRUE_RESID, KC_NEWTON_UPDATE, KC_NORM, KC_CONVERT, KC_NN, KC_APPLY_PC, KC_TIME_UPDATE, KC_COUNT
+  KC_TRUE_RESID, KC_NEWTON_UPDATE, KC_NORM, KC_CONVERT, KC_NN, KC_APPLY_PC, KC_TIME_STEP, KC_COUNT
 };
 
 // ---- launchers (defined in m1_kernels.hip / m1_krylov.hip) ----
@@ -69,9 +69,10 @@ bool launch_apply_pre(int nd, bool cpl, const Geom& g, const Scheme& sc, const C
                       const VI* u, VO* y, hipStream_t s, const int* skip);
 void launch_residual(int nd, bool cpl, const Geom& g, const Scheme& sc, const Coefs<double>& cf, const Bdry& bd,
                      const double* Uk, const double* Un, double* out_negR, hipStream_t s);
-// explicit (semi = false) or semi-implicit time update from b = -R(U^n)
-void launch_time_update(int nd, bool cpl, bool semi, const Geom& g, const Scheme& sc, const Coefs<double>& cf,
-                        const double* Un, const double* b, double* U, hipStream_t s);
+// one explicit (semi = false) or semi-implicit time step Un -> Uo (distinct buffers);
+// reads only sigma and rho_cv of the coefficient slab
+void launch_time_step(int nd, bool cpl, bool semi, const Geom& g, const Scheme& sc, const Coefs<double>& cf,
+                      const Bdry& bd, const double* Un, double* Uo, hipStream_t s);
 template <typename R, typename VI, typename VO>
 void launch_bj(int nd, bool cpl, const Geom& g, const Coefs<R>& cf, const VI* r, VO* z, hipStream_t s,
                const int* skip = nullptr);

@@ -870,9 +870,11 @@ template bool launch_apply_pre<float, float, float>(int, bool, const Geom&, cons
                                                     const Bdry&, const float*, float*, hipStream_t, const int*);
 
 // ----------------------------------------------------------------------------
-// Explicit and semi-implicit time steps (Sect. 3.1): the new state from
-// b = -R(U^n), the Newton right-hand side evaluated at U^k = U^n.  There R(U^n)
-// is the flux divergence H plus the source part S(U^n), so U^n - H = U^n + b + S(U^n).
+// Explicit and semi-implicit time steps (Sect. 3.1), one fused kernel per step:
+// the residual R(U^n) of the scheme evaluated at U^k = U^n (closure, HLL speeds
+// and alpha of the time-n state, computed on the fly, no stored face
+// coefficients), then the per-cell update from b = -R(U^n).  There R(U^n) is
+// the flux divergence H plus the source part S(U^n), so U^n - H = U^n + b + S(U^n):
 //   explicit:      U = U^n + b on the radiation rows, T = T^n + b_T/(rho c_v)
 //   semi-implicit: sources at the new level, per cell (centred flux source):
 //     F_m = (F_m^n - H_Fm)/(1 + k), k = c dt sigma
@@ -883,28 +885,21 @@ template bool launch_apply_pre<float, float, float>(int, bool, const Geom&, cons
 constexpr int kTNewtonMax = 60;
 
 template <int NR, bool CPL, bool SEMI>
-__global__ __launch_bounds__(256) void k_time_update(int64_t N, Scheme sc, const double* __restrict__ sigma,
-                                                     const double* __restrict__ rcv, const double* __restrict__ Un,
-                                                     const double* __restrict__ b, double* __restrict__ U) {
-  const int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (cell >= N) return;
-  const double En = Un[cell], b0 = b[cell];
+__device__ __forceinline__ void time_update_cell(const Scheme& sc, double sig, double rc, const double* un,
+                                                 const double* b, double* out) {
   if (!SEMI) {
 #pragma unroll
-    for (int q = 0; q < NR; ++q) U[q * N + cell] = Un[q * N + cell] + b[q * N + cell];
-    if (CPL) U[NR * N + cell] = Un[NR * N + cell] + b[NR * N + cell] / rcv[cell];
+    for (int q = 0; q < NR; ++q) out[q] = un[q] + b[q];
+    if (CPL) out[NR] = un[NR] + b[NR] / rc;
     return;
   }
-  const double k = sc.cdt * sigma[cell];
+  const double k = sc.cdt * sig;
   const double inv = 1.0 / (1.0 + k);
 #pragma unroll
-  for (int q = 1; q < NR; ++q) {
-    const double Fn = Un[q * N + cell];
-    U[q * N + cell] = (Fn + b[q * N + cell] + k * Fn) * inv;
-  }
+  for (int q = 1; q < NR; ++q) out[q] = (un[q] + b[q] + k * un[q]) * inv;
   if (CPL) {
-    const double Tn = Un[NR * N + cell], rc = rcv[cell];
-    const double Es = En + b0 - k * (sc.a_r * Tn * Tn * Tn * Tn - En);
+    const double En = un[0], Tn = un[NR];
+    const double Es = En + b[0] - k * (sc.a_r * Tn * Tn * Tn * Tn - En);
     const double w = k * inv;
     double T = Tn;
     for (int it = 0; it < kTNewtonMax; ++it) {
@@ -914,27 +909,323 @@ __global__ __launch_bounds__(256) void k_time_update(int64_t N, Scheme sc, const
       T -= dT;
       if (fabs(dT) <= 1e-15 * fabs(T)) break;
     }
-    U[NR * N + cell] = T;
-    U[cell] = (Es + k * sc.a_r * T * T * T * T) * inv;
+    out[NR] = T;
+    out[0] = (Es + k * sc.a_r * T * T * T * T) * inv;
   } else if (sc.src == SRC_ABS) {
-    U[cell] = (En + b0 + k * En) * inv;
+    out[0] = (un[0] + b[0] + k * un[0]) * inv;
   } else {
-    U[cell] = En + b0;
+    out[0] = un[0] + b[0];
   }
 }
 
-void launch_time_update(int nd, bool cpl, bool semi, const Geom& g, const Scheme& sc, const Coefs<double>& cf,
-                        const double* Un, const double* b, double* U, hipStream_t s) {
-  const int64_t grd = (g.N + 255) / 256;
-#define M1_TU(NR_, CPL_, SEMI_) k_time_update<NR_, CPL_, SEMI_><<<grd, 256, 0, s>>>(g.N, sc, cf.sigma, cf.rcv, Un, b, U)
-  if (nd == 2) {
-    if (cpl) { if (semi) M1_TU(3, true, true); else M1_TU(3, true, false); }
-    else { if (semi) M1_TU(3, false, true); else M1_TU(3, false, false); }
-  } else {
-    if (cpl) { if (semi) M1_TU(4, true, true); else M1_TU(4, true, false); }
-    else { if (semi) M1_TU(4, false, true); else M1_TU(4, false, false); }
+// What a face along direction d needs from the cell (or ghost) on one side.
+template <int ND> struct Side {
+  double u[1 + ND];  // E, F
+  double q[ND];      // c^2 D_{dm} E, m = 0..ND-1
+  double lmax, lmin, f, sig;
+};
+
+template <int ND>
+__device__ __forceinline__ void make_side(const ClosureState<ND>& cs, const double* u, double sig, int d,
+                                          const Scheme& sc, Side<ND>& S) {
+#pragma unroll
+  for (int c = 0; c < 1 + ND; ++c) S.u[c] = u[c];
+#pragma unroll
+  for (int m = 0; m < ND; ++m) S.q[m] = c2D<ND>(cs, d, m, sc.c2) * u[0];
+  wave_speeds<ND>(cs, d, sc.c, sc.p1, S.lmax, S.lmin);
+  S.f = cs.f;
+  S.sig = sig;
+}
+
+// HLL flux (with alpha on the energy row) through the face between L and R along d
+template <int ND>
+__device__ __forceinline__ void face_flux(const Side<ND>& L, const Side<ND>& R, int d, const Scheme& sc, double& FE,
+                                          double* FP) {
+  const FaceCoef fc = face_coef(L.lmax, L.lmin, R.lmax, R.lmin, 0.5 * (L.sig + R.sig), 0.5 * (L.f + R.f), sc);
+  const double b = 1.0 - fc.a;
+  FE = fc.alpha * (fc.a * L.u[1 + d] + b * R.u[1 + d] + fc.dd * (R.u[0] - L.u[0]));
+#pragma unroll
+  for (int m = 0; m < ND; ++m) FP[m] = fc.a * L.q[m] + b * R.q[m] + fc.dd * (R.u[1 + m] - L.u[1 + m]);
+}
+
+// residual contributions of direction d (fluxes and the well-balanced source)
+template <int ND>
+__device__ __forceinline__ void add_direction(const Side<ND>& Lf, const Side<ND>& S, const Side<ND>& Rt, int d,
+                                              const Scheme& sc, double* ys) {
+  double FEp, FEm, FPp[ND], FPm[ND];
+  face_flux<ND>(S, Rt, d, sc, FEp, FPp);
+  face_flux<ND>(Lf, S, d, sc, FEm, FPm);
+  ys[0] += sc.s * (FEp - FEm);
+#pragma unroll
+  for (int m = 0; m < ND; ++m) ys[1 + m] += sc.s * (FPp[m] - FPm[m]);
+  if (sc.wb)
+    ys[1 + d] += 0.25 * sc.cdt * (0.5 * (S.sig + Rt.sig) * (S.u[1 + d] + Rt.u[1 + d]) +
+                                  0.5 * (S.sig + Lf.sig) * (Lf.u[1 + d] + S.u[1 + d]));
+}
+
+// sources of the residual at U^k = U^n, then the update of one cell
+template <int ND, bool CPL, bool SEMI>
+__device__ __forceinline__ void finish_cell(const Scheme& sc, double sig, double rc, const double* xs, double* ys,
+                                            double* out) {
+  constexpr int NR = 1 + ND;
+  constexpr int NU = NR + (CPL ? 1 : 0);
+  if (!sc.wb) {
+#pragma unroll
+    for (int m = 0; m < ND; ++m) ys[1 + m] += sc.cdt * sig * xs[1 + m];
   }
-#undef M1_TU
+  if (sc.src == SRC_ABS) ys[0] += sc.cdt * sig * xs[0];
+  if (CPL) {
+    const double T = xs[NU - 1];
+    const double exch = sc.cdt * sig * (sc.a_r * T * T * T * T - xs[0]);
+    ys[NU - 1] = exch;
+    ys[0] -= exch;
+  }
+  double b[NU];
+#pragma unroll
+  for (int c = 0; c < NU; ++c) b[c] = -ys[c];
+  time_update_cell<NR, CPL, SEMI>(sc, sig, rc, xs, b, out);
+}
+
+// Direct form (3D, and 2D when the LDS tile is switched off): a thread per cell
+// evaluates the closures of its 2 ND neighbours itself.
+template <int ND, bool CPL, bool SEMI>
+__global__ __launch_bounds__(256) void k_step_direct(Geom g, Scheme sc, const double* __restrict__ sigma,
+                                                     const double* __restrict__ rcv, Bdry bd,
+                                                     const double* __restrict__ Un, double* __restrict__ Uo) {
+  constexpr int NR = 1 + ND;
+  constexpr int NU = NR + (CPL ? 1 : 0);
+  CellPos p;
+  if (!cell_pos(g, p)) return;
+  const int64_t N = g.N;
+  double xs[NU], ys[NU], out[NU];
+#pragma unroll
+  for (int c = 0; c < NU; ++c) { xs[c] = Un[c * N + p.cell]; ys[c] = 0.0; }
+  const double sig = sigma[p.cell];
+  const ClosureState<ND> cs = closure<ND>(xs[0], xs + 1, sc.c, sc.p1);
+  // neighbour (or ghost) of this cell on side `side` of direction d
+  auto side_of = [&](int d, int side, Side<ND>& S) {
+    const Nb r = neighbour(g, p, d, side);
+    double u[NR];
+    double sg;
+    if (r.kind == 0) {
+#pragma unroll
+      for (int c = 0; c < NR; ++c) u[c] = Un[c * N + r.nb];
+      sg = sigma[r.nb];
+    } else {
+      const int face = 2 * d + side;
+      ghost_state<ND>(g.bc[face], d, bd.plane[face], bd.mask[face], r.pidx, g.plane_n[d], xs, u);
+      sg = sig;
+    }
+    make_side<ND>(closure<ND>(u[0], u + 1, sc.c, sc.p1), u, sg, d, sc, S);
+  };
+#pragma unroll
+  for (int d = 0; d < ND; ++d) {
+    Side<ND> S, Lf, Rt;
+    make_side<ND>(cs, xs, sig, d, sc, S);
+    side_of(d, 1, Rt);
+    side_of(d, 0, Lf);
+    add_direction<ND>(Lf, S, Rt, d, sc, ys);
+  }
+  finish_cell<ND, CPL, SEMI>(sc, sig, CPL ? rcv[p.cell] : 1.0, xs, ys, out);
+#pragma unroll
+  for (int c = 0; c < NU; ++c) Uo[c * N + p.cell] = out[c];
+}
+
+// 2D LDS form: a workgroup owns a 64 x SY tile (XCD-aware tile order, as the
+// operator kernel).  Every cell of its (64+2) x (SY+2) halo tile is staged once
+// with its closure (state, c^2 D E, speeds along x and y, f, sigma: 12 doubles),
+// then each face of the tile gets its HLL flux once, and each cell sums its four
+// faces: one closure per cell and one flux per face, instead of one per
+// neighbour and two per face.  The face fluxes are kept in registers until the
+// closure data is dead, then written over it, so the LDS footprint stays at the
+// 12 staged doubles per halo cell (38 KB at SY = 4).
+template <int SY> __host__ __device__ inline int step_tiles(int nx, int ny) {
+  return ((nx + LX - 1) / LX) * ((ny + SY - 1) / SY);
+}
+
+template <bool CPL, bool SEMI, int SY>
+__global__ __launch_bounds__(LX * SY) void k_step2d_lds(Geom g, Scheme sc, const double* __restrict__ sigma,
+                                                        const double* __restrict__ rcv, Bdry bd,
+                                                        const double* __restrict__ Un, double* __restrict__ Uo) {
+  constexpr int NR = 3;
+  constexpr int NU = NR + (CPL ? 1 : 0);
+  constexpr int SHY = SY + 2;
+  constexpr int NT = LX * SY;
+  constexpr int PL = SHY * LHX;                       // one staged quantity
+  constexpr int NFX = (LX + 1) * SY, NFY = LX * (SY + 1);
+  constexpr int KF = (NFX + NFY + NT - 1) / NT;       // faces per thread
+  // staged quantities k: 0-2 E, F_x, F_y; 3-5 c^2 D E (xx, xy, yy); 6-9 speeds
+  // (x max, x min, y max, y min); 10 f; 11 sigma.  Face fluxes reuse k = 3..10.
+  static_assert(3 * (NFX + NFY) <= 8 * PL, "face fluxes must fit over the dead closure data");
+  __shared__ double sb[12 * PL];
+  auto at = [&](int k, int b, int a) -> double& { return sb[k * PL + b * LHX + a]; };
+  double* fx = sb + 3 * PL;          // [3][SY][LX+1]: face a is left of cell column a
+  double* fy = fx + 3 * NFX;         // [3][SY+1][LX]: face b is below cell row b
+  const int64_t N = g.N;
+  const int nx = g.n[0], ny = g.n[1];
+  const int gx = (nx + LX - 1) / LX;
+  const int gt = step_tiles<SY>(nx, ny);
+  const int per = (gt + 7) / 8;
+  const int T = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+  if (T >= gt) return;
+  const int tbx = T % gx, tby = T / gx;
+  const int i0 = tbx * LX - 1, j0 = tby * SY - 1;
+  // ---- stage the halo tile with its closures ----
+  for (int t = threadIdx.x; t < PL; t += NT) {
+    const int li = t % LHX, lj = t / LHX;
+    int gi = i0 + li, gj = j0 + lj;
+    const bool outx = gi < 0 || gi >= nx, outy = gj < 0 || gj >= ny;
+    double u[NR] = {0.0, 0.0, 0.0}, q[3] = {0.0, 0.0, 0.0}, lam[4] = {0.0, 0.0, 0.0, 0.0}, f = 0.0, sg = 0.0;
+    // halo corners and cells beyond the ghost layer stay zero (their faces are not used)
+    if (!(outx && outy) && gi < nx + 1 && gj < ny + 1) {
+      int face = -1, d = 0;
+      if (outx) {
+        d = 0;
+        if (g.bc[0] == BC_PERIODIC) gi = (gi + nx) % nx;
+        else { face = gi < 0 ? 0 : 1; gi = gi < 0 ? 0 : nx - 1; }
+      } else if (outy) {
+        d = 1;
+        if (g.bc[2] == BC_PERIODIC) gj = (gj + ny) % ny;
+        else { face = gj < 0 ? 2 : 3; gj = gj < 0 ? 0 : ny - 1; }
+      }
+      const int64_t cell = (int64_t)gj * nx + gi;
+#pragma unroll
+      for (int c = 0; c < NR; ++c) u[c] = Un[c * N + cell];
+      sg = sigma[cell];
+      if (face >= 0) {
+        double ub[NR];
+#pragma unroll
+        for (int c = 0; c < NR; ++c) ub[c] = u[c];
+        const int64_t pidx = d == 0 ? (int64_t)gj : (int64_t)gi;
+        ghost_state<2>(g.bc[face], d, bd.plane[face], bd.mask[face], pidx, g.plane_n[d], ub, u);
+      }
+      const ClosureState<2> cs = closure<2>(u[0], u + 1, sc.c, sc.p1);
+      q[0] = c2D<2>(cs, 0, 0, sc.c2) * u[0];
+      q[1] = c2D<2>(cs, 0, 1, sc.c2) * u[0];
+      q[2] = c2D<2>(cs, 1, 1, sc.c2) * u[0];
+      wave_speeds<2>(cs, 0, sc.c, sc.p1, lam[0], lam[1]);
+      wave_speeds<2>(cs, 1, sc.c, sc.p1, lam[2], lam[3]);
+      f = cs.f;
+    }
+#pragma unroll
+    for (int c = 0; c < NR; ++c) at(c, lj, li) = u[c];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) at(3 + c, lj, li) = q[c];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) at(6 + c, lj, li) = lam[c];
+    at(10, lj, li) = f;
+    at(11, lj, li) = sg;
+  }
+  __syncthreads();
+  auto load = [&](int d, int a, int b, Side<2>& S) {
+#pragma unroll
+    for (int c = 0; c < NR; ++c) S.u[c] = at(c, b, a);
+    S.q[0] = at(3 + d, b, a);
+    S.q[1] = at(4 + d, b, a);
+    S.lmax = at(6 + 2 * d, b, a);
+    S.lmin = at(7 + 2 * d, b, a);
+    S.f = at(10, b, a);
+    S.sig = at(11, b, a);
+  };
+  // ---- one flux per face, held in registers ----
+  double ff[KF][3];
+#pragma unroll
+  for (int k = 0; k < KF; ++k) {
+    const int t = threadIdx.x + k * NT;
+    if (t < NFX + NFY) {
+      Side<2> L, R;
+      if (t < NFX) {
+        const int a = t % (LX + 1), r = t / (LX + 1);
+        load(0, a, r + 1, L);
+        load(0, a + 1, r + 1, R);
+        face_flux<2>(L, R, 0, sc, ff[k][0], &ff[k][1]);
+      } else {
+        const int v = t - NFX;
+        const int a = v % LX, b = v / LX;
+        load(1, a + 1, b, L);
+        load(1, a + 1, b + 1, R);
+        face_flux<2>(L, R, 1, sc, ff[k][0], &ff[k][1]);
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < KF; ++k) {
+    const int t = threadIdx.x + k * NT;
+    if (t < NFX) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) fx[c * NFX + t] = ff[k][c];
+    } else if (t < NFX + NFY) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) fy[c * NFY + (t - NFX)] = ff[k][c];
+    }
+  }
+  __syncthreads();
+  // ---- each cell: divergence of its four faces, sources, update ----
+  const int tx = threadIdx.x % LX, ty = threadIdx.x / LX;
+  const int i = tbx * LX + tx, j = tby * SY + ty;
+  if (i >= nx || j >= ny) return;
+  const int64_t cell = (int64_t)j * nx + i;
+  const int li = tx + 1, lj = ty + 1;
+  double xs[NU], ys[NU], out[NU];
+#pragma unroll
+  for (int c = 0; c < NR; ++c) xs[c] = at(c, lj, li);
+  if (CPL) xs[NU - 1] = Un[(NU - 1) * N + cell];
+#pragma unroll
+  for (int c = 0; c < NU; ++c) ys[c] = 0.0;
+  const double sig = at(11, lj, li);
+  // x: faces tx (minus) and tx + 1 (plus) of row ty; y: faces ty and ty + 1 of column tx
+  const int xm = ty * (LX + 1) + tx, ym = ty * LX + tx;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) ys[c] += sc.s * (fx[c * NFX + xm + 1] - fx[c * NFX + xm]);
+  if (sc.wb)
+    ys[1] += 0.25 * sc.cdt * (0.5 * (sig + at(11, lj, li + 1)) * (xs[1] + at(1, lj, li + 1)) +
+                              0.5 * (sig + at(11, lj, li - 1)) * (at(1, lj, li - 1) + xs[1]));
+#pragma unroll
+  for (int c = 0; c < 3; ++c) ys[c] += sc.s * (fy[c * NFY + ym + LX] - fy[c * NFY + ym]);
+  if (sc.wb)
+    ys[2] += 0.25 * sc.cdt * (0.5 * (sig + at(11, lj + 1, li)) * (xs[2] + at(2, lj + 1, li)) +
+                              0.5 * (sig + at(11, lj - 1, li)) * (at(2, lj - 1, li) + xs[2]));
+  finish_cell<2, CPL, SEMI>(sc, sig, CPL ? rcv[cell] : 1.0, xs, ys, out);
+#pragma unroll
+  for (int c = 0; c < NU; ++c) Uo[c * N + cell] = out[c];
+}
+
+// tile height of the 2D step kernel (cells per tile 64 x sy; M1_STEP_TILE_Y = 4 or 8)
+static int step_tile_y() {
+  static int sy = 0;
+  if (!sy) {
+    const char* e = getenv("M1_STEP_TILE_Y");
+    sy = (e && atoi(e) == 4) ? 4 : 8;
+  }
+  return sy;
+}
+
+void launch_time_step(int nd, bool cpl, bool semi, const Geom& g, const Scheme& sc, const Coefs<double>& cf,
+                      const Bdry& bd, const double* Un, double* Uo, hipStream_t s) {
+  if (nd == 2 && use_lds_2d()) {
+    const int sy = step_tile_y();
+#define M1_TS(CPL_, SEMI_, SY_)                                                                       \
+  k_step2d_lds<CPL_, SEMI_, SY_><<<dim3(8 * ((step_tiles<SY_>(g.n[0], g.n[1]) + 7) / 8)), LX * SY_, 0, s>>>( \
+      g, sc, cf.sigma, cf.rcv, bd, Un, Uo)
+#define M1_TS_Y(CPL_, SEMI_) \
+  if (sy == 4) M1_TS(CPL_, SEMI_, 4); else M1_TS(CPL_, SEMI_, 8)
+    if (cpl) { if (semi) { M1_TS_Y(true, true); } else { M1_TS_Y(true, false); } }
+    else { if (semi) { M1_TS_Y(false, true); } else { M1_TS_Y(false, false); } }
+#undef M1_TS_Y
+#undef M1_TS
+    return;
+  }
+  dim3 blk(TX, TY), grd((g.n[0] + TX - 1) / TX, (g.rows + TY - 1) / TY);
+#define M1_TD(ND_, CPL_, SEMI_) k_step_direct<ND_, CPL_, SEMI_><<<grd, blk, 0, s>>>(g, sc, cf.sigma, cf.rcv, bd, Un, Uo)
+  if (nd == 2) {
+    if (cpl) { if (semi) M1_TD(2, true, true); else M1_TD(2, true, false); }
+    else { if (semi) M1_TD(2, false, true); else M1_TD(2, false, false); }
+  } else {
+    if (cpl) { if (semi) M1_TD(3, true, true); else M1_TD(3, true, false); }
+    else { if (semi) M1_TD(3, false, true); else M1_TD(3, false, false); }
+  }
+#undef M1_TD
 }
 
 // explicit instantiations

@@ -117,6 +117,47 @@ def test_semi_implicit_without_opacity_is_the_explicit_step_bitwise(src):
         s.close()
 
 
+@pytest.mark.parametrize("src,n", [("coupled_t", (70, 9)), ("absorption", (23, 19, 11))])
+def test_nsteps_in_one_call_equals_single_steps_bitwise(src, n):
+    import torch
+    import paper_2011_13926_amd as P
+    _say("nsteps", src, n)
+    bc = BC2 if len(n) == 2 else BC3
+    p = W.random_problem(n, 26, source=src, flux_source="centered", bc=bc, dt=0.2, fmax=0.5,
+                         sigma_range=(1e-2, 1e0))
+    Un = _state(p)
+    s = P.Solver(p)
+    try:
+        for kind in ("explicit_step", "semi_implicit_step"):
+            Ua = s.to_device(Un)
+            Ub = s.to_device(Un)
+            getattr(s, kind)(Ua, nsteps=7)
+            for _ in range(7):
+                getattr(s, kind)(Ub)
+            assert torch.equal(Ua, Ub), kind
+    finally:
+        s.close()
+
+
+def test_time_step_keeps_the_linearisation():
+    """A time step between m1_linearize and m1_residual does not change R."""
+    import paper_2011_13926_amd as P
+    _say("linearisation kept")
+    p = W.random_problem((40, 33), 27, source="absorption", flux_source="centered", bc=BC2, dt=0.3)
+    U = _state(p, "0")
+    Un = _state(p)
+    s = P.Solver(p, U_lin=U, U_n=Un)
+    try:
+        R0 = s.residual().cpu().numpy()
+        V = s.to_device(Un)
+        s.semi_implicit_step(V, nsteps=3)
+        s.explicit_step(V)
+        R1 = s.residual().cpu().numpy()
+        assert np.array_equal(R0, R1)
+    finally:
+        s.close()
+
+
 def test_semi_implicit_rejects_the_well_balanced_source_and_bad_input():
     import torch
     import paper_2011_13926_amd as P
@@ -131,6 +172,9 @@ def test_semi_implicit_rejects_the_well_balanced_source_and_bad_input():
         assert st == P.M1_ERR_INVALID_ARG and torch.equal(U, before)
         for bad_dt in (0.0, -1.0, float("nan")):
             st, _ = s.explicit_step(U, dt=bad_dt, raise_on_fail=False)
+            assert st == P.M1_ERR_INVALID_ARG and torch.equal(U, before)
+        for bad_n in (0, -3):
+            st, _ = s.explicit_step(U, nsteps=bad_n, raise_on_fail=False)
             assert st == P.M1_ERR_INVALID_ARG and torch.equal(U, before)
         U[0, 3, 4] = -1.0
         st, _ = s.explicit_step(U, raise_on_fail=False)
@@ -186,8 +230,7 @@ def test_beam45_many_steps_matches_oracle_and_paper_widths():
         s = P.Solver(p)
         try:
             U = s.to_device(U0)
-            for _ in range(500):
-                s.semi_implicit_step(U)
+            s.semi_implicit_step(U, nsteps=500)
             got = U.cpu().numpy()
         finally:
             s.close()
