@@ -95,6 +95,9 @@ def parse():
                     help="turn rocprofv3 CSV output under DIR/{trace,fetch,write,copy_fetch,copy_write} into "
                          "profiles/<workload>_kernels.md and profiles/<workload>_traffic.json")
     ap.add_argument("--profile-commands", default="", help="text recorded with --summarize-profiles")
+    ap.add_argument("--profile-name", default=None,
+                    help="label of the summaries written by --summarize-profiles (default: the workload; "
+                         "'<workload>_<scheme>' for the explicit and semi-implicit benchmarks)")
     return ap.parse_args()
 
 
@@ -471,7 +474,7 @@ def main():
         copy_calibration()
         return
     if args.summarize_profiles:
-        summarize_profiles(args.summarize_profiles, args.workload, args.profile_commands)
+        summarize_profiles(args.summarize_profiles, args.profile_name or args.workload, args.profile_commands)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
