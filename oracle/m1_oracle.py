@@ -822,3 +822,65 @@ def discrete_diffusion_step(sigma, E, dt, c=1.0, dx=1.0):
     A = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
                       shape=(N, N))
     return spla.spsolve(A.tocsc(), E.ravel()).reshape(shape)
+
+
+def equilibrium_diffusion_step(T, Tn, dt, sigma, rho_cv, c=1.0, a_r=1.0, dx=1.0, left=None, right="outflow",
+                               newton_max=60):
+    """Backward-Euler step of the equilibrium diffusion limit (Eq. "diffusionEqua") on a 1D row.
+
+    The total energy E + rho c_v T with E = a_r T^4 obeys
+        (E_i + rho_cv_i T_i) - (E_i^n + rho_cv_i T_i^n)
+            = dt/dx^2 [k_{i+1/2} (E_{i+1} - E_i) - k_{i-1/2} (E_i - E_{i-1})],
+    k = c / (3 sigma_face) with sigma_face the arithmetic mean of the two cells
+    (the face opacity of the scheme's asymptotic correction).  Boundaries: `left`
+    a temperature held in a ghost cell one cell beyond the first (with the first
+    cell's sigma), or None for no flux; `right` "outflow" (no diffusive flux);
+    left = "periodic" wraps both ends.  T is the Newton starting guess (usually
+    T^n); Newton on T with the tridiagonal Jacobian, stopping once |dT| <= 1e-14 T.
+    """
+    from scipy.linalg import solve_banded
+
+    T = np.array(T, dtype=float, copy=True)
+    Tn = np.asarray(Tn, float)
+    sig = np.asarray(sigma, float)
+    rc = np.broadcast_to(np.asarray(rho_cv, float), T.shape)
+    n = T.size
+    periodic = isinstance(left, str) and left == "periodic"
+    if periodic:
+        kr = c / (3.0 * 0.5 * (sig + np.roll(sig, -1)))          # face i+1/2, i = 0..n-1 (wraps)
+    else:
+        kr = np.zeros(n)
+        kr[:-1] = c / (3.0 * 0.5 * (sig[:-1] + sig[1:]))         # right face closed: outflow, no flux
+    kl = np.roll(kr, 1)
+    if not periodic:
+        kl[0] = c / (3.0 * sig[0]) if left is not None else 0.0
+    lam = dt / (dx * dx)
+    total_n = a_r * Tn ** 4 + rc * Tn
+    Eg = a_r * float(left) ** 4 if (left is not None and not periodic) else 0.0
+    for _ in range(newton_max):
+        E = a_r * T ** 4
+        dE = 4.0 * a_r * T ** 3
+        Er = np.roll(E, -1)
+        El = np.roll(E, 1)
+        if not periodic:
+            Er[-1] = E[-1]
+            El[0] = Eg
+        g = E + rc * T - total_n - lam * (kr * (Er - E) - kl * (E - El))
+        diag = dE + rc + lam * (kr + kl) * dE
+        up = -lam * kr * np.roll(dE, -1)      # d g_i / d T_{i+1}
+        lo = -lam * kl * np.roll(dE, 1)       # d g_i / d T_{i-1}
+        if periodic:
+            J = np.diag(diag) + np.diag(up[:-1], 1) + np.diag(lo[1:], -1)
+            J[-1, 0] += up[-1]
+            J[0, -1] += lo[0]
+            d = np.linalg.solve(J, g)
+        else:
+            ab = np.zeros((3, n))
+            ab[0, 1:] = up[:-1]
+            ab[1] = diag
+            ab[2, :-1] = lo[1:]
+            d = solve_banded((1, 1), ab, g)
+        T = T - d
+        if np.all(np.abs(d) <= 1e-14 * np.abs(T)):
+            break
+    return T
