@@ -44,3 +44,29 @@ def test_equilibrium_diffusion_without_heat_capacity_is_the_linear_diffusion_ste
     Te = O.equilibrium_diffusion_step(T, T, 30.0, s, 0.0, left="periodic")
     Ed = O.discrete_diffusion_step(s[None, :], (T ** 4)[None, :], 30.0)[0]
     assert np.abs(Te ** 4 - Ed).max() <= 1e-12 * Ed.max()
+
+
+def test_marshak_wave_asymptotic_preserving_scheme_reaches_the_diffusion_reference():
+    """Sect. 5.1 (nondimensional): 400 cells at sigma dx = 25, gas coupled (rho c_v = 1),
+    a source at T = 1 lit on the left of a medium at 0.3.  Ten implicit steps of the
+    scheme with the asymptotic correction (dt = 1e4, c sigma dt = 2.5e5) against ten
+    backward-Euler steps of the equilibrium diffusion limit: the gas temperature agrees
+    to 1e-3 in relative L2 and the wave front (T = 0.65) sits in the same cell.  A
+    dropped or mis-scaled alpha moves the front by a hundred cells (plain HLL: 214
+    against 45)."""
+    import workloads as W
+    n, dt, nsteps, T0 = 400, 1e4, 10, 0.3
+    Tref = np.full(n, T0)
+    for _ in range(nsteps):
+        Tref = O.equilibrium_diffusion_step(Tref, Tref, dt, np.full(n, 25.0), 1.0, left=1.0)
+    p = W.marshak_1d(dt=dt, ap=True)
+    sch = O.Scheme.from_problem(p)
+    U = np.stack([p["E"], p["F"][0], p["F"][1], p["T"]])
+    for _ in range(nsteps):
+        r = O.implicit_step(sch, p["sigma"], p["rho_cv"], U, dt, rtol=1e-10, newton_rtol=1e-8, newton_max=30,
+                            max_iters=40000)
+        assert r.converged
+        U = r.U
+    Tg = U[3, 0]
+    assert np.linalg.norm(Tg - Tref) / np.linalg.norm(Tref) <= 1e-3
+    assert int(np.argmax(Tg < 0.65)) == int(np.argmax(Tref < 0.65)) == 45

@@ -206,6 +206,48 @@ def beam45(n=128, dt=0.5, lambda_floor=0.0, t_background=0.3, t_beam=1.0):
     return p
 
 
+def marshak_1d(n=400, sigma_dx=25.0, rho_cv=1.0, t0=0.3, t_source=1.0, dt=1e4, ap=True):
+    """1D Marshak wave (Sect. 5.1) on an n x 1 grid (y periodic), no randomness.
+
+    Constant sigma (sigma dx = 25 as in the paper) and rho c_v; gas and radiation
+    start in equilibrium at t0 (E = a_r t0^4, F = 0); the -x face is Dirichlet
+    with E = a_r t_source^4, F = 0 (the source lit at t = 0), the +x face outflow.
+    Nondimensional (c = a_r = dx = 1): in the paper's CGS units the radiation
+    could not heat the gas within the quoted time, so only the comparison AP
+    against plain HLL carries over.  Well-balanced flux source; ap toggles the
+    asymptotic correction (ap = False is the standard HLL scheme).
+    """
+    p = base_problem((n, 1), dt=dt, source="coupled_t", flux_source="wb", ap=ap,
+                     bc=["dirichlet", "outflow", "periodic", "periodic"])
+    p["sigma"] = np.full((1, n), float(sigma_dx) / p["dx"])
+    p["rho_cv"] = np.full((1, n), float(rho_cv))
+    p["E"] = np.full((1, n), p["a_r"] * t0 ** 4)
+    p["F"] = np.zeros((2, 1, n))
+    p["T"] = np.full((1, n), float(t0))
+    p["ghost"][0] = np.array([[p["a_r"] * t_source ** 4], [0.0], [0.0]])
+    return p
+
+
+def opacity_jump_1d(n=100, sigma_dx=100.0, t0=0.3, t_source=1.0, dt=1e5, flux_source="wb"):
+    """Steady state across a jump of opacity (Sect. 5.2) on an n x 1 grid.
+
+    sigma dx = 100 on the left half (the paper's 10^4 cm^-1 at dx = 0.01 cm) and
+    0 on the right half; radiation only (at the steady state the exchange with
+    the gas vanishes, so the flux must be constant in x either way); E0 =
+    a_r t0^4, F0 = 0; -x face Dirichlet E = a_r t_source^4, F = 0; +x outflow.
+    flux_source: "wb" (Eq. "wb_smart") or "centered" (Eq. "wb_naive").
+    """
+    p = base_problem((n, 1), dt=dt, source="none", flux_source=flux_source,
+                     bc=["dirichlet", "outflow", "periodic", "periodic"])
+    p["sigma"] = np.where(np.arange(n) < n // 2, float(sigma_dx) / p["dx"], 0.0)[None, :]
+    p["rho_cv"] = None
+    p["E"] = np.full((1, n), p["a_r"] * t0 ** 4)
+    p["F"] = np.zeros((2, 1, n))
+    p["T"] = None
+    p["ghost"][0] = np.array([[p["a_r"] * t_source ** 4], [0.0], [0.0]])
+    return p
+
+
 def gaussian_random_field(shape, seed, slope=-11.0 / 3.0):
     """Zero-mean, unit-variance periodic Gaussian random field.
 
