@@ -884,3 +884,35 @@ def equilibrium_diffusion_step(T, Tn, dt, sigma, rho_cv, c=1.0, a_r=1.0, dx=1.0,
         if np.all(np.abs(d) <= 1e-14 * np.abs(T)):
             break
     return T
+
+
+def velocity_sources(sch, sigma, U, u):
+    """The velocity-dependent source terms (Sect. 2.3), per cell, with P = D(E, F) E:
+        S_E(u) = sigma/c [u.F + E u.u + u.(u.P)]
+        S_F(u) = sigma u.P + sigma a_r T^4 u + sigma/c^2 u (u.F)
+    T is the gas-temperature row when the state has one; without it there is no
+    emission term (a_r T^4 -> 0).  u: (ndim, *grid).  Returns (S_E, S_F)."""
+    c, nd = sch.c, sch.ndim
+    E = U[0]
+    F = U[1:1 + nd]
+    D = closure(E, F, c, sch.closure)[3]
+    u = np.asarray(u, float)
+    uP = [E * sum(u[l] * D[l][m] for l in range(nd)) for m in range(nd)]   # (u.P)_m
+    uF = sum(u[m] * F[m] for m in range(nd))
+    uu = sum(u[m] * u[m] for m in range(nd))
+    uuP = sum(u[m] * uP[m] for m in range(nd))
+    SE = sigma / c * (uF + E * uu + uuP)
+    emis = sch.a_r * U[sch.nrad] ** 4 if sch.source == "coupled_t" else 0.0
+    SF = np.stack([sigma * uP[m] + sigma * emis * u[m] + sigma / c ** 2 * u[m] * uF for m in range(nd)])
+    return SE, SF
+
+
+def velocity_source_step(sch, sigma, U, u, dt):
+    """Step 3 of the splitting (Sect. 3.2): the velocity-dependent sources added
+    explicitly to the radiation, E += dt S_E(u), F += dt c S_F(u); the gas rows are
+    left to the hydrodynamics."""
+    SE, SF = velocity_sources(sch, sigma, U, u)
+    V = np.array(U, dtype=float, copy=True)
+    V[0] = U[0] + dt * SE
+    V[1:1 + sch.ndim] = U[1:1 + sch.ndim] + dt * sch.c * SF
+    return V
