@@ -230,6 +230,22 @@ m1_status m1_explicit_step(m1_ctx* ctx, m1_state* U, double dt, int32_t nsteps, 
  * m1_explicit_step; the CFL bound still applies, for any sigma. */
 m1_status m1_semi_implicit_step(m1_ctx* ctx, m1_state* U, double dt, int32_t nsteps, m1_stats* stats);
 
+/* Step 3 of the splitting (Sect. 3.2): the velocity-dependent sources of Sect. 2.3,
+ * added explicitly and cell-centred after the radiation step,
+ *   E += dt S_E(u),  S_E = sigma/c [u.F + E u.u + u.(u.P)]
+ *   F += dt c S_F(u), S_F = sigma u.P + sigma a_r T^4 u + sigma/c^2 u (u.F)
+ * with P = D(E, F) E (the closure of Sect. 2.2) and sigma the context's opacity.
+ * Without a T row (M1_SRC_NONE, M1_SRC_ABSORPTION) there is no emission term; T
+ * itself is not changed (the matching gas terms belong to the hydrodynamics).
+ * U: the state (device, in/out, not retained); ux, uy, uz: the material velocity,
+ * N doubles each, same cell order (uz ignored in 2D, may be NULL there).  dt > 0,
+ * U.E > 0 and all inputs finite, else M1_ERR_INVALID_ARG / M1_ERR_NONFINITE and U
+ * unchanged; a non-finite result returns M1_ERR_NONFINITE, U unchanged.  stats
+ * (may be NULL): cells_f_gt_1 of the result, wall time.  Blocks until done; the
+ * context's linearisation is kept. */
+m1_status m1_velocity_sources(m1_ctx* ctx, m1_state* U, const double* ux, const double* uy, const double* uz,
+                              double dt, m1_stats* stats);
+
 void m1_destroy(m1_ctx* ctx);
 const char* m1_last_error(const m1_ctx* ctx);
 

@@ -6,7 +6,7 @@ not been built this module raises on import -- there is no CPU fallback.
 
 Low level: ``m1_setup``, ``m1_linearize``, ``m1_apply_operator``,
 ``m1_precondition``, ``m1_residual``, ``m1_implicit_step``, ``m1_explicit_step``,
-``m1_semi_implicit_step``, ``m1_destroy``,
+``m1_semi_implicit_step``, ``m1_velocity_sources``, ``m1_destroy``,
 ``m1_last_error``, ``m1_profile_enable``, ``m1_profile_query`` mirror the C
 functions one to one (pointers are passed as Python ints / ctypes structs).
 High level: :class:`Solver` builds the structs from a problem description.
@@ -92,6 +92,7 @@ _sig = {
     "m1_implicit_step": (ctypes.c_int32, [_vp, _P(M1State), ctypes.c_double, _P(M1Stats)]),
     "m1_explicit_step": (ctypes.c_int32, [_vp, _P(M1State), ctypes.c_double, ctypes.c_int32, _P(M1Stats)]),
     "m1_semi_implicit_step": (ctypes.c_int32, [_vp, _P(M1State), ctypes.c_double, ctypes.c_int32, _P(M1Stats)]),
+    "m1_velocity_sources": (ctypes.c_int32, [_vp, _P(M1State), _vp, _vp, _vp, ctypes.c_double, _P(M1Stats)]),
     "m1_destroy": (None, [_vp]),
     "m1_last_error": (ctypes.c_char_p, [_vp]),
     "m1_profile_enable": (ctypes.c_int32, [_vp, ctypes.c_int32]),
@@ -137,6 +138,7 @@ m1_residual = _lib.m1_residual
 m1_implicit_step = _lib.m1_implicit_step
 m1_explicit_step = _lib.m1_explicit_step
 m1_semi_implicit_step = _lib.m1_semi_implicit_step
+m1_velocity_sources = _lib.m1_velocity_sources
 m1_destroy = _lib.m1_destroy
 m1_last_error = _lib.m1_last_error
 m1_profile_enable = _lib.m1_profile_enable
@@ -339,6 +341,19 @@ class Solver:
     def semi_implicit_step(self, U, dt=None, nsteps=1, *, raise_on_fail=True):
         """nsteps semi-implicit steps (sources implicit, fluxes explicit) of U in place (centred flux source)."""
         return self._time_step(_lib.m1_semi_implicit_step, U, dt, nsteps, raise_on_fail)
+
+    def velocity_sources(self, U, u, dt=None, *, raise_on_fail=True):
+        """Add the velocity-dependent sources to U in place; u: device tensor (ndim, *grid)."""
+        u = self.torch.as_tensor(u, dtype=self.torch.float64).to(self.device)
+        u = u.reshape((self.ndim,) + self.shape).contiguous()
+        ptr = [u[m].data_ptr() for m in range(self.ndim)] + [None] * (3 - self.ndim)
+        stats = M1Stats()
+        st = _lib.m1_velocity_sources(self.ctx, ctypes.byref(state_struct(U, self.ndim, self.coupled)), ptr[0],
+                                      ptr[1], ptr[2], float(dt if dt is not None else self.p["dt"]),
+                                      ctypes.byref(stats))
+        if raise_on_fail and st != M1_OK:
+            raise M1Error(st, _lib.m1_last_error(self.ctx).decode())
+        return st, stats.as_dict()
 
     def set_network(self, net):
         self._net = net

@@ -23,7 +23,7 @@ namespace {
 const char* kClassNames[KC_COUNT] = {"setup",   "setup_bj", "residual",   "apply",         "block_jacobi",
                                      "arnoldi_dot", "arnoldi_scalar", "arnoldi_update", "x_update",
                                      "true_residual", "newton_update", "norm", "convert", "learned_pc", "apply_bj_fused",
-                                     "time_step"};
+                                     "time_step", "velocity_sources"};
 
 struct Profiler {
   bool on = false;
@@ -599,6 +599,44 @@ m1_status time_steps(m1_ctx* c, m1_state* U, double dt, int32_t nsteps, m1_stats
   return M1_OK;
 }
 
+// step 3 of the splitting: the velocity-dependent sources, explicitly, on the
+// context's work vectors b (in) and x (out) so the linearisation stays
+m1_status velocity_sources(m1_ctx* c, m1_state* U, const double* ux, const double* uy, const double* uz, double dt,
+                           m1_stats* stats) {
+  if (!c) return M1_ERR_INVALID_ARG;
+  const auto t0 = std::chrono::steady_clock::now();
+  if (!(std::isfinite(dt) && dt > 0)) { c->err = "dt must be finite and > 0"; return M1_ERR_INVALID_ARG; }
+  const double* u[3] = {ux, uy, uz};
+  for (int d = 0; d < c->nd; ++d)
+    if (!u[d]) { c->err = "velocity component is NULL"; return M1_ERR_INVALID_ARG; }
+  m1_status st;
+  if ((st = copy_state_in(c, U, c->b)) != M1_OK) return st;
+  if ((st = check_array(c, c->b, c->n, 0, "U", M1_ERR_NONFINITE)) != M1_OK) return st;
+  if ((st = check_array(c, c->b, c->g.N, 1, "U.E", M1_ERR_INVALID_ARG)) != M1_OK) return st;
+  for (int d = 0; d < c->nd; ++d)
+    if ((st = check_array(c, u[d], c->g.N, 0, "u", M1_ERR_NONFINITE)) != M1_OK) return st;
+  const double bytes = 8.0 * (2.0 * c->nu + 1.0 + c->nd) * cells(c);
+  timed(c, KC_VELOCITY, bytes, [&] {
+    launch_velocity_sources(c->nd, c->cpl, c->g, c->sc, c->cf64.sigma, c->b, u, dt, c->x, c->stream);
+  });
+  HIPCHK(c, hipGetLastError());
+  unsigned long long nf = 0;
+  k_zero_u64<<<1, 64, 0, c->stream>>>(c->dcount);
+  launch_count_f(c->nd, c->g, c->x, c->cfg.c, c->dcount, c->stream);
+  HIPCHK(c, hipMemcpyAsync(&nf, c->dcount, sizeof(nf), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  prof_collect(c);
+  if ((st = check_array(c, c->x, c->n, 0, "U after the velocity sources", M1_ERR_NONFINITE)) != M1_OK) return st;
+  if ((st = copy_state_out(c, c->x, U)) != M1_OK) return st;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (stats) {
+    *stats = m1_stats{};
+    stats->cells_f_gt_1 = (int64_t)nf;
+    stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+  return M1_OK;
+}
+
 // ============================================================================
 // C ABI
 // ============================================================================
@@ -985,6 +1023,11 @@ m1_status m1_explicit_step(m1_ctx* c, m1_state* U, double dt, int32_t nsteps, m1
 
 m1_status m1_semi_implicit_step(m1_ctx* c, m1_state* U, double dt, int32_t nsteps, m1_stats* stats) {
   return time_steps(c, U, dt, nsteps, stats, true);
+}
+
+m1_status m1_velocity_sources(m1_ctx* c, m1_state* U, const double* ux, const double* uy, const double* uz,
+                              double dt, m1_stats* stats) {
+  return velocity_sources(c, U, ux, uy, uz, dt, stats);
 }
 
 m1_status m1_set_network(m1_ctx* c, m1nn* net) {

@@ -50,7 +50,7 @@ struct GmresState {
 
 enum KernelClass {
   KC_SETUP = 0, KC_SETUP_BJ, KC_RESIDUAL, KC_APPLY, KC_BJ, KC_DOT, KC_SCALAR, KC_UPDATE, KC_XUPDATE,
-  KC_TRUE_RESID, KC_NEWTON_UPDATE, KC_NORM, KC_CONVERT, KC_NN, KC_APPLY_PC, KC_TIME_STEP, KC_COUNT
+  KC_TRUE_RESID, KC_NEWTON_UPDATE, KC_NORM, KC_CONVERT, KC_NN, KC_APPLY_PC, KC_TIME_STEP, KC_VELOCITY, KC_COUNT
 };
 
 // ---- launchers (defined in m1_kernels.hip / m1_krylov.hip) ----
@@ -73,6 +73,9 @@ void launch_residual(int nd, bool cpl, const Geom& g, const Scheme& sc, const Co
 // reads only sigma and rho_cv of the coefficient slab
 void launch_time_step(int nd, bool cpl, bool semi, const Geom& g, const Scheme& sc, const Coefs<double>& cf,
                       const Bdry& bd, const double* Un, double* Uo, hipStream_t s);
+// velocity-dependent sources added explicitly: U -> V (distinct buffers); u[0..nd-1] device fields
+void launch_velocity_sources(int nd, bool cpl, const Geom& g, const Scheme& sc, const double* sigma, const double* U,
+                             const double* const* u, double dt, double* V, hipStream_t s);
 template <typename R, typename VI, typename VO>
 void launch_bj(int nd, bool cpl, const Geom& g, const Coefs<R>& cf, const VI* r, VO* z, hipStream_t s,
                const int* skip = nullptr);

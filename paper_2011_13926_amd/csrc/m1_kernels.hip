@@ -1228,6 +1228,69 @@ void launch_time_step(int nd, bool cpl, bool semi, const Geom& g, const Scheme& 
 #undef M1_TD
 }
 
+// ----------------------------------------------------------------------------
+// Velocity-dependent sources (Sect. 2.3), added explicitly after the radiation
+// step (Sect. 3.2, step 3), cell-centred:
+//   S_E(u) = sigma/c [u.F + E u.u + u.(u.P)]
+//   S_F(u) = sigma u.P + sigma a_r T^4 u + sigma/c^2 u (u.F),   P = D(E, F) E
+//   E += dt S_E,  F += dt c S_F;  other rows copied (without a T row there is no
+//   emission term).  U -> V, distinct buffers.
+// ----------------------------------------------------------------------------
+template <int ND, bool CPL>
+__global__ __launch_bounds__(256) void k_velocity_sources(int64_t N, Scheme sc, const double* __restrict__ sigma,
+                                                          const double* __restrict__ U, const double* __restrict__ ux,
+                                                          const double* __restrict__ uy, const double* __restrict__ uz,
+                                                          double dt, double* __restrict__ V) {
+  constexpr int NU = 1 + ND + (CPL ? 1 : 0);
+  const int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (cell >= N) return;
+  const double E = U[cell];
+  double F[ND], u[ND];
+#pragma unroll
+  for (int m = 0; m < ND; ++m) F[m] = U[(1 + m) * N + cell];
+  u[0] = ux[cell];
+  u[1] = uy[cell];
+  if (ND == 3) u[ND - 1] = uz[cell];
+  const double sig = sigma[cell];
+  const ClosureState<ND> cs = closure<ND>(E, F, sc.c, sc.p1);
+  const double iso = 0.5 * (1.0 - cs.chi), aniso = 0.5 * (3.0 * cs.chi - 1.0);
+  double un = 0.0, uF = 0.0, uu = 0.0;
+#pragma unroll
+  for (int m = 0; m < ND; ++m) {
+    un += u[m] * cs.nv[m];
+    uF += u[m] * F[m];
+    uu += u[m] * u[m];
+  }
+  double uP[ND], uuP = 0.0;
+#pragma unroll
+  for (int m = 0; m < ND; ++m) {
+    uP[m] = E * (iso * u[m] + aniso * un * cs.nv[m]);
+    uuP += u[m] * uP[m];
+  }
+  double emis = 0.0;
+  if (CPL) {
+    const double T = U[(NU - 1) * N + cell];
+    emis = sc.a_r * T * T * T * T;
+    V[(NU - 1) * N + cell] = T;
+  }
+  V[cell] = E + dt * (sig / sc.c * (uF + E * uu + uuP));
+#pragma unroll
+  for (int m = 0; m < ND; ++m)
+    V[(1 + m) * N + cell] = F[m] + dt * sc.c * (sig * uP[m] + sig * emis * u[m] + sig / sc.c2 * u[m] * uF);
+}
+
+void launch_velocity_sources(int nd, bool cpl, const Geom& g, const Scheme& sc, const double* sigma, const double* U,
+                             const double* const* u, double dt, double* V, hipStream_t s) {
+  const int64_t grd = (g.N + 255) / 256;
+  if (nd == 2) {
+    if (cpl) k_velocity_sources<2, true><<<grd, 256, 0, s>>>(g.N, sc, sigma, U, u[0], u[1], nullptr, dt, V);
+    else k_velocity_sources<2, false><<<grd, 256, 0, s>>>(g.N, sc, sigma, U, u[0], u[1], nullptr, dt, V);
+  } else {
+    if (cpl) k_velocity_sources<3, true><<<grd, 256, 0, s>>>(g.N, sc, sigma, U, u[0], u[1], u[2], dt, V);
+    else k_velocity_sources<3, false><<<grd, 256, 0, s>>>(g.N, sc, sigma, U, u[0], u[1], u[2], dt, V);
+  }
+}
+
 // explicit instantiations
 template void launch_apply<double, double, double>(int, bool, int, const Geom&, const Scheme&, const Coefs<double>&,
                                                    const Bdry&, const double*, const double*, double*, hipStream_t, const int*);

@@ -342,7 +342,7 @@ def voronoi_opacity(n=(512, 512), seed=0, nsites=64, ngauss=4, dt=100.0, floor=1
 
 
 def ionization_front(n=(192, 192, 192), seed=192, dt=100.0, sigma0=1e-2,
-                     jump=1e4, patch=4, floor=1e-6, with_velocity=False, mach=0.5):
+                     jump=1e4, patch=4, floor=1e-6, with_velocity=False, mach=0.5, sound_speed=3.3e-5):
     """3D ionisation-front-like absorption run.
 
     rho: lognormal from the GRF of `seed` (as the coupled workload, sigma_ln=1).
@@ -352,7 +352,8 @@ def ionization_front(n=(192, 192, 192), seed=192, dt=100.0, sigma0=1e-2,
     all other faces are outflow (ghost_mask 1 on the patch, 0 elsewhere).
     E0 = floor, F0 = 0, absorption source (no gas-temperature row).
     If with_velocity, a solenoidal velocity v = curl A (A: three GRFs of seeds
-    seed+1..seed+3) scaled to rms Mach `mach` is attached as p['velocity'];
+    seed+1..seed+3) scaled to rms Mach `mach` at the sound speed `sound_speed`
+    (in units of c; 3.3e-5 c is 10 km/s, ionised gas) is attached as p['velocity'];
     the implicit radiation step does not use it (hydrodynamics is frozen).
     """
     nx, ny, nz = n
@@ -385,7 +386,7 @@ def ionization_front(n=(192, 192, 192), seed=192, dt=100.0, sigma0=1e-2,
         vy = dd(A[0], 0) - dd(A[2], 2)
         vz = dd(A[1], 2) - dd(A[0], 1)
         rms = np.sqrt((vx ** 2 + vy ** 2 + vz ** 2).mean())
-        p["velocity"] = np.stack([vx, vy, vz]) * (mach / rms)
+        p["velocity"] = np.stack([vx, vy, vz]) * (mach * sound_speed / rms)
     return p
 
 
