@@ -30,9 +30,14 @@ def _log(*a):
     print("[train_nn]", *a, file=sys.stderr, flush=True)
 
 
-def problem(seed, n=512, dt=100.0):
+WORKLOAD = "voronoi"
+
+
+def problem(seed, n=512, dt=None):
     import workloads as W
-    return W.voronoi_opacity(n=(n, n), seed=seed, dt=dt)
+    if WORKLOAD == "diffusive":
+        return W.diffusive_lognormal(n=(n, n), seed=seed, dt=1000.0 if dt is None else dt)
+    return W.voronoi_opacity(n=(n, n), seed=seed, dt=100.0 if dt is None else dt)
 
 
 def generate_pairs(P, torch, p, steps, newton_max=6, rtol=1e-10, partial=(30, 90)):
@@ -97,7 +102,7 @@ def heldout_loss(torch, net, pairs):
     return float(np.mean(vals)) if vals else float("nan")
 
 
-def evaluate(P, torch, net, seeds, n=512, rtol=1e-8, dt=100.0):
+def evaluate(P, torch, net, seeds, n=512, rtol=1e-8, dt=None):
     """GMRES iterations and time to rtol with block-Jacobi vs the learned preconditioner
     on the first Newton linear system of each held-out problem."""
     out = []
@@ -141,7 +146,12 @@ def main():
     ap.add_argument("--report", default=None)
     ap.add_argument("--channels", default=",".join(str(c) for c in CHANNELS))
     ap.add_argument("--no-solve-eval", action="store_true", help="skip the FGMRES comparison on held-out seeds")
+    ap.add_argument("--workload", default="voronoi", choices=["voronoi", "diffusive"],
+                    help="voronoi: workloads.voronoi_opacity at dt = 100; diffusive: workloads.diffusive_lognormal "
+                         "at dt = 1000")
     args = ap.parse_args()
+    global WORKLOAD
+    WORKLOAD = args.workload
     channels = tuple(int(v) for v in args.channels.split(","))
     import torch
 
@@ -161,7 +171,7 @@ def main():
     hl = heldout_loss(torch, net, held)
     _log(f"held-out loss {hl:.4f} on {len(held)} pairs")
     ev = [] if args.no_solve_eval else evaluate(P, torch, net, _seeds(args.heldout), args.n)
-    rep = {"pairs": len(pairs), "iters": args.iters, "channels": list(channels),
+    rep = {"workload": args.workload, "n": args.n, "pairs": len(pairs), "iters": args.iters, "channels": list(channels),
            "loss_first100": float(np.mean(hist[:100])), "loss_last100": float(np.mean(hist[-100:])),
            "heldout_pairs": len(held), "heldout_loss": hl, "heldout": ev}
     if args.report:

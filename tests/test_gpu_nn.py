@@ -167,3 +167,31 @@ def test_features_and_target_layout():
     assert np.allclose(f[:, :, 6], np.log10(1 + p["sigma"] * p["dt"]) / 4, rtol=1e-6)
     fx = U[1] / U[0]
     assert np.allclose(f[:, :, 7], fx, rtol=1e-6, atol=1e-7)
+
+
+def test_flexible_gmres_with_a_zero_network_is_block_jacobi_gmres():
+    """With every weight zero the network's correction is exactly zero, the learned
+    preconditioner is block-Jacobi, and the flexible solve takes exactly the
+    block-Jacobi iteration count (the flexible basis bookkeeping is exact for a
+    linear preconditioner)."""
+    import paper_2011_13926_amd as P
+    import workloads as W
+    p = W.diffusive_lognormal(n=(128, 128), seed=1000)
+    U0 = np.stack([p["E"], p["F"][0], p["F"][1]])
+    net = P.Net(9, 3, (32, 48, 64, 64), Hmax=128, Wmax=128)
+    s_bj = P.Solver(p, U_lin=U0, U_n=U0, rtol=1e-8, max_iters=5000)
+    s_nn = P.Solver(p, U_lin=U0, U_n=U0, rtol=1e-8, max_iters=5000, pc="learned")
+    try:
+        net.set_params(np.zeros(net.param_count, np.float32))
+        s_nn.set_network(net)
+        b = -s_bj.residual()
+        xb, stb, sb = s_bj.solve_linear(b)
+        xl, stl, sl = s_nn.solve_linear(b)
+        assert stb == P.M1_OK and stl == P.M1_OK and sl["fell_back"] == 0
+        assert sl["krylov_iters"] == sb["krylov_iters"]
+        import torch
+        assert float(torch.linalg.vector_norm(xl - xb) / torch.linalg.vector_norm(xb)) <= 1e-10
+    finally:
+        s_bj.close()
+        s_nn.close()
+        net.close()

@@ -297,6 +297,46 @@ def coupled_lognormal(n=(256, 256, 256), seeds=(13926, 13927), dt=100.0,
     return p
 
 
+def diffusive_lognormal(n=(256, 256), seed=0, dt=1000.0, sigma_range=(3.0, 300.0), ngauss=6, floor=1e-6):
+    """2D periodic optically thick medium with a smooth opacity field.
+
+    log sigma = log lo + (log hi - log lo) Phi(g), g the k^(-11/3) Gaussian random
+    field of `seed` (unit variance), Phi the normal CDF; then, with
+    numpy.random.default_rng(seed + 7919), for each of ngauss energy bumps:
+    centre x ~ U[0, nx), centre y ~ U[0, ny), width ~ U[4, 16], log10 amplitude
+    ~ U[0, 2].  E = floor + bumps, F = 0, radiation only, well-balanced source.
+    At dt = 1000 the diffusion length sqrt(c dt / 3 sigma) spans 1-10 cells.
+    """
+    from scipy.special import ndtr
+
+    nx, ny = n
+    p = base_problem(n, dt=dt)
+    g = gaussian_random_field(grid_shape(n), seed)
+    g = g / max(float(g.std()), 1e-300)
+    lo, hi = np.log10(sigma_range[0]), np.log10(sigma_range[1])
+    p["sigma"] = 10.0 ** (lo + (hi - lo) * ndtr(g))
+    rng = np.random.default_rng(seed + 7919)
+    x = np.arange(nx) + 0.5
+    y = np.arange(ny) + 0.5
+
+    def pdist(a, b, L):
+        d = np.abs(a - b)
+        return np.minimum(d, L - d)
+
+    E = np.full((ny, nx), float(floor))
+    for _ in range(ngauss):
+        cx = rng.uniform(0, nx)
+        cy = rng.uniform(0, ny)
+        w = rng.uniform(4.0, 16.0)
+        amp = 10.0 ** rng.uniform(0.0, 2.0)
+        E += amp * np.exp(-(pdist(x[None, :], cx, nx) ** 2 + pdist(y[:, None], cy, ny) ** 2) / (2 * w * w))
+    p["E"] = E
+    p["F"] = np.zeros((2, ny, nx))
+    p["T"] = None
+    p["rho_cv"] = None
+    return p
+
+
 def voronoi_opacity(n=(512, 512), seed=0, nsites=64, ngauss=4, dt=100.0, floor=1e-6):
     """2D periodic Voronoi opacity field with Gaussian energy bumps.
 
