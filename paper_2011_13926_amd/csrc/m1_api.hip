@@ -86,7 +86,6 @@ struct m1_ctx {
   // flexible GMRES (learned preconditioner)
   m1nn* net = nullptr;
   void* Z = nullptr;
-  void* zt = nullptr;
   int use_learned = 0;   // 1 while the current solve uses the network
   // pinned host read-back
   double* hscal = nullptr;
@@ -288,7 +287,7 @@ void free_all(m1_ctx* c) {
     if (c->mask[f]) hipFree(c->mask[f]);
   }
   void* bufs[] = {c->Uk, c->Un, c->Uprev, c->fn, c->coef64, c->coef32, c->V, c->b, c->x, c->u[0], c->u[1],
-                  c->p, c->z, c->part, c->gs, c->dscal, c->dcount, c->Z, c->zt};
+                  c->p, c->z, c->part, c->gs, c->dscal, c->dcount, c->Z};
   for (void* b : bufs)
     if (b) hipFree(b);
   if (c->hscal) hipHostFree(c->hscal);
@@ -438,7 +437,6 @@ m1_status gmres(m1_ctx* c, double bnorm, SolveResult& res, const Coefs<R>& cfi) 
   const int use_pc = !learned && c->cfg.pc != M1_PC_NONE;
   const bool fused = use_pc && fused_apply_available(c->nd);
   R* Z = (R*)c->Z;
-  R* zt = (R*)c->zt;
   HIPCHK(c, hipMemsetAsync(c->x, 0, sizeof(double) * n, c->stream));
   // r = b
   launch_copy_cast<double, TV>(c->b, u[0], n, c->stream);
@@ -453,21 +451,39 @@ m1_status gmres(m1_ctx* c, double bnorm, SolveResult& res, const Coefs<R>& cfi) 
     ++cycles;
     const int steps = std::min(c->m, budget - total);
     launch_cycle_init(c->gs, c->dscal + 1, fixed ? 0.0 : rtol * bnorm, tol_rel, c->stream);
-    for (int j = 0; j < steps; ++j) {
-      TV* uj = u[j & 1];
-      TV* un = u[(j + 1) & 1];
-      if (learned) {
+    if (learned) {
+      // Flexible GMRES in the standard Arnoldi order: the network is nonlinear, so it
+      // is applied to the orthonormal v_j (the delayed one-reduction form applies the
+      // preconditioner before orthogonalisation and would scale the network's
+      // nonlinear part by ||u_j||/nu).  V_0 = r/beta, then per iteration: z_j = P(v_j)
+      // stored as Z_j, w = A z_j, one reduction over [V_0..V_j, w], the Hessenberg
+      // column, and v_{j+1} = (w - V s)/nu.
+      timed(c, KC_DOT, 1.0 * n * sizeof(TV), [&] { launch_dot<TV>(0, V, vs, u[0], nullptr, n, c->part, c->nb, c->gs, c->stream); }, 0, 0);
+      timed(c, KC_SCALAR, c->nb * 8.0, [&] { launch_scalar(0, 0, c->part, c->nb, c->gs, c->stream, 1); }, 0, 0);
+      timed(c, KC_UPDATE, 4.0 * n * sizeof(TV), [&] { launch_update<TV>(0, V, vs, u[0], u[0], u[1], n, c->gs, c->stream); }, 0, 1);
+      for (int j = 0; j < steps; ++j) {
+        TV* vj = V + (int64_t)j * vs;
+        R* zj = Z + (int64_t)j * vs;
         timed(c, KC_NN, 0.0, [&] {
-          launch_dot<TV>(0, nullptr, 0, uj, nullptr, n, c->part, c->nb, c->gs, c->stream);
+          launch_dot<TV>(0, nullptr, 0, vj, nullptr, n, c->part, c->nb, c->gs, c->stream);
           launch_reduce(c->part, 1, c->nb, c->dscal + 2, c->stream);
-          launch_nn_features<TV>(c->g.N, uj, c->dscal + 2, c->cf64.bjinv, c->Uk, c->cf64.sigma, c->cfg.c, c->sc.cdt,
+          launch_nn_features<TV>(c->g.N, vj, c->dscal + 2, c->cf64.bjinv, c->Uk, c->cf64.sigma, c->cfg.c, c->sc.cdt,
                                  nn_cin_pad(c->net), nn_input(c->net), nullptr, c->stream, &c->gs->done);
           nn_run(c->net, c->g.n[1], c->g.n[0], c->stream, &c->gs->done);
-          launch_nn_combine<TV, R>(c->g.N, uj, c->dscal + 2, c->cf64.bjinv, nn_output(c->net), zt, c->stream,
+          launch_nn_combine<TV, R>(c->g.N, vj, c->dscal + 2, c->cf64.bjinv, nn_output(c->net), zj, c->stream,
                                    &c->gs->done);
         }, j, 0);
-        timed(c, KC_APPLY, bytes_apply(c, sizeof(R), sizeof(R), sizeof(TV), false), [&] { launch_apply<R, R, TV>(c->nd, c->cpl, 0, c->g, c->sc, cfi, bd, zt, nullptr, p, c->stream, &c->gs->done); }, j, 0);
-      } else if (fused) {
+        timed(c, KC_APPLY, bytes_apply(c, sizeof(R), sizeof(R), sizeof(TV), false), [&] { launch_apply<R, R, TV>(c->nd, c->cpl, 0, c->g, c->sc, cfi, bd, zj, nullptr, p, c->stream, &c->gs->done); }, j, 0);
+        timed(c, KC_DOT, (j + 2.0) * n * sizeof(TV), [&] { launch_dot<TV>(j + 1, V, vs, p, nullptr, n, c->part, c->nb, c->gs, c->stream); }, j, 0);
+        timed(c, KC_SCALAR, (j + 2.0) * c->nb * 8.0, [&] { launch_scalar(j + 1, j == steps - 1 ? 1 : 0, c->part, c->nb, c->gs, c->stream, 1); }, j, 0);
+        if (j < steps - 1)
+          timed(c, KC_UPDATE, (j + 4.0) * n * sizeof(TV), [&] { launch_update<TV>(j + 1, V, vs, p, p, u[1], n, c->gs, c->stream); }, j, 1);
+      }
+    }
+    for (int j = 0; j < (learned ? 0 : steps); ++j) {
+      TV* uj = u[j & 1];
+      TV* un = u[(j + 1) & 1];
+      if (fused) {
         // fused: p = A M^{-1} u_j (block-Jacobi applied while staging the halo tile)
         timed(c, KC_APPLY_PC, bytes_apply(c, sizeof(R), sizeof(TV), sizeof(TV), false) +
                                   (double)c->nu * c->nu * sizeof(R) * cells(c), [&] {
@@ -482,10 +498,11 @@ m1_status gmres(m1_ctx* c, double bnorm, SolveResult& res, const Coefs<R>& cfi) 
       timed(c, KC_DOT, (j + 2.0) * n * sizeof(TV), [&] { launch_dot<TV>(j, V, vs, uj, p, n, c->part, c->nb, c->gs, c->stream); }, j, 0);
       timed(c, KC_SCALAR, (2.0 * j + 2.0) * c->nb * 8.0, [&] { launch_scalar(j, 0, c->part, c->nb, c->gs, c->stream); }, j, 0);
       timed(c, KC_UPDATE, (j + 4.0) * n * sizeof(TV), [&] { launch_update<TV>(j, V, vs, uj, p, un, n, c->gs, c->stream); }, j, 1);
-      if (learned) timed(c, KC_UPDATE, (j + 2.0) * n * sizeof(R), [&] { launch_zupdate<R>(j, Z, vs, zt, n, c->gs, c->stream); }, j, 1);
     }
-    timed(c, KC_DOT, (steps + 1.0) * n * sizeof(TV), [&] { launch_dot<TV>(steps, V, vs, u[steps & 1], nullptr, n, c->part, c->nb, c->gs, c->stream); }, steps, 2);
-    timed(c, KC_SCALAR, (steps + 1.0) * c->nb * 8.0, [&] { launch_scalar(steps, 1, c->part, c->nb, c->gs, c->stream); }, steps, 2);
+    if (!learned) {
+      timed(c, KC_DOT, (steps + 1.0) * n * sizeof(TV), [&] { launch_dot<TV>(steps, V, vs, u[steps & 1], nullptr, n, c->part, c->nb, c->gs, c->stream); }, steps, 2);
+      timed(c, KC_SCALAR, (steps + 1.0) * c->nb * 8.0, [&] { launch_scalar(steps, 1, c->part, c->nb, c->gs, c->stream); }, steps, 2);
+    }
     if (learned) {
       timed(c, KC_XUPDATE, (double)steps * n * sizeof(R) + 16.0 * n, [&] { launch_xupdate<R, R>(c->nd, c->cpl, c->g, cfi, Z, vs, c->gs, c->x, 0, c->stream); });
     } else {
@@ -760,8 +777,6 @@ m1_status m1_setup(const m1_config* cfg, const m1_fields* fields, const m1_state
     char* a = nullptr;
     if ((st = dalloc(c, &a, (int64_t)(c->m + 1) * c->vs * (int64_t)rs)) != M1_OK) return fail(st);
     c->Z = a;
-    if ((st = dalloc(c, &a, c->n * (int64_t)rs)) != M1_OK) return fail(st);
-    c->zt = a;
   }
   if ((st = dalloc(c, &c->part, (int64_t)(2 * kMaxRestart + 2) * c->nb)) != M1_OK) return fail(st);
   if ((st = dalloc(c, &c->gs, 1)) != M1_OK) return fail(st);

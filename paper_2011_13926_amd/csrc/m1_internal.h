@@ -86,12 +86,11 @@ int dot_blocks(int64_t n);
 template <typename TV>
 void launch_dot(int j, const TV* V, int64_t vstride, const TV* u, const TV* p, int64_t n, double* partials, int nb,
                 const GmresState* gs, hipStream_t s);
-void launch_scalar(int j, int final_step, const double* partials, int nb, GmresState* gs, hipStream_t s);
+void launch_scalar(int j, int final_step, const double* partials, int nb, GmresState* gs, hipStream_t s,
+                   int classical = 0);
 template <typename TV>
 void launch_update(int j, TV* V, int64_t vstride, const TV* u, const TV* p, TV* unext, int64_t n,
                    const GmresState* gs, hipStream_t s);
-template <typename TZ>
-void launch_zupdate(int j, TZ* Z, int64_t vs, const TZ* zt, int64_t n, const GmresState* gs, hipStream_t s);
 template <typename R, typename TV>
 void launch_xupdate(int nd, bool cpl, const Geom& g, const Coefs<R>& cf, const TV* V, int64_t vstride,
                     const GmresState* gs, double* x, int use_pc, hipStream_t s);

@@ -212,10 +212,13 @@ void launch_dot(int j, const TV* V, int64_t vs, const TV* u, const TV* p, int64_
 constexpr int kScalarThreads = 1024;
 constexpr int kLd = kMaxRestart + 1;
 
-__global__ __launch_bounds__(kScalarThreads) void k_scalar(int j, int final_step, const double* __restrict__ part,
-                                                           int nb, GmresState* gs) {
+// classical = 1: the standard Arnoldi ordering (flexible GMRES with a nonlinear
+// preconditioner): the column is s = V^T w alone (no delayed part), and the update
+// coefficients normalise w against V: coef_s = s, coef_t = 0, cc = 0, inv_nu = 1/nu.
+__global__ __launch_bounds__(kScalarThreads) void k_scalar(int j, int final_step, int classical,
+                                                           const double* __restrict__ part, int nb, GmresState* gs) {
   if (gs->done) return;
-  const int hasp = !final_step;
+  const int hasp = !final_step && !classical;
   const int nv = hasp ? 2 * j + 2 : j + 1;
   const int tid = threadIdx.x;
   __shared__ double psum[kScalarThreads];
@@ -375,6 +378,20 @@ __global__ __launch_bounds__(kScalarThreads) void k_scalar(int j, int final_step
     return;
   }
   const double nu = sh_nu;
+  if (classical) {
+    for (int i = tid; i <= j; i += kScalarThreads) {
+      if (i < j) {
+        gs->coef_s[i] = s[i];
+        gs->coef_t[i] = 0.0;
+      }
+      gs->hprev[i] = 0.0;
+    }
+    if (tid == 0) {
+      gs->cc = 0.0;
+      gs->inv_nu = 1.0 / nu;
+    }
+    return;
+  }
   // (5) (H s)[r], r = 0..j, with the unrotated Hessenberg (columns 0..j-1)
   for (int r = tid; r <= j; r += kScalarThreads) {
     double acc = 0.0;
@@ -398,8 +415,9 @@ __global__ __launch_bounds__(kScalarThreads) void k_scalar(int j, int final_step
   }
 }
 
-void launch_scalar(int j, int final_step, const double* partials, int nb, GmresState* gs, hipStream_t s) {
-  k_scalar<<<1, kScalarThreads, 0, s>>>(j, final_step, partials, nb, gs);
+void launch_scalar(int j, int final_step, const double* partials, int nb, GmresState* gs, hipStream_t s,
+                   int classical) {
+  k_scalar<<<1, kScalarThreads, 0, s>>>(j, final_step, classical, partials, nb, gs);
 }
 
 // ----------------------------------------------------------------------------
@@ -515,45 +533,6 @@ void launch_update(int j, TV* V, int64_t vs, const TV* u, const TV* p, TV* unext
                    hipStream_t s) {
   upd_dispatch<TV>(std::make_integer_sequence<int, kMaxRestart>{}, j, V, vs, u, p, unext, n, gs, s);
 }
-
-// flexible GMRES: z_j = (z~_j - Z_j s)/nu, the preconditioned vector that matches q_j
-template <int J, typename TZ>
-__global__ __launch_bounds__(kDotThreads) void k_zupdate(TZ* __restrict__ Z, int64_t vs, const TZ* __restrict__ zt,
-                                                         int64_t n, const GmresState* __restrict__ gs) {
-  if (gs->done) return;
-  double cs_[J > 0 ? J : 1];
-#pragma unroll
-  for (int i = 0; i < J; ++i) cs_[i] = gs->coef_s[i];
-  const double inv = gs->inv_nu;
-  TZ* __restrict__ zj = Z + (int64_t)J * vs;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
-    double a = (double)zt[e];
-#pragma unroll
-    for (int i = 0; i < J; ++i) a -= cs_[i] * (double)Z[i * vs + e];
-    zj[e] = (TZ)(a * inv);
-  }
-}
-
-template <int J, typename TZ>
-static void zupd_one(TZ* Z, int64_t vs, const TZ* zt, int64_t n, const GmresState* gs, hipStream_t s) {
-  k_zupdate<J, TZ><<<dot_blocks(n), kDotThreads, 0, s>>>(Z, vs, zt, n, gs);
-}
-
-template <typename TZ, int... Js>
-static void zupd_dispatch(std::integer_sequence<int, Js...>, int j, TZ* Z, int64_t vs, const TZ* zt, int64_t n,
-                          const GmresState* gs, hipStream_t s) {
-  using Fn = void (*)(TZ*, int64_t, const TZ*, int64_t, const GmresState*, hipStream_t);
-  static const Fn tab[] = {&zupd_one<Js, TZ>...};
-  tab[j](Z, vs, zt, n, gs, s);
-}
-
-template <typename TZ>
-void launch_zupdate(int j, TZ* Z, int64_t vs, const TZ* zt, int64_t n, const GmresState* gs, hipStream_t s) {
-  zupd_dispatch<TZ>(std::make_integer_sequence<int, kMaxRestart>{}, j, Z, vs, zt, n, gs, s);
-}
-
-template void launch_zupdate<double>(int, double*, int64_t, const double*, int64_t, const GmresState*, hipStream_t);
-template void launch_zupdate<float>(int, float*, int64_t, const float*, int64_t, const GmresState*, hipStream_t);
 
 // ----------------------------------------------------------------------------
 // a7: x += M^{-1} (Q_k y)
