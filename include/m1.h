@@ -268,8 +268,9 @@ int32_t m1_kernel_class_count(void);
  * between levels, nearest upsampling + skip concatenation on the way up, and a
  * 1x1 head with cout channels.  BF16 MFMA kernels, FP32 accumulation, FP32
  * master weights with Adam.  x, y, target: device FP32 arrays H x W x channels.
- * Used inside flexible GMRES as z = M^{-1} r + (|r|/s) NN(features(r)),
- * s = sqrt(3N), with block-Jacobi as fallback (m1_stats.fell_back).
+ * Used inside flexible GMRES as z = M^{-1} (r + (|r|/s) NN(features(r))),
+ * s = sqrt(3N): the network corrects the residual and block-Jacobi maps it to
+ * each cell's scale; block-Jacobi is the fallback (m1_stats.fell_back).
  * ------------------------------------------------------------------------- */
 typedef struct m1nn m1nn;
 
@@ -299,7 +300,9 @@ m1_status m1_set_network(m1_ctx* ctx, m1nn* net);
 /* Network input features (H x W x 9 FP32) of a residual vector r at the current
  * linearisation: s r/|r| (3), s M^{-1} r/|r| (3), log10(1 + c sigma dt)/4, f_x, f_y. */
 m1_status m1_nn_features(m1_ctx* ctx, const double* r, float* features);
-/* Training target s (e - M^{-1} r)/|r| (H x W x 3 FP32) for a residual r with error e. */
+/* Training target s (M e - r)/|r| (H x W x 3 FP32) for a residual r with error e, M the
+ * diagonal block of A (for e = A^{-1} r this is s (M - A) e/|r|, what the network must add
+ * to r so that M^{-1} maps it onto e). */
 m1_status m1_nn_target(m1_ctx* ctx, const double* r, const double* e, float* target);
 /* Solve A x = b at the current linearisation with the configured GMRES and
  * preconditioner (x0 = 0).  stats may be NULL.  Blocks. */

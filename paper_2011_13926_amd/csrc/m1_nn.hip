@@ -959,13 +959,15 @@ __global__ void k_nn_combine(int64_t N, const TV* __restrict__ r, const double* 
   if (skip && *skip) return;
   const double rn = sqrt(fmax(rnorm2[0], 0.0));
   const double back = rn / sqrt(3.0 * (double)N);
+  // z = M^{-1} (r + (|r|/s) y): the network corrects the residual, block-Jacobi maps
+  // the corrected residual to each cell's own scale
   for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < N; p += (int64_t)gridDim.x * blockDim.x) {
     double rv[3];
-    for (int k = 0; k < 3; ++k) rv[k] = (double)r[k * N + p];
+    for (int k = 0; k < 3; ++k) rv[k] = (double)r[k * N + p] + back * (double)y[p * 3 + k];
     for (int k = 0; k < 3; ++k) {
       double acc = 0.0;
       for (int q = 0; q < 3; ++q) acc += bjinv[(k * 3 + q) * N + p] * rv[q];
-      z[k * N + p] = (TZ)(acc + back * (double)y[p * 3 + k]);
+      z[k * N + p] = (TZ)acc;
     }
   }
 }
@@ -981,11 +983,31 @@ __global__ void k_nn_target(int64_t N, const double* __restrict__ r, const doubl
                             float* __restrict__ t) {
   const double rn = sqrt(fmax(rnorm2[0], 0.0));
   const double sc = rn > 0 ? sqrt(3.0 * (double)N) / rn : 0.0;
+  // t = s (M e - r)/|r| with M the diagonal block (the inverse of the stored inverse,
+  // by cofactors): the residual correction that M^{-1} maps onto the error e
   for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < N; p += (int64_t)gridDim.x * blockDim.x) {
+    double B[3][3];
+    for (int k = 0; k < 3; ++k)
+      for (int q = 0; q < 3; ++q) B[k][q] = bjinv[(k * 3 + q) * N + p];
+    const double c00 = B[1][1] * B[2][2] - B[1][2] * B[2][1];
+    const double c01 = B[1][2] * B[2][0] - B[1][0] * B[2][2];
+    const double c02 = B[1][0] * B[2][1] - B[1][1] * B[2][0];
+    const double det = B[0][0] * c00 + B[0][1] * c01 + B[0][2] * c02;
+    double M[3][3];
+    M[0][0] = c00;
+    M[1][0] = c01;
+    M[2][0] = c02;
+    M[0][1] = B[0][2] * B[2][1] - B[0][1] * B[2][2];
+    M[1][1] = B[0][0] * B[2][2] - B[0][2] * B[2][0];
+    M[2][1] = B[0][1] * B[2][0] - B[0][0] * B[2][1];
+    M[0][2] = B[0][1] * B[1][2] - B[0][2] * B[1][1];
+    M[1][2] = B[0][2] * B[1][0] - B[0][0] * B[1][2];
+    M[2][2] = B[0][0] * B[1][1] - B[0][1] * B[1][0];
+    const double idet = 1.0 / det;
     for (int k = 0; k < 3; ++k) {
       double acc = 0.0;
-      for (int q = 0; q < 3; ++q) acc += bjinv[(k * 3 + q) * N + p] * r[q * N + p];
-      t[p * 3 + k] = (float)(sc * (e[k * N + p] - acc));
+      for (int q = 0; q < 3; ++q) acc += M[k][q] * idet * e[q * N + p];
+      t[p * 3 + k] = (float)(sc * (acc - r[k * N + p]));
     }
   }
 }

@@ -160,10 +160,12 @@ def test_features_and_target_layout():
     N_ = 16 * 24
     sc = np.sqrt(3 * N_) / np.linalg.norm(r)
     z = M(r)
+    # the diagonal block applied to e (target: s (M e - r)/|r|)
+    Me = np.einsum("nij,nj->ni", M.blocks, e.reshape(3, -1).T).T.reshape(e.shape)
     for k in range(3):
         assert np.allclose(f[:, :, k], sc * r[k], rtol=1e-6, atol=1e-6)
         assert np.allclose(f[:, :, 3 + k], sc * z[k], rtol=1e-5, atol=1e-5)
-        assert np.allclose(t[:, :, k], sc * (e[k] - z[k]), rtol=1e-5, atol=1e-5)
+        assert np.allclose(t[:, :, k], sc * (Me[k] - r[k]), rtol=1e-5, atol=1e-5)
     assert np.allclose(f[:, :, 6], np.log10(1 + p["sigma"] * p["dt"]) / 4, rtol=1e-6)
     fx = U[1] / U[0]
     assert np.allclose(f[:, :, 7], fx, rtol=1e-6, atol=1e-7)
