@@ -464,7 +464,11 @@ m1_status gmres(m1_ctx* c, double bnorm, SolveResult& res, const Coefs<R>& cfi) 
       for (int j = 0; j < steps; ++j) {
         TV* vj = V + (int64_t)j * vs;
         R* zj = Z + (int64_t)j * vs;
-        timed(c, KC_NN, 0.0, [&] {
+        // the network on the cycle's first direction (the normalised restart residual,
+        // the kind of input it is trained on), block-Jacobi on the Krylov directions
+        if (j > 0) {
+          timed(c, KC_BJ, bytes_bj(c, sizeof(R), sizeof(TV), sizeof(R)), [&] { launch_bj<R, TV, R>(c->nd, c->cpl, c->g, cfi, vj, zj, c->stream, &c->gs->done); }, j, 0);
+        } else timed(c, KC_NN, 0.0, [&] {
           launch_dot<TV>(0, nullptr, 0, vj, nullptr, n, c->part, c->nb, c->gs, c->stream);
           launch_reduce(c->part, 1, c->nb, c->dscal + 2, c->stream);
           launch_nn_features<TV>(c->g.N, vj, c->dscal + 2, c->cf64.bjinv, c->Uk, c->cf64.sigma, c->cfg.c, c->sc.cdt,

@@ -60,3 +60,41 @@ def test_learned_preconditioner_gain_on_heldout_seed(seed):
         s_bj.close()
         s_nn.close()
         net.close()
+
+
+DIFF_WEIGHTS = os.path.join(os.path.dirname(HERE), "paper_2011_13926_amd", "weights", "unet_diffusive256.bin")
+
+
+@pytest.mark.skipif(not os.path.exists(DIFF_WEIGHTS), reason="no trained weights committed")
+@pytest.mark.parametrize("seed", [1000, 1002])
+def test_learned_preconditioner_on_heldout_diffusive_field(seed):
+    """Weights trained by train_nn.py --workload diffusive --n 256 (seeds 0-7, 3 000 steps,
+    lr 3e-4).  On held-out fields the flexible solve converges without falling back,
+    takes at most 1.25x the block-Jacobi iterations (the network is applied to each
+    cycle's restart residual), and meets the same true-residual tolerance."""
+    import torch
+    import paper_2011_13926_amd as P
+    p = W.diffusive_lognormal(n=(256, 256), seed=seed)
+    U0 = np.stack([p["E"], p["F"][0], p["F"][1]])
+    net = P.Net(9, 3, (32, 48, 64, 64), Hmax=256, Wmax=256)
+    net.load(DIFF_WEIGHTS)
+    s_bj = P.Solver(p, U_lin=U0, U_n=U0, rtol=1e-8, max_iters=5000)
+    s_nn = P.Solver(p, U_lin=U0, U_n=U0, rtol=1e-8, max_iters=5000, pc="learned")
+    try:
+        s_nn.set_network(net)
+        b = -s_bj.residual()
+        xb, stb, sb = s_bj.solve_linear(b)
+        xl, stl, sl = s_nn.solve_linear(b)
+        _say(f"seed {seed}: block-Jacobi {sb['krylov_iters']} it, learned {sl['krylov_iters']} it "
+             f"(ratio {sb['krylov_iters'] / max(sl['krylov_iters'], 1):.2f}), fell_back={sl['fell_back']}")
+        assert stb == P.M1_OK and stl == P.M1_OK and sl["fell_back"] == 0
+        assert sl["krylov_iters"] <= 1.25 * sb["krylov_iters"]
+        # both solves promise ||b - A x|| <= 1e-8 ||b||; the solutions then agree to
+        # about the condition number times that
+        res = float(torch.linalg.vector_norm(b - s_bj.apply_operator(xl)) / torch.linalg.vector_norm(b))
+        assert res <= 2e-8
+        assert float(torch.linalg.vector_norm(xl - xb) / torch.linalg.vector_norm(xb)) <= 1e-4
+    finally:
+        s_bj.close()
+        s_nn.close()
+        net.close()
