@@ -35,7 +35,8 @@
  *
  * Errors: every call returns an m1_status; nothing aborts or throws across the
  * ABI.  Host-side arguments are validated before any launch.  On M1_NOT_CONVERGED
- * m1_implicit_step leaves the caller's state unchanged and still fills the stats.
+ * and M1_NOT_ADMISSIBLE m1_implicit_step leaves the caller's state unchanged and
+ * still fills the stats.
  * m1_last_error() gives a human-readable message for the last failure.
  */
 #ifndef M1_H
@@ -53,6 +54,8 @@ typedef struct m1_ctx m1_ctx;
 typedef enum {
   M1_OK = 0,
   M1_NOT_CONVERGED = 1,     /* Newton or GMRES hit its iteration cap */
+  M1_NOT_ADMISSIBLE = 2,    /* the step converged to a root with E <= 0 in some cell (the scheme is not
+                               positivity preserving, Sect. 3.1.3); the state is left unchanged */
   M1_ERR_INVALID_ARG = -1,  /* bad pointer, size, enum or scalar */
   M1_ERR_OUT_OF_MEMORY = -2,
   M1_ERR_HIP = -3,          /* a HIP runtime call failed */
@@ -166,6 +169,8 @@ typedef struct {
   double rel_residual;       /* last linear solve's true relative residual */
   double nonlinear_residual; /* ||R(U_final)|| / ||R(U^n)|| */
   int64_t cells_f_gt_1;      /* cells with |F| > (1 + 1e-12) c E after the step (Sect. 3.1.3 caveat) */
+  int64_t cells_e_nonpos;    /* implicit step: cells with E <= 0 in the final iterate (> 0 gives
+                                M1_NOT_ADMISSIBLE); 0 for the other calls */
   double seconds;            /* wall time of the call */
 } m1_stats;
 
@@ -201,6 +206,9 @@ m1_status m1_precondition(m1_ctx* ctx, const double* r, double* z);
 m1_status m1_residual(m1_ctx* ctx, double* R);
 
 /* One implicit step: U holds U^n on entry and U^{n+1} on M1_OK.  dt > 0.
+ * U.E > 0 on entry.  A converged iterate with E <= 0 in any cell is not committed:
+ * the call returns M1_NOT_ADMISSIBLE with stats.cells_e_nonpos set (U unchanged),
+ * so an M1_OK result is always a valid input of the next step.
  * stats may be NULL.  Blocks until the step's status is known. */
 m1_status m1_implicit_step(m1_ctx* ctx, m1_state* U, double dt, m1_stats* stats);
 
@@ -282,6 +290,10 @@ int64_t m1nn_param_count(const m1nn* net);
 m1_status m1nn_set_params(m1nn* net, const float* host, int64_t count);
 m1_status m1nn_get_params(m1nn* net, float* host, int64_t count);
 m1_status m1nn_get_grads(m1nn* net, float* host, int64_t count);
+/* Draw initial parameters in the library: He-normal 3x3 weights N(0, 2/(9 C_in)) (He et
+ * al. 2015), zero biases, head weights N(0, 1/C_0) * head_scale.  Deterministic in seed
+ * (SplitMix64 counter stream, Box-Muller).  Resets nothing else (Adam moments kept). */
+m1_status m1nn_init_params(m1nn* net, uint64_t seed, float head_scale);
 m1_status m1nn_forward(m1nn* net, const float* x, int32_t H, int32_t W, float* y);
 /* forward + relative loss |y - t|^2/|t|^2 + backward (gradients kept for get_grads / adam_step) */
 m1_status m1nn_backward(m1nn* net, const float* x, const float* target, int32_t H, int32_t W, double* loss);

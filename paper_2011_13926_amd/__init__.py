@@ -32,7 +32,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 # ---------------------------------------------------------------------------
 # enums and structs (must match include/m1.h)
 # ---------------------------------------------------------------------------
-M1_OK, M1_NOT_CONVERGED = 0, 1
+M1_OK, M1_NOT_CONVERGED, M1_NOT_ADMISSIBLE = 0, 1, 2
 M1_ERR_INVALID_ARG, M1_ERR_OUT_OF_MEMORY, M1_ERR_HIP, M1_ERR_NONFINITE, M1_ERR_STATE = -1, -2, -3, -4, -5
 SOURCE = {"none": 0, "absorption": 1, "coupled_t": 2}
 FLUX_SOURCE = {"wb": 0, "centered": 1}
@@ -71,7 +71,7 @@ class M1Stats(ctypes.Structure):
     _fields_ = [("newton_iters", ctypes.c_int32), ("krylov_iters", ctypes.c_int32),
                 ("restarts", ctypes.c_int32), ("fell_back", ctypes.c_int32),
                 ("rel_residual", ctypes.c_double), ("nonlinear_residual", ctypes.c_double),
-                ("cells_f_gt_1", ctypes.c_int64), ("seconds", ctypes.c_double)]
+                ("cells_f_gt_1", ctypes.c_int64), ("cells_e_nonpos", ctypes.c_int64), ("seconds", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -109,6 +109,7 @@ _sig = {
     "m1nn_param_count": (ctypes.c_int64, [_vp]),
     "m1nn_set_params": (ctypes.c_int32, [_vp, _vp, ctypes.c_int64]),
     "m1nn_get_params": (ctypes.c_int32, [_vp, _vp, ctypes.c_int64]),
+    "m1nn_init_params": (ctypes.c_int32, [_vp, ctypes.c_uint64, ctypes.c_float]),
     "m1nn_get_grads": (ctypes.c_int32, [_vp, _vp, ctypes.c_int64]),
     "m1nn_forward": (ctypes.c_int32, [_vp, _vp, ctypes.c_int32, ctypes.c_int32, _vp]),
     "m1nn_backward": (ctypes.c_int32, [_vp, _vp, _vp, ctypes.c_int32, ctypes.c_int32, _P(ctypes.c_double)]),
@@ -154,6 +155,7 @@ m1nn_create = _lib.m1nn_create
 m1nn_param_count = _lib.m1nn_param_count
 m1nn_set_params = _lib.m1nn_set_params
 m1nn_get_params = _lib.m1nn_get_params
+m1nn_init_params = _lib.m1nn_init_params
 m1nn_get_grads = _lib.m1nn_get_grads
 m1nn_forward = _lib.m1nn_forward
 m1nn_backward = _lib.m1nn_backward
@@ -436,6 +438,10 @@ class Net:
         import numpy as np
         a = np.ascontiguousarray(flat, dtype=np.float32)
         self._check(_lib.m1nn_set_params(self.handle, a.ctypes.data, a.size))
+
+    def init_params(self, seed=0, head_scale=0.1):
+        """He-normal initial weights drawn by the library (m1nn_init_params)."""
+        self._check(_lib.m1nn_init_params(self.handle, int(seed), float(head_scale)))
 
     def get_params(self):
         import numpy as np

@@ -247,6 +247,15 @@ __global__ void k_check(const double* a, int64_t n, int positive, unsigned long 
   if ((threadIdx.x & 63) == 0 && ballot) atomicAdd(bad, 1ull);
 }
 
+// Number of entries with !(a > 0) (E <= 0 or NaN) into cnt[0].
+__global__ void k_count_nonpos(const double* a, int64_t n, unsigned long long* cnt) {
+  unsigned long long local = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    local += !(a[i] > 0.0) ? 1ull : 0ull;
+  for (int off = 32; off > 0; off >>= 1) local += __shfl_down(local, off, 64);
+  if ((threadIdx.x & 63) == 0 && local) atomicAdd(cnt, local);
+}
+
 __global__ void k_zero_u64(unsigned long long* p) {
   if (threadIdx.x == 0) p[0] = 0ull;
 }
@@ -615,6 +624,7 @@ m1_status time_steps(m1_ctx* c, m1_state* U, double dt, int32_t nsteps, m1_stats
     stats->rel_residual = 0.0;
     stats->nonlinear_residual = 0.0;
     stats->cells_f_gt_1 = (int64_t)nf;
+    stats->cells_e_nonpos = 0;
     stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   }
   return M1_OK;
@@ -674,6 +684,7 @@ const char* m1_status_string(int32_t s) {
     case M1_ERR_OUT_OF_MEMORY: return "M1_ERR_OUT_OF_MEMORY";
     case M1_ERR_HIP: return "M1_ERR_HIP";
     case M1_ERR_NONFINITE: return "M1_ERR_NONFINITE";
+    case M1_NOT_ADMISSIBLE: return "M1_NOT_ADMISSIBLE";
     case M1_ERR_STATE: return "M1_ERR_STATE";
   }
   return "unknown status";
@@ -1011,13 +1022,20 @@ m1_status m1_implicit_step(m1_ctx* c, m1_state* U, double dt, m1_stats* stats) {
     ++it;
   }
   finish();
-  unsigned long long nf = 0;
+  unsigned long long nf = 0, ne = 0;
   k_zero_u64<<<1, 64, 0, c->stream>>>(c->dcount);
   launch_count_f(c->nd, c->g, c->Uk, c->cfg.c, c->dcount, c->stream);
   HIPCHK(c, hipMemcpyAsync(&nf, c->dcount, sizeof(nf), hipMemcpyDeviceToHost, c->stream));
+  k_zero_u64<<<1, 64, 0, c->stream>>>(c->dcount);
+  {
+    const int64_t grd = std::max<int64_t>(1, std::min<int64_t>((c->g.N + 255) / 256, 2048));
+    k_count_nonpos<<<grd, 256, 0, c->stream>>>(c->Uk, c->g.N, c->dcount);
+  }
+  HIPCHK(c, hipMemcpyAsync(&ne, c->dcount, sizeof(ne), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   prof_collect(c);
-  if (converged) {
+  const bool admissible = ne == 0;
+  if (converged && admissible) {
     if ((st = copy_state_out(c, c->Uk, U)) != M1_OK) return st;
     HIPCHK(c, hipStreamSynchronize(c->stream));
   }
@@ -1029,10 +1047,15 @@ m1_status m1_implicit_step(m1_ctx* c, m1_state* U, double dt, m1_stats* stats) {
     stats->rel_residual = lin_rel;
     stats->nonlinear_residual = rel;
     stats->cells_f_gt_1 = (int64_t)nf;
+    stats->cells_e_nonpos = (int64_t)ne;
     stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   }
   if (nonfinite) { c->err = "non-finite value in the Newton/GMRES iteration"; return M1_ERR_NONFINITE; }
   if (!converged) { c->err = "Newton iteration did not converge"; return M1_NOT_CONVERGED; }
+  if (!admissible) {
+    c->err = "the converged state has E <= 0 in " + std::to_string(ne) + " cells (not admissible)";
+    return M1_NOT_ADMISSIBLE;
+  }
   return M1_OK;
 }
 

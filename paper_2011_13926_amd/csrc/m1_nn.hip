@@ -792,6 +792,48 @@ m1_status m1nn_set_params(m1nn* n, const float* host, int64_t count) {
 m1_status m1nn_get_params(m1nn* n, float* host, int64_t count) { return copy_params(n, host, count, false, false); }
 m1_status m1nn_get_grads(m1nn* n, float* host, int64_t count) { return copy_params(n, host, count, false, true); }
 
+// He-normal initial weights (He et al. 2015: N(0, 2/fan_in) with fan_in = 9 C_in for a 3x3
+// convolution), zero biases, the 1x1 head N(0, 1/C) scaled by head_scale.  Normal draws:
+// SplitMix64 (Steele, Lea & Flood 2014) on the counter seed*2^32 + k gives two 53-bit
+// uniforms per pair, mapped by the Box-Muller transform; parameters are visited in the
+// definition order of m1nn_set_params, so a given seed always gives the same weights.
+m1_status m1nn_init_params(m1nn* n, uint64_t seed, float head_scale) {
+  if (!n || !std::isfinite(head_scale)) return M1_ERR_INVALID_ARG;
+  uint64_t ctr = seed << 32;
+  auto splitmix = [&]() {
+    uint64_t z = (ctr += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+  };
+  bool have = false;
+  double spare = 0.0;
+  auto normal = [&]() {
+    if (have) { have = false; return spare; }
+    const double u1 = ((splitmix() >> 11) + 1.0) * 0x1.0p-53;   // (0, 1]
+    const double u2 = (splitmix() >> 11) * 0x1.0p-53;           // [0, 1)
+    const double rad = std::sqrt(-2.0 * std::log(u1));
+    const double ang = 6.283185307179586477 * u2;
+    spare = rad * std::sin(ang);
+    have = true;
+    return rad * std::cos(ang);
+  };
+  const int64_t cnt = m1nn_param_count(n);
+  std::vector<float> h(cnt, 0.f);
+  int64_t k = 0;
+  for (auto& c : n->conv) {
+    const double sd = std::sqrt(2.0 / (9.0 * c.cin_true));
+    const int64_t nw = (int64_t)9 * c.cin_true * c.cout;
+    for (int64_t i = 0; i < nw; ++i) h[k++] = (float)(sd * normal());
+    k += c.cout;   // biases stay 0
+  }
+  const double sdh = std::sqrt(1.0 / n->ch[0]) * head_scale;
+  for (int64_t i = 0; i < (int64_t)n->ch[0] * n->cout; ++i) h[k++] = (float)(sdh * normal());
+  k += n->cout;
+  if (k != cnt) { n->err = "parameter layout mismatch"; return M1_ERR_INVALID_ARG; }
+  return m1nn_set_params(n, h.data(), cnt);
+}
+
 m1_status m1nn_forward(m1nn* n, const float* x, int32_t H, int32_t W, float* y) {
   if (!n || !x || !y) return M1_ERR_INVALID_ARG;
   m1_status st = check_size(n, H, W);

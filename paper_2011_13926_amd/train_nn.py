@@ -75,11 +75,9 @@ def generate_pairs(P, torch, p, steps, newton_max=6, rtol=1e-10, partial=(30, 90
 
 
 def train(P, torch, pairs, iters, lr=1e-3, seed=0, net=None, n=512, log_every=100, channels=CHANNELS):
-    from oracle import nn_oracle as N  # initial weights only (He-normal draw)
     if net is None:
         net = P.Net(9, 3, channels, Hmax=n, Wmax=n)
-        params = N.init_params(9, list(channels), 3, seed=seed, head_scale=0.1)
-        net.set_params(N.flatten_params(params, 9, list(channels), 3).astype(np.float32))
+        net.init_params(seed=seed, head_scale=0.1)
     rng = np.random.default_rng(seed)
     hist = []
     for it in range(iters):

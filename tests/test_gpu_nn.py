@@ -56,7 +56,10 @@ def test_mfma_network_forward_matches_oracle():
     ref = N.forward(params, x.astype(np.float64), CH, act_round=N.bf16_round)
     err = _rel(y, ref)
     _say(f"  forward relative L2 vs oracle (BF16 emulated): {err:.2e}")
-    assert err <= 1e-2
+    # both sides round the same activations to BF16; what remains is the FP32
+    # accumulation order and rare rounding-boundary flips (measured 1.0e-4)
+    assert err <= 1e-3
+    assert np.max(np.abs(y - ref)) <= 1e-2 * np.max(np.abs(ref))
 
 
 def test_mfma_network_gradients_match_oracle():
@@ -86,8 +89,62 @@ def test_mfma_network_gradients_match_oracle():
             k += ref.size
             err = _rel(got, ref)
             worst = max(worst, err)
-            assert err <= 5e-2, (name, part, err)
+            assert err <= 1e-2, (name, part, err)   # measured worst 2.6e-3
     _say(f"  worst per-tensor gradient relative L2: {worst:.2e}")
+
+
+def test_adam_step_matches_oracle():
+    """Two Adam steps on the GPU (FP32 master weights and moments) against the oracle's
+    Adam in FP64 fed with the same gradients."""
+    import paper_2011_13926_amd as P
+    _say("nn adam 16x16")
+    params, flat = _random_net_params(9)
+    rng = np.random.default_rng(10)
+    net = P.Net(CIN, COUT, CH, Hmax=16, Wmax=16)
+    ref = N.unflatten_params(flat.astype(np.float64), CIN, CH, COUT)
+    state = {}
+    try:
+        net.set_params(flat)
+        for step, lr in enumerate((1e-2, 3e-3)):
+            x = rng.standard_normal((16, 16, CIN)).astype(np.float32)
+            t = rng.standard_normal((16, 16, COUT)).astype(np.float32)
+            before = net.get_params().astype(np.float64)
+            net.backward(x, t)
+            g = N.unflatten_params(net.get_grads().astype(np.float64), CIN, CH, COUT)
+            net.adam_step(lr)
+            got = net.get_params().astype(np.float64)
+            ref = N.adam_step(ref, g, state, lr=lr)
+            want = N.flatten_params(ref, CIN, CH, COUT)
+            e_par = _rel(got, want)
+            e_upd = _rel(got - before, want - before)
+            _say(f"  step {step}: params {e_par:.2e}, update {e_upd:.2e}")
+            assert e_par <= 1e-6 and e_upd <= 1e-4
+    finally:
+        net.close()
+
+
+def test_library_initial_weights():
+    """m1nn_init_params: deterministic in the seed, zero biases, He-normal spread per layer."""
+    import paper_2011_13926_amd as P
+    _say("nn init")
+    net = P.Net(CIN, COUT, CH, Hmax=16, Wmax=16)
+    try:
+        net.init_params(seed=5, head_scale=0.1)
+        a = net.get_params()
+        net.init_params(seed=5, head_scale=0.1)
+        b = net.get_params()
+        net.init_params(seed=6, head_scale=0.1)
+        c = net.get_params()
+    finally:
+        net.close()
+    assert np.array_equal(a, b) and not np.array_equal(a, c)
+    prm = N.unflatten_params(a.astype(np.float64), CIN, CH, COUT)
+    for name, kind, ci, co in N.layer_specs(CIN, CH, COUT):
+        w = prm[name + ".w"]
+        assert np.all(prm[name + ".b"] == 0.0)
+        sd = np.sqrt(2.0 / (9 * ci)) if kind == "conv3" else 0.1 / np.sqrt(ci)
+        assert abs(w.mean()) <= 5 * sd / np.sqrt(w.size)
+        assert abs(w.std() / sd - 1.0) <= 6 / np.sqrt(w.size) + 0.02, name
 
 
 def test_training_reduces_the_loss():

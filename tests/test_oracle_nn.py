@@ -105,3 +105,54 @@ def test_bf16_ties_to_even():
     assert N.bf16_round(np.array([1.0 + 2 ** -8]))[0] == 1.0
     # 1 + 3*2^-8 is half-way between 1 + 2^-7 (odd) and 1 + 2^-6 (even): goes up
     assert N.bf16_round(np.array([1.0 + 3 * 2 ** -8]))[0] == 1.0 + 2 ** -6
+
+
+# ---------------------------------------------------------------------------
+# Adam (Kingma & Ba 2015, Algorithm 1)
+# ---------------------------------------------------------------------------
+def test_adam_first_step_moves_each_parameter_by_lr_times_the_gradient_sign():
+    """After one step the bias-corrected moments are g and g^2 exactly, so every
+    parameter moves by -lr g/(|g| + eps): a dropped bias correction moves it by
+    about 3.16 lr instead."""
+    g = np.array([2.0, -0.5, 1e-3, -7.0])
+    p = {"w": np.array([1.0, 2.0, 3.0, 4.0])}
+    N.adam_step(p, {"w": g}, {}, lr=0.01, eps=1e-8)
+    assert np.allclose(p["w"], [1.0, 2.0, 3.0, 4.0] - 0.01 * g / (np.abs(g) + 1e-8), rtol=0, atol=1e-15)
+
+
+def test_adam_constant_gradient_moves_lr_per_step():
+    """With a constant gradient the corrected moments stay g and g^2 for every t."""
+    g = np.array([[0.3, -4.0], [1.0, 2.5]])
+    p = {"w": np.zeros((2, 2)), "b": np.ones(3)}
+    gb = np.array([1.0, -1.0, 0.25])
+    st = {}
+    for _ in range(7):
+        N.adam_step(p, {"w": g, "b": gb}, st, lr=1e-3, eps=0.0)
+    assert st["t"] == 7
+    assert np.allclose(p["w"], -7e-3 * np.sign(g), rtol=0, atol=1e-15)
+    assert np.allclose(p["b"], 1.0 - 7e-3 * np.sign(gb), rtol=0, atol=1e-15)
+
+
+def test_adam_two_steps_worked_example():
+    """Hand-worked two steps with g1 = 2, g2 = -1, beta1 = 0.9, beta2 = 0.999, eps = 0:
+    m2 = 0.9*0.1*2 + 0.1*(-1) = 0.08, corrected by 1 - 0.81 = 0.19;
+    v2 = 0.999*0.001*4 + 0.001*1 = 0.004996, corrected by 1 - 0.998001 = 0.001999.
+    Swapping the two decay rates or the moments changes the second step."""
+    p = {"w": np.array([0.0])}
+    st = {}
+    N.adam_step(p, {"w": np.array([2.0])}, st, lr=0.1, eps=0.0)
+    assert p["w"][0] == pytest.approx(-0.1, abs=1e-15)
+    N.adam_step(p, {"w": np.array([-1.0])}, st, lr=0.1, eps=0.0)
+    step2 = 0.1 * (0.08 / 0.19) / np.sqrt(0.004996 / 0.001999)
+    assert p["w"][0] == pytest.approx(-0.1 - step2, rel=1e-13)
+    assert step2 == pytest.approx(0.026633, rel=1e-4)
+
+
+def test_adam_is_invariant_to_gradient_scale():
+    rng = np.random.default_rng(3)
+    gs = [rng.standard_normal(5) for _ in range(4)]
+    pa, pb, sa, sb = {"w": np.zeros(5)}, {"w": np.zeros(5)}, {}, {}
+    for g in gs:
+        N.adam_step(pa, {"w": g}, sa, lr=1e-2, eps=0.0)
+        N.adam_step(pb, {"w": 1e3 * g}, sb, lr=1e-2, eps=0.0)
+    assert np.allclose(pa["w"], pb["w"], rtol=1e-12, atol=0)

@@ -98,6 +98,62 @@ def random_problem(n, seed, *, source="none", flux_source="wb", bc=None,
     return p
 
 
+def edge_problem(n, seed, *, source="none", flux_source="wb", bc=None, dt=3.0,
+                 sigma_range=(1e-2, 1e2)):
+    """Random inputs that reach the closure's guard branches.
+
+    Starts from random_problem(n, seed, fmax=0.9, ...) and then, for the
+    linearisation state and for the time-n state alike, with one generator
+    (seed + 7919) in this draw order: a per-cell class u ~ U[0, 1) and, per cell,
+    a reduced-flux magnitude g ~ U[0.9, 3] and an energy e ~ U[0, 0.5].  Classes:
+      u < 0.25          : |F| = g c E (super-luminal flux, clamped by the closure)
+      0.25 <= u < 0.35  : F = 0 exactly
+      0.35 <= u < 0.42  : E = -e (non-positive energy, F kept)
+      0.42 <= u < 0.45  : E = 0 exactly
+    Then two stripes of reduced flux exactly 1, tangent to the faces between
+    them: the cells of columns x = nx//3 and nx//3 + 1 carry F = c E along y (2D),
+    or the cells of planes z = nz//3 and nz//3 + 1 carry F = c E along z (3D), so
+    the faces between two such cells have both wave speeds zero on both sides.
+    """
+    p = random_problem(n, seed, source=source, flux_source=flux_source, bc=bc, dt=dt, fmax=0.9,
+                       sigma_range=sigma_range)
+    rng = np.random.default_rng(seed + 7919)
+    ndim = len(n)
+    g_shape = grid_shape(n)
+
+    def modify(E, F):
+        E = E.copy()
+        F = F.copy()
+        u = rng.uniform(0.0, 1.0, size=g_shape)
+        g = rng.uniform(0.9, 3.0, size=g_shape)
+        e = rng.uniform(0.0, 0.5, size=g_shape)
+        mag = np.sqrt((F * F).sum(axis=0))
+        unit = np.where(mag > 0, F / np.where(mag > 0, mag, 1.0), 0.0)
+        sup = u < 0.25
+        F[:, sup] = (p["c"] * g * E)[sup] * unit[:, sup]
+        F[:, (u >= 0.25) & (u < 0.35)] = 0.0
+        neg = (u >= 0.35) & (u < 0.42)
+        E[neg] = -e[neg]
+        E[(u >= 0.42) & (u < 0.45)] = 0.0
+        if ndim == 2:
+            i0 = n[0] // 3
+            for i in (i0, min(i0 + 1, n[0] - 1)):
+                E[:, i] = rng.uniform(0.5, 2.0, size=E.shape[0])
+                F[:, :, i] = 0.0
+                F[1, :, i] = p["c"] * E[:, i]
+        else:
+            k0 = n[2] // 3
+            for k in (k0, min(k0 + 1, n[2] - 1)):
+                E[k] = rng.uniform(0.5, 2.0, size=E.shape[1:])
+                F[:, k] = 0.0
+                F[2, k] = p["c"] * E[k]
+        return E, F
+
+    p["E"], p["F"] = modify(p["E"], p["F"])
+    p["En"], p["Fn"] = modify(p["En"], p["Fn"])
+    return p
+
+
 def random_vector(n_total, seed):
     """A seeded standard-normal vector (for operator / preconditioner probes)."""
     return np.random.default_rng(seed).standard_normal(n_total)
