@@ -601,13 +601,16 @@ def mass_diagonal(sch, rho_cv):
 
 def implicit_step(sch, sigma, rho_cv, Un, dt, *, restart=30, rtol=1e-10, max_iters=20000,
                   newton_max=20, newton_rtol=None, fixed_iters=0, pc="bj",
-                  psi0=0.0, ptc_rtol=0.0, line_search=False, clip=0.0, forcing=0.0):
+                  psi0=0.0, ptc_rtol=0.0, line_search=False, clip=0.0, forcing=0.0, mg_opts=None):
     """Advance Un by one backward-Euler step (Sect. 3.1, Sect. 3.3.1).
 
     Newton loop: linearise at U^k, b = -R(U^k); stop when
     ||R(U^k)|| <= newton_rtol ||R(U^0)||; else solve A^k delta = b by GMRES and
     set U^{k+1} = U^k + delta.  With fixed_iters > 0 exactly newton_max linear
     solves of exactly fixed_iters GMRES iterations are made (no early exit).
+
+    pc: "bj" (block-Jacobi), "mg" (the aggregation multigrid V-cycle of
+    m1_multigrid, options mg_opts) or "none".
 
     Four optional additions change the path to the root, never the root
     itself (the residual R is untouched).  They are solver additions; the
@@ -665,7 +668,13 @@ def implicit_step(sch, sigma, rho_cv, Un, dt, *, restart=30, rtol=1e-10, max_ite
         if not np.isfinite(rn):
             break
         shift = psi * mass if psi > 0 else None
-        M = BlockJacobi(lin, shift) if pc == "bj" else (lambda v: v)
+        if pc == "bj":
+            M = BlockJacobi(lin, shift)
+        elif pc == "mg":
+            from .m1_multigrid import Multigrid
+            M = Multigrid(lin, shift=shift, **(mg_opts or {}))
+        else:
+            M = lambda v: v
         if shift is None:
             op = lambda v: apply_operator(lin, v)
         else:
