@@ -96,7 +96,14 @@ typedef enum {
 } m1_bc;
 
 typedef enum { M1_FP64 = 0, M1_MIXED = 1 } m1_precision;
-typedef enum { M1_PC_BLOCK_JACOBI = 0, M1_PC_NONE = 1, M1_PC_LEARNED = 2 } m1_pc;
+/* Preconditioners: block-Jacobi (the exact n_u x n_u diagonal blocks), none, the
+ * learned one (flexible GMRES, block-Jacobi fallback), or aggregation multigrid:
+ * one V(mg_nu1, mg_nu2) cycle per application on a hierarchy of 2 x 2 (x 2)
+ * aggregates with Galerkin coarse operators A_{l+1} = P^T A_l P (P piecewise
+ * constant), damped block-Jacobi smoothing and an exact coarsest solve -- the
+ * geometric counterpart of the algebraic multigrid the paper found best
+ * (Sect. 4.1-4.2). */
+typedef enum { M1_PC_BLOCK_JACOBI = 0, M1_PC_NONE = 1, M1_PC_LEARNED = 2, M1_PC_MULTIGRID = 3 } m1_pc;
 
 typedef struct {
   int32_t ndim;            /* 2 or 3 */
@@ -142,6 +149,13 @@ typedef struct {
                               solves to max(rtol, min(0.1, newton_forcing ||R_k||/||R_0||)); the
                               looser of this and the PTC tolerance applies; 0: rtol */
   const char* nn_weights_path; /* host string or NULL (learned preconditioner) */
+  /* aggregation multigrid (pc = M1_PC_MULTIGRID; ignored otherwise) */
+  double mg_omega;         /* damping of the block-Jacobi smoother, in (0, 2) */
+  int32_t mg_nu1;          /* pre-smoothing sweeps, 0..4 */
+  int32_t mg_nu2;          /* post-smoothing sweeps, 0..4 */
+  int32_t mg_nmin;         /* coarsen while an extent exceeds this (>= 2; 0: 8 in 2D, 4 in 3D); the
+                              coarsest level (solved exactly) may hold at most 512 unknowns */
+  int32_t mg_reserved;     /* must be 0 */
 } m1_config;
 
 typedef struct {

@@ -40,7 +40,7 @@ CLOSURE = {"m1": 0, "p1": 1}
 LINEARIZATION = {"newton": 0, "picard": 1}
 BC = {"periodic": 0, "outflow": 1, "dirichlet": 2, "reflect": 3}
 PRECISION = {"fp64": 0, "mixed": 1}
-PC = {"bj": 0, "none": 1, "learned": 2}
+PC = {"bj": 0, "none": 1, "learned": 2, "mg": 3}
 
 
 class M1Config(ctypes.Structure):
@@ -55,6 +55,8 @@ class M1Config(ctypes.Structure):
         ("newton_rtol", ctypes.c_double), ("inner_rtol", ctypes.c_double), ("ptc_psi0", ctypes.c_double),
         ("ptc_rtol", ctypes.c_double), ("positivity_clip", ctypes.c_double), ("newton_forcing", ctypes.c_double),
         ("nn_weights_path", ctypes.c_char_p),
+        ("mg_omega", ctypes.c_double), ("mg_nu1", ctypes.c_int32), ("mg_nu2", ctypes.c_int32),
+        ("mg_nmin", ctypes.c_int32), ("mg_reserved", ctypes.c_int32),
     ]
 
 
@@ -182,7 +184,8 @@ def kernel_classes():
 # ---------------------------------------------------------------------------
 def make_config(p, *, precision="fp64", pc="bj", restart=30, max_iters=20000, newton_max=20, fixed_iters=0,
                 rtol=1e-10, newton_rtol=None, inner_rtol=1e-6, basis_fp32=False, line_search=False,
-                ptc_psi0=0.0, ptc_rtol=0.0, positivity_clip=0.0, newton_forcing=0.0):
+                ptc_psi0=0.0, ptc_rtol=0.0, positivity_clip=0.0, newton_forcing=0.0, mg_omega=0.7, mg_nu1=1,
+                mg_nu2=1, mg_nmin=0):
     """m1_config from a problem description (the dict layout of ``workloads``)."""
     cfg = M1Config()
     cfg.ndim = p["ndim"]
@@ -208,6 +211,7 @@ def make_config(p, *, precision="fp64", pc="bj", restart=30, max_iters=20000, ne
     cfg.ptc_psi0, cfg.ptc_rtol, cfg.positivity_clip = ptc_psi0, ptc_rtol, positivity_clip
     cfg.newton_forcing = newton_forcing
     cfg.nn_weights_path = None
+    cfg.mg_omega, cfg.mg_nu1, cfg.mg_nu2, cfg.mg_nmin, cfg.mg_reserved = mg_omega, mg_nu1, mg_nu2, mg_nmin, 0
     return cfg
 
 

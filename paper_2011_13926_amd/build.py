@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIBDIR = os.path.join(HERE, "lib")
 LIB = os.path.join(LIBDIR, "libm1.so")
-SOURCES = ["m1_kernels.hip", "m1_krylov.hip", "m1_nn.hip", "m1_api.hip"]
+SOURCES = ["m1_kernels.hip", "m1_krylov.hip", "m1_nn.hip", "m1_multigrid.hip", "m1_api.hip"]
 ARCH = os.environ.get("M1_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"

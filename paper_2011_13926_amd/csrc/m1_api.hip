@@ -23,7 +23,7 @@ namespace {
 const char* kClassNames[KC_COUNT] = {"setup",   "setup_bj", "residual",   "apply",         "block_jacobi",
                                      "arnoldi_dot", "arnoldi_scalar", "arnoldi_update", "x_update",
                                      "true_residual", "newton_update", "norm", "convert", "learned_pc", "apply_bj_fused",
-                                     "time_step", "velocity_sources"};
+                                     "time_step", "velocity_sources", "multigrid", "multigrid_setup"};
 
 struct Profiler {
   bool on = false;
@@ -87,6 +87,9 @@ struct m1_ctx {
   m1nn* net = nullptr;
   void* Z = nullptr;
   int use_learned = 0;   // 1 while the current solve uses the network
+  // aggregation multigrid (pc = M1_PC_MULTIGRID)
+  MgHierarchy mg;
+  double* xw = nullptr;  // V y before the preconditioner at the end of a cycle
   // pinned host read-back
   double* hscal = nullptr;
   Profiler prof;
@@ -121,7 +124,7 @@ hipEvent_t prof_event(m1_ctx* c) {
 // the solver's run time at 512^2.  Other classes are timed on every launch.
 bool per_iteration_class(int kc) {
   return kc == KC_APPLY || kc == KC_BJ || kc == KC_DOT || kc == KC_SCALAR || kc == KC_UPDATE || kc == KC_NN ||
-         kc == KC_APPLY_PC;
+         kc == KC_APPLY_PC || kc == KC_MG;
 }
 
 // Launch with optional HIP-event timing; `bytes` is the launch's algorithmic
@@ -200,7 +203,7 @@ m1_status validate_config(const m1_config* c, std::string& err) {
   }
   if (c->source < 0 || c->source > 2 || c->flux_source < 0 || c->flux_source > 1 || c->closure < 0 ||
       c->closure > 1 || c->linearization < 0 || c->linearization > 1 || c->precision < 0 || c->precision > 1 ||
-      c->pc < 0 || c->pc > 2) {
+      c->pc < 0 || c->pc > 3) {
     err = "enum value out of range";
     return M1_ERR_INVALID_ARG;
   }
@@ -208,6 +211,12 @@ m1_status validate_config(const m1_config* c, std::string& err) {
     err = "the learned preconditioner is for 2D radiation-only problems";
     return M1_ERR_INVALID_ARG;
   }
+  if (c->pc == M1_PC_MULTIGRID) {
+    if (!(finite(c->mg_omega) && c->mg_omega > 0 && c->mg_omega < 2)) { err = "mg_omega must be in (0, 2)"; return M1_ERR_INVALID_ARG; }
+    if (c->mg_nu1 < 0 || c->mg_nu1 > 4 || c->mg_nu2 < 0 || c->mg_nu2 > 4) { err = "mg_nu1 and mg_nu2 must be in 0..4"; return M1_ERR_INVALID_ARG; }
+    if (c->mg_nmin != 0 && c->mg_nmin < 2) { err = "mg_nmin must be 0 or >= 2"; return M1_ERR_INVALID_ARG; }
+  }
+  if (c->mg_reserved != 0) { err = "mg_reserved must be 0"; return M1_ERR_INVALID_ARG; }
   if (!(finite(c->lambda_floor) && c->lambda_floor >= 0)) { err = "lambda_floor must be >= 0"; return M1_ERR_INVALID_ARG; }
   for (int f = 0; f < 2 * c->ndim; ++f) {
     if (c->bc[f] < 0 || c->bc[f] > 3) { err = "bc value out of range"; return M1_ERR_INVALID_ARG; }
@@ -296,9 +305,16 @@ void free_all(m1_ctx* c) {
     if (c->mask[f]) hipFree(c->mask[f]);
   }
   void* bufs[] = {c->Uk, c->Un, c->Uprev, c->fn, c->coef64, c->coef32, c->V, c->b, c->x, c->u[0], c->u[1],
-                  c->p, c->z, c->part, c->gs, c->dscal, c->dcount, c->Z};
+                  c->p, c->z, c->part, c->gs, c->dscal, c->dcount, c->Z, c->xw,
+                  c->mg.Ainv64, c->mg.Ainv32, c->mg.work, c->mg.bad};
   for (void* b : bufs)
     if (b) hipFree(b);
+  for (int l = 0; l < c->mg.nlev; ++l) {
+    MgLevel& L = c->mg.lev[l];
+    void* lb[] = {L.S64, L.S32, L.Dinv64, L.Dinv32, L.b, L.z, L.w, L.t};
+    for (void* b : lb)
+      if (b) hipFree(b);
+  }
   if (c->hscal) hipHostFree(c->hscal);
   for (auto e : c->prof.pool) hipEventDestroy(e);
 }
@@ -354,6 +370,39 @@ Bdry bdry(const m1_ctx* c) {
   return b;
 }
 
+// grid sizes, strides, boundary kinds and plane sizes of a validated configuration
+void fill_geom(const m1_config& cfg, Geom& g) {
+  const int nd = cfg.ndim;
+  g.n[0] = (int)cfg.n[0];
+  g.n[1] = (int)cfg.n[1];
+  g.n[2] = nd == 3 ? (int)cfg.n[2] : 1;
+  g.rows = g.n[1] * g.n[2];
+  g.N = (int64_t)g.n[0] * g.n[1] * g.n[2];
+  g.stride[0] = 1;
+  g.stride[1] = g.n[0];
+  g.stride[2] = (int64_t)g.n[0] * g.n[1];
+  for (int f = 0; f < 6; ++f) g.bc[f] = f < 2 * nd ? cfg.bc[f] : M1_BC_PERIODIC;
+  g.plane_n[0] = g.n[1] * g.n[2];
+  g.plane_n[1] = g.n[0] * g.n[2];
+  g.plane_n[2] = g.n[0] * g.n[1];
+}
+
+// scheme constants of a validated configuration (dt-derived ones left to set_dt)
+void fill_scheme(const m1_config& cfg, Scheme& sc) {
+  sc.c = cfg.c;
+  sc.c2 = cfg.c * cfg.c;
+  sc.a_r = cfg.a_r;
+  sc.dx = cfg.dx;
+  sc.dx_c = cfg.dx / cfg.c;
+  sc.lambda_floor = cfg.lambda_floor;
+  sc.src = cfg.source;
+  sc.wb = cfg.flux_source == M1_FSRC_WELL_BALANCED;
+  sc.ap = cfg.ap_correction != 0;
+  sc.p1 = cfg.closure == M1_CLOSURE_P1;
+  sc.newton = cfg.linearization == M1_LIN_NEWTON;
+  sc.psi = 0.0;
+}
+
 void set_dt(m1_ctx* c, double dt) {
   c->sc.dt = dt;
   c->sc.s = dt / c->cfg.dx;
@@ -382,6 +431,73 @@ m1_status copy_state_out(m1_ctx* c, const double* src, m1_state* U) {
   return M1_OK;
 }
 
+// ---- aggregation multigrid: hierarchy sizes, algorithmic bytes, finest-level operator ----
+int mg_default_nmin(int nd) { return nd == 2 ? 8 : 4; }
+
+// level extents: halve (rounding up) until every extent is <= nmin
+void mg_levels(const m1_ctx* c, MgHierarchy& h) {
+  const int nmin = c->cfg.mg_nmin > 0 ? c->cfg.mg_nmin : mg_default_nmin(c->nd);
+  MgGeom g{};
+  for (int d = 0; d < 3; ++d) {
+    g.n[d] = c->g.n[d];
+    g.per[d] = d < c->nd && c->g.bc[2 * d] == M1_BC_PERIODIC;
+  }
+  h.nlev = 0;
+  while (true) {
+    g.N = (int64_t)g.n[0] * g.n[1] * g.n[2];
+    h.lev[h.nlev++].g = g;
+    if (std::max(g.n[0], std::max(g.n[1], g.n[2])) <= nmin || h.nlev == kMgMaxLevels) break;
+    for (int d = 0; d < 3; ++d) g.n[d] = (g.n[d] + 1) / 2;
+  }
+}
+
+// one V-cycle: finest level (two applies, block-Jacobi sweeps, restriction,
+// prolongation) plus, per coarse level, the down and up kernels (stencil,
+// inverse diagonal, vectors) -- each array element once per kernel
+double mg_cycle_bytes(const m1_ctx* c, size_t rs) {
+  const MgHierarchy& h = c->mg;
+  const double nu = c->nu, nb = 1 + 2 * c->nd;
+  const double N0 = cells(c);
+  double b = 0.0;
+  const int sweeps0 = h.nu1 + h.nu2;
+  b += sweeps0 * (bytes_apply(c, rs, rs, rs, false) + (4.0 * nu + nu * nu) * rs * N0);
+  b += 2.0 * nu * rs * N0 + 2.0 * nu * rs * N0;   // restriction, prolongation
+  for (int l = 1; l < h.nlev; ++l) {
+    const double Nl = (double)h.lev[l].g.N;
+    if (l + 1 == h.nlev) b += (nu * Nl) * (nu * Nl) * rs + 2.0 * nu * Nl * rs;
+    else b += (h.nu1 + h.nu2) * ((nb * nu * nu + nu * nu) + 4.0 * nu) * rs * Nl;
+  }
+  return b;
+}
+
+double mg_setup_bytes(const m1_ctx* c) {
+  const MgHierarchy& h = c->mg;
+  const double nu = c->nu, nb = 1 + 2 * c->nd;
+  double b = bytes_setup_bj(c) + nb * nu * nu * 8.0 * cells(c);
+  for (int l = 1; l < h.nlev; ++l) b += (nb * nu * nu + nu * nu) * 8.0 * (double)h.lev[l].g.N;
+  return b;
+}
+
+template <typename R> const Coefs<R>& coefs_of(const m1_ctx* c);
+template <> const Coefs<double>& coefs_of<double>(const m1_ctx* c) { return c->cf64; }
+template <> const Coefs<float>& coefs_of<float>(const m1_ctx* c) { return c->cf32; }
+
+template <typename R>
+void mg_fine_apply(const void* self, const R* x, R* y, hipStream_t s, const int* skip) {
+  const m1_ctx* c = (const m1_ctx*)self;
+  launch_apply<R, R, R>(c->nd, c->cpl, 0, c->g, c->sc, coefs_of<R>(c), bdry(c), x, nullptr, y, s, skip);
+}
+
+template <typename R> MgFine<R> mg_fine(const m1_ctx* c) {
+  MgFine<R> f;
+  f.nd = c->nd;
+  f.nu = c->nu;
+  f.bjinv = coefs_of<R>(c).bjinv;
+  f.apply = &mg_fine_apply<R>;
+  f.self = c;
+  return f;
+}
+
 // Linearise at c->Uk with time-level state c->Un (|f^n| already in c->fn).
 // block-Jacobi inverses of the current coefficients with the current shift
 // sc.psi, then the FP32 shadow of the whole slab (mixed precision)
@@ -389,6 +505,22 @@ m1_status build_bj(m1_ctx* c) {
   const Bdry bd = bdry(c);
   timed(c, KC_SETUP_BJ, bytes_setup_bj(c), [&] { launch_setup_bj(c->nd, c->cpl, c->g, c->sc, c->cf64, bd, c->stream); });
   if (mixed(c)) timed(c, KC_CONVERT, 12.0 * c->coef_len, [&] { launch_convert(c->coef64, c->coef32, c->coef_len, c->stream); });
+  if (c->cfg.pc == M1_PC_MULTIGRID) {
+    MgHierarchy& h = c->mg;
+    const int nb = 1 + 2 * c->nd, bs = c->nu * c->nu;
+    timed(c, KC_MG_SETUP, mg_setup_bytes(c), [&] {
+      launch_fine_stencil(c->nd, c->cpl, c->g, c->sc, c->cf64, bd, h.lev[0].S64, c->stream);
+      mg_build(h, c->nd, c->nu, c->stream);
+      if (mixed(c)) {
+        for (int l = 1; l < h.nlev; ++l) {
+          launch_convert(h.lev[l].S64, h.lev[l].S32, (int64_t)nb * bs * h.lev[l].g.N, c->stream);
+          if (h.lev[l].Dinv64) launch_convert(h.lev[l].Dinv64, h.lev[l].Dinv32, (int64_t)bs * h.lev[l].g.N, c->stream);
+        }
+        const int64_t nc = (int64_t)c->nu * h.lev[h.nlev - 1].g.N;
+        launch_convert(h.Ainv64, h.Ainv32, nc * nc, c->stream);
+      }
+    });
+  }
   HIPCHK(c, hipGetLastError());
   c->bj_ready = true;
   c->bj_psi = c->sc.psi;
@@ -444,7 +576,9 @@ m1_status gmres(m1_ctx* c, double bnorm, SolveResult& res, const Coefs<R>& cfi) 
   const double tol_rel = (mixed(c) && !fixed) ? c->cfg.inner_rtol : 0.0;
   const bool learned = c->use_learned && c->net;
   const int use_pc = !learned && c->cfg.pc != M1_PC_NONE;
-  const bool fused = use_pc && fused_apply_available(c->nd);
+  const bool use_mg = use_pc && c->cfg.pc == M1_PC_MULTIGRID;
+  const bool fused = use_pc && !use_mg && fused_apply_available(c->nd);
+  const MgFine<R> mgf = mg_fine<R>(c);
   R* Z = (R*)c->Z;
   HIPCHK(c, hipMemsetAsync(c->x, 0, sizeof(double) * n, c->stream));
   // r = b
@@ -502,6 +636,9 @@ m1_status gmres(m1_ctx* c, double bnorm, SolveResult& res, const Coefs<R>& cfi) 
                                   (double)c->nu * c->nu * sizeof(R) * cells(c), [&] {
           launch_apply_pre<R, TV, TV>(c->nd, c->cpl, c->g, c->sc, cfi, bd, uj, p, c->stream, &c->gs->done);
         }, j, 0);
+      } else if (use_mg) {
+        timed(c, KC_MG, mg_cycle_bytes(c, sizeof(R)), [&] { mg_vcycle<R, TV>(c->mg, mgf, uj, z, c->stream, &c->gs->done); }, j, 0);
+        timed(c, KC_APPLY, bytes_apply(c, sizeof(R), sizeof(R), sizeof(TV), false), [&] { launch_apply<R, R, TV>(c->nd, c->cpl, 0, c->g, c->sc, cfi, bd, z, nullptr, p, c->stream, &c->gs->done); }, j, 0);
       } else if (use_pc) {
         timed(c, KC_BJ, bytes_bj(c, sizeof(R), sizeof(TV), sizeof(R)), [&] { launch_bj<R, TV, R>(c->nd, c->cpl, c->g, cfi, uj, z, c->stream, &c->gs->done); }, j, 0);
         timed(c, KC_APPLY, bytes_apply(c, sizeof(R), sizeof(R), sizeof(TV), false), [&] { launch_apply<R, R, TV>(c->nd, c->cpl, 0, c->g, c->sc, cfi, bd, z, nullptr, p, c->stream, &c->gs->done); }, j, 0);
@@ -518,6 +655,12 @@ m1_status gmres(m1_ctx* c, double bnorm, SolveResult& res, const Coefs<R>& cfi) 
     }
     if (learned) {
       timed(c, KC_XUPDATE, (double)steps * n * sizeof(R) + 16.0 * n, [&] { launch_xupdate<R, R>(c->nd, c->cpl, c->g, cfi, Z, vs, c->gs, c->x, 0, c->stream); });
+    } else if (use_mg) {
+      // x += M^{-1} (V y): V y into xw, one cycle, then the FP64 update
+      HIPCHK(c, hipMemsetAsync(c->xw, 0, sizeof(double) * n, c->stream));
+      timed(c, KC_XUPDATE, (double)steps * n * sizeof(TV) + 16.0 * n, [&] { launch_xupdate<R, TV>(c->nd, c->cpl, c->g, cfi, V, vs, c->gs, c->xw, 0, c->stream); });
+      timed(c, KC_MG, mg_cycle_bytes(c, sizeof(R)), [&] { mg_vcycle<R, double>(c->mg, mgf, c->xw, z, c->stream, nullptr); });
+      mg_axpy<R>(z, c->x, n, c->stream);
     } else {
       timed(c, KC_XUPDATE, (double)steps * n * sizeof(TV) + 16.0 * n + (use_pc ? (double)c->nu * c->nu * sizeof(R) * cells(c) : 0.0), [&] { launch_xupdate<R, TV>(c->nd, c->cpl, c->g, cfi, V, vs, c->gs, c->x, use_pc, c->stream); });
     }
@@ -720,32 +863,9 @@ m1_status m1_setup(const m1_config* cfg, const m1_fields* fields, const m1_state
   c->m = cfg->restart;
   c->stream = (hipStream_t)hip_stream;
   hipGetDevice(&c->device);
-  Geom& g = c->g;
-  g.n[0] = (int)cfg->n[0];
-  g.n[1] = (int)cfg->n[1];
-  g.n[2] = c->nd == 3 ? (int)cfg->n[2] : 1;
-  g.rows = g.n[1] * g.n[2];
-  g.N = (int64_t)g.n[0] * g.n[1] * g.n[2];
-  g.stride[0] = 1;
-  g.stride[1] = g.n[0];
-  g.stride[2] = (int64_t)g.n[0] * g.n[1];
-  for (int f = 0; f < 6; ++f) g.bc[f] = f < 2 * c->nd ? cfg->bc[f] : M1_BC_PERIODIC;
-  g.plane_n[0] = g.n[1] * g.n[2];
-  g.plane_n[1] = g.n[0] * g.n[2];
-  g.plane_n[2] = g.n[0] * g.n[1];
-  Scheme& sc = c->sc;
-  sc.c = cfg->c;
-  sc.c2 = cfg->c * cfg->c;
-  sc.a_r = cfg->a_r;
-  sc.dx = cfg->dx;
-  sc.dx_c = cfg->dx / cfg->c;
-  sc.lambda_floor = cfg->lambda_floor;
-  sc.src = cfg->source;
-  sc.wb = cfg->flux_source == M1_FSRC_WELL_BALANCED;
-  sc.ap = cfg->ap_correction != 0;
-  sc.p1 = cfg->closure == M1_CLOSURE_P1;
-  sc.newton = cfg->linearization == M1_LIN_NEWTON;
-  sc.psi = 0.0;
+  fill_geom(*cfg, c->g);
+  fill_scheme(*cfg, c->sc);
+  const Geom& g = c->g;
   set_dt(c, U_lin ? dt : 1.0);
   c->n = (int64_t)c->nu * g.N;
   c->vs = (c->n + 63) / 64 * 64;
@@ -792,6 +912,48 @@ m1_status m1_setup(const m1_config* cfg, const m1_fields* fields, const m1_state
     char* a = nullptr;
     if ((st = dalloc(c, &a, (int64_t)(c->m + 1) * c->vs * (int64_t)rs)) != M1_OK) return fail(st);
     c->Z = a;
+  }
+  if (cfg->pc == M1_PC_MULTIGRID) {
+    MgHierarchy& h = c->mg;
+    h.omega = cfg->mg_omega;
+    h.nu1 = cfg->mg_nu1;
+    h.nu2 = cfg->mg_nu2;
+    mg_levels(c, h);
+    const int64_t ncoarse = (int64_t)c->nu * h.lev[h.nlev - 1].g.N;
+    if (ncoarse > kMgMaxCoarse) {
+      c->err = "multigrid: the coarsest level has " + std::to_string(ncoarse) + " unknowns (at most " +
+               std::to_string(kMgMaxCoarse) + "); lower mg_nmin";
+      return fail(M1_ERR_INVALID_ARG);
+    }
+    const int64_t nbs = (int64_t)(1 + 2 * c->nd) * c->nu * c->nu;
+    for (int l = 0; l < h.nlev; ++l) {
+      MgLevel& L = h.lev[l];
+      const int64_t Nl = L.g.N;
+      const bool coarsest = l + 1 == h.nlev;
+      if ((st = dalloc(c, &L.S64, nbs * Nl)) != M1_OK) return fail(st);
+      if (l > 0 && mixed(c) && (st = dalloc(c, &L.S32, nbs * Nl)) != M1_OK) return fail(st);
+      if (l > 0 && !coarsest) {
+        if ((st = dalloc(c, &L.Dinv64, (int64_t)c->nu * c->nu * Nl)) != M1_OK) return fail(st);
+        if (mixed(c) && (st = dalloc(c, &L.Dinv32, (int64_t)c->nu * c->nu * Nl)) != M1_OK) return fail(st);
+      }
+      double* v = nullptr;
+      if ((st = dalloc(c, &v, (int64_t)c->nu * Nl)) != M1_OK) return fail(st);
+      L.b = v;
+      if ((st = dalloc(c, &v, (int64_t)c->nu * Nl)) != M1_OK) return fail(st);
+      L.z = v;
+      if ((st = dalloc(c, &v, (int64_t)c->nu * Nl)) != M1_OK) return fail(st);
+      L.w = v;
+      if (l == 0) {
+        if ((st = dalloc(c, &v, (int64_t)c->nu * Nl)) != M1_OK) return fail(st);
+        L.t = v;
+      }
+    }
+    if ((st = dalloc(c, &h.Ainv64, ncoarse * ncoarse)) != M1_OK) return fail(st);
+    if (mixed(c) && (st = dalloc(c, &h.Ainv32, ncoarse * ncoarse)) != M1_OK) return fail(st);
+    if ((st = dalloc(c, &h.work, 2 * ncoarse * ncoarse)) != M1_OK) return fail(st);
+    if ((st = dalloc(c, &h.bad, 1)) != M1_OK) return fail(st);
+    if (!hip_ok(c, hipMemsetAsync(h.bad, 0, sizeof(int), c->stream), "memset")) return fail(M1_ERR_HIP);
+    if ((st = dalloc(c, &c->xw, c->n)) != M1_OK) return fail(st);
   }
   if ((st = dalloc(c, &c->part, (int64_t)(2 * kMaxRestart + 2) * c->nb)) != M1_OK) return fail(st);
   if ((st = dalloc(c, &c->gs, 1)) != M1_OK) return fail(st);
@@ -880,7 +1042,13 @@ m1_status m1_precondition(m1_ctx* c, const double* r, double* z) {
   }
   m1_status st;
   if ((st = ensure_bj(c)) != M1_OK) return st;
-  timed(c, KC_BJ, bytes_bj(c, 8, 8, 8), [&] { launch_bj<double, double, double>(c->nd, c->cpl, c->g, c->cf64, r, z, c->stream); });
+  if (c->cfg.pc == M1_PC_MULTIGRID) {
+    if (r == z) { c->err = "the multigrid preconditioner needs distinct r and z"; return M1_ERR_INVALID_ARG; }
+    const MgFine<double> f = mg_fine<double>(c);
+    timed(c, KC_MG, mg_cycle_bytes(c, 8), [&] { mg_vcycle<double, double>(c->mg, f, r, z, c->stream, nullptr); });
+  } else {
+    timed(c, KC_BJ, bytes_bj(c, 8, 8, 8), [&] { launch_bj<double, double, double>(c->nd, c->cpl, c->g, c->cf64, r, z, c->stream); });
+  }
   HIPCHK(c, hipGetLastError());
   return M1_OK;
 }

@@ -226,4 +226,49 @@ __device__ __forceinline__ double ghost_weight(int bc, int d, int comp, const do
   return 1.0;  // outflow
 }
 
+// --- small dense blocks ----------------------------------------------------------
+// Inverse of an NU x NU block by Gauss-Jordan elimination with partial pivoting
+// (A is overwritten); false if a pivot is zero.
+template <int NU>
+__device__ __forceinline__ bool invert_block(double (&A)[NU][NU], double (&Ai)[NU][NU]) {
+#pragma unroll
+  for (int r = 0; r < NU; ++r)
+#pragma unroll
+    for (int c = 0; c < NU; ++c) Ai[r][c] = r == c ? 1.0 : 0.0;
+  bool ok = true;
+#pragma unroll
+  for (int col = 0; col < NU; ++col) {
+    // partial pivoting (rows col..NU-1)
+    int piv = col;
+    double best = fabs(A[col][col]);
+#pragma unroll
+    for (int r = col + 1; r < NU; ++r) {
+      const double v = fabs(A[r][col]);
+      if (v > best) { best = v; piv = r; }
+    }
+    ok = ok && best > 0.0;
+#pragma unroll
+    for (int r = col + 1; r < NU; ++r) {
+      if (r == piv) {
+#pragma unroll
+        for (int c = 0; c < NU; ++c) {
+          double t = A[col][c]; A[col][c] = A[r][c]; A[r][c] = t;
+          t = Ai[col][c]; Ai[col][c] = Ai[r][c]; Ai[r][c] = t;
+        }
+      }
+    }
+    const double inv = 1.0 / A[col][col];
+#pragma unroll
+    for (int c = 0; c < NU; ++c) { A[col][c] *= inv; Ai[col][c] *= inv; }
+#pragma unroll
+    for (int r = 0; r < NU; ++r) {
+      if (r == col) continue;
+      const double f = A[r][col];
+#pragma unroll
+      for (int c = 0; c < NU; ++c) { A[r][c] -= f * A[col][c]; Ai[r][c] -= f * Ai[col][c]; }
+    }
+  }
+  return ok;
+}
+
 }  // namespace m1

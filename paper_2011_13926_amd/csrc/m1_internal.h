@@ -48,9 +48,67 @@ struct GmresState {
   double y[kMaxRestart];
 };
 
+// ---- aggregation multigrid (m1_multigrid.hip) ----
+struct MgGeom {
+  int n[3];      // extents (x, y, z; 1 beyond ndim)
+  int64_t N;     // cells
+  int per[3];    // periodic axes
+};
+
+// One level: explicit block stencil S (block 0 diagonal, block 1 + 2d + side the
+// neighbour along d, entry (r, c) of block b at S[((b * NU + r) * NU + c) * N + cell]),
+// inverse diagonal blocks, and the cycle's vectors (NU * N values of the
+// preconditioner's type; 8 bytes each are reserved).  Level 0 is the grid of the
+// step: its S64 is the finest stencil, only used to form level 1.
+struct MgLevel {
+  MgGeom g{};
+  double* S64 = nullptr;
+  float* S32 = nullptr;
+  double* Dinv64 = nullptr;
+  float* Dinv32 = nullptr;
+  void* b = nullptr;
+  void* z = nullptr;
+  void* w = nullptr;
+  void* t = nullptr;
+};
+
+constexpr int kMgMaxLevels = 24;
+constexpr int kMgMaxCoarse = 1024;   // unknowns of the coarsest level (dense inverse)
+
+struct MgHierarchy {
+  int nlev = 0;
+  int nu1 = 1, nu2 = 1;
+  double omega = 0.7;
+  MgLevel lev[kMgMaxLevels];
+  double* Ainv64 = nullptr;   // coarsest level inverse, row-major
+  float* Ainv32 = nullptr;
+  double* work = nullptr;     // Gauss-Jordan workspace n x 2n
+  int* bad = nullptr;         // a zero pivot was met (device flag)
+};
+
+// The finest level as the cycle sees it: the context's block-Jacobi inverses and
+// y = A x with the matrix-free operator.
+template <typename R> struct MgFine {
+  int nd = 2, nu = 3;
+  const R* bjinv = nullptr;
+  void (*apply)(const void* self, const R* x, R* y, hipStream_t s, const int* skip) = nullptr;
+  const void* self = nullptr;
+  void operator()(const R* x, R* y, hipStream_t s, const int* skip) const { apply(self, x, y, s, skip); }
+};
+
+// stencils of levels 1.. (Galerkin), their inverse diagonal blocks, the coarsest inverse (FP64)
+void mg_build(MgHierarchy& h, int nd, int nu, hipStream_t s);
+// z = one V-cycle applied to r (r of the input type TIN, z of the preconditioner's type R)
+template <typename R, typename TIN>
+void mg_vcycle(const MgHierarchy& h, const MgFine<R>& fine, const TIN* r, R* z, hipStream_t s, const int* skip);
+template <typename R> void mg_axpy(const R* z, double* x, int64_t n, hipStream_t s);
+void launch_fine_stencil(int nd, bool cpl, const Geom& g, const Scheme& sc, const Coefs<double>& cf, const Bdry& bd,
+                         double* S, hipStream_t s);
+
 enum KernelClass {
   KC_SETUP = 0, KC_SETUP_BJ, KC_RESIDUAL, KC_APPLY, KC_BJ, KC_DOT, KC_SCALAR, KC_UPDATE, KC_XUPDATE,
-  KC_TRUE_RESID, KC_NEWTON_UPDATE, KC_NORM, KC_CONVERT, KC_NN, KC_APPLY_PC, KC_TIME_STEP, KC_VELOCITY, KC_COUNT
+  KC_TRUE_RESID, KC_NEWTON_UPDATE, KC_NORM, KC_CONVERT, KC_NN, KC_APPLY_PC, KC_TIME_STEP, KC_VELOCITY, KC_MG,
+  KC_MG_SETUP, KC_COUNT
 };
 
 // ---- launchers (defined in m1_kernels.hip / m1_krylov.hip) ----

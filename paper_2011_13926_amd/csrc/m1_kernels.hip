@@ -200,56 +200,26 @@ __device__ __forceinline__ void minus_face(const Geom& g, const Coefs<R>& cf, co
 // ----------------------------------------------------------------------------
 // Block-Jacobi: assemble the exact diagonal block of A and invert it
 // ----------------------------------------------------------------------------
-template <int NU>
-__device__ __forceinline__ bool invert_block(double (&A)[NU][NU], double (&Ai)[NU][NU]) {
-#pragma unroll
-  for (int r = 0; r < NU; ++r)
-#pragma unroll
-    for (int c = 0; c < NU; ++c) Ai[r][c] = r == c ? 1.0 : 0.0;
-  bool ok = true;
-#pragma unroll
-  for (int col = 0; col < NU; ++col) {
-    // partial pivoting (rows col..NU-1)
-    int piv = col;
-    double best = fabs(A[col][col]);
-#pragma unroll
-    for (int r = col + 1; r < NU; ++r) {
-      const double v = fabs(A[r][col]);
-      if (v > best) { best = v; piv = r; }
-    }
-    ok = ok && best > 0.0;
-#pragma unroll
-    for (int r = col + 1; r < NU; ++r) {
-      if (r == piv) {
-#pragma unroll
-        for (int c = 0; c < NU; ++c) {
-          double t = A[col][c]; A[col][c] = A[r][c]; A[r][c] = t;
-          t = Ai[col][c]; Ai[col][c] = Ai[r][c]; Ai[r][c] = t;
-        }
-      }
-    }
-    const double inv = 1.0 / A[col][col];
-#pragma unroll
-    for (int c = 0; c < NU; ++c) { A[col][c] *= inv; Ai[col][c] *= inv; }
-#pragma unroll
-    for (int r = 0; r < NU; ++r) {
-      if (r == col) continue;
-      const double f = A[r][col];
-#pragma unroll
-      for (int c = 0; c < NU; ++c) { A[r][c] -= f * A[col][c]; Ai[r][c] -= f * Ai[col][c]; }
-    }
-  }
-  return ok;
-}
 
-template <int ND, bool CPL>
-__global__ __launch_bounds__(256) void k_setup_bj(Geom g, Scheme sc, Coefs<double> cf, Bdry bd) {
+// STENCIL: instead of the inverse, write the explicit block stencil of the cell's
+// row of A (the multigrid's finest level): block 0 the diagonal block, block
+// 1 + 2d + side the coupling to the neighbour along d (side 0 lower, 1 upper; zero
+// where the neighbour is a ghost, whose coupling is in the diagonal block, or the
+// cell itself), entry (r, c) of block b at S[((b * NU + r) * NU + c) * N + cell].
+template <int ND, bool CPL, bool STENCIL>
+__global__ __launch_bounds__(256) void k_setup_bj(Geom g, Scheme sc, Coefs<double> cf, Bdry bd, double* __restrict__ S) {
   using Dm = Dims<ND>;
   constexpr int NR = 1 + ND;
   constexpr int NU = NR + (CPL ? 1 : 0);
   CellPos p;
   if (!cell_pos(g, p)) return;
   const int64_t N = g.N;
+  auto put_block = [&](int blk, const double (&Bk)[NU][NU]) {
+#pragma unroll
+    for (int rr = 0; rr < NU; ++rr)
+#pragma unroll
+      for (int c = 0; c < NU; ++c) S[((blk * NU + rr) * NU + c) * N + p.cell] = Bk[rr][c];
+  };
   double B[NU][NU];
 #pragma unroll
   for (int r = 0; r < NU; ++r)
@@ -294,6 +264,25 @@ __global__ __launch_bounds__(256) void k_setup_bj(Geom g, Scheme sc, Coefs<doubl
         for (int k = 0; k < NR; ++k) JR[m][k] = Js[m][k];
       sigR = cf.sigma[r.nb];
     }
+    if (STENCIL) {
+      double Nbk[NU][NU];
+#pragma unroll
+      for (int rr = 0; rr < NU; ++rr)
+#pragma unroll
+        for (int c = 0; c < NU; ++c) Nbk[rr][c] = 0.0;
+      if (r.kind == 0 && r.nb != p.cell) {
+        Nbk[0][0] = s * al * dd;
+        Nbk[0][1 + d] = s * al * b;
+#pragma unroll
+        for (int m = 0; m < ND; ++m) {
+#pragma unroll
+          for (int k = 0; k < NR; ++k) Nbk[1 + m][k] = s * b * cf.jac[(pair_index<ND>(d, m) * NR + k) * N + r.nb];
+          Nbk[1 + m][1 + m] += s * dd;
+        }
+        if (sc.wb) Nbk[1 + d][1 + d] += 0.25 * sc.cdt * (0.5 * (sig + sigR));
+      }
+      put_block(2 + 2 * d, Nbk);
+    }
     B[0][0] += s * al * dd * (gR[0] - 1.0);
     B[0][1 + d] += s * al * (a + b * gR[1 + d]);
 #pragma unroll
@@ -330,6 +319,25 @@ __global__ __launch_bounds__(256) void k_setup_bj(Geom g, Scheme sc, Coefs<doubl
         for (int k = 0; k < NR; ++k) JL[m][k] = Js[m][k];
       sigL = cf.sigma[l.nb];
     }
+    if (STENCIL) {
+      double Nbk[NU][NU];
+#pragma unroll
+      for (int rr = 0; rr < NU; ++rr)
+#pragma unroll
+        for (int c = 0; c < NU; ++c) Nbk[rr][c] = 0.0;
+      if (l.kind == 0 && l.nb != p.cell) {
+        Nbk[0][0] = s * alm * ddm;
+        Nbk[0][1 + d] = -s * alm * am;
+#pragma unroll
+        for (int m = 0; m < ND; ++m) {
+#pragma unroll
+          for (int k = 0; k < NR; ++k) Nbk[1 + m][k] = -s * am * cf.jac[(pair_index<ND>(d, m) * NR + k) * N + l.nb];
+          Nbk[1 + m][1 + m] += s * ddm;
+        }
+        if (sc.wb) Nbk[1 + d][1 + d] += 0.25 * sc.cdt * (0.5 * (sig + sigL));
+      }
+      put_block(1 + 2 * d, Nbk);
+    }
     B[0][1 + d] -= s * alm * (am * gL[1 + d] + bm);
     B[0][0] -= s * alm * ddm * (1.0 - gL[0]);
 #pragma unroll
@@ -361,6 +369,10 @@ __global__ __launch_bounds__(256) void k_setup_bj(Geom g, Scheme sc, Coefs<doubl
     for (int r = 0; r < NR; ++r) B[r][r] += sc.psi;
     if (CPL) B[NU - 1][NU - 1] += sc.psi * cf.rcv[p.cell];
   }
+  if (STENCIL) {
+    put_block(0, B);
+    return;
+  }
   double Bi[NU][NU];
   invert_block<NU>(B, Bi);
 #pragma unroll
@@ -373,11 +385,23 @@ void launch_setup_bj(int nd, bool cpl, const Geom& g, const Scheme& sc, const Co
                      hipStream_t s) {
   dim3 blk(TX, TY), grd((g.n[0] + TX - 1) / TX, (g.rows + TY - 1) / TY);
   if (nd == 2) {
-    if (cpl) k_setup_bj<2, true><<<grd, blk, 0, s>>>(g, sc, cf, bd);
-    else k_setup_bj<2, false><<<grd, blk, 0, s>>>(g, sc, cf, bd);
+    if (cpl) k_setup_bj<2, true, false><<<grd, blk, 0, s>>>(g, sc, cf, bd, nullptr);
+    else k_setup_bj<2, false, false><<<grd, blk, 0, s>>>(g, sc, cf, bd, nullptr);
   } else {
-    if (cpl) k_setup_bj<3, true><<<grd, blk, 0, s>>>(g, sc, cf, bd);
-    else k_setup_bj<3, false><<<grd, blk, 0, s>>>(g, sc, cf, bd);
+    if (cpl) k_setup_bj<3, true, false><<<grd, blk, 0, s>>>(g, sc, cf, bd, nullptr);
+    else k_setup_bj<3, false, false><<<grd, blk, 0, s>>>(g, sc, cf, bd, nullptr);
+  }
+}
+
+void launch_fine_stencil(int nd, bool cpl, const Geom& g, const Scheme& sc, const Coefs<double>& cf, const Bdry& bd,
+                         double* S, hipStream_t s) {
+  dim3 blk(TX, TY), grd((g.n[0] + TX - 1) / TX, (g.rows + TY - 1) / TY);
+  if (nd == 2) {
+    if (cpl) k_setup_bj<2, true, true><<<grd, blk, 0, s>>>(g, sc, cf, bd, S);
+    else k_setup_bj<2, false, true><<<grd, blk, 0, s>>>(g, sc, cf, bd, S);
+  } else {
+    if (cpl) k_setup_bj<3, true, true><<<grd, blk, 0, s>>>(g, sc, cf, bd, S);
+    else k_setup_bj<3, false, true><<<grd, blk, 0, s>>>(g, sc, cf, bd, S);
   }
 }
 

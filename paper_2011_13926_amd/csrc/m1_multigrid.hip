@@ -1,0 +1,618 @@
+// Aggregation multigrid preconditioner for gfx950.
+//
+// Not in the paper's own solver set-up verbatim: the method's implicit systems
+// were solved with Trilinos preconditioners, algebraic multigrid being the best
+// (about ten Krylov iterations against about 250 for damped Jacobi, Sect.
+// 4.1-4.2).  Here the hierarchy is geometric: level l+1 has one cell per 2 x 2
+// (x 2) aggregate of level-l cells; prolongation is piecewise constant,
+// restriction its transpose (the sum over an aggregate), and the coarse
+// operators are the Galerkin products A_{l+1} = P^T A_l P, held as explicit
+// block stencils (one n_u x n_u diagonal block and one block per face
+// neighbour and cell).  Damped block-Jacobi smoothing, a V(nu1, nu2) cycle from
+// zero, and an exact solve (a precomputed dense inverse) on the coarsest level.
+//
+// The finest level stays matrix-free (the operator kernels of m1_kernels.hip
+// and the context's block-Jacobi inverses); its explicit stencil is written once
+// per linearisation only to form level 1.  Coarse-level kernels are fused per
+// level: on the way down one kernel forms the residual of every child cell,
+// restricts it and takes the first smoothing sweep of the coarser level; on the
+// way up one kernel prolongs and takes the first smoothing sweep.  Stencil
+// entries and vectors are component-major (SoA) per level, so consecutive
+// threads (cells) read consecutive addresses.
+#include <algorithm>
+#include <vector>
+
+#include "m1_internal.h"
+
+namespace m1 {
+
+constexpr int kMgThreads = 256;
+
+// (i, j, k) of a level-local cell index
+__device__ __forceinline__ void mg_idx(const MgGeom& g, int64_t cell, int* id) {
+  id[0] = (int)(cell % g.n[0]);
+  const int64_t r = cell / g.n[0];
+  id[1] = (int)(r % g.n[1]);
+  id[2] = (int)(r / g.n[1]);
+}
+
+__device__ __forceinline__ int64_t mg_lin(const MgGeom& g, const int* id) {
+  return ((int64_t)id[2] * g.n[1] + id[1]) * g.n[0] + id[0];
+}
+
+// neighbour of cell id along d (side 0 lower, 1 upper): -1 if it is outside a
+// non-periodic boundary
+__device__ __forceinline__ int64_t mg_nb(const MgGeom& g, const int* id, int d, int side) {
+  int j[3] = {id[0], id[1], id[2]};
+  j[d] += side ? 1 : -1;
+  if (j[d] < 0 || j[d] >= g.n[d]) {
+    if (!g.per[d]) return -1;
+    j[d] = (j[d] + g.n[d]) % g.n[d];
+  }
+  return mg_lin(g, j);
+}
+
+// aggregate (coarse cell) of a fine cell
+__device__ __forceinline__ int64_t mg_parent(const MgGeom& gf, const MgGeom& gc, int64_t cell) {
+  int id[3];
+  mg_idx(gf, cell, id);
+  id[0] >>= 1;
+  id[1] >>= 1;
+  id[2] >>= 1;
+  return mg_lin(gc, id);
+}
+
+// ----------------------------------------------------------------------------
+// Galerkin coarse operator from the finer level's stencil (FP64).  One thread
+// per (coarse cell, output block): the diagonal block collects every child's
+// diagonal block and the child-to-child couplings inside the aggregate (and
+// couplings that wrap onto the aggregate itself); face block (d, side)
+// collects the children's couplings that leave the aggregate on that face.
+// ----------------------------------------------------------------------------
+template <int ND, int NU>
+__global__ __launch_bounds__(kMgThreads) void k_mg_galerkin(MgGeom gf, MgGeom gc, const double* __restrict__ Sf,
+                                                            double* __restrict__ Sc) {
+  constexpr int NB = 1 + 2 * ND;
+  constexpr int BS = NU * NU;
+  const int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int blk = blockIdx.y;
+  if (I >= gc.N) return;
+  int ci[3];
+  mg_idx(gc, I, ci);
+  double acc[BS];
+#pragma unroll
+  for (int q = 0; q < BS; ++q) acc[q] = 0.0;
+  const int64_t Nf = gf.N;
+  for (int cz = 0; cz < (ND == 3 ? 2 : 1); ++cz)
+    for (int cy = 0; cy < 2; ++cy)
+      for (int cx = 0; cx < 2; ++cx) {
+        int f[3] = {2 * ci[0] + cx, 2 * ci[1] + cy, ND == 3 ? 2 * ci[2] + cz : 0};
+        if (f[0] >= gf.n[0] || f[1] >= gf.n[1] || f[2] >= gf.n[2]) continue;
+        const int64_t c = mg_lin(gf, f);
+        if (blk == 0) {
+#pragma unroll
+          for (int q = 0; q < BS; ++q) acc[q] += Sf[(int64_t)q * Nf + c];
+        }
+#pragma unroll
+        for (int d = 0; d < ND; ++d)
+#pragma unroll
+          for (int side = 0; side < 2; ++side) {
+            const int b = 1 + 2 * d + side;
+            const int64_t j = mg_nb(gf, f, d, side);
+            if (j < 0) continue;
+            const bool inside = mg_parent(gf, gc, j) == I;
+            if ((blk == 0 && inside) || (blk == b && !inside)) {
+#pragma unroll
+              for (int q = 0; q < BS; ++q) acc[q] += Sf[((int64_t)b * BS + q) * Nf + c];
+            }
+          }
+      }
+#pragma unroll
+  for (int q = 0; q < BS; ++q) Sc[((int64_t)blk * BS + q) * gc.N + I] = acc[q];
+  (void)NB;
+}
+
+// inverse of every cell's diagonal block (FP64)
+template <int NU>
+__global__ __launch_bounds__(kMgThreads) void k_mg_invert(int64_t N, const double* __restrict__ S,
+                                                          double* __restrict__ Dinv, int* __restrict__ bad) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= N) return;
+  double A[NU][NU], Ai[NU][NU];
+#pragma unroll
+  for (int r = 0; r < NU; ++r)
+#pragma unroll
+    for (int k = 0; k < NU; ++k) A[r][k] = S[(int64_t)(r * NU + k) * N + c];
+  const bool ok = invert_block<NU>(A, Ai);
+  if (!ok) atomicOr(bad, 1);
+#pragma unroll
+  for (int r = 0; r < NU; ++r)
+#pragma unroll
+    for (int k = 0; k < NU; ++k) Dinv[(int64_t)(r * NU + k) * N + c] = Ai[r][k];
+}
+
+// ----------------------------------------------------------------------------
+// Coarsest level: dense matrix of the stencil (component-major unknowns,
+// row = comp * N + cell), inverted by Gauss-Jordan elimination with partial
+// pivoting in one workgroup.  W: n x 2n workspace, Ainv: n x n row-major.
+// ----------------------------------------------------------------------------
+constexpr int kGjThreads = 1024;
+
+template <int ND, int NU>
+__global__ __launch_bounds__(kGjThreads) void k_mg_dense_inverse(MgGeom g, const double* __restrict__ S,
+                                                                 double* __restrict__ W, double* __restrict__ Ainv,
+                                                                 int* __restrict__ bad) {
+  constexpr int BS = NU * NU;
+  const int64_t N = g.N;
+  const int n = (int)(NU * N);
+  const int n2 = 2 * n;
+  const int tid = threadIdx.x;
+  for (int64_t e = tid; e < (int64_t)n * n2; e += kGjThreads) {
+    const int r = (int)(e / n2), c = (int)(e % n2);
+    W[e] = (c >= n) ? (c - n == r ? 1.0 : 0.0) : 0.0;
+  }
+  __syncthreads();
+  // scatter the stencil (one thread per cell)
+  for (int64_t cell = tid; cell < N; cell += kGjThreads) {
+    int id[3];
+    mg_idx(g, cell, id);
+    for (int rr = 0; rr < NU; ++rr)
+      for (int k = 0; k < NU; ++k) {
+        const int64_t row = rr * N + cell;
+        W[row * n2 + k * N + cell] += S[(int64_t)(rr * NU + k) * N + cell];
+        for (int d = 0; d < ND; ++d)
+          for (int side = 0; side < 2; ++side) {
+            const int64_t j = mg_nb(g, id, d, side);
+            if (j < 0) continue;
+            const int b = 1 + 2 * d + side;
+            W[row * n2 + k * N + j] += S[((int64_t)b * BS + rr * NU + k) * N + cell];
+          }
+      }
+  }
+  __syncthreads();
+  __shared__ int s_piv;
+  __shared__ double s_val[kGjThreads];
+  __shared__ int s_idx[kGjThreads];
+  for (int col = 0; col < n; ++col) {
+    // pivot: largest |W[r][col]|, r >= col (ties: smallest row)
+    double best = -1.0;
+    int bi = col;
+    for (int r = col + tid; r < n; r += kGjThreads) {
+      const double v = fabs(W[(int64_t)r * n2 + col]);
+      if (v > best) { best = v; bi = r; }
+    }
+    s_val[tid] = best;
+    s_idx[tid] = bi;
+    __syncthreads();
+    for (int off = kGjThreads / 2; off > 0; off >>= 1) {
+      if (tid < off) {
+        const double v2 = s_val[tid + off];
+        const int i2 = s_idx[tid + off];
+        if (v2 > s_val[tid] || (v2 == s_val[tid] && i2 < s_idx[tid])) {
+          s_val[tid] = v2;
+          s_idx[tid] = i2;
+        }
+      }
+      __syncthreads();
+    }
+    if (tid == 0) {
+      s_piv = s_idx[0];
+      if (!(s_val[0] > 0.0)) atomicOr(bad, 1);
+    }
+    __syncthreads();
+    const int piv = s_piv;
+    if (piv != col) {
+      for (int c = tid; c < n2; c += kGjThreads) {
+        const double t = W[(int64_t)col * n2 + c];
+        W[(int64_t)col * n2 + c] = W[(int64_t)piv * n2 + c];
+        W[(int64_t)piv * n2 + c] = t;
+      }
+    }
+    __syncthreads();
+    const double inv = 1.0 / W[(int64_t)col * n2 + col];
+    __syncthreads();
+    for (int c = tid; c < n2; c += kGjThreads) W[(int64_t)col * n2 + c] *= inv;
+    __syncthreads();
+    // eliminate column col from every other row
+    for (int64_t e = tid; e < (int64_t)n * n2; e += kGjThreads) {
+      const int r = (int)(e / n2), c = (int)(e % n2);
+      if (r == col || c == col) continue;
+      const double f = W[(int64_t)r * n2 + col];
+      if (f != 0.0) W[e] -= f * W[(int64_t)col * n2 + c];
+    }
+    __syncthreads();
+    for (int r = tid; r < n; r += kGjThreads)
+      if (r != col) W[(int64_t)r * n2 + col] = 0.0;
+    __syncthreads();
+  }
+  for (int64_t e = tid; e < (int64_t)n * n; e += kGjThreads) {
+    const int r = (int)(e / n), c = (int)(e % n);
+    Ainv[e] = W[(int64_t)r * n2 + n + c];
+  }
+}
+
+// z = Ainv b on the coarsest level (one wavefront per row)
+template <typename R>
+__global__ __launch_bounds__(256) void k_mg_coarse_solve(int n, const R* __restrict__ Ainv, const R* __restrict__ b,
+                                                         R* __restrict__ z, const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  const int lane = threadIdx.x & 63;
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= n) return;
+  double acc = 0.0;
+  for (int c = lane; c < n; c += 64) acc += (double)Ainv[(int64_t)row * n + c] * (double)b[c];
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  if (lane == 0) z[row] = (R)acc;
+}
+
+// ----------------------------------------------------------------------------
+// Finest level (matrix-free operator, the context's block-Jacobi inverses)
+// ----------------------------------------------------------------------------
+// z0 = omega M^{-1} r (or, with zp, z = zp + omega M^{-1} (r - t)); r of the input type
+template <int NU, typename R, typename TIN>
+__global__ __launch_bounds__(kMgThreads) void k_mg_fine_smooth(int64_t N, const R* __restrict__ inv, R omega,
+                                                               const TIN* __restrict__ r, const R* __restrict__ t,
+                                                               const R* __restrict__ zp, R* __restrict__ z,
+                                                               const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= N) return;
+  R rv[NU];
+#pragma unroll
+  for (int k = 0; k < NU; ++k) rv[k] = (R)r[k * N + c] - (t ? t[k * N + c] : (R)0);
+#pragma unroll
+  for (int rr = 0; rr < NU; ++rr) {
+    R acc = (R)0;
+#pragma unroll
+    for (int k = 0; k < NU; ++k) acc += inv[(rr * NU + k) * N + c] * rv[k];
+    z[rr * N + c] = (zp ? zp[rr * N + c] : (R)0) + omega * acc;
+  }
+}
+
+// level 1 from the finest level: b1 = P^T (r - t) (t = A z0, or none when z0 = 0)
+// and the first sweep z1 = omega D1^{-1} b1 (z1 = 0 without pre-smoothing)
+template <int ND, int NU, typename R, typename TIN>
+__global__ __launch_bounds__(kMgThreads) void k_mg_restrict_fine(MgGeom gf, MgGeom gc, const TIN* __restrict__ r,
+                                                                 const R* __restrict__ t, const R* __restrict__ Dinv,
+                                                                 R omega, int smooth, R* __restrict__ b1,
+                                                                 R* __restrict__ z1, const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  const int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= gc.N) return;
+  int ci[3];
+  mg_idx(gc, I, ci);
+  R acc[NU];
+#pragma unroll
+  for (int k = 0; k < NU; ++k) acc[k] = (R)0;
+  for (int cz = 0; cz < (ND == 3 ? 2 : 1); ++cz)
+    for (int cy = 0; cy < 2; ++cy)
+      for (int cx = 0; cx < 2; ++cx) {
+        int f[3] = {2 * ci[0] + cx, 2 * ci[1] + cy, ND == 3 ? 2 * ci[2] + cz : 0};
+        if (f[0] >= gf.n[0] || f[1] >= gf.n[1] || f[2] >= gf.n[2]) continue;
+        const int64_t c = mg_lin(gf, f);
+#pragma unroll
+        for (int k = 0; k < NU; ++k) acc[k] += (R)r[k * gf.N + c] - (t ? t[k * gf.N + c] : (R)0);
+      }
+  const int64_t Nc = gc.N;
+#pragma unroll
+  for (int k = 0; k < NU; ++k) b1[k * Nc + I] = acc[k];
+#pragma unroll
+  for (int rr = 0; rr < NU; ++rr) {
+    R z = (R)0;
+    if (smooth) {
+#pragma unroll
+      for (int k = 0; k < NU; ++k) z += Dinv[(rr * NU + k) * Nc + I] * acc[k];
+      z *= omega;
+    }
+    z1[rr * Nc + I] = z;
+  }
+}
+
+// zp = z0 + P z1 on the finest level
+template <int ND, int NU, typename R>
+__global__ __launch_bounds__(kMgThreads) void k_mg_prolong_fine(MgGeom gf, MgGeom gc, const R* __restrict__ z0,
+                                                                const R* __restrict__ z1, R* __restrict__ zp,
+                                                                const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= gf.N) return;
+  const int64_t I = mg_parent(gf, gc, c);
+#pragma unroll
+  for (int k = 0; k < NU; ++k) zp[k * gf.N + c] = z0[k * gf.N + c] + z1[k * gc.N + I];
+}
+
+// ----------------------------------------------------------------------------
+// Coarse levels (explicit stencils)
+// ----------------------------------------------------------------------------
+// y = S x at cell c (x given by a functor of (cell, comp))
+template <int ND, int NU, typename R, typename X>
+__device__ __forceinline__ void mg_row(const MgGeom& g, const R* __restrict__ S, int64_t c, const int* id, X&& x,
+                                       R (&y)[NU]) {
+  constexpr int BS = NU * NU;
+  const int64_t N = g.N;
+  R xs[NU];
+#pragma unroll
+  for (int k = 0; k < NU; ++k) xs[k] = x(c, k);
+#pragma unroll
+  for (int rr = 0; rr < NU; ++rr) {
+    R acc = (R)0;
+#pragma unroll
+    for (int k = 0; k < NU; ++k) acc += S[(int64_t)(rr * NU + k) * N + c] * xs[k];
+    y[rr] = acc;
+  }
+#pragma unroll
+  for (int d = 0; d < ND; ++d)
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+      const int64_t j = mg_nb(g, id, d, side);
+      if (j < 0) continue;
+      const int b = 1 + 2 * d + side;
+      R xn[NU];
+#pragma unroll
+      for (int k = 0; k < NU; ++k) xn[k] = x(j, k);
+#pragma unroll
+      for (int rr = 0; rr < NU; ++rr) {
+        R acc = (R)0;
+#pragma unroll
+        for (int k = 0; k < NU; ++k) acc += S[((int64_t)b * BS + rr * NU + k) * N + c] * xn[k];
+        y[rr] += acc;
+      }
+    }
+}
+
+// down from level l to l+1: b_{l+1} = P^T (b_l - A_l z_l), z_{l+1} = omega D^{-1} b_{l+1} (or 0)
+template <int ND, int NU, typename R>
+__global__ __launch_bounds__(kMgThreads) void k_mg_down(MgGeom gf, MgGeom gc, const R* __restrict__ S,
+                                                        const R* __restrict__ bf, const R* __restrict__ zf,
+                                                        const R* __restrict__ Dinvc, R omega, int smooth,
+                                                        R* __restrict__ bc, R* __restrict__ zc,
+                                                        const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  const int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= gc.N) return;
+  int ci[3];
+  mg_idx(gc, I, ci);
+  R acc[NU];
+#pragma unroll
+  for (int k = 0; k < NU; ++k) acc[k] = (R)0;
+  const int64_t Nf = gf.N;
+  auto xf = [&](int64_t cell, int k) { return zf[k * Nf + cell]; };
+  for (int cz = 0; cz < (ND == 3 ? 2 : 1); ++cz)
+    for (int cy = 0; cy < 2; ++cy)
+      for (int cx = 0; cx < 2; ++cx) {
+        int f[3] = {2 * ci[0] + cx, 2 * ci[1] + cy, ND == 3 ? 2 * ci[2] + cz : 0};
+        if (f[0] >= gf.n[0] || f[1] >= gf.n[1] || f[2] >= gf.n[2]) continue;
+        const int64_t c = mg_lin(gf, f);
+        R y[NU];
+        mg_row<ND, NU, R>(gf, S, c, f, xf, y);
+#pragma unroll
+        for (int k = 0; k < NU; ++k) acc[k] += bf[k * Nf + c] - y[k];
+      }
+  const int64_t Nc = gc.N;
+#pragma unroll
+  for (int k = 0; k < NU; ++k) bc[k * Nc + I] = acc[k];
+#pragma unroll
+  for (int rr = 0; rr < NU; ++rr) {
+    R z = (R)0;
+    if (smooth) {
+#pragma unroll
+      for (int k = 0; k < NU; ++k) z += Dinvc[(rr * NU + k) * Nc + I] * acc[k];
+      z *= omega;
+    }
+    zc[rr * Nc + I] = z;
+  }
+}
+
+// one damped block-Jacobi sweep on a coarse level, with an optional
+// prolongation of the coarser correction first (zc != nullptr):
+//   zp = z + P zc,  out = zp + omega D^{-1} (b - A zp)
+template <int ND, int NU, typename R>
+__global__ __launch_bounds__(kMgThreads) void k_mg_smooth(MgGeom g, MgGeom gc, const R* __restrict__ S,
+                                                          const R* __restrict__ Dinv, R omega, const R* __restrict__ b,
+                                                          const R* __restrict__ z, const R* __restrict__ zc,
+                                                          R* __restrict__ out, const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= g.N) return;
+  int id[3];
+  mg_idx(g, c, id);
+  const int64_t N = g.N;
+  auto zp = [&](int64_t cell, int k) {
+    R v = z[k * N + cell];
+    if (zc) v += zc[k * gc.N + mg_parent(g, gc, cell)];
+    return v;
+  };
+  R y[NU];
+  mg_row<ND, NU, R>(g, S, c, id, zp, y);
+  R rv[NU];
+#pragma unroll
+  for (int k = 0; k < NU; ++k) rv[k] = b[k * N + c] - y[k];
+#pragma unroll
+  for (int rr = 0; rr < NU; ++rr) {
+    R acc = (R)0;
+#pragma unroll
+    for (int k = 0; k < NU; ++k) acc += Dinv[(rr * NU + k) * N + c] * rv[k];
+    out[rr * N + c] = zp(c, rr) + omega * acc;
+  }
+}
+
+// out = z + P zc (prolongation without smoothing; z may be NULL for zero)
+template <int NU, typename R>
+__global__ __launch_bounds__(kMgThreads) void k_mg_prolong(MgGeom g, MgGeom gc, const R* __restrict__ z,
+                                                           const R* __restrict__ zc, R* __restrict__ out,
+                                                           const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= g.N) return;
+  const int64_t I = mg_parent(g, gc, c);
+#pragma unroll
+  for (int k = 0; k < NU; ++k) out[k * g.N + c] = (z ? z[k * g.N + c] : (R)0) + zc[k * gc.N + I];
+}
+
+// out = (R) in
+template <typename R, typename TIN>
+__global__ __launch_bounds__(kMgThreads) void k_mg_cast(int64_t n, const TIN* __restrict__ in, R* __restrict__ out,
+                                                        const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) out[e] = (R)in[e];
+}
+
+// x += z (FP64 solution update by a preconditioned correction)
+template <typename R>
+__global__ __launch_bounds__(kMgThreads) void k_mg_axpy(int64_t n, const R* __restrict__ z, double* __restrict__ x) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) x[e] += (double)z[e];
+}
+
+// ----------------------------------------------------------------------------
+// host side
+// ----------------------------------------------------------------------------
+static inline unsigned grid1(int64_t n) { return (unsigned)((n + kMgThreads - 1) / kMgThreads); }
+
+#define M1_MG_NU_SWITCH(NU_EXPR, CALL) \
+  switch (NU_EXPR) {                   \
+    case 3: { constexpr int NU = 3; CALL; } break; \
+    case 4: { constexpr int NU = 4; CALL; } break; \
+    case 5: { constexpr int NU = 5; CALL; } break; \
+  }
+
+void mg_build(MgHierarchy& h, int nd, int nu, hipStream_t s) {
+  // level l+1 stencils from level l (FP64), diagonal inverses, coarsest inverse
+  for (int l = 0; l + 1 < h.nlev; ++l) {
+    const MgGeom& gf = h.lev[l].g;
+    const MgGeom& gc = h.lev[l + 1].g;
+    dim3 grd(grid1(gc.N), 1 + 2 * nd);
+    if (nd == 2) { M1_MG_NU_SWITCH(nu, (k_mg_galerkin<2, NU><<<grd, kMgThreads, 0, s>>>(gf, gc, h.lev[l].S64, h.lev[l + 1].S64))) }
+    else { M1_MG_NU_SWITCH(nu, (k_mg_galerkin<3, NU><<<grd, kMgThreads, 0, s>>>(gf, gc, h.lev[l].S64, h.lev[l + 1].S64))) }
+  }
+  for (int l = 1; l + 1 < h.nlev; ++l) {
+    M1_MG_NU_SWITCH(nu, (k_mg_invert<NU><<<grid1(h.lev[l].g.N), kMgThreads, 0, s>>>(h.lev[l].g.N, h.lev[l].S64, h.lev[l].Dinv64, h.bad)))
+  }
+  const MgLevel& L = h.lev[h.nlev - 1];
+  if (nd == 2) { M1_MG_NU_SWITCH(nu, (k_mg_dense_inverse<2, NU><<<1, kGjThreads, 0, s>>>(L.g, L.S64, h.work, h.Ainv64, h.bad))) }
+  else { M1_MG_NU_SWITCH(nu, (k_mg_dense_inverse<3, NU><<<1, kGjThreads, 0, s>>>(L.g, L.S64, h.work, h.Ainv64, h.bad))) }
+}
+
+template <typename R> static const R* stencil(const MgLevel& L);
+template <> const double* stencil<double>(const MgLevel& L) { return L.S64; }
+template <> const float* stencil<float>(const MgLevel& L) { return L.S32; }
+template <typename R> static const R* dinv(const MgLevel& L);
+template <> const double* dinv<double>(const MgLevel& L) { return L.Dinv64; }
+template <> const float* dinv<float>(const MgLevel& L) { return L.Dinv32; }
+template <typename R> static const R* ainv(const MgHierarchy& h);
+template <> const double* ainv<double>(const MgHierarchy& h) { return h.Ainv64; }
+template <> const float* ainv<float>(const MgHierarchy& h) { return h.Ainv32; }
+
+template <typename R, typename TIN>
+void mg_vcycle(const MgHierarchy& h, const MgFine<R>& fine, const TIN* r, R* z, hipStream_t s, const int* skip) {
+  const int nd = fine.nd;
+  const int nu = fine.nu;
+  const R om = (R)h.omega;
+  const MgGeom& g0 = h.lev[0].g;
+  const int64_t N0 = g0.N;
+  R* z0 = (R*)h.lev[0].z;
+  R* zp = (R*)h.lev[0].w;
+  R* t = (R*)h.lev[0].t;
+  if (h.nlev == 1) {
+    // the grid is already at the coarsest size: the cycle is the exact solve
+    const int64_t n = (int64_t)nu * N0;
+    k_mg_cast<R, TIN><<<grid1(n), kMgThreads, 0, s>>>(n, r, (R*)h.lev[0].b, skip);
+    k_mg_coarse_solve<R><<<(unsigned)((n + 3) / 4), 256, 0, s>>>((int)n, ainv<R>(h), (const R*)h.lev[0].b, z, skip);
+    return;
+  }
+  // ---- finest level, down ----
+  if (h.nu1 > 0) {
+    M1_MG_NU_SWITCH(nu, (k_mg_fine_smooth<NU, R, TIN><<<grid1(N0), kMgThreads, 0, s>>>(N0, fine.bjinv, om, r, nullptr, nullptr, z0, skip)))
+    for (int k = 1; k < h.nu1; ++k) {
+      fine(z0, t, s, skip);
+      M1_MG_NU_SWITCH(nu, (k_mg_fine_smooth<NU, R, TIN><<<grid1(N0), kMgThreads, 0, s>>>(N0, fine.bjinv, om, r, t, z0, zp, skip)))
+      std::swap(z0, zp);
+    }
+    fine(z0, t, s, skip);
+  }
+  {
+    const MgLevel& L1 = h.lev[1];
+    const int sm = (h.nu1 > 0 && h.nlev > 2) ? 1 : 0;
+    const R* tt = h.nu1 > 0 ? t : nullptr;
+    if (nd == 2) { M1_MG_NU_SWITCH(nu, (k_mg_restrict_fine<2, NU, R, TIN><<<grid1(L1.g.N), kMgThreads, 0, s>>>(g0, L1.g, r, tt, dinv<R>(L1), om, sm, (R*)L1.b, (R*)L1.z, skip))) }
+    else { M1_MG_NU_SWITCH(nu, (k_mg_restrict_fine<3, NU, R, TIN><<<grid1(L1.g.N), kMgThreads, 0, s>>>(g0, L1.g, r, tt, dinv<R>(L1), om, sm, (R*)L1.b, (R*)L1.z, skip))) }
+  }
+  // ---- coarse levels, down ----
+  // level l holds b_l and z_l (first sweep done, or zero); extra sweeps ping-pong z <-> w
+  std::vector<R*> zl(h.nlev), wl(h.nlev);
+  for (int l = 1; l < h.nlev; ++l) {
+    zl[l] = (R*)h.lev[l].z;
+    wl[l] = (R*)h.lev[l].w;
+  }
+  for (int l = 1; l + 1 < h.nlev; ++l) {
+    const MgLevel& L = h.lev[l];
+    const MgLevel& C = h.lev[l + 1];
+    for (int k = 1; k < h.nu1; ++k) {
+      if (nd == 2) { M1_MG_NU_SWITCH(nu, (k_mg_smooth<2, NU, R><<<grid1(L.g.N), kMgThreads, 0, s>>>(L.g, C.g, stencil<R>(L), dinv<R>(L), om, (const R*)L.b, zl[l], nullptr, wl[l], skip))) }
+      else { M1_MG_NU_SWITCH(nu, (k_mg_smooth<3, NU, R><<<grid1(L.g.N), kMgThreads, 0, s>>>(L.g, C.g, stencil<R>(L), dinv<R>(L), om, (const R*)L.b, zl[l], nullptr, wl[l], skip))) }
+      std::swap(zl[l], wl[l]);
+    }
+    const int sm = (h.nu1 > 0 && l + 2 < h.nlev) ? 1 : 0;
+    if (nd == 2) { M1_MG_NU_SWITCH(nu, (k_mg_down<2, NU, R><<<grid1(C.g.N), kMgThreads, 0, s>>>(L.g, C.g, stencil<R>(L), (const R*)L.b, zl[l], dinv<R>(C), om, sm, (R*)C.b, zl[l + 1], skip))) }
+    else { M1_MG_NU_SWITCH(nu, (k_mg_down<3, NU, R><<<grid1(C.g.N), kMgThreads, 0, s>>>(L.g, C.g, stencil<R>(L), (const R*)L.b, zl[l], dinv<R>(C), om, sm, (R*)C.b, zl[l + 1], skip))) }
+  }
+  // ---- coarsest: exact ----
+  {
+    const int last = h.nlev - 1;
+    const MgLevel& L = h.lev[last];
+    const int n = (int)(nu * L.g.N);
+    k_mg_coarse_solve<R><<<(n + 3) / 4, 256, 0, s>>>(n, ainv<R>(h), (const R*)L.b, zl[last], skip);
+  }
+  // ---- coarse levels, up ----
+  for (int l = h.nlev - 2; l >= 1; --l) {
+    const MgLevel& L = h.lev[l];
+    const MgLevel& C = h.lev[l + 1];
+    if (h.nu2 > 0) {
+      if (nd == 2) { M1_MG_NU_SWITCH(nu, (k_mg_smooth<2, NU, R><<<grid1(L.g.N), kMgThreads, 0, s>>>(L.g, C.g, stencil<R>(L), dinv<R>(L), om, (const R*)L.b, zl[l], zl[l + 1], wl[l], skip))) }
+      else { M1_MG_NU_SWITCH(nu, (k_mg_smooth<3, NU, R><<<grid1(L.g.N), kMgThreads, 0, s>>>(L.g, C.g, stencil<R>(L), dinv<R>(L), om, (const R*)L.b, zl[l], zl[l + 1], wl[l], skip))) }
+      std::swap(zl[l], wl[l]);
+      for (int k = 1; k < h.nu2; ++k) {
+        if (nd == 2) { M1_MG_NU_SWITCH(nu, (k_mg_smooth<2, NU, R><<<grid1(L.g.N), kMgThreads, 0, s>>>(L.g, C.g, stencil<R>(L), dinv<R>(L), om, (const R*)L.b, zl[l], nullptr, wl[l], skip))) }
+        else { M1_MG_NU_SWITCH(nu, (k_mg_smooth<3, NU, R><<<grid1(L.g.N), kMgThreads, 0, s>>>(L.g, C.g, stencil<R>(L), dinv<R>(L), om, (const R*)L.b, zl[l], nullptr, wl[l], skip))) }
+        std::swap(zl[l], wl[l]);
+      }
+    } else {
+      M1_MG_NU_SWITCH(nu, (k_mg_prolong<NU, R><<<grid1(L.g.N), kMgThreads, 0, s>>>(L.g, C.g, zl[l], zl[l + 1], wl[l], skip)))
+      std::swap(zl[l], wl[l]);
+    }
+  }
+  // ---- finest level, up ----
+  {
+    const MgLevel& L1 = h.lev[1];
+    R* out = h.nu2 > 0 ? zp : z;
+    const R* zin = h.nu1 > 0 ? z0 : nullptr;
+    if (zin) {
+      if (nd == 2) { M1_MG_NU_SWITCH(nu, (k_mg_prolong_fine<2, NU, R><<<grid1(N0), kMgThreads, 0, s>>>(g0, L1.g, zin, zl[1], out, skip))) }
+      else { M1_MG_NU_SWITCH(nu, (k_mg_prolong_fine<3, NU, R><<<grid1(N0), kMgThreads, 0, s>>>(g0, L1.g, zin, zl[1], out, skip))) }
+    } else {
+      // z0 = 0: the prolonged coarse correction alone
+      M1_MG_NU_SWITCH(nu, (k_mg_prolong<NU, R><<<grid1(N0), kMgThreads, 0, s>>>(g0, L1.g, nullptr, zl[1], out, skip)))
+    }
+    for (int k = 0; k < h.nu2; ++k) {
+      R* src = (k % 2 == 0) ? zp : z0;
+      R* dst = (k == h.nu2 - 1) ? z : ((k % 2 == 0) ? z0 : zp);
+      fine(src, t, s, skip);
+      M1_MG_NU_SWITCH(nu, (k_mg_fine_smooth<NU, R, TIN><<<grid1(N0), kMgThreads, 0, s>>>(N0, fine.bjinv, om, r, t, src, dst, skip)))
+    }
+  }
+}
+
+template <typename R>
+void mg_axpy(const R* z, double* x, int64_t n, hipStream_t s) {
+  k_mg_axpy<R><<<grid1(n), kMgThreads, 0, s>>>(n, z, x);
+}
+
+template void mg_vcycle<double, double>(const MgHierarchy&, const MgFine<double>&, const double*, double*, hipStream_t, const int*);
+template void mg_vcycle<float, double>(const MgHierarchy&, const MgFine<float>&, const double*, float*, hipStream_t, const int*);
+template void mg_vcycle<float, float>(const MgHierarchy&, const MgFine<float>&, const float*, float*, hipStream_t, const int*);
+template void mg_axpy<double>(const double*, double*, int64_t, hipStream_t);
+template void mg_axpy<float>(const float*, double*, int64_t, hipStream_t);
+
+}  // namespace m1
