@@ -268,6 +268,22 @@ m1_status m1_semi_implicit_step(m1_ctx* ctx, m1_state* U, double dt, int32_t nst
 m1_status m1_velocity_sources(m1_ctx* ctx, m1_state* U, const double* ux, const double* uy, const double* uz,
                               double dt, m1_stats* stats);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the explicit (semi = 0)
+ * or semi-implicit (semi = 1) steps of m1_explicit_step / m1_semi_implicit_step
+ * without a context.  The call allocates nothing: its work memory (two state
+ * buffers and a counter) is one static device array of the library, 64 MiB +
+ * 256 B per GPU, held from the library's first use on that GPU until the
+ * process ends.  Limit: n_u * N <= 4 194 304 (e.g. 1024 x 1024 in 2D radiation
+ * only, 100^3 in 3D with 4 unknowns); larger grids return M1_ERR_INVALID_ARG.
+ * cfg and fields are read as by m1_setup (fields are used in place, not copied,
+ * and validated on every call); U, dt, nsteps, stats and the results are those
+ * of m1_explicit_step / m1_semi_implicit_step, bit for bit.  hip_stream: a
+ * stream of the current device (NULL = default).  Calls that overlap on one GPU
+ * share the array and race: serialise them.  Errors: m1_last_error(NULL). */
+m1_status m1_time_steps_noalloc(const m1_config* cfg, const m1_fields* fields, m1_state* U, double dt,
+                                int32_t nsteps, int32_t semi, void* hip_stream, m1_stats* stats);
+
 void m1_destroy(m1_ctx* ctx);
 const char* m1_last_error(const m1_ctx* ctx);
 

@@ -6,7 +6,7 @@ not been built this module raises on import -- there is no CPU fallback.
 
 Low level: ``m1_setup``, ``m1_linearize``, ``m1_apply_operator``,
 ``m1_precondition``, ``m1_residual``, ``m1_implicit_step``, ``m1_explicit_step``,
-``m1_semi_implicit_step``, ``m1_velocity_sources``, ``m1_destroy``,
+``m1_semi_implicit_step``, ``m1_velocity_sources``, ``m1_time_steps_noalloc``, ``m1_destroy``,
 ``m1_last_error``, ``m1_profile_enable``, ``m1_profile_query`` mirror the C
 functions one to one (pointers are passed as Python ints / ctypes structs).
 High level: :class:`Solver` builds the structs from a problem description.
@@ -95,6 +95,8 @@ _sig = {
     "m1_explicit_step": (ctypes.c_int32, [_vp, _P(M1State), ctypes.c_double, ctypes.c_int32, _P(M1Stats)]),
     "m1_semi_implicit_step": (ctypes.c_int32, [_vp, _P(M1State), ctypes.c_double, ctypes.c_int32, _P(M1Stats)]),
     "m1_velocity_sources": (ctypes.c_int32, [_vp, _P(M1State), _vp, _vp, _vp, ctypes.c_double, _P(M1Stats)]),
+    "m1_time_steps_noalloc": (ctypes.c_int32, [_P(M1Config), _P(M1Fields), _P(M1State), ctypes.c_double,
+                                               ctypes.c_int32, ctypes.c_int32, _vp, _P(M1Stats)]),
     "m1_destroy": (None, [_vp]),
     "m1_last_error": (ctypes.c_char_p, [_vp]),
     "m1_profile_enable": (ctypes.c_int32, [_vp, ctypes.c_int32]),
@@ -142,6 +144,7 @@ m1_implicit_step = _lib.m1_implicit_step
 m1_explicit_step = _lib.m1_explicit_step
 m1_semi_implicit_step = _lib.m1_semi_implicit_step
 m1_velocity_sources = _lib.m1_velocity_sources
+m1_time_steps_noalloc = _lib.m1_time_steps_noalloc
 m1_destroy = _lib.m1_destroy
 m1_last_error = _lib.m1_last_error
 m1_profile_enable = _lib.m1_profile_enable

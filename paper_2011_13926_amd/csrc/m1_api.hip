@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -250,7 +251,8 @@ __global__ void k_check(const double* a, int64_t n, int positive, unsigned long 
   bool b = false;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     const double v = a[i];
-    b = b || !isfinite(v) || (positive == 1 && !(v > 0.0)) || (positive == 2 && !(v >= 0.0));
+    b = b || !isfinite(v) || (positive == 1 && !(v > 0.0)) || (positive == 2 && !(v >= 0.0)) ||
+        (positive == 3 && !(v == 0.0 || v == 1.0));
   }
   const unsigned long long ballot = __ballot(b);
   if ((threadIdx.x & 63) == 0 && ballot) atomicAdd(bad, 1ull);
@@ -269,7 +271,8 @@ __global__ void k_zero_u64(unsigned long long* p) {
   if (threadIdx.x == 0) p[0] = 0ull;
 }
 
-// Count entries that are non-finite (positive = 0), or also <= 0 (1), or < 0 (2).
+// Count entries that are non-finite (positive = 0), or also <= 0 (1), or < 0 (2),
+// or other than 0 and 1 (3).
 m1_status check_array(m1_ctx* c, const double* a, int64_t n, int positive, const char* name, m1_status code) {
   k_zero_u64<<<1, 64, 0, c->stream>>>(c->dcount);
   const int64_t grd = std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 2048));
@@ -812,6 +815,166 @@ m1_status velocity_sources(m1_ctx* c, m1_state* U, const double* ux, const doubl
 }
 
 // ============================================================================
+// Explicit / semi-implicit steps that allocate nothing.  Their work memory (two
+// state buffers for the ping-pong and a counter) is the file-scope array
+// `scratch` below, whose device address is looked up once per device with
+// hipGetSymbolAddress; host code only ever passes that address on (the array's
+// name in host code is a host-side stand-in, not a device pointer).
+// ============================================================================
+constexpr int64_t kNoAllocMaxVector = int64_t(1) << 22;   // n_u * N <= 4 Mi doubles (32 MiB)
+constexpr int64_t kNoAllocCounterOff = 2 * kNoAllocMaxVector;
+constexpr int64_t kScratchDoubles = kNoAllocCounterOff + 32; // + 256 B for the counter
+constexpr int kMaxDevices = 64;
+
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// device address of `scratch` on the current device (looked up on first use)
+m1_status scratch_on_device(double** out, std::string& err) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) { err = std::string("hipGetDevice: ") + hipGetErrorString(e); return M1_ERR_HIP; }
+  if (dev < 0 || dev >= kMaxDevices) { err = "device index beyond the supported range"; return M1_ERR_INVALID_ARG; }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      err = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+      return M1_ERR_HIP;
+    }
+    g_scratch_ptr[dev] = (double*)ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return M1_OK;
+}
+
+// count of entries of a[0..n) failing k_check's `mode` test, through the scratch counter
+m1_status noalloc_check(const double* a, int64_t n, int mode, unsigned long long* cnt, hipStream_t s,
+                        unsigned long long& bad, std::string& err) {
+  k_zero_u64<<<1, 64, 0, s>>>(cnt);
+  const int64_t grd = std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 2048));
+  k_check<<<grd, 256, 0, s>>>(a, n, mode, cnt);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipMemcpyAsync(&bad, cnt, sizeof(bad), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) { err = std::string("check: ") + hipGetErrorString(e); return M1_ERR_HIP; }
+  return M1_OK;
+}
+
+m1_status time_steps_noalloc(const m1_config* cfg, const m1_fields* fields, m1_state* U, double dt,
+                             int32_t nsteps, int32_t semi, void* hip_stream, m1_stats* stats, std::string& err) {
+  const auto t0 = std::chrono::steady_clock::now();
+  m1_status st = validate_config(cfg, err);
+  if (st != M1_OK) return st;
+  if (!fields || !fields->sigma) { err = "fields or fields->sigma is NULL"; return M1_ERR_INVALID_ARG; }
+  const bool cpl = cfg->source == M1_SRC_COUPLED_T;
+  if (cpl && !fields->rho_cv) { err = "rho_cv is NULL"; return M1_ERR_INVALID_ARG; }
+  for (int f = 0; f < 2 * cfg->ndim; ++f)
+    if (cfg->bc[f] == M1_BC_DIRICHLET && !fields->bc_ghost[f]) { err = "Dirichlet face without bc_ghost"; return M1_ERR_INVALID_ARG; }
+  if (!(std::isfinite(dt) && dt > 0)) { err = "dt must be finite and > 0"; return M1_ERR_INVALID_ARG; }
+  if (nsteps < 1) { err = "nsteps must be >= 1"; return M1_ERR_INVALID_ARG; }
+  if (semi != 0 && semi != 1) { err = "semi must be 0 or 1"; return M1_ERR_INVALID_ARG; }
+  if (semi && cfg->flux_source != M1_FSRC_CENTERED) {
+    err = "the semi-implicit step needs the centred flux source (the well-balanced source couples cells)";
+    return M1_ERR_INVALID_ARG;
+  }
+  const int nd = cfg->ndim;
+  if (!U || !U->E) { err = "state E is NULL"; return M1_ERR_INVALID_ARG; }
+  for (int d = 0; d < nd; ++d)
+    if (!U->F[d]) { err = "state F[d] is NULL"; return M1_ERR_INVALID_ARG; }
+  if (cpl && !U->T) { err = "state T is NULL (coupled source)"; return M1_ERR_INVALID_ARG; }
+  Geom g;
+  fill_geom(*cfg, g);
+  const int nu = nu_of(*cfg);
+  const int64_t N = g.N;
+  const int64_t n = (int64_t)nu * N;
+  if (n > kNoAllocMaxVector) {
+    err = "n_u * N = " + std::to_string(n) + " exceeds the no-allocation limit of " +
+          std::to_string(kNoAllocMaxVector) + " values";
+    return M1_ERR_INVALID_ARG;
+  }
+  double* base = nullptr;
+  if ((st = scratch_on_device(&base, err)) != M1_OK) return st;
+  hipStream_t s = (hipStream_t)hip_stream;
+  double* src = base;
+  double* dst = base + kNoAllocMaxVector;
+  unsigned long long* cnt = reinterpret_cast<unsigned long long*>(base + kNoAllocCounterOff);
+  unsigned long long bad = 0;
+  // the caller's fields are used in place: validate them as m1_setup does
+  if ((st = noalloc_check(fields->sigma, N, 2, cnt, s, bad, err)) != M1_OK) return st;
+  if (bad) { err = "sigma has non-finite or negative entries"; return M1_ERR_NONFINITE; }
+  if (cpl) {
+    if ((st = noalloc_check(fields->rho_cv, N, 1, cnt, s, bad, err)) != M1_OK) return st;
+    if (bad) { err = "rho_cv has non-finite or non-positive entries"; return M1_ERR_NONFINITE; }
+  }
+  Bdry bd{};
+  for (int f = 0; f < 2 * nd; ++f) {
+    if (g.bc[f] != M1_BC_DIRICHLET) continue;
+    const int64_t pn = g.plane_n[f / 2];
+    if ((st = noalloc_check(fields->bc_ghost[f], (int64_t)(1 + nd) * pn, 0, cnt, s, bad, err)) != M1_OK) return st;
+    if (bad) { err = "bc_ghost has non-finite entries"; return M1_ERR_NONFINITE; }
+    bd.plane[f] = fields->bc_ghost[f];
+    if (fields->bc_mask[f]) {
+      if ((st = noalloc_check(fields->bc_mask[f], pn, 3, cnt, s, bad, err)) != M1_OK) return st;
+      if (bad) { err = "bc_mask values must be 0 or 1"; return M1_ERR_INVALID_ARG; }
+      bd.mask[f] = fields->bc_mask[f];
+    }
+  }
+  // state in, checked as by m1_explicit_step
+  const size_t bytes = sizeof(double) * (size_t)N;
+  const double* comps[5] = {U->E, U->F[0], U->F[1], U->F[2], U->T};
+  hipError_t e = hipSuccess;
+  for (int k = 0; k < nu && e == hipSuccess; ++k) {
+    const double* from = k == 0 ? comps[0] : (k <= nd ? comps[k] : comps[4]);
+    e = hipMemcpyAsync(src + (int64_t)k * N, from, bytes, hipMemcpyDeviceToDevice, s);
+  }
+  if (e != hipSuccess) { err = std::string("copy in: ") + hipGetErrorString(e); return M1_ERR_HIP; }
+  if ((st = noalloc_check(src, n, 0, cnt, s, bad, err)) != M1_OK) return st;
+  if (bad) { err = "U has non-finite entries"; return M1_ERR_NONFINITE; }
+  if ((st = noalloc_check(src, N, 1, cnt, s, bad, err)) != M1_OK) return st;
+  if (bad) { err = "U.E has non-finite or non-positive entries"; return M1_ERR_INVALID_ARG; }
+  Scheme sc;
+  fill_scheme(*cfg, sc);
+  sc.dt = dt;
+  sc.s = dt / cfg->dx;
+  sc.cdt = cfg->c * dt;
+  Coefs<double> cf{};
+  cf.sigma = const_cast<double*>(fields->sigma);
+  cf.rcv = cpl ? const_cast<double*>(fields->rho_cv) : nullptr;
+  for (int32_t k = 0; k < nsteps; ++k) {
+    launch_time_step(nd, cpl, semi != 0, g, sc, cf, bd, src, dst, s);
+    std::swap(src, dst);
+  }
+  e = hipGetLastError();
+  if (e != hipSuccess) { err = std::string("time step launch: ") + hipGetErrorString(e); return M1_ERR_HIP; }
+  unsigned long long nf = 0;
+  k_zero_u64<<<1, 64, 0, s>>>(cnt);
+  launch_count_f(nd, g, src, cfg->c, cnt, s);
+  e = hipGetLastError();
+  if (e == hipSuccess) e = hipMemcpyAsync(&nf, cnt, sizeof(nf), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) { err = std::string("count: ") + hipGetErrorString(e); return M1_ERR_HIP; }
+  if ((st = noalloc_check(src, n, 0, cnt, s, bad, err)) != M1_OK) return st;
+  if (bad) { err = "U^(n+nsteps) has non-finite entries"; return M1_ERR_NONFINITE; }
+  double* outs[5] = {U->E, U->F[0], U->F[1], U->F[2], U->T};
+  for (int k = 0; k < nu && e == hipSuccess; ++k) {
+    double* to = k == 0 ? outs[0] : (k <= nd ? outs[k] : outs[4]);
+    e = hipMemcpyAsync(to, src + (int64_t)k * N, bytes, hipMemcpyDeviceToDevice, s);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) { err = std::string("copy out: ") + hipGetErrorString(e); return M1_ERR_HIP; }
+  if (stats) {
+    *stats = m1_stats{};
+    stats->cells_f_gt_1 = (int64_t)nf;
+    stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+  return M1_OK;
+}
+
+// ============================================================================
 // C ABI
 // ============================================================================
 extern "C" {
@@ -1233,6 +1396,14 @@ m1_status m1_explicit_step(m1_ctx* c, m1_state* U, double dt, int32_t nsteps, m1
 
 m1_status m1_semi_implicit_step(m1_ctx* c, m1_state* U, double dt, int32_t nsteps, m1_stats* stats) {
   return time_steps(c, U, dt, nsteps, stats, true);
+}
+
+m1_status m1_time_steps_noalloc(const m1_config* cfg, const m1_fields* fields, m1_state* U, double dt,
+                                int32_t nsteps, int32_t semi, void* hip_stream, m1_stats* stats) {
+  std::string err;
+  const m1_status st = time_steps_noalloc(cfg, fields, U, dt, nsteps, semi, hip_stream, stats, err);
+  if (st != M1_OK) g_setup_err = err;
+  return st;
 }
 
 m1_status m1_velocity_sources(m1_ctx* c, m1_state* U, const double* ux, const double* uy, const double* uz,
