@@ -64,6 +64,7 @@ class Scheme:
     lambda_floor: float = 0.0
     linearization: str = "newton"  # newton (tensor differentiated) | picard (tensor frozen)
     bc: tuple = ("periodic",) * 6
+    wb_boundary: bool = False     # Eq. "boundaryCondition" at non-periodic faces (well-balanced source only)
     ghost: dict = field(default_factory=dict)       # face -> (1+ndim, *plane)
     ghost_mask: dict = field(default_factory=dict)  # face -> plane weights
 
@@ -93,6 +94,7 @@ class Scheme:
                       closure=p.get("closure", "m1"), ap=p["ap"],
                       lambda_floor=p["lambda_floor"], bc=tuple(p["bc"]),
                       linearization=p.get("linearization", "newton"),
+                      wb_boundary=bool(p.get("wb_boundary", False)),
                       ghost=dict(p.get("ghost", {})),
                       ghost_mask=dict(p.get("ghost_mask", {})))
 
@@ -434,9 +436,23 @@ def operator(lin, X, mode):
             Y[1 + m] += s * (flux_F(plus, X, Xr, q_self, q_right, m) - flux_F(minus, Xl, X, q_left, q_self, m))
         if sch.flux_source == "wb":
             # {sigma F_d}_i = 1/2 (sigma_{i+1/2} F_{i+1/2} + sigma_{i-1/2} F_{i-1/2}),
-            # F_{i+1/2} = (F_i + F_{i+1}) / 2, faces normal to d (Eq. "wb_smart")
-            Y[1 + d] += c * dt * 0.25 * (plus["sigf"] * (X[1 + d] + Xr[1 + d])
-                                         + minus["sigf"] * (Xl[1 + d] + X[1 + d]))
+            # F_{i+1/2} = (F_i + F_{i+1}) / 2, faces normal to d (Eq. "wb_smart");
+            # below, hi and lo are twice the face values sigma F of the two faces
+            hi = plus["sigf"] * (X[1 + d] + Xr[1 + d])
+            lo = minus["sigf"] * (Xl[1 + d] + X[1 + d])
+            if sch.wb_boundary:
+                # Eq. "boundaryCondition": on a face between a cell and a ghost, sigma F is
+                # -c (P_dd(inside) - P_dd(outside)) / dx with the pressure of the ghost state
+                # (q = c^2 P, so sigma F = -(q_R - q_L) / (c dx))
+                shp = [1] * (X.ndim - 1)
+                shp[ax] = N
+                at_lo = np.zeros(N, bool)
+                at_hi = np.zeros(N, bool)
+                at_lo[0] = sch.bc[2 * d] != "periodic"
+                at_hi[N - 1] = sch.bc[2 * d + 1] != "periodic"
+                lo = np.where(at_lo.reshape(shp), -2.0 * (q_self[d] - q_left[d]) / (c * sch.dx), lo)
+                hi = np.where(at_hi.reshape(shp), -2.0 * (q_right[d] - q_self[d]) / (c * sch.dx), hi)
+            Y[1 + d] += c * dt * 0.25 * (hi + lo)
     sig = lin.sigma
     if sch.flux_source == "centered":
         for m in range(ndim):

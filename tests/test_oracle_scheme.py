@@ -359,3 +359,103 @@ def test_gmres_fixed_iterations_is_the_krylov_minimiser():
     x_ref = Minv @ (Q @ c)
     assert res.iters == k
     assert np.linalg.norm(res.x - x_ref) <= 1e-9 * np.linalg.norm(x_ref)
+
+
+# ---------------------------------------------------------------------------
+# Eq. "boundaryCondition" (Sect. 3.1.2): the well-balanced relation
+# sigma F = -c dP/dx imposed on the faces between a cell and a ghost
+# ---------------------------------------------------------------------------
+WBB_CASES = [((6, 5), ("dirichlet", "dirichlet", "periodic", "periodic"), 0),
+             ((5, 6), ("periodic", "periodic", "dirichlet", "dirichlet"), 1),
+             ((4, 3, 5), ("periodic", "periodic", "periodic", "periodic", "dirichlet", "dirichlet"), 2)]
+
+
+@pytest.mark.parametrize("n,bc,d", WBB_CASES)
+def test_boundary_closure_equals_face_average_when_ghost_obeys_it(n, bc, d):
+    """With the P1 closure (P = E I / 3, independent of F) choose the ghost planes of the
+    two faces normal to d so that the default face value sigma_f (F_g + F_b)/2 already
+    equals -c (P_inside - P_outside)/dx: the residual with and without the boundary closure
+    must then be identical.  A wrong sign, factor, opacity, cell size or pressure component
+    in the closure breaks the equality."""
+    p = W.random_problem(n, 31, flux_source="wb", bc=bc, closure="p1", dt=1.5)
+    p["dx"] = 0.7
+    nd = len(n)
+    ax = nd - 1 - d
+    sch = O.Scheme.from_problem(p)
+    U = O.state_from_problem(p, "U")
+    c, dx = p["c"], p["dx"]
+    for side in (0, 1):
+        face = 2 * d + side
+        b = np.take(U, [0 if side == 0 else n[d] - 1], axis=ax + 1).squeeze(ax + 1)    # boundary cells (1+nd.., plane)
+        sig_b = np.take(p["sigma"], [0 if side == 0 else n[d] - 1], axis=ax).squeeze(ax)
+        g = np.array(p["ghost"][face], dtype=float)                                   # (1+nd, plane)
+        # sigma_f F_f = -c (P_R - P_L)/dx with P = E/3; the ghost sits on the left (side 0) or right
+        PL, PR = (g[0] / 3.0, b[0] / 3.0) if side == 0 else (b[0] / 3.0, g[0] / 3.0)
+        sigF = -c * (PR - PL) / dx
+        g[1 + d] = 2.0 * sigF / sig_b - b[1 + d]
+        p["ghost"][face] = g
+    for wbb in (False, True):
+        p["wb_boundary"] = wbb
+        sch = O.Scheme.from_problem(p)
+        lin = O.linearize(sch, p["sigma"], p.get("rho_cv"), U, O.state_from_problem(p, "n"), p["dt"])
+        R = O.residual(lin)
+        if not wbb:
+            R0 = R
+    assert np.abs(R - R0).max() <= 1e-13 * np.abs(R0).max()
+    # the equality is not trivial: with another ghost F the two forms differ
+    p["ghost"][2 * d][1 + d] += 0.3
+    rs = {}
+    for wbb in (False, True):
+        p["wb_boundary"] = wbb
+        sch = O.Scheme.from_problem(p)
+        lin = O.linearize(sch, p["sigma"], p.get("rho_cv"), U, O.state_from_problem(p, "n"), p["dt"])
+        rs[wbb] = O.residual(lin)
+    assert np.abs(rs[True] - rs[False]).max() > 1e-6 * np.abs(R0).max()
+
+
+WBB_LIN_CASES = [((5, 4), ("dirichlet", "outflow", "reflect", "dirichlet"), "none"),
+                 ((5, 4), ("outflow", "reflect", "periodic", "periodic"), "coupled_t"),
+                 ((3, 4, 3), ("outflow", "dirichlet", "reflect", "outflow", "dirichlet", "reflect"), "absorption")]
+
+
+@pytest.mark.parametrize("n,bc,src", WBB_LIN_CASES)
+@pytest.mark.parametrize("lz", ["newton", "picard"])
+def test_boundary_closure_linearisation_and_blocks(n, bc, src, lz):
+    """With the boundary closure on (M1 closure): A v is the central difference of R
+    (Newton linearisation; with the tensor frozen, of R with D held at the iterate), the
+    block-Jacobi blocks are the diagonal blocks of the dense assembly, and the closure
+    changes the operator only in boundary cells."""
+    p = W.random_problem(n, 32, source=src, flux_source="wb", bc=bc, fmax=0.6)
+    p["linearization"] = lz
+    p["wb_boundary"] = True
+    lin = _lin(p)
+    U = lin.Ulin
+    v = np.random.default_rng(5).standard_normal(U.shape)
+    Av = O.apply_operator(lin, v)
+    if lz == "newton":
+        h = 1e-5
+        fd = (O.residual(lin, U + h * v) - O.residual(lin, U - h * v)) / (2 * h)
+        assert np.allclose(fd, Av, rtol=1e-8, atol=1e-8 * np.abs(Av).max())
+    A = O.assemble_dense(lin)
+    nu = lin.sch.nu
+    N = A.shape[0] // nu
+    blocks = O.diagonal_blocks(lin)
+    for cell in range(N):
+        idx = [k * N + cell for k in range(nu)]
+        assert np.allclose(blocks[cell], A[np.ix_(idx, idx)], rtol=1e-13, atol=1e-13 * np.abs(A).max())
+    p["wb_boundary"] = False
+    Av0 = O.apply_operator(_lin(p), v)
+    diff = np.abs(Av - Av0).reshape(nu, *lin.sch.shape).max(axis=0)
+    interior = np.ones(lin.sch.shape, bool)
+    for d in range(len(n)):
+        ax = len(n) - 1 - d
+        if bc[2 * d] != "periodic":
+            sl = [slice(None)] * len(n)
+            sl[ax] = 0
+            interior[tuple(sl)] = False
+        if bc[2 * d + 1] != "periodic":
+            sl = [slice(None)] * len(n)
+            sl[ax] = n[d] - 1
+            interior[tuple(sl)] = False
+    assert diff[interior].max() == 0.0
+    assert diff[~interior].max() > 0.0
