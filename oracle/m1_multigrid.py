@@ -18,7 +18,8 @@ grid, written from the textbook definition of a multigrid V-cycle:
   assembled matrices);
 * smoother: damped block-Jacobi, x <- x + omega D_l^{-1} (b - A_l x), with D_l
   the n_u x n_u diagonal block of every cell of A_l;
-* V(nu1, nu2) cycle from x = 0; the coarsest level is solved exactly (LU).
+* V(nu1, nu2) cycle from x = 0 (optionally other sweep counts below the finest
+  level); the coarsest level is solved exactly (LU).
 
 The cycle is a fixed linear map of its input, so it serves as the right
 preconditioner of GMRES unchanged.  Vectors are component-major, index
@@ -123,10 +124,14 @@ def block_diagonal(A, nu, N):
 class Multigrid:
     """z = M^{-1} r, one V(nu1, nu2) cycle of aggregation multigrid on A(lin) (+ diag(shift))."""
 
-    def __init__(self, lin, *, omega=0.7, nu1=1, nu2=1, nmin=8, shift=None, A=None):
+    def __init__(self, lin, *, omega=0.7, nu1=1, nu2=1, nmin=8, shift=None, A=None, nu1_coarse=None,
+                 nu2_coarse=None):
         sch = lin.sch
         self.nu = nu = sch.nu
         self.omega, self.nu1, self.nu2, self.nmin = float(omega), int(nu1), int(nu2), int(nmin)
+        # sweeps on the levels below the finest (default: the same as on the finest)
+        self.nu1c = self.nu1 if nu1_coarse is None else int(nu1_coarse)
+        self.nu2c = self.nu2 if nu2_coarse is None else int(nu2_coarse)
         A = assemble_sparse(lin, shift) if A is None else A.tocsr()
         shape = tuple(sch.shape)
         self.levels = []
@@ -153,12 +158,13 @@ class Multigrid:
         lev = self.levels[l]
         if "lu" in lev:
             return lev["lu"].solve(b)
+        nu1, nu2 = (self.nu1, self.nu2) if l == 0 else (self.nu1c, self.nu2c)
         x = np.zeros_like(b)
-        for _ in range(self.nu1):
+        for _ in range(nu1):
             x = self.smooth(lev, x, b)
         rc = lev["P"].T @ (b - lev["A"] @ x)
         x = x + lev["P"] @ self.vcycle(l + 1, rc)
-        for _ in range(self.nu2):
+        for _ in range(nu2):
             x = self.smooth(lev, x, b)
         return x
 
