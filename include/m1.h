@@ -35,8 +35,8 @@
  *
  * Errors: every call returns an m1_status; nothing aborts or throws across the
  * ABI.  Host-side arguments are validated before any launch.  On M1_NOT_CONVERGED
- * and M1_NOT_ADMISSIBLE m1_implicit_step leaves the caller's state unchanged and
- * still fills the stats.
+ * and M1_NOT_ADMISSIBLE m1_implicit_step leaves the caller's state unchanged (unless
+ * newton_flags bit 1 asks for the non-admissible root) and still fills the stats.
  * m1_last_error() gives a human-readable message for the last failure.
  */
 #ifndef M1_H
@@ -112,7 +112,10 @@ typedef struct {
                               (Armijo); if none passes, with
                               ptc_psi0 > 0 the step is rejected (U kept, psi = max(10 psi,
                               1e-3 ptc_psi0)), else the trial with the smallest ||R|| is taken
-                              (never in fixed-iteration mode) */
+                              (never in fixed-iteration mode);
+                              bit 1: a converged root with E <= 0 in some cell is written to U
+                              (the call still returns M1_NOT_ADMISSIBLE; for diagnostics and
+                              for measuring what the solver does on such roots) */
   int64_t n[3];            /* nx, ny, nz (nz ignored in 2D); each >= 1 */
   double dx;               /* cell size (> 0) */
   double c;                /* speed of light (> 0) */
@@ -155,7 +158,13 @@ typedef struct {
   int32_t mg_nu2;          /* post-smoothing sweeps, 0..4 */
   int32_t mg_nmin;         /* coarsen while an extent exceeds this (>= 2; 0: 8 in 2D, 4 in 3D); the
                               coarsest level (solved exactly) may hold at most 512 unknowns */
-  int32_t mg_reserved;     /* must be 0 */
+  int32_t wb_boundary;     /* 1: Eq. "boundaryCondition" (Sect. 3.1.2): on every face between a cell and a
+                              ghost the well-balanced source takes sigma F = -c (P_dd(inside) -
+                              P_dd(ghost)) / dx instead of the face average (well-balanced source
+                              only; the implicit step, residual, operator and preconditioners honour
+                              it, the explicit and semi-implicit steps refuse it); 0: off */
+  int32_t mg_nu1_coarse;   /* multigrid sweeps on the levels below the finest, 0..4; -1: mg_nu1 */
+  int32_t mg_nu2_coarse;   /* likewise for mg_nu2 */
 } m1_config;
 
 typedef struct {
@@ -297,6 +306,9 @@ const char* m1_last_error(const m1_ctx* ctx);
  * Class ids 0..m1_kernel_class_count()-1, names from m1_kernel_class_name. */
 m1_status m1_profile_enable(m1_ctx* ctx, int32_t on);
 m1_status m1_profile_query(m1_ctx* ctx, int32_t kclass, int64_t* launches, double* total_ms, double* total_bytes);
+/* Launches of a class issued while profiling was on, timed or not (the sampled classes'
+ * total time is about total_ms * issued / launches). */
+m1_status m1_profile_issued(m1_ctx* ctx, int32_t kclass, int64_t* issued);
 const char* m1_kernel_class_name(int32_t kclass);
 int32_t m1_kernel_class_count(void);
 

@@ -56,7 +56,8 @@ class M1Config(ctypes.Structure):
         ("ptc_rtol", ctypes.c_double), ("positivity_clip", ctypes.c_double), ("newton_forcing", ctypes.c_double),
         ("nn_weights_path", ctypes.c_char_p),
         ("mg_omega", ctypes.c_double), ("mg_nu1", ctypes.c_int32), ("mg_nu2", ctypes.c_int32),
-        ("mg_nmin", ctypes.c_int32), ("mg_reserved", ctypes.c_int32),
+        ("mg_nmin", ctypes.c_int32), ("wb_boundary", ctypes.c_int32), ("mg_nu1_coarse", ctypes.c_int32),
+        ("mg_nu2_coarse", ctypes.c_int32),
     ]
 
 
@@ -102,6 +103,7 @@ _sig = {
     "m1_profile_enable": (ctypes.c_int32, [_vp, ctypes.c_int32]),
     "m1_profile_query": (ctypes.c_int32, [_vp, ctypes.c_int32, _P(ctypes.c_int64), _P(ctypes.c_double),
                                           _P(ctypes.c_double)]),
+    "m1_profile_issued": (ctypes.c_int32, [_vp, ctypes.c_int32, _P(ctypes.c_int64)]),
     "m1_kernel_class_name": (ctypes.c_char_p, [ctypes.c_int32]),
     "m1_kernel_class_count": (ctypes.c_int32, []),
     "m1_set_network": (ctypes.c_int32, [_vp, _vp]),
@@ -149,6 +151,7 @@ m1_destroy = _lib.m1_destroy
 m1_last_error = _lib.m1_last_error
 m1_profile_enable = _lib.m1_profile_enable
 m1_profile_query = _lib.m1_profile_query
+m1_profile_issued = _lib.m1_profile_issued
 m1_kernel_class_name = _lib.m1_kernel_class_name
 m1_kernel_class_count = _lib.m1_kernel_class_count
 m1_status_string = _lib.m1_status_string
@@ -188,11 +191,11 @@ def kernel_classes():
 def make_config(p, *, precision="fp64", pc="bj", restart=30, max_iters=20000, newton_max=20, fixed_iters=0,
                 rtol=1e-10, newton_rtol=None, inner_rtol=1e-6, basis_fp32=False, line_search=False,
                 ptc_psi0=0.0, ptc_rtol=0.0, positivity_clip=0.0, newton_forcing=0.0, mg_omega=0.7, mg_nu1=1,
-                mg_nu2=1, mg_nmin=0):
+                mg_nu2=1, mg_nmin=0, mg_nu1_coarse=-1, mg_nu2_coarse=-1, commit_nonadmissible=False):
     """m1_config from a problem description (the dict layout of ``workloads``)."""
     cfg = M1Config()
     cfg.ndim = p["ndim"]
-    cfg.newton_flags = 1 if line_search else 0
+    cfg.newton_flags = (1 if line_search else 0) | (2 if commit_nonadmissible else 0)
     for d in range(3):
         cfg.n[d] = p["n"][d] if d < p["ndim"] else 1
     cfg.dx, cfg.c, cfg.a_r = p["dx"], p["c"], p["a_r"]
@@ -214,7 +217,9 @@ def make_config(p, *, precision="fp64", pc="bj", restart=30, max_iters=20000, ne
     cfg.ptc_psi0, cfg.ptc_rtol, cfg.positivity_clip = ptc_psi0, ptc_rtol, positivity_clip
     cfg.newton_forcing = newton_forcing
     cfg.nn_weights_path = None
-    cfg.mg_omega, cfg.mg_nu1, cfg.mg_nu2, cfg.mg_nmin, cfg.mg_reserved = mg_omega, mg_nu1, mg_nu2, mg_nmin, 0
+    cfg.mg_omega, cfg.mg_nu1, cfg.mg_nu2, cfg.mg_nmin = mg_omega, mg_nu1, mg_nu2, mg_nmin
+    cfg.wb_boundary = 1 if p.get("wb_boundary", False) else 0
+    cfg.mg_nu1_coarse, cfg.mg_nu2_coarse = mg_nu1_coarse, mg_nu2_coarse
     return cfg
 
 
@@ -401,7 +406,9 @@ class Solver:
             nbytes = ctypes.c_double()
             self._check(_lib.m1_profile_query(self.ctx, k, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(nbytes)))
             if n.value:
-                out[name] = {"launches": n.value, "ms": ms.value, "bytes": nbytes.value}
+                issued = ctypes.c_int64()
+                self._check(_lib.m1_profile_issued(self.ctx, k, ctypes.byref(issued)))
+                out[name] = {"launches": n.value, "ms": ms.value, "bytes": nbytes.value, "issued": issued.value}
         return out
 
     def close(self):

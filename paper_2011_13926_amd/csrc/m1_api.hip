@@ -24,7 +24,8 @@ namespace {
 const char* kClassNames[KC_COUNT] = {"setup",   "setup_bj", "residual",   "apply",         "block_jacobi",
                                      "arnoldi_dot", "arnoldi_scalar", "arnoldi_update", "x_update",
                                      "true_residual", "newton_update", "norm", "convert", "learned_pc", "apply_bj_fused",
-                                     "time_step", "velocity_sources", "multigrid", "multigrid_setup"};
+                                     "time_step", "velocity_sources", "mg_setup", "mg_fine", "mg_smooth",
+                                     "mg_down", "mg_coarse_solve"};
 
 struct Profiler {
   bool on = false;
@@ -125,7 +126,7 @@ hipEvent_t prof_event(m1_ctx* c) {
 // the solver's run time at 512^2.  Other classes are timed on every launch.
 bool per_iteration_class(int kc) {
   return kc == KC_APPLY || kc == KC_BJ || kc == KC_DOT || kc == KC_SCALAR || kc == KC_UPDATE || kc == KC_NN ||
-         kc == KC_APPLY_PC || kc == KC_MG;
+         kc == KC_APPLY_PC || kc == KC_MG_FINE || kc == KC_MG_SMOOTH || kc == KC_MG_DOWN || kc == KC_MG_COARSE;
 }
 
 // Launch with optional HIP-event timing; `bytes` is the launch's algorithmic
@@ -215,9 +216,18 @@ m1_status validate_config(const m1_config* c, std::string& err) {
   if (c->pc == M1_PC_MULTIGRID) {
     if (!(finite(c->mg_omega) && c->mg_omega > 0 && c->mg_omega < 2)) { err = "mg_omega must be in (0, 2)"; return M1_ERR_INVALID_ARG; }
     if (c->mg_nu1 < 0 || c->mg_nu1 > 4 || c->mg_nu2 < 0 || c->mg_nu2 > 4) { err = "mg_nu1 and mg_nu2 must be in 0..4"; return M1_ERR_INVALID_ARG; }
+    if (c->mg_nu1_coarse < -1 || c->mg_nu1_coarse > 4 || c->mg_nu2_coarse < -1 || c->mg_nu2_coarse > 4) {
+      err = "mg_nu1_coarse and mg_nu2_coarse must be in -1..4";
+      return M1_ERR_INVALID_ARG;
+    }
     if (c->mg_nmin != 0 && c->mg_nmin < 2) { err = "mg_nmin must be 0 or >= 2"; return M1_ERR_INVALID_ARG; }
   }
-  if (c->mg_reserved != 0) { err = "mg_reserved must be 0"; return M1_ERR_INVALID_ARG; }
+  if (c->wb_boundary != 0 && c->wb_boundary != 1) { err = "wb_boundary must be 0 or 1"; return M1_ERR_INVALID_ARG; }
+  if (c->wb_boundary && c->flux_source != M1_FSRC_WELL_BALANCED) {
+    err = "wb_boundary needs the well-balanced flux source";
+    return M1_ERR_INVALID_ARG;
+  }
+  if (c->newton_flags & ~3) { err = "newton_flags: only bits 0 and 1 are defined"; return M1_ERR_INVALID_ARG; }
   if (!(finite(c->lambda_floor) && c->lambda_floor >= 0)) { err = "lambda_floor must be >= 0"; return M1_ERR_INVALID_ARG; }
   for (int f = 0; f < 2 * c->ndim; ++f) {
     if (c->bc[f] < 0 || c->bc[f] > 3) { err = "bc value out of range"; return M1_ERR_INVALID_ARG; }
@@ -404,6 +414,8 @@ void fill_scheme(const m1_config& cfg, Scheme& sc) {
   sc.p1 = cfg.closure == M1_CLOSURE_P1;
   sc.newton = cfg.linearization == M1_LIN_NEWTON;
   sc.psi = 0.0;
+  sc.wbb = cfg.wb_boundary;
+  sc.inv_cdx = 1.0 / (cfg.c * cfg.dx);
 }
 
 void set_dt(m1_ctx* c, double dt) {
@@ -454,25 +466,6 @@ void mg_levels(const m1_ctx* c, MgHierarchy& h) {
   }
 }
 
-// one V-cycle: finest level (two applies, block-Jacobi sweeps, restriction,
-// prolongation) plus, per coarse level, the down and up kernels (stencil,
-// inverse diagonal, vectors) -- each array element once per kernel
-double mg_cycle_bytes(const m1_ctx* c, size_t rs) {
-  const MgHierarchy& h = c->mg;
-  const double nu = c->nu, nb = 1 + 2 * c->nd;
-  const double N0 = cells(c);
-  double b = 0.0;
-  const int sweeps0 = h.nu1 + h.nu2;
-  b += sweeps0 * (bytes_apply(c, rs, rs, rs, false) + (4.0 * nu + nu * nu) * rs * N0);
-  b += 2.0 * nu * rs * N0 + 2.0 * nu * rs * N0;   // restriction, prolongation
-  for (int l = 1; l < h.nlev; ++l) {
-    const double Nl = (double)h.lev[l].g.N;
-    if (l + 1 == h.nlev) b += (nu * Nl) * (nu * Nl) * rs + 2.0 * nu * Nl * rs;
-    else b += (h.nu1 + h.nu2) * ((nb * nu * nu + nu * nu) + 4.0 * nu) * rs * Nl;
-  }
-  return b;
-}
-
 double mg_setup_bytes(const m1_ctx* c) {
   const MgHierarchy& h = c->mg;
   const double nu = c->nu, nb = 1 + 2 * c->nd;
@@ -495,6 +488,7 @@ template <typename R> MgFine<R> mg_fine(const m1_ctx* c) {
   MgFine<R> f;
   f.nd = c->nd;
   f.nu = c->nu;
+  f.apply_bytes = bytes_apply(c, sizeof(R), sizeof(R), sizeof(R), false);
   f.bjinv = coefs_of<R>(c).bjinv;
   f.apply = &mg_fine_apply<R>;
   f.self = c;
@@ -640,7 +634,8 @@ m1_status gmres(m1_ctx* c, double bnorm, SolveResult& res, const Coefs<R>& cfi) 
           launch_apply_pre<R, TV, TV>(c->nd, c->cpl, c->g, c->sc, cfi, bd, uj, p, c->stream, &c->gs->done);
         }, j, 0);
       } else if (use_mg) {
-        timed(c, KC_MG, mg_cycle_bytes(c, sizeof(R)), [&] { mg_vcycle<R, TV>(c->mg, mgf, uj, z, c->stream, &c->gs->done); }, j, 0);
+        const MgWrap wrap = [&](int kc, double bytes, const std::function<void()>& launch) { timed(c, kc, bytes, launch, j, 0); };
+        mg_vcycle<R, TV>(c->mg, mgf, uj, z, c->stream, &c->gs->done, c->prof.on ? &wrap : nullptr);
         timed(c, KC_APPLY, bytes_apply(c, sizeof(R), sizeof(R), sizeof(TV), false), [&] { launch_apply<R, R, TV>(c->nd, c->cpl, 0, c->g, c->sc, cfi, bd, z, nullptr, p, c->stream, &c->gs->done); }, j, 0);
       } else if (use_pc) {
         timed(c, KC_BJ, bytes_bj(c, sizeof(R), sizeof(TV), sizeof(R)), [&] { launch_bj<R, TV, R>(c->nd, c->cpl, c->g, cfi, uj, z, c->stream, &c->gs->done); }, j, 0);
@@ -662,7 +657,10 @@ m1_status gmres(m1_ctx* c, double bnorm, SolveResult& res, const Coefs<R>& cfi) 
       // x += M^{-1} (V y): V y into xw, one cycle, then the FP64 update
       HIPCHK(c, hipMemsetAsync(c->xw, 0, sizeof(double) * n, c->stream));
       timed(c, KC_XUPDATE, (double)steps * n * sizeof(TV) + 16.0 * n, [&] { launch_xupdate<R, TV>(c->nd, c->cpl, c->g, cfi, V, vs, c->gs, c->xw, 0, c->stream); });
-      timed(c, KC_MG, mg_cycle_bytes(c, sizeof(R)), [&] { mg_vcycle<R, double>(c->mg, mgf, c->xw, z, c->stream, nullptr); });
+      {
+        const MgWrap wrap = [&](int kc, double bytes, const std::function<void()>& launch) { timed(c, kc, bytes, launch); };
+        mg_vcycle<R, double>(c->mg, mgf, c->xw, z, c->stream, nullptr, c->prof.on ? &wrap : nullptr);
+      }
       mg_axpy<R>(z, c->x, n, c->stream);
     } else {
       timed(c, KC_XUPDATE, (double)steps * n * sizeof(TV) + 16.0 * n + (use_pc ? (double)c->nu * c->nu * sizeof(R) * cells(c) : 0.0), [&] { launch_xupdate<R, TV>(c->nd, c->cpl, c->g, cfi, V, vs, c->gs, c->x, use_pc, c->stream); });
@@ -731,6 +729,10 @@ m1_status time_steps(m1_ctx* c, m1_state* U, double dt, int32_t nsteps, m1_stats
   if (nsteps < 1) { c->err = "nsteps must be >= 1"; return M1_ERR_INVALID_ARG; }
   if (semi && c->cfg.flux_source != M1_FSRC_CENTERED) {
     c->err = "the semi-implicit step needs the centred flux source (the well-balanced source couples cells)";
+    return M1_ERR_INVALID_ARG;
+  }
+  if (c->cfg.wb_boundary) {
+    c->err = "the explicit steps do not implement the boundary closure (wb_boundary)";
     return M1_ERR_INVALID_ARG;
   }
   m1_status st;
@@ -879,6 +881,10 @@ m1_status time_steps_noalloc(const m1_config* cfg, const m1_fields* fields, m1_s
   if (semi != 0 && semi != 1) { err = "semi must be 0 or 1"; return M1_ERR_INVALID_ARG; }
   if (semi && cfg->flux_source != M1_FSRC_CENTERED) {
     err = "the semi-implicit step needs the centred flux source (the well-balanced source couples cells)";
+    return M1_ERR_INVALID_ARG;
+  }
+  if (cfg->wb_boundary) {
+    err = "the explicit steps do not implement the boundary closure (wb_boundary)";
     return M1_ERR_INVALID_ARG;
   }
   const int nd = cfg->ndim;
@@ -1081,6 +1087,8 @@ m1_status m1_setup(const m1_config* cfg, const m1_fields* fields, const m1_state
     h.omega = cfg->mg_omega;
     h.nu1 = cfg->mg_nu1;
     h.nu2 = cfg->mg_nu2;
+    h.nu1c = cfg->mg_nu1_coarse >= 0 ? cfg->mg_nu1_coarse : cfg->mg_nu1;
+    h.nu2c = cfg->mg_nu2_coarse >= 0 ? cfg->mg_nu2_coarse : cfg->mg_nu2;
     mg_levels(c, h);
     const int64_t ncoarse = (int64_t)c->nu * h.lev[h.nlev - 1].g.N;
     if (ncoarse > kMgMaxCoarse) {
@@ -1208,7 +1216,8 @@ m1_status m1_precondition(m1_ctx* c, const double* r, double* z) {
   if (c->cfg.pc == M1_PC_MULTIGRID) {
     if (r == z) { c->err = "the multigrid preconditioner needs distinct r and z"; return M1_ERR_INVALID_ARG; }
     const MgFine<double> f = mg_fine<double>(c);
-    timed(c, KC_MG, mg_cycle_bytes(c, 8), [&] { mg_vcycle<double, double>(c->mg, f, r, z, c->stream, nullptr); });
+    const MgWrap wrap = [&](int kc, double bytes, const std::function<void()>& launch) { timed(c, kc, bytes, launch); };
+    mg_vcycle<double, double>(c->mg, f, r, z, c->stream, nullptr, c->prof.on ? &wrap : nullptr);
   } else {
     timed(c, KC_BJ, bytes_bj(c, 8, 8, 8), [&] { launch_bj<double, double, double>(c->nd, c->cpl, c->g, c->cf64, r, z, c->stream); });
   }
@@ -1366,7 +1375,8 @@ m1_status m1_implicit_step(m1_ctx* c, m1_state* U, double dt, m1_stats* stats) {
   HIPCHK(c, hipStreamSynchronize(c->stream));
   prof_collect(c);
   const bool admissible = ne == 0;
-  if (converged && admissible) {
+  // newton_flags bit 1: a converged root with E <= 0 is still written back
+  if (converged && (admissible || (c->cfg.newton_flags & 2))) {
     if ((st = copy_state_out(c, c->Uk, U)) != M1_OK) return st;
     HIPCHK(c, hipStreamSynchronize(c->stream));
   }
@@ -1512,6 +1522,12 @@ m1_status m1_profile_query(m1_ctx* c, int32_t kc, int64_t* launches, double* tot
   *launches = c->prof.launches[kc];
   *total_ms = c->prof.ms[kc];
   if (total_bytes) *total_bytes = c->prof.bytes[kc];
+  return M1_OK;
+}
+
+m1_status m1_profile_issued(m1_ctx* c, int32_t kc, int64_t* issued) {
+  if (!c || kc < 0 || kc >= KC_COUNT || !issued) return M1_ERR_INVALID_ARG;
+  *issued = c->prof.seen[kc];
   return M1_OK;
 }
 

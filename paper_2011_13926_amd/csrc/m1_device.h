@@ -54,6 +54,8 @@ struct Scheme {
   int newton;        // differentiate the tensor (1) or freeze it (0)
   double psi;        // pseudo-transient shift of the linear operator (0: none)
   double dx_c;       // dx / c (the asymptotic correction's scale)
+  int wbb;           // well-balanced boundary closure (Eq. "boundaryCondition") on non-periodic faces
+  double inv_cdx;    // 1 / (c dx)
 };
 
 __device__ __forceinline__ int64_t plane_index(int d, int i, int j, int k, const Geom& g) {

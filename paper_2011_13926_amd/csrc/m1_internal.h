@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <functional>
+
 #include "m1_device.h"
 
 namespace m1 {
@@ -77,7 +79,8 @@ constexpr int kMgMaxCoarse = 1024;   // unknowns of the coarsest level (dense in
 
 struct MgHierarchy {
   int nlev = 0;
-  int nu1 = 1, nu2 = 1;
+  int nu1 = 1, nu2 = 1;     // sweeps on the finest level
+  int nu1c = 1, nu2c = 1;   // sweeps on the coarser levels
   double omega = 0.7;
   MgLevel lev[kMgMaxLevels];
   double* Ainv64 = nullptr;   // coarsest level inverse, row-major
@@ -90,6 +93,7 @@ struct MgHierarchy {
 // y = A x with the matrix-free operator.
 template <typename R> struct MgFine {
   int nd = 2, nu = 3;
+  double apply_bytes = 0.0;   // algorithmic bytes of one finest-level apply
   const R* bjinv = nullptr;
   void (*apply)(const void* self, const R* x, R* y, hipStream_t s, const int* skip) = nullptr;
   const void* self = nullptr;
@@ -98,17 +102,20 @@ template <typename R> struct MgFine {
 
 // stencils of levels 1.. (Galerkin), their inverse diagonal blocks, the coarsest inverse (FP64)
 void mg_build(MgHierarchy& h, int nd, int nu, hipStream_t s);
+// optional timing hook: called with each launch's kernel class and algorithmic bytes
+using MgWrap = std::function<void(int kclass, double bytes, const std::function<void()>& launch)>;
 // z = one V-cycle applied to r (r of the input type TIN, z of the preconditioner's type R)
 template <typename R, typename TIN>
-void mg_vcycle(const MgHierarchy& h, const MgFine<R>& fine, const TIN* r, R* z, hipStream_t s, const int* skip);
+void mg_vcycle(const MgHierarchy& h, const MgFine<R>& fine, const TIN* r, R* z, hipStream_t s, const int* skip,
+               const MgWrap* wrap = nullptr);
 template <typename R> void mg_axpy(const R* z, double* x, int64_t n, hipStream_t s);
 void launch_fine_stencil(int nd, bool cpl, const Geom& g, const Scheme& sc, const Coefs<double>& cf, const Bdry& bd,
                          double* S, hipStream_t s);
 
 enum KernelClass {
   KC_SETUP = 0, KC_SETUP_BJ, KC_RESIDUAL, KC_APPLY, KC_BJ, KC_DOT, KC_SCALAR, KC_UPDATE, KC_XUPDATE,
-  KC_TRUE_RESID, KC_NEWTON_UPDATE, KC_NORM, KC_CONVERT, KC_NN, KC_APPLY_PC, KC_TIME_STEP, KC_VELOCITY, KC_MG,
-  KC_MG_SETUP, KC_COUNT
+  KC_TRUE_RESID, KC_NEWTON_UPDATE, KC_NORM, KC_CONVERT, KC_NN, KC_APPLY_PC, KC_TIME_STEP, KC_VELOCITY, KC_MG_SETUP,
+  KC_MG_FINE, KC_MG_SMOOTH, KC_MG_DOWN, KC_MG_COARSE, KC_COUNT
 };
 
 // ---- launchers (defined in m1_kernels.hip / m1_krylov.hip) ----

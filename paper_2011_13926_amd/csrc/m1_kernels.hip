@@ -347,7 +347,26 @@ __global__ __launch_bounds__(256) void k_setup_bj(Geom g, Scheme sc, Coefs<doubl
       B[1 + m][1 + m] -= s * ddm * (1.0 - gL[1 + m]);
     }
     if (sc.wb) {
-      B[1 + d][1 + d] += 0.25 * sc.cdt * (0.5 * (sig + sigR) * (1.0 + gR[1 + d]) + 0.5 * (sig + sigL) * (gL[1 + d] + 1.0));
+      // self-coupling of the well-balanced source (hi: + face, lo: - face); with the
+      // boundary closure a face to a ghost contributes -s/2 (q_R - q_L) with q = J x
+      // (the ghost's x = g x of this cell)
+      if (sc.wbb && (r.kind == 1 || l.kind == 1)) {
+        if (r.kind == 1) {
+#pragma unroll
+          for (int k = 0; k < NR; ++k) B[1 + d][k] -= 0.5 * s * (JR[d][k] * gR[k] - Js[d][k]);
+        } else {
+          B[1 + d][1 + d] += 0.25 * sc.cdt * (0.5 * (sig + sigR) * (1.0 + gR[1 + d]));
+        }
+        if (l.kind == 1) {
+#pragma unroll
+          for (int k = 0; k < NR; ++k) B[1 + d][k] -= 0.5 * s * (Js[d][k] - JL[d][k] * gL[k]);
+        } else {
+          B[1 + d][1 + d] += 0.25 * sc.cdt * (0.5 * (sig + sigL) * (gL[1 + d] + 1.0));
+        }
+      } else {
+        B[1 + d][1 + d] +=
+            0.25 * sc.cdt * (0.5 * (sig + sigR) * (1.0 + gR[1 + d]) + 0.5 * (sig + sigL) * (gL[1 + d] + 1.0));
+      }
     }
   }
   if (!sc.wb) {
@@ -531,9 +550,16 @@ __global__ __launch_bounds__(256) void k_stencil(Geom g, Scheme sc, Coefs<R> cf,
       ys[1 + m] += s * (FPp - FPm);
     }
     if (sc.wb) {
-      // {sigma F_d}: trapezoidal face average over the two faces normal to d
-      ys[1 + d] += (R)0.25 * cdt *
-                   ((R)0.5 * (sig + sigR) * (xs[1 + d] + xr[1 + d]) + (R)0.5 * (sig + sigL) * (xl[1 + d] + xs[1 + d]));
+      // {sigma F_d}: trapezoidal face average over the two faces normal to d (hi, lo: twice
+      // the face values); with the boundary closure a face to a ghost takes
+      // sigma F = -c (P_dd(right) - P_dd(left)) / dx (q = c^2 P)
+      R hi = (R)0.5 * (sig + sigR) * (xs[1 + d] + xr[1 + d]);
+      R lo = (R)0.5 * (sig + sigL) * (xl[1 + d] + xs[1 + d]);
+      if (sc.wbb) {
+        if (r.kind == 1) hi = -(R)2 * (qr[d] - qs[d]) * (R)sc.inv_cdx;
+        if (l.kind == 1) lo = -(R)2 * (qs[d] - ql[d]) * (R)sc.inv_cdx;
+      }
+      ys[1 + d] += (R)0.25 * cdt * (hi + lo);
     }
   }
   if (!sc.wb) {
@@ -753,8 +779,15 @@ __global__ __launch_bounds__(kApply2dThreads) void k_apply2d_lds(Geom g, Scheme 
         ys[1 + m] += s * (FPp - FPm);
       }
       if (sc.wb) {
-        ys[1 + d] += (R)0.25 * cdt *
-                     ((R)0.5 * (sig + sigR) * (xs[1 + d] + xr[1 + d]) + (R)0.5 * (sig + sigL) * (xl[1 + d] + xs[1 + d]));
+        R hi = (R)0.5 * (sig + sigR) * (xs[1 + d] + xr[1 + d]);
+        R lo = (R)0.5 * (sig + sigL) * (xl[1 + d] + xs[1 + d]);
+        if (sc.wbb) {
+          // boundary closure on faces to a ghost (the halo tile holds the ghost's q)
+          const int id = d == 0 ? i : j, n = d == 0 ? nx : ny;
+          if (id == n - 1 && g.bc[2 * d + 1] != BC_PERIODIC) hi = -(R)2 * (qr[d] - qs[d]) * (R)sc.inv_cdx;
+          if (id == 0 && g.bc[2 * d] != BC_PERIODIC) lo = -(R)2 * (qs[d] - ql[d]) * (R)sc.inv_cdx;
+        }
+        ys[1 + d] += (R)0.25 * cdt * (hi + lo);
       }
     }
     if (!sc.wb) {

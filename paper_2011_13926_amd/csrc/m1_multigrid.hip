@@ -20,6 +20,7 @@
 // entries and vectors are component-major (SoA) per level, so consecutive
 // threads (cells) read consecutive addresses.
 #include <algorithm>
+#include <functional>
 #include <vector>
 
 #include "m1_internal.h"
@@ -28,16 +29,21 @@ namespace m1 {
 
 constexpr int kMgThreads = 256;
 
-// (i, j, k) of a level-local cell index
+// (i, j, k) of a level-local cell index; a level has at most 2^31 cells, so the
+// index arithmetic is 32-bit unsigned (64-bit division is a long instruction
+// sequence on the GPU and dominated the small coarse-level kernels)
 __device__ __forceinline__ void mg_idx(const MgGeom& g, int64_t cell, int* id) {
-  id[0] = (int)(cell % g.n[0]);
-  const int64_t r = cell / g.n[0];
-  id[1] = (int)(r % g.n[1]);
-  id[2] = (int)(r / g.n[1]);
+  const unsigned c = (unsigned)cell;
+  const unsigned nx = (unsigned)g.n[0], ny = (unsigned)g.n[1];
+  const unsigned r = c / nx;
+  id[0] = (int)(c - r * nx);
+  const unsigned k = r / ny;
+  id[1] = (int)(r - k * ny);
+  id[2] = (int)k;
 }
 
 __device__ __forceinline__ int64_t mg_lin(const MgGeom& g, const int* id) {
-  return ((int64_t)id[2] * g.n[1] + id[1]) * g.n[0] + id[0];
+  return (int64_t)(((unsigned)id[2] * (unsigned)g.n[1] + (unsigned)id[1]) * (unsigned)g.n[0] + (unsigned)id[0]);
 }
 
 // neighbour of cell id along d (side 0 lower, 1 upper): -1 if it is outside a
@@ -47,19 +53,35 @@ __device__ __forceinline__ int64_t mg_nb(const MgGeom& g, const int* id, int d, 
   j[d] += side ? 1 : -1;
   if (j[d] < 0 || j[d] >= g.n[d]) {
     if (!g.per[d]) return -1;
-    j[d] = (j[d] + g.n[d]) % g.n[d];
+    j[d] = j[d] < 0 ? g.n[d] - 1 : 0;
   }
   return mg_lin(g, j);
 }
 
-// aggregate (coarse cell) of a fine cell
+// the same, also returning the neighbour's (i, j, k)
+__device__ __forceinline__ int64_t mg_nb_id(const MgGeom& g, const int* id, int d, int side, int* j) {
+  j[0] = id[0];
+  j[1] = id[1];
+  j[2] = id[2];
+  j[d] += side ? 1 : -1;
+  if (j[d] < 0 || j[d] >= g.n[d]) {
+    if (!g.per[d]) return -1;
+    j[d] = j[d] < 0 ? g.n[d] - 1 : 0;
+  }
+  return mg_lin(g, j);
+}
+
+// aggregate (coarse cell) of the fine cell at (i, j, k): no division
+__device__ __forceinline__ int64_t mg_parent_id(const MgGeom& gc, const int* id) {
+  const int p[3] = {id[0] >> 1, id[1] >> 1, id[2] >> 1};
+  return mg_lin(gc, p);
+}
+
+// aggregate of a fine cell index
 __device__ __forceinline__ int64_t mg_parent(const MgGeom& gf, const MgGeom& gc, int64_t cell) {
   int id[3];
   mg_idx(gf, cell, id);
-  id[0] >>= 1;
-  id[1] >>= 1;
-  id[2] >>= 1;
-  return mg_lin(gc, id);
+  return mg_parent_id(gc, id);
 }
 
 // ----------------------------------------------------------------------------
@@ -147,10 +169,8 @@ __global__ __launch_bounds__(kGjThreads) void k_mg_dense_inverse(MgGeom g, const
   const int n = (int)(NU * N);
   const int n2 = 2 * n;
   const int tid = threadIdx.x;
-  for (int64_t e = tid; e < (int64_t)n * n2; e += kGjThreads) {
-    const int r = (int)(e / n2), c = (int)(e % n2);
-    W[e] = (c >= n) ? (c - n == r ? 1.0 : 0.0) : 0.0;
-  }
+  for (int r = tid >> 6; r < n; r += kGjThreads / 64)
+    for (int c = tid & 63; c < n2; c += 64) W[(int64_t)r * n2 + c] = (c >= n && c - n == r) ? 1.0 : 0.0;
   __syncthreads();
   // scatter the stencil (one thread per cell)
   for (int64_t cell = tid; cell < N; cell += kGjThreads) {
@@ -173,6 +193,7 @@ __global__ __launch_bounds__(kGjThreads) void k_mg_dense_inverse(MgGeom g, const
   __shared__ int s_piv;
   __shared__ double s_val[kGjThreads];
   __shared__ int s_idx[kGjThreads];
+  const int lane = tid & 63, wave = tid >> 6, nwave = kGjThreads / 64;
   for (int col = 0; col < n; ++col) {
     // pivot: largest |W[r][col]|, r >= col (ties: smallest row)
     double best = -1.0;
@@ -201,34 +222,37 @@ __global__ __launch_bounds__(kGjThreads) void k_mg_dense_inverse(MgGeom g, const
     }
     __syncthreads();
     const int piv = s_piv;
+    double* prow = W + (int64_t)col * n2;
     if (piv != col) {
+      double* qrow = W + (int64_t)piv * n2;
       for (int c = tid; c < n2; c += kGjThreads) {
-        const double t = W[(int64_t)col * n2 + c];
-        W[(int64_t)col * n2 + c] = W[(int64_t)piv * n2 + c];
-        W[(int64_t)piv * n2 + c] = t;
+        const double t = prow[c];
+        prow[c] = qrow[c];
+        qrow[c] = t;
       }
     }
     __syncthreads();
-    const double inv = 1.0 / W[(int64_t)col * n2 + col];
+    const double inv = 1.0 / prow[col];
     __syncthreads();
-    for (int c = tid; c < n2; c += kGjThreads) W[(int64_t)col * n2 + c] *= inv;
+    for (int c = tid; c < n2; c += kGjThreads) prow[c] *= inv;
     __syncthreads();
-    // eliminate column col from every other row
-    for (int64_t e = tid; e < (int64_t)n * n2; e += kGjThreads) {
-      const int r = (int)(e / n2), c = (int)(e % n2);
-      if (r == col || c == col) continue;
-      const double f = W[(int64_t)r * n2 + col];
-      if (f != 0.0) W[e] -= f * W[(int64_t)col * n2 + c];
+    // eliminate column col from every other row: one wavefront per row, lanes
+    // over the columns (the pivot column itself is cleared afterwards)
+    for (int r = wave; r < n; r += nwave) {
+      if (r == col) continue;
+      double* row = W + (int64_t)r * n2;
+      const double f = row[col];
+      if (f == 0.0) continue;
+      for (int c = lane; c < n2; c += 64)
+        if (c != col) row[c] -= f * prow[c];
     }
     __syncthreads();
     for (int r = tid; r < n; r += kGjThreads)
       if (r != col) W[(int64_t)r * n2 + col] = 0.0;
     __syncthreads();
   }
-  for (int64_t e = tid; e < (int64_t)n * n; e += kGjThreads) {
-    const int r = (int)(e / n), c = (int)(e % n);
-    Ainv[e] = W[(int64_t)r * n2 + n + c];
-  }
+  for (int r = wave; r < n; r += nwave)
+    for (int c = lane; c < n; c += 64) Ainv[(int64_t)r * n + c] = W[(int64_t)r * n2 + n + c];
 }
 
 // z = Ainv b on the coarsest level (one wavefront per row)
@@ -325,7 +349,7 @@ __global__ __launch_bounds__(kMgThreads) void k_mg_prolong_fine(MgGeom gf, MgGeo
 // ----------------------------------------------------------------------------
 // Coarse levels (explicit stencils)
 // ----------------------------------------------------------------------------
-// y = S x at cell c (x given by a functor of (cell, comp))
+// y = S x at cell c (x given by a functor of (cell, its (i, j, k), comp))
 template <int ND, int NU, typename R, typename X>
 __device__ __forceinline__ void mg_row(const MgGeom& g, const R* __restrict__ S, int64_t c, const int* id, X&& x,
                                        R (&y)[NU]) {
@@ -333,7 +357,7 @@ __device__ __forceinline__ void mg_row(const MgGeom& g, const R* __restrict__ S,
   const int64_t N = g.N;
   R xs[NU];
 #pragma unroll
-  for (int k = 0; k < NU; ++k) xs[k] = x(c, k);
+  for (int k = 0; k < NU; ++k) xs[k] = x(c, id, k);
 #pragma unroll
   for (int rr = 0; rr < NU; ++rr) {
     R acc = (R)0;
@@ -345,12 +369,13 @@ __device__ __forceinline__ void mg_row(const MgGeom& g, const R* __restrict__ S,
   for (int d = 0; d < ND; ++d)
 #pragma unroll
     for (int side = 0; side < 2; ++side) {
-      const int64_t j = mg_nb(g, id, d, side);
+      int jid[3];
+      const int64_t j = mg_nb_id(g, id, d, side, jid);
       if (j < 0) continue;
       const int b = 1 + 2 * d + side;
       R xn[NU];
 #pragma unroll
-      for (int k = 0; k < NU; ++k) xn[k] = x(j, k);
+      for (int k = 0; k < NU; ++k) xn[k] = x(j, jid, k);
 #pragma unroll
       for (int rr = 0; rr < NU; ++rr) {
         R acc = (R)0;
@@ -361,34 +386,48 @@ __device__ __forceinline__ void mg_row(const MgGeom& g, const R* __restrict__ S,
     }
 }
 
-// down from level l to l+1: b_{l+1} = P^T (b_l - A_l z_l), z_{l+1} = omega D^{-1} b_{l+1} (or 0)
+// down from level l to l+1: b_{l+1} = P^T (b_l - A_l z_l), z_{l+1} = omega D^{-1} b_{l+1}
+// (or 0 without pre-smoothing).
+// One thread per child: the 2^ND children of a coarse
+// cell sit on consecutive lanes of one wavefront, each forms its own residual,
+// two or three butterfly exchanges sum them, and the group's first lane writes the
+// coarse values.  (One thread per coarse cell walked the children one after the
+// other: a four- or eight-fold longer chain of dependent loads.)
 template <int ND, int NU, typename R>
-__global__ __launch_bounds__(kMgThreads) void k_mg_down(MgGeom gf, MgGeom gc, const R* __restrict__ S,
-                                                        const R* __restrict__ bf, const R* __restrict__ zf,
-                                                        const R* __restrict__ Dinvc, R omega, int smooth,
-                                                        R* __restrict__ bc, R* __restrict__ zc,
-                                                        const int* __restrict__ skip) {
+__global__ __launch_bounds__(kMgThreads) void k_mg_down_lanes(MgGeom gf, MgGeom gc, const R* __restrict__ S,
+                                                              const R* __restrict__ bf, const R* __restrict__ zf,
+                                                              const R* __restrict__ Dinvc, R omega, int smooth,
+                                                              R* __restrict__ bc, R* __restrict__ zc,
+                                                              const int* __restrict__ skip) {
   if (skip && *skip) return;
-  const int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (I >= gc.N) return;
-  int ci[3];
-  mg_idx(gc, I, ci);
+  constexpr int G = ND == 3 ? 8 : 4;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t I = t / G;
+  const int child = (int)(t % G);
+  const bool live = I < gc.N;   // every lane of a group has the same I
   R acc[NU];
 #pragma unroll
   for (int k = 0; k < NU; ++k) acc[k] = (R)0;
-  const int64_t Nf = gf.N;
-  auto xf = [&](int64_t cell, int k) { return zf[k * Nf + cell]; };
-  for (int cz = 0; cz < (ND == 3 ? 2 : 1); ++cz)
-    for (int cy = 0; cy < 2; ++cy)
-      for (int cx = 0; cx < 2; ++cx) {
-        int f[3] = {2 * ci[0] + cx, 2 * ci[1] + cy, ND == 3 ? 2 * ci[2] + cz : 0};
-        if (f[0] >= gf.n[0] || f[1] >= gf.n[1] || f[2] >= gf.n[2]) continue;
-        const int64_t c = mg_lin(gf, f);
-        R y[NU];
-        mg_row<ND, NU, R>(gf, S, c, f, xf, y);
+  int ci[3] = {0, 0, 0};
+  if (live) {
+    mg_idx(gc, I, ci);
+    int f[3] = {2 * ci[0] + (child & 1), 2 * ci[1] + ((child >> 1) & 1), ND == 3 ? 2 * ci[2] + (child >> 2) : 0};
+    if (f[0] < gf.n[0] && f[1] < gf.n[1] && f[2] < gf.n[2]) {
+      const int64_t Nf = gf.N;
+      const int64_t c = mg_lin(gf, f);
+      auto xf = [&](int64_t cell, const int*, int k) { return zf[k * Nf + cell]; };
+      R y[NU];
+      mg_row<ND, NU, R>(gf, S, c, f, xf, y);
 #pragma unroll
-        for (int k = 0; k < NU; ++k) acc[k] += bf[k * Nf + c] - y[k];
-      }
+      for (int k = 0; k < NU; ++k) acc[k] = bf[k * Nf + c] - y[k];
+    }
+  }
+  // butterfly sum over the group (lanes t ^ 1, t ^ 2 [, t ^ 4]); fixed order
+#pragma unroll
+  for (int off = 1; off < G; off <<= 1)
+#pragma unroll
+    for (int k = 0; k < NU; ++k) acc[k] += __shfl_xor(acc[k], off, 64);
+  if (!live || child != 0) return;
   const int64_t Nc = gc.N;
 #pragma unroll
   for (int k = 0; k < NU; ++k) bc[k * Nc + I] = acc[k];
@@ -418,9 +457,9 @@ __global__ __launch_bounds__(kMgThreads) void k_mg_smooth(MgGeom g, MgGeom gc, c
   int id[3];
   mg_idx(g, c, id);
   const int64_t N = g.N;
-  auto zp = [&](int64_t cell, int k) {
+  auto zp = [&](int64_t cell, const int* cid, int k) {
     R v = z[k * N + cell];
-    if (zc) v += zc[k * gc.N + mg_parent(g, gc, cell)];
+    if (zc) v += zc[k * gc.N + mg_parent_id(gc, cid)];
     return v;
   };
   R y[NU];
@@ -433,7 +472,7 @@ __global__ __launch_bounds__(kMgThreads) void k_mg_smooth(MgGeom g, MgGeom gc, c
     R acc = (R)0;
 #pragma unroll
     for (int k = 0; k < NU; ++k) acc += Dinv[(rr * NU + k) * N + c] * rv[k];
-    out[rr * N + c] = zp(c, rr) + omega * acc;
+    out[rr * N + c] = zp(c, id, rr) + omega * acc;
   }
 }
 
@@ -506,7 +545,8 @@ template <> const double* ainv<double>(const MgHierarchy& h) { return h.Ainv64; 
 template <> const float* ainv<float>(const MgHierarchy& h) { return h.Ainv32; }
 
 template <typename R, typename TIN>
-void mg_vcycle(const MgHierarchy& h, const MgFine<R>& fine, const TIN* r, R* z, hipStream_t s, const int* skip) {
+void mg_vcycle(const MgHierarchy& h, const MgFine<R>& fine, const TIN* r, R* z, hipStream_t s, const int* skip,
+               const MgWrap* wrap) {
   const int nd = fine.nd;
   const int nu = fine.nu;
   const R om = (R)h.omega;
@@ -515,29 +555,46 @@ void mg_vcycle(const MgHierarchy& h, const MgFine<R>& fine, const TIN* r, R* z, 
   R* z0 = (R*)h.lev[0].z;
   R* zp = (R*)h.lev[0].w;
   R* t = (R*)h.lev[0].t;
+  const double rs = sizeof(R), ti = sizeof(TIN), nb = 1 + 2 * nd, cu = nu, bs = (double)nu * nu;
+  const double agg = nd == 3 ? 8.0 : 4.0;
+  // every launch goes through the optional timing hook with its class and algorithmic bytes
+  auto run = [&](int kc, double bytes, const std::function<void()>& launch) {
+    if (wrap && *wrap) (*wrap)(kc, bytes, launch);
+    else launch();
+  };
+  const double fine_apply_bytes = fine.apply_bytes;
+  auto fine_smooth_bytes = [&](bool with_t, bool with_zp) {
+    return N0 * (cu * ti + bs * rs + cu * rs + (with_t ? cu * rs : 0.0) + (with_zp ? cu * rs : 0.0));
+  };
+  auto smooth_bytes = [&](const MgLevel& L, bool prolong) {
+    return (double)L.g.N * (nb * bs + bs + 3.0 * cu) * rs + (prolong ? (double)L.g.N / agg * cu * rs : 0.0);
+  };
   if (h.nlev == 1) {
     // the grid is already at the coarsest size: the cycle is the exact solve
     const int64_t n = (int64_t)nu * N0;
-    k_mg_cast<R, TIN><<<grid1(n), kMgThreads, 0, s>>>(n, r, (R*)h.lev[0].b, skip);
-    k_mg_coarse_solve<R><<<(unsigned)((n + 3) / 4), 256, 0, s>>>((int)n, ainv<R>(h), (const R*)h.lev[0].b, z, skip);
+    run(KC_MG_FINE, (double)n * (ti + rs), [&] { k_mg_cast<R, TIN><<<grid1(n), kMgThreads, 0, s>>>(n, r, (R*)h.lev[0].b, skip); });
+    run(KC_MG_COARSE, ((double)n * n + 2.0 * n) * rs, [&] { k_mg_coarse_solve<R><<<(unsigned)((n + 3) / 4), 256, 0, s>>>((int)n, ainv<R>(h), (const R*)h.lev[0].b, z, skip); });
     return;
   }
   // ---- finest level, down ----
   if (h.nu1 > 0) {
-    M1_MG_NU_SWITCH(nu, (k_mg_fine_smooth<NU, R, TIN><<<grid1(N0), kMgThreads, 0, s>>>(N0, fine.bjinv, om, r, nullptr, nullptr, z0, skip)))
+    run(KC_MG_FINE, fine_smooth_bytes(false, false), [&] { M1_MG_NU_SWITCH(nu, (k_mg_fine_smooth<NU, R, TIN><<<grid1(N0), kMgThreads, 0, s>>>(N0, fine.bjinv, om, r, nullptr, nullptr, z0, skip))) });
     for (int k = 1; k < h.nu1; ++k) {
-      fine(z0, t, s, skip);
-      M1_MG_NU_SWITCH(nu, (k_mg_fine_smooth<NU, R, TIN><<<grid1(N0), kMgThreads, 0, s>>>(N0, fine.bjinv, om, r, t, z0, zp, skip)))
+      run(KC_APPLY, fine_apply_bytes, [&] { fine(z0, t, s, skip); });
+      run(KC_MG_FINE, fine_smooth_bytes(true, true), [&] { M1_MG_NU_SWITCH(nu, (k_mg_fine_smooth<NU, R, TIN><<<grid1(N0), kMgThreads, 0, s>>>(N0, fine.bjinv, om, r, t, z0, zp, skip))) });
       std::swap(z0, zp);
     }
-    fine(z0, t, s, skip);
+    run(KC_APPLY, fine_apply_bytes, [&] { fine(z0, t, s, skip); });
   }
   {
     const MgLevel& L1 = h.lev[1];
-    const int sm = (h.nu1 > 0 && h.nlev > 2) ? 1 : 0;
+    const int sm = (h.nu1c > 0 && h.nlev > 2) ? 1 : 0;
     const R* tt = h.nu1 > 0 ? t : nullptr;
-    if (nd == 2) { M1_MG_NU_SWITCH(nu, (k_mg_restrict_fine<2, NU, R, TIN><<<grid1(L1.g.N), kMgThreads, 0, s>>>(g0, L1.g, r, tt, dinv<R>(L1), om, sm, (R*)L1.b, (R*)L1.z, skip))) }
-    else { M1_MG_NU_SWITCH(nu, (k_mg_restrict_fine<3, NU, R, TIN><<<grid1(L1.g.N), kMgThreads, 0, s>>>(g0, L1.g, r, tt, dinv<R>(L1), om, sm, (R*)L1.b, (R*)L1.z, skip))) }
+    const double bytes = (double)N0 * cu * (ti + (tt ? rs : 0.0)) + (double)L1.g.N * (2.0 * cu + (sm ? bs : 0.0)) * rs;
+    run(KC_MG_FINE, bytes, [&] {
+      if (nd == 2) { M1_MG_NU_SWITCH(nu, (k_mg_restrict_fine<2, NU, R, TIN><<<grid1(L1.g.N), kMgThreads, 0, s>>>(g0, L1.g, r, tt, dinv<R>(L1), om, sm, (R*)L1.b, (R*)L1.z, skip))) }
+      else { M1_MG_NU_SWITCH(nu, (k_mg_restrict_fine<3, NU, R, TIN><<<grid1(L1.g.N), kMgThreads, 0, s>>>(g0, L1.g, r, tt, dinv<R>(L1), om, sm, (R*)L1.b, (R*)L1.z, skip))) }
+    });
   }
   // ---- coarse levels, down ----
   // level l holds b_l and z_l (first sweep done, or zero); extra sweeps ping-pong z <-> w
@@ -549,37 +606,46 @@ void mg_vcycle(const MgHierarchy& h, const MgFine<R>& fine, const TIN* r, R* z, 
   for (int l = 1; l + 1 < h.nlev; ++l) {
     const MgLevel& L = h.lev[l];
     const MgLevel& C = h.lev[l + 1];
-    for (int k = 1; k < h.nu1; ++k) {
-      if (nd == 2) { M1_MG_NU_SWITCH(nu, (k_mg_smooth<2, NU, R><<<grid1(L.g.N), kMgThreads, 0, s>>>(L.g, C.g, stencil<R>(L), dinv<R>(L), om, (const R*)L.b, zl[l], nullptr, wl[l], skip))) }
-      else { M1_MG_NU_SWITCH(nu, (k_mg_smooth<3, NU, R><<<grid1(L.g.N), kMgThreads, 0, s>>>(L.g, C.g, stencil<R>(L), dinv<R>(L), om, (const R*)L.b, zl[l], nullptr, wl[l], skip))) }
+    for (int k = 1; k < h.nu1c; ++k) {
+      run(KC_MG_SMOOTH, smooth_bytes(L, false), [&] {
+        if (nd == 2) { M1_MG_NU_SWITCH(nu, (k_mg_smooth<2, NU, R><<<grid1(L.g.N), kMgThreads, 0, s>>>(L.g, C.g, stencil<R>(L), dinv<R>(L), om, (const R*)L.b, zl[l], nullptr, wl[l], skip))) }
+        else { M1_MG_NU_SWITCH(nu, (k_mg_smooth<3, NU, R><<<grid1(L.g.N), kMgThreads, 0, s>>>(L.g, C.g, stencil<R>(L), dinv<R>(L), om, (const R*)L.b, zl[l], nullptr, wl[l], skip))) }
+      });
       std::swap(zl[l], wl[l]);
     }
-    const int sm = (h.nu1 > 0 && l + 2 < h.nlev) ? 1 : 0;
-    if (nd == 2) { M1_MG_NU_SWITCH(nu, (k_mg_down<2, NU, R><<<grid1(C.g.N), kMgThreads, 0, s>>>(L.g, C.g, stencil<R>(L), (const R*)L.b, zl[l], dinv<R>(C), om, sm, (R*)C.b, zl[l + 1], skip))) }
-    else { M1_MG_NU_SWITCH(nu, (k_mg_down<3, NU, R><<<grid1(C.g.N), kMgThreads, 0, s>>>(L.g, C.g, stencil<R>(L), (const R*)L.b, zl[l], dinv<R>(C), om, sm, (R*)C.b, zl[l + 1], skip))) }
+    const int sm = (h.nu1c > 0 && l + 2 < h.nlev) ? 1 : 0;
+    const double bytes = (double)L.g.N * (nb * bs + 2.0 * cu) * rs + (double)C.g.N * (2.0 * cu + (sm ? bs : 0.0)) * rs;
+    run(KC_MG_DOWN, bytes, [&] {
+      if (nd == 2) { M1_MG_NU_SWITCH(nu, (k_mg_down_lanes<2, NU, R><<<grid1(4 * C.g.N), kMgThreads, 0, s>>>(L.g, C.g, stencil<R>(L), (const R*)L.b, zl[l], dinv<R>(C), om, sm, (R*)C.b, zl[l + 1], skip))) }
+      else { M1_MG_NU_SWITCH(nu, (k_mg_down_lanes<3, NU, R><<<grid1(8 * C.g.N), kMgThreads, 0, s>>>(L.g, C.g, stencil<R>(L), (const R*)L.b, zl[l], dinv<R>(C), om, sm, (R*)C.b, zl[l + 1], skip))) }
+    });
   }
-  // ---- coarsest: exact ----
   {
+    // ---- coarsest: exact ----
     const int last = h.nlev - 1;
     const MgLevel& L = h.lev[last];
     const int n = (int)(nu * L.g.N);
-    k_mg_coarse_solve<R><<<(n + 3) / 4, 256, 0, s>>>(n, ainv<R>(h), (const R*)L.b, zl[last], skip);
+    run(KC_MG_COARSE, ((double)n * n + 2.0 * n) * rs, [&] { k_mg_coarse_solve<R><<<(n + 3) / 4, 256, 0, s>>>(n, ainv<R>(h), (const R*)L.b, zl[last], skip); });
   }
   // ---- coarse levels, up ----
   for (int l = h.nlev - 2; l >= 1; --l) {
     const MgLevel& L = h.lev[l];
     const MgLevel& C = h.lev[l + 1];
-    if (h.nu2 > 0) {
-      if (nd == 2) { M1_MG_NU_SWITCH(nu, (k_mg_smooth<2, NU, R><<<grid1(L.g.N), kMgThreads, 0, s>>>(L.g, C.g, stencil<R>(L), dinv<R>(L), om, (const R*)L.b, zl[l], zl[l + 1], wl[l], skip))) }
-      else { M1_MG_NU_SWITCH(nu, (k_mg_smooth<3, NU, R><<<grid1(L.g.N), kMgThreads, 0, s>>>(L.g, C.g, stencil<R>(L), dinv<R>(L), om, (const R*)L.b, zl[l], zl[l + 1], wl[l], skip))) }
+    if (h.nu2c > 0) {
+      run(KC_MG_SMOOTH, smooth_bytes(L, true), [&] {
+        if (nd == 2) { M1_MG_NU_SWITCH(nu, (k_mg_smooth<2, NU, R><<<grid1(L.g.N), kMgThreads, 0, s>>>(L.g, C.g, stencil<R>(L), dinv<R>(L), om, (const R*)L.b, zl[l], zl[l + 1], wl[l], skip))) }
+        else { M1_MG_NU_SWITCH(nu, (k_mg_smooth<3, NU, R><<<grid1(L.g.N), kMgThreads, 0, s>>>(L.g, C.g, stencil<R>(L), dinv<R>(L), om, (const R*)L.b, zl[l], zl[l + 1], wl[l], skip))) }
+      });
       std::swap(zl[l], wl[l]);
-      for (int k = 1; k < h.nu2; ++k) {
-        if (nd == 2) { M1_MG_NU_SWITCH(nu, (k_mg_smooth<2, NU, R><<<grid1(L.g.N), kMgThreads, 0, s>>>(L.g, C.g, stencil<R>(L), dinv<R>(L), om, (const R*)L.b, zl[l], nullptr, wl[l], skip))) }
-        else { M1_MG_NU_SWITCH(nu, (k_mg_smooth<3, NU, R><<<grid1(L.g.N), kMgThreads, 0, s>>>(L.g, C.g, stencil<R>(L), dinv<R>(L), om, (const R*)L.b, zl[l], nullptr, wl[l], skip))) }
+      for (int k = 1; k < h.nu2c; ++k) {
+        run(KC_MG_SMOOTH, smooth_bytes(L, false), [&] {
+          if (nd == 2) { M1_MG_NU_SWITCH(nu, (k_mg_smooth<2, NU, R><<<grid1(L.g.N), kMgThreads, 0, s>>>(L.g, C.g, stencil<R>(L), dinv<R>(L), om, (const R*)L.b, zl[l], nullptr, wl[l], skip))) }
+          else { M1_MG_NU_SWITCH(nu, (k_mg_smooth<3, NU, R><<<grid1(L.g.N), kMgThreads, 0, s>>>(L.g, C.g, stencil<R>(L), dinv<R>(L), om, (const R*)L.b, zl[l], nullptr, wl[l], skip))) }
+        });
         std::swap(zl[l], wl[l]);
       }
     } else {
-      M1_MG_NU_SWITCH(nu, (k_mg_prolong<NU, R><<<grid1(L.g.N), kMgThreads, 0, s>>>(L.g, C.g, zl[l], zl[l + 1], wl[l], skip)))
+      run(KC_MG_SMOOTH, ((double)L.g.N * 2.0 + (double)C.g.N) * cu * rs, [&] { M1_MG_NU_SWITCH(nu, (k_mg_prolong<NU, R><<<grid1(L.g.N), kMgThreads, 0, s>>>(L.g, C.g, zl[l], zl[l + 1], wl[l], skip))) });
       std::swap(zl[l], wl[l]);
     }
   }
@@ -588,18 +654,21 @@ void mg_vcycle(const MgHierarchy& h, const MgFine<R>& fine, const TIN* r, R* z, 
     const MgLevel& L1 = h.lev[1];
     R* out = h.nu2 > 0 ? zp : z;
     const R* zin = h.nu1 > 0 ? z0 : nullptr;
+    const double bytes = ((double)N0 * ((zin ? 1.0 : 0.0) + 1.0) + (double)L1.g.N) * cu * rs;
     if (zin) {
-      if (nd == 2) { M1_MG_NU_SWITCH(nu, (k_mg_prolong_fine<2, NU, R><<<grid1(N0), kMgThreads, 0, s>>>(g0, L1.g, zin, zl[1], out, skip))) }
-      else { M1_MG_NU_SWITCH(nu, (k_mg_prolong_fine<3, NU, R><<<grid1(N0), kMgThreads, 0, s>>>(g0, L1.g, zin, zl[1], out, skip))) }
+      run(KC_MG_FINE, bytes, [&] {
+        if (nd == 2) { M1_MG_NU_SWITCH(nu, (k_mg_prolong_fine<2, NU, R><<<grid1(N0), kMgThreads, 0, s>>>(g0, L1.g, zin, zl[1], out, skip))) }
+        else { M1_MG_NU_SWITCH(nu, (k_mg_prolong_fine<3, NU, R><<<grid1(N0), kMgThreads, 0, s>>>(g0, L1.g, zin, zl[1], out, skip))) }
+      });
     } else {
       // z0 = 0: the prolonged coarse correction alone
-      M1_MG_NU_SWITCH(nu, (k_mg_prolong<NU, R><<<grid1(N0), kMgThreads, 0, s>>>(g0, L1.g, nullptr, zl[1], out, skip)))
+      run(KC_MG_FINE, bytes, [&] { M1_MG_NU_SWITCH(nu, (k_mg_prolong<NU, R><<<grid1(N0), kMgThreads, 0, s>>>(g0, L1.g, nullptr, zl[1], out, skip))) });
     }
     for (int k = 0; k < h.nu2; ++k) {
       R* src = (k % 2 == 0) ? zp : z0;
       R* dst = (k == h.nu2 - 1) ? z : ((k % 2 == 0) ? z0 : zp);
-      fine(src, t, s, skip);
-      M1_MG_NU_SWITCH(nu, (k_mg_fine_smooth<NU, R, TIN><<<grid1(N0), kMgThreads, 0, s>>>(N0, fine.bjinv, om, r, t, src, dst, skip)))
+      run(KC_APPLY, fine_apply_bytes, [&] { fine(src, t, s, skip); });
+      run(KC_MG_FINE, fine_smooth_bytes(true, true), [&] { M1_MG_NU_SWITCH(nu, (k_mg_fine_smooth<NU, R, TIN><<<grid1(N0), kMgThreads, 0, s>>>(N0, fine.bjinv, om, r, t, src, dst, skip))) });
     }
   }
 }
@@ -609,9 +678,12 @@ void mg_axpy(const R* z, double* x, int64_t n, hipStream_t s) {
   k_mg_axpy<R><<<grid1(n), kMgThreads, 0, s>>>(n, z, x);
 }
 
-template void mg_vcycle<double, double>(const MgHierarchy&, const MgFine<double>&, const double*, double*, hipStream_t, const int*);
-template void mg_vcycle<float, double>(const MgHierarchy&, const MgFine<float>&, const double*, float*, hipStream_t, const int*);
-template void mg_vcycle<float, float>(const MgHierarchy&, const MgFine<float>&, const float*, float*, hipStream_t, const int*);
+template void mg_vcycle<double, double>(const MgHierarchy&, const MgFine<double>&, const double*, double*, hipStream_t,
+                                        const int*, const MgWrap*);
+template void mg_vcycle<float, double>(const MgHierarchy&, const MgFine<float>&, const double*, float*, hipStream_t,
+                                       const int*, const MgWrap*);
+template void mg_vcycle<float, float>(const MgHierarchy&, const MgFine<float>&, const float*, float*, hipStream_t,
+                                      const int*, const MgWrap*);
 template void mg_axpy<double>(const double*, double*, int64_t, hipStream_t);
 template void mg_axpy<float>(const float*, double*, int64_t, hipStream_t);
 

@@ -325,7 +325,7 @@ def test_error_paths_on_gpu():
 
 
 @pytest.mark.parametrize("basis32", [False, True])
-@pytest.mark.parametrize("n,bc,src,fs", STEP_CASES[:3])
+@pytest.mark.parametrize("n,bc,src,fs", STEP_CASES)
 def test_mixed_precision_step_matches_fp64_oracle(n, bc, src, fs, basis32):
     """FP32 operator/preconditioner (and optionally FP32 basis) inside FP64-residual GMRES
     (iterative refinement): solved to 1e-10, the state is within 1e-8 of the FP64 oracle."""
@@ -346,3 +346,83 @@ def test_mixed_precision_step_matches_fp64_oracle(n, bc, src, fs, basis32):
         assert err <= 1e-8
     finally:
         s.close()
+
+
+# ---------------------------------------------------------------------------
+# The boundary closure of Eq. "boundaryCondition" (wb_boundary, off by default)
+# ---------------------------------------------------------------------------
+WBB_CASES = [((41, 23), BC2["mixed"], "none", "newton"), ((41, 23), BC2["walls"], "coupled_t", "newton"),
+             ((41, 23), BC2["mixed"], "absorption", "picard"), ((1, 7), ("periodic", "periodic", "dirichlet", "outflow"), "none", "newton"),
+             ((13, 11, 9), BC3["mixed"], "none", "newton"), ((13, 11, 9), BC3["open"], "coupled_t", "newton")]
+
+
+@pytest.mark.parametrize("n,bc,src,lz", WBB_CASES)
+def test_kernel_parity_boundary_closure(n, bc, src, lz):
+    """Residual, operator and block-Jacobi with the boundary closure on, element by
+    element against the oracle; the closure changes the boundary cells."""
+    import paper_2011_13926_amd as P
+    _say("kernel parity, boundary closure", n, bc, src, lz)
+    p = _problem(n, bc, src, "wb", lz)
+    p["wb_boundary"] = True
+    sch = O.Scheme.from_problem(p)
+    U = O.state_from_problem(p, "U")
+    Un = O.state_from_problem(p, "n")
+    lin = O.linearize(sch, p["sigma"], p.get("rho_cv"), U, Un, p["dt"])
+    x = W.random_vector(U.size, 3).reshape(U.shape)
+    s = P.Solver(p, U_lin=U, U_n=Un, dt=p["dt"])
+    try:
+        R_gpu = s.residual().cpu().numpy()
+        y_gpu = s.apply_operator(x).cpu().numpy()
+        z_gpu = s.precondition(x).cpu().numpy()
+    finally:
+        s.close()
+    R_ref = O.residual(lin)
+    y_ref = O.apply_operator(lin, x)
+    z_ref = O.BlockJacobi(lin)(x)
+    assert _rel(R_gpu, R_ref) <= 1e-13 and _maxabs_by_component(R_gpu, R_ref) <= 1e-13
+    assert _rel(y_gpu, y_ref) <= 1e-13 and _maxabs_by_component(y_gpu, y_ref) <= 1e-13
+    assert _rel(z_gpu, z_ref) <= 1e-12 and _maxabs_by_component(z_gpu, z_ref) <= 1e-12
+    p["wb_boundary"] = False
+    lin0 = O.linearize(O.Scheme.from_problem(p), p["sigma"], p.get("rho_cv"), U, Un, p["dt"])
+    assert _rel(R_ref, O.residual(lin0)) > 1e-8
+
+
+@pytest.mark.parametrize("pc", ["bj", "mg"])
+@pytest.mark.parametrize("n,bc,src", [((40, 33), BC2["mixed"], "none"), ((12, 10, 9), BC3["open"], "coupled_t")])
+def test_step_fixed_iterations_boundary_closure(n, bc, src, pc):
+    """Fixed-iteration implicit step with the boundary closure (block-Jacobi and multigrid)."""
+    import paper_2011_13926_amd as P
+    _say("fixed-iteration step, boundary closure", n, bc, src, pc)
+    p = _problem(n, bc, src, "wb", "newton", seed=11, dt=2.0, fmax=0.6)
+    p["wb_boundary"] = True
+    sch = O.Scheme.from_problem(p)
+    Un = O.state_from_problem(p, "n")
+    mg_opts = dict(nmin=8 if len(n) == 2 else 4)
+    ref = O.implicit_step(sch, p["sigma"], p.get("rho_cv"), Un, p["dt"], restart=30, newton_max=2, fixed_iters=15,
+                          pc=pc, mg_opts=mg_opts)
+    s = P.Solver(p, restart=30, newton_max=2, fixed_iters=15, pc=pc)
+    try:
+        U = s.to_device(Un)
+        st, stats = s.implicit_step(U)
+        got = U.cpu().numpy()
+        for c in range(got.shape[0]):
+            assert _rel(got[c] - Un[c], ref.U[c] - Un[c]) <= 1e-10, c
+    finally:
+        s.close()
+
+
+def test_boundary_closure_rejected_where_not_implemented():
+    import paper_2011_13926_amd as P
+    p = _problem((16, 12), BC2["mixed"], "none", "wb", "newton")
+    p["wb_boundary"] = True
+    s = P.Solver(p)
+    try:
+        U = s.to_device(O.state_from_problem(p, "n"))
+        st, _ = s.explicit_step(U, dt=0.2, raise_on_fail=False)
+        assert st == P.M1_ERR_INVALID_ARG
+    finally:
+        s.close()
+    q = _problem((16, 12), BC2["mixed"], "none", "centered", "newton")
+    q["wb_boundary"] = True
+    with pytest.raises(P.M1Error):
+        P.Solver(q)
