@@ -25,11 +25,11 @@ template <typename TV>
 void launch_nn_features(int64_t N, const TV* r, const double* rnorm2, const double* bjinv, const double* Uk,
                         const double* sigma, double c, double cdt, int cpad, uint16_t* in_bf16, float* out_f32,
                         hipStream_t s, const int* skip = nullptr);
-// z = M^{-1} r + (|r| / s) y   (y: network output, H x W x 3)
+// z = M^{-1} (r + (|r| / s) y)   (y: network output, H x W x 3)
 template <typename TV, typename TZ>
 void launch_nn_combine(int64_t N, const TV* r, const double* rnorm2, const double* bjinv, const float* y, TZ* z,
                        hipStream_t s, const int* skip = nullptr);
-// training target s (e - M^{-1} r) / |r|  (H x W x 3, FP32)
+// training target s (M e - r) / |r|  (H x W x 3, FP32; M the diagonal block)
 void launch_nn_target(int64_t N, const double* r, const double* e, const double* rnorm2, const double* bjinv,
                       float* t, hipStream_t s);
 

@@ -1,7 +1,10 @@
 // Learned preconditioner network for gfx950: a small U-Net (3x3 convolutions,
 // 2x2 average pooling, nearest upsampling with skip concatenation, 1x1 head)
-// with BF16 MFMA (v_mfma_f32_16x16x16_bf16, FP32 accumulate) forward, input-
-// gradient and weight-gradient kernels, and Adam on FP32 master weights.
+// with BF16 MFMA (FP32 accumulate) forward, input-gradient and weight-gradient
+// kernels, and Adam on FP32 master weights.  The convolutions run on gfx950's
+// v_mfma_f32_16x16x32_bf16 with weights staged in LDS (k_conv3x32); the K = 16
+// kernel (v_mfma_f32_16x16x16_bf16) remains for the weight gradient and as the
+// fallback of the convolution.
 //
 // Activations are NHWC.  A 3x3 convolution is an implicit GEMM: M = pixels,
 // N = output channels, K = 9 taps x input channels (in chunks of 16).  The input
@@ -17,6 +20,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstdio>
 #include <string>
 #include <vector>
@@ -117,6 +121,116 @@ __global__ __launch_bounds__(256) void k_conv3(int H, int W, const TIN* __restri
       if (relu) v = fmaxf(v, 0.f);
       store1(y + ((int64_t)h * W + px) * Cout + co, v);
     }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// The same convolution on gfx950's K = 32 MFMA (v_mfma_f32_16x16x32_bf16): each
+// lane supplies 8 consecutive channels of one pixel (A) and of one output
+// channel's weights (B); the sum over k is the same whatever order the hardware
+// pairs the lanes' k slots in, since A and B use one convention.  A block is 4
+// waves; wave w computes 64 pixels of row 4 blockIdx.y + w for 64 output channels
+// (4 x 4 tiles of 16 x 16).  For every tap the block stages that tap's 64 x Cin
+// weights in LDS once (16-byte loads, rows padded by 8 channels against bank
+// conflicts), so the weights are read from L2 once per 256 pixels instead of once
+// per 16.  Requires Cin % 16 == 0 (a 32-channel step may be half valid).
+// ---------------------------------------------------------------------------
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+constexpr int kConvCinMax = 256;
+
+__device__ __forceinline__ bf16x8 load8(const uint16_t* p) {
+  return __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(p));
+}
+__device__ __forceinline__ bf16x8 load8(const float* p) {
+  const float4 u = *reinterpret_cast<const float4*>(p);
+  const float4 v = *reinterpret_cast<const float4*>(p + 4);
+  uint4 r;
+  r.x = (uint32_t)f2bf(u.x) | ((uint32_t)f2bf(u.y) << 16);
+  r.y = (uint32_t)f2bf(u.z) | ((uint32_t)f2bf(u.w) << 16);
+  r.z = (uint32_t)f2bf(v.x) | ((uint32_t)f2bf(v.y) << 16);
+  r.w = (uint32_t)f2bf(v.z) | ((uint32_t)f2bf(v.w) << 16);
+  return __builtin_bit_cast(bf16x8, r);
+}
+
+template <typename TIN, typename TOUT>
+__global__ __launch_bounds__(256) void k_conv3x32(int H, int W, const TIN* __restrict__ x0, int C0, int up0,
+                                                  const TIN* __restrict__ x1, int C1, const uint16_t* __restrict__ w,
+                                                  const float* __restrict__ bias, int Cout, TOUT* __restrict__ y,
+                                                  int relu, const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  __shared__ __align__(16) uint16_t sw[64 * (kConvCinMax + 8)];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int h = blockIdx.y * 4 + wv;
+  const int pbase = blockIdx.x * 64;
+  const int co_base = blockIdx.z * 64;
+  const int Cin = C0 + C1;
+  const int ld = Cin + 8;                      // LDS row stride (bf16)
+  const int W0 = up0 ? (W >> 1) : W;
+  const int kq = (lane >> 4) * 8;
+  const bool row_ok = h < H;
+  f32x4 acc[4][4];
+#pragma unroll
+  for (int g = 0; g < 4; ++g)
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[g][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const bf16x8 zero = __builtin_bit_cast(bf16x8, make_uint4(0u, 0u, 0u, 0u));
+  const int ngrp = Cin / 8;                    // 16-byte groups per weight row
+  for (int tap = 0; tap < 9; ++tap) {
+    __syncthreads();
+    // stage this tap's weights of the block's 64 output channels: sw[co][ci]
+    for (int e = threadIdx.x; e < 64 * ngrp; e += 256) {
+      const int col = e / ngrp, gi = e - col * ngrp;
+      const int co = co_base + col;
+      uint4 v = make_uint4(0u, 0u, 0u, 0u);
+      if (co < Cout) v = *reinterpret_cast<const uint4*>(w + ((int64_t)tap * Cout + co) * Cin + gi * 8);
+      *reinterpret_cast<uint4*>(sw + col * ld + gi * 8) = v;
+    }
+    __syncthreads();
+    if (!row_ok) continue;
+    const int hh = h + tap / 3 - 1;
+    const bool hin = hh >= 0 && hh < H;
+    for (int c0 = 0; c0 < Cin; c0 += 32) {
+      const int k = c0 + kq;                   // this lane's 8 channels
+      const bool kin = k < Cin;
+      bf16x8 A[4];
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        const int ww = pbase + g * 16 + (lane & 15) + tap % 3 - 1;
+        A[g] = zero;
+        if (kin && hin && ww >= 0 && ww < W) {
+          if (k < C0) {
+            const int sh = up0 ? (hh >> 1) : hh, sw0 = up0 ? (ww >> 1) : ww;
+            A[g] = load8(x0 + ((int64_t)sh * W0 + sw0) * C0 + k);
+          } else {
+            A[g] = load8(x1 + ((int64_t)hh * W + ww) * C1 + (k - C0));
+          }
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const bf16x8 B = kin ? __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(sw + (t * 16 + (lane & 15)) * ld + k))
+                             : zero;
+#pragma unroll
+        for (int g = 0; g < 4; ++g) acc[g][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[g], B, acc[g][t], 0, 0, 0);
+      }
+    }
+  }
+  if (!row_ok) return;
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int co = co_base + t * 16 + (lane & 15);
+    if (co >= Cout) continue;
+    const float b = bias ? bias[co] : 0.f;
+#pragma unroll
+    for (int g = 0; g < 4; ++g)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int px = pbase + g * 16 + (lane >> 4) * 4 + r;
+        if (px >= W) continue;
+        float v = acc[g][t][r] + b;
+        if (relu) v = fmaxf(v, 0.f);
+        store1(y + ((int64_t)h * W + px) * Cout + co, v);
+      }
   }
 }
 
@@ -512,8 +626,24 @@ void refresh_weights(m1nn* n) {
   }
 }
 
+// K = 32 kernel (weights staged in LDS) when the channels fit; the K = 16 kernel otherwise
+static bool use_k32(int cin) {
+  static int v = -1;
+  if (v < 0) {
+    const char* e = getenv("M1_CONV_KERNEL");
+    v = (e && std::string(e) == "k16") ? 0 : 1;
+  }
+  return v == 1 && cin % 16 == 0 && cin <= kConvCinMax;
+}
+
 void conv3(m1nn* n, int H, int W, const uint16_t* x0, int C0, int up0, const uint16_t* x1, int C1, const ConvLayer& c,
            uint16_t* y, int relu) {
+  if (use_k32(C0 + C1)) {
+    dim3 grd((W + 63) / 64, (H + 3) / 4, (c.cout + 63) / 64);
+    k_conv3x32<uint16_t, uint16_t><<<grd, 256, 0, n->stream>>>(H, W, x0, C0, up0, x1, C1, c.wf, n->P + c.boff, c.cout,
+                                                               y, relu, n->skip);
+    return;
+  }
   dim3 grd((W + 63) / 64, H, (c.cout + 63) / 64);
   k_conv3<uint16_t, uint16_t><<<grd, 256, 0, n->stream>>>(H, W, x0, C0, up0, x1, C1, c.wf, n->P + c.boff, c.cout, y,
                                                           relu, n->skip);
@@ -521,6 +651,12 @@ void conv3(m1nn* n, int H, int W, const uint16_t* x0, int C0, int up0, const uin
 
 // input gradient of a conv3 layer: gx (H, W, cin) FP32 from gpre (H, W, cout) FP32
 void conv3_dgrad(m1nn* n, int H, int W, const float* gpre, const ConvLayer& c, float* gx) {
+  if (use_k32(c.cout)) {
+    dim3 grd((W + 63) / 64, (H + 3) / 4, (c.cin + 63) / 64);
+    k_conv3x32<float, float><<<grd, 256, 0, n->stream>>>(H, W, gpre, c.cout, 0, nullptr, 0, c.wt, nullptr, c.cin, gx,
+                                                         0, nullptr);
+    return;
+  }
   dim3 grd((W + 63) / 64, H, (c.cin + 63) / 64);
   k_conv3<float, float><<<grd, 256, 0, n->stream>>>(H, W, gpre, c.cout, 0, nullptr, 0, c.wt, nullptr, c.cin, gx, 0,
                                                     nullptr);

@@ -1,9 +1,10 @@
 """What the trained network gains over block-Jacobi alone.
 
-Loads the committed weights (trained on the Voronoi 512^2 workload by
-paper_2011_13926_amd/train_nn.py on solver-generated residual/error pairs) and
-solves the first Newton system of held-out seeds to 1e-8 with flexible GMRES +
-learned preconditioner and with block-Jacobi GMRES.  Both must converge (the
+Loads the committed weights (trained on the diffusive lognormal 256^2 workload
+by paper_2011_13926_amd/train_nn.py on solver-generated residual/error pairs;
+no Voronoi weights are committed, so those cases skip) and solves the first
+Newton system of held-out seeds to 1e-8 with flexible GMRES + learned
+preconditioner and with block-Jacobi GMRES.  Both must converge (the
 fallback keeps the learned solve safe); the iteration and time ratios are
 printed and recorded, and the learned solution must agree with the
 block-Jacobi one to the tolerance."""
@@ -66,12 +67,15 @@ DIFF_WEIGHTS = os.path.join(os.path.dirname(HERE), "paper_2011_13926_amd", "weig
 
 
 @pytest.mark.skipif(not os.path.exists(DIFF_WEIGHTS), reason="no trained weights committed")
-@pytest.mark.parametrize("seed", [1000, 1002])
+@pytest.mark.parametrize("seed", [1000, 1001, 1002, 1003])
 def test_learned_preconditioner_on_heldout_diffusive_field(seed):
     """Weights trained by train_nn.py --workload diffusive --n 256 (seeds 0-7, 3 000 steps,
-    lr 3e-4).  On held-out fields the flexible solve converges without falling back,
-    takes at most 1.25x the block-Jacobi iterations (the network is applied to each
-    cycle's restart residual), and meets the same true-residual tolerance."""
+    lr 3e-4; the initial draw by m1nn_init_params, no oracle involved).  On the held-out
+    fields 1000-1003 the flexible solve converges without falling back, needs fewer GMRES
+    iterations than block-Jacobi (the network is applied to each cycle's restart
+    residual; measured 190/195/152/196 against 203/229/194/229), and meets the same
+    true-residual tolerance.  (It is not faster: a 256^2 forward pass costs about as much
+    as the iterations it saves.)"""
     import torch
     import paper_2011_13926_amd as P
     p = W.diffusive_lognormal(n=(256, 256), seed=seed)
@@ -88,7 +92,7 @@ def test_learned_preconditioner_on_heldout_diffusive_field(seed):
         _say(f"seed {seed}: block-Jacobi {sb['krylov_iters']} it, learned {sl['krylov_iters']} it "
              f"(ratio {sb['krylov_iters'] / max(sl['krylov_iters'], 1):.2f}), fell_back={sl['fell_back']}")
         assert stb == P.M1_OK and stl == P.M1_OK and sl["fell_back"] == 0
-        assert sl["krylov_iters"] <= 1.25 * sb["krylov_iters"]
+        assert sl["krylov_iters"] < sb["krylov_iters"]
         # both solves promise ||b - A x|| <= 1e-8 ||b||; the solutions then agree to
         # about the condition number times that
         res = float(torch.linalg.vector_norm(b - s_bj.apply_operator(xl)) / torch.linalg.vector_norm(b))
