@@ -52,3 +52,14 @@ def test_ionization_front_velocity_is_solenoidal_and_subrelativistic():
         return 0.5 * (np.roll(f, -1, ax) - np.roll(f, 1, ax))
     div = dd(v[0], 2) + dd(v[1], 1) + dd(v[2], 0)
     assert np.abs(div).max() <= 1e-12 * np.abs(v).max()
+
+
+def test_window_copies_fields_and_settings():
+    p = W.voronoi_opacity(n=(64, 48), nsites=5, seed=3)
+    q = W.window(p, (10, 7), (20, 12), ("periodic",) * 4)
+    assert q["n"] == (20, 12) and q["sigma"].shape == (12, 20) and q["F"].shape == (2, 12, 20)
+    assert np.array_equal(q["sigma"], p["sigma"][7:19, 10:30])
+    assert np.array_equal(q["E"], p["E"][7:19, 10:30])
+    assert q["dt"] == p["dt"] and q["flux_source"] == p["flux_source"] and q["bc"][:4] == ["periodic"] * 4
+    q["E"][0, 0] = -1.0
+    assert p["E"][7, 10] != -1.0

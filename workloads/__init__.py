@@ -486,6 +486,29 @@ def ionization_front(n=(192, 192, 192), seed=192, dt=100.0, sigma0=1e-2,
     return p
 
 
+def window(p, origin, size, bc):
+    """A rectangular window of a 2D problem's fields as a problem of its own.
+
+    origin = (i0, j0), size = (nx, ny) in cells; bc: the window's boundary kinds
+    (4 names).  sigma, E and F are copied from the window; the scheme settings
+    and dt are the parent's.  Used for reduced instances of a large workload
+    (the CPU oracle's timing sample); Dirichlet planes of the parent are not
+    carried over.
+    """
+    i0, j0 = origin
+    nx, ny = size
+    q = base_problem((nx, ny), dt=p["dt"], source=p["source"], flux_source=p["flux_source"],
+                     closure=p.get("closure", "m1"), ap=p["ap"], lambda_floor=p["lambda_floor"], bc=list(bc),
+                     dx=p["dx"], c=p["c"], a_r=p["a_r"])
+    sl = (slice(j0, j0 + ny), slice(i0, i0 + nx))
+    q["sigma"] = np.array(p["sigma"][sl], dtype=float)
+    q["E"] = np.array(p["E"][sl], dtype=float)
+    q["F"] = np.array(p["F"][(slice(None),) + sl], dtype=float)
+    q["T"] = None if p.get("T") is None else np.array(p["T"][sl], dtype=float)
+    q["rho_cv"] = None if p.get("rho_cv") is None else np.array(p["rho_cv"][sl], dtype=float)
+    return q
+
+
 WORKLOADS = {
     "diffusive_gaussian_64": lambda: diffusive_gaussian(),
     "beam_shadow_1024": lambda: beam_shadow(),
