@@ -63,7 +63,7 @@ CLASS_KERNEL = {
     "time_step": ("k_step2d_lds<", "k_step_direct<"),
     "mg_fine": ("k_mg_fine_smooth<", "k_mg_restrict_fine<", "k_mg_prolong_fine<", "k_mg_cast<"),
     "mg_smooth": ("k_mg_smooth<", "k_mg_prolong<"),
-    "mg_down": ("k_mg_down<",),
+    "mg_down": ("k_mg_down_lanes<",),
     "mg_coarse_solve": ("k_mg_coarse_solve<",),
     "mg_setup": ("k_mg_galerkin<", "k_mg_invert<", "k_mg_dense_inverse<", "k_setup_bj<2, false, true",
                  "k_setup_bj<2, true, true", "k_setup_bj<3, false, true", "k_setup_bj<3, true, true"),
