@@ -61,7 +61,7 @@ CLASS_KERNEL = {
     "true_residual": ("k_apply2d_lds<false, 1", "k_apply2d_lds<true, 1", "k_stencil<2, false, 1",
                       "k_stencil<2, true, 1", "k_stencil<3, false, 1", "k_stencil<3, true, 1"),
     "time_step": ("k_step2d_lds<", "k_step_direct<"),
-    "mg_fine": ("k_mg_fine_smooth<", "k_mg_restrict_fine<", "k_mg_prolong_fine<", "k_mg_cast<"),
+    "mg_fine": ("k_mg_fine_smooth<", "k_mg_restrict_fine<", "k_mg_prolong_fine<", "k_mg_cast<", "k_mg_sweep2d<"),
     "mg_smooth": ("k_mg_smooth<", "k_mg_prolong<"),
     "mg_down": ("k_mg_down_lanes<",),
     "mg_coarse_solve": ("k_mg_coarse_solve<",),
@@ -680,7 +680,10 @@ def main():
     pick = max(mixed, key=lambda k: mixed[k]["cell_updates_per_s"]) if mixed else None
     head = results[pick] if pick else None
     base = results.get("fp64_bj")
-    roof, roof_apply = roofline(head["kernels"] if head else {}, workload)
+    # kernel rooflines: of the headline variant, else (no variant converged) of the first one run
+    rname = pick or next(iter(results), None)
+    rsrc = results[rname] if rname else None
+    roof, roof_apply = roofline(rsrc["kernels"] if rsrc else {}, workload)
     out = {
         "metric": METRIC,
         "value": head["cell_updates_per_s"] if head else None,
@@ -705,7 +708,8 @@ def main():
         "variants": {k: {kk: vv for kk, vv in v.items() if kk not in ("kernels", "U")} for k, v in results.items()},
         "roofline": roof,
         "roofline_apply": roof_apply,
-        "kernels": head["kernels"] if head else None,
+        "roofline_variant": rname,
+        "kernels": rsrc["kernels"] if rsrc else None,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, U0, results, workload)

@@ -11,6 +11,7 @@
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/m1.h"
@@ -398,6 +399,7 @@ void fill_geom(const m1_config& cfg, Geom& g) {
   g.plane_n[0] = g.n[1] * g.n[2];
   g.plane_n[1] = g.n[0] * g.n[2];
   g.plane_n[2] = g.n[0] * g.n[1];
+  g.order3d = 0;
 }
 
 // scheme constants of a validated configuration (dt-derived ones left to set_dt)
@@ -484,13 +486,28 @@ void mg_fine_apply(const void* self, const R* x, R* y, hipStream_t s, const int*
   launch_apply<R, R, R>(c->nd, c->cpl, 0, c->g, c->sc, coefs_of<R>(c), bdry(c), x, nullptr, y, s, skip);
 }
 
+template <typename R>
+bool mg_fine_sweep(const void* self, int op, int xin, const void* r, int r_fp64, const R* zin, const R* zc, R omega,
+                   R* out, const R* dinv1, int sm, R* b1, R* z1, hipStream_t s, const int* skip) {
+  const m1_ctx* c = (const m1_ctx*)self;
+  if (r_fp64)
+    return launch_mg_sweep2d<R, double>(c->nd, c->cpl, op, xin, c->g, c->sc, coefs_of<R>(c), bdry(c),
+                                        (const double*)r, zin, zc, omega, out, dinv1, sm, b1, z1, s, skip);
+  if constexpr (std::is_same<R, float>::value)
+    return launch_mg_sweep2d<float, float>(c->nd, c->cpl, op, xin, c->g, c->sc, coefs_of<float>(c), bdry(c),
+                                           (const float*)r, zin, zc, omega, out, dinv1, sm, b1, z1, s, skip);
+  return false;
+}
+
 template <typename R> MgFine<R> mg_fine(const m1_ctx* c) {
   MgFine<R> f;
   f.nd = c->nd;
   f.nu = c->nu;
   f.apply_bytes = bytes_apply(c, sizeof(R), sizeof(R), sizeof(R), false);
+  f.coef_bytes = bytes_apply(c, sizeof(R), 0, 0, false);
   f.bjinv = coefs_of<R>(c).bjinv;
   f.apply = &mg_fine_apply<R>;
+  f.sweep = fused_apply_available(c->nd) ? &mg_fine_sweep<R> : nullptr;
   f.self = c;
   return f;
 }

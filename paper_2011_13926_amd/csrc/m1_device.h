@@ -39,6 +39,7 @@ struct Geom {
   int64_t stride[3]; // 1, nx, nx*ny
   int bc[6];
   int plane_n[3];    // number of cells on a plane normal to d
+  int order3d;       // launch order of the cell kernels in 3D (set by the launchers; 0 rows, 1 pencils)
 };
 
 // Scheme constants and per-step scalars (passed by value).

@@ -94,8 +94,13 @@ struct MgHierarchy {
 template <typename R> struct MgFine {
   int nd = 2, nu = 3;
   double apply_bytes = 0.0;   // algorithmic bytes of one finest-level apply
+  double coef_bytes = 0.0;    // of which the operator's coefficients (no vectors)
   const R* bjinv = nullptr;
   void (*apply)(const void* self, const R* x, R* y, hipStream_t s, const int* skip) = nullptr;
+  // fused sweep / restricted residual on the staged operator (launch_mg_sweep2d; r of
+  // FP64 or FP32 type as r_fp64 says); null where not available (3D, direct apply)
+  bool (*sweep)(const void* self, int op, int xin, const void* r, int r_fp64, const R* zin, const R* zc, R omega,
+                R* out, const R* dinv1, int sm, R* b1, R* z1, hipStream_t s, const int* skip) = nullptr;
   const void* self = nullptr;
   void operator()(const R* x, R* y, hipStream_t s, const int* skip) const { apply(self, x, y, s, skip); }
 };
@@ -129,6 +134,14 @@ template <typename R, typename VI, typename VO>
 void launch_apply(int nd, bool cpl, int mode, const Geom& g, const Scheme& sc, const Coefs<R>& cf, const Bdry& bd,
                   const VI* x, const double* b, VO* y, hipStream_t s, const int* skip = nullptr);
 bool fused_apply_available(int nd);
+// multigrid finest level in 2D (LDS-staged operator): op 0 out = x + omega M^{-1} (r - A x),
+// op 1 b1 = P^T (r - A x) and z1 = omega D1^{-1} b1 (0 unless sm); the input x is zin
+// (xin 0), zin + P zc (xin 1; zin may be null) or omega M^{-1} r (xin 2).  False when
+// not available.
+template <typename R, typename TIN>
+bool launch_mg_sweep2d(int nd, bool cpl, int op, int xin, const Geom& g, const Scheme& sc, const Coefs<R>& cf,
+                       const Bdry& bd, const TIN* r, const R* zin, const R* zc, R omega, R* out, const R* dinv1, int sm,
+                       R* b1, R* z1, hipStream_t s, const int* skip);
 template <typename R, typename VI, typename VO>
 bool launch_apply_pre(int nd, bool cpl, const Geom& g, const Scheme& sc, const Coefs<R>& cf, const Bdry& bd,
                       const VI* u, VO* y, hipStream_t s, const int* skip);

@@ -3,8 +3,16 @@
 // evaluates the residual R(U) or applies the linearised operator A.
 //
 // Thread mapping of the stencil kernels: a 64 x 4 block covers 64 consecutive x
-// cells (one wavefront per grid row, coalesced SoA loads) on 4 rows; blockIdx.y
-// walks rows (j + ny*k).
+// cells (one wavefront per grid row, coalesced SoA loads) on 4 rows.  In 2D
+// blockIdx.y walks rows.  In 3D the blocks are launched 1D in "pencil" order:
+// workgroups go to the 8 XCDs round-robin by launch index and each XCD has its
+// own L2, so launch index L takes work item (L % 8) * per + L / 8 (per = items / 8,
+// rounded up) and every XCD owns a contiguous run of items; an item is one
+// 64 x 4 x 1 tile, ordered z-fastest within chunks of kChunkZ planes, then x-tile,
+// then y-tile, then z-chunk.  A cell's data is then read by its z-neighbours'
+// blocks (the adjacent items) and its y-neighbours' blocks (a few dozen items
+// away) while it is still in the XCD's L2; in row order a z-neighbour plane lies
+// a whole plane (8 MB of Jacobians at 192^2) away.
 #include <algorithm>
 #include <cstdlib>
 #include <string>
@@ -15,13 +23,39 @@ namespace m1 {
 
 constexpr int TX = 64;
 constexpr int TY = 4;
+constexpr int kChunkZ = 16;
 
 struct CellPos {
   int idx[3];
   int64_t cell;
 };
 
+__host__ __device__ inline int pencil_items(const Geom& g) {
+  return ((g.n[0] + TX - 1) / TX) * ((g.n[1] + TY - 1) / TY) * kChunkZ * ((g.n[2] + kChunkZ - 1) / kChunkZ);
+}
+
 __device__ __forceinline__ bool cell_pos(const Geom& g, CellPos& p) {
+  if (g.order3d) {
+    const int items = pencil_items(g);
+    const int per = (items + 7) / 8;
+    const int L = blockIdx.x;
+    const int item = (L % 8) * per + L / 8;
+    if (item >= items) return false;
+    const int gx = (g.n[0] + TX - 1) / TX, gy = (g.n[1] + TY - 1) / TY;
+    const int zl = item % kChunkZ;
+    int r = item / kChunkZ;
+    const int xt = r % gx;
+    r /= gx;
+    const int yt = r % gy;
+    const int zc = r / gy;
+    const int i = xt * TX + threadIdx.x, j = yt * TY + threadIdx.y, k = zc * kChunkZ + zl;
+    if (i >= g.n[0] || j >= g.n[1] || k >= g.n[2]) return false;
+    p.idx[0] = i;
+    p.idx[1] = j;
+    p.idx[2] = k;
+    p.cell = ((int64_t)k * g.n[1] + j) * g.n[0] + i;
+    return true;
+  }
   const int i = blockIdx.x * TX + threadIdx.x;
   const int row = blockIdx.y * TY + threadIdx.y;
   if (i >= g.n[0] || row >= g.rows) return false;
@@ -30,6 +64,27 @@ __device__ __forceinline__ bool cell_pos(const Geom& g, CellPos& p) {
   p.idx[2] = row / g.n[1];
   p.cell = (int64_t)row * g.n[0] + i;
   return true;
+}
+
+// Launch shape of the cell kernels (64 x 4 blocks): rows in 2D, XCD pencils in 3D
+// (M1_ORDER3D=rows keeps the row order in 3D).
+static int g_order3d = -1;
+struct CellLaunch {
+  Geom g;
+  dim3 grd, blk;
+};
+static CellLaunch cell_launch(const Geom& g0) {
+  if (g_order3d < 0) {
+    const char* e = getenv("M1_ORDER3D");
+    g_order3d = (e && std::string(e) == "rows") ? 0 : 1;
+  }
+  CellLaunch L;
+  L.g = g0;
+  L.blk = dim3(TX, TY);
+  L.g.order3d = (g0.n[2] > 1 && g_order3d == 1) ? 1 : 0;
+  if (L.g.order3d) L.grd = dim3(8 * ((pencil_items(g0) + 7) / 8));
+  else L.grd = dim3((g0.n[0] + TX - 1) / TX, (g0.rows + TY - 1) / TY);
+  return L;
 }
 
 // Neighbour along direction d on side (0 = lower, 1 = upper).
@@ -72,9 +127,9 @@ __global__ __launch_bounds__(256) void k_fn(Geom g, Scheme sc, const double* __r
 }
 
 void launch_fn(int nd, const Geom& g, const Scheme& sc, const double* Un, double* fn, hipStream_t s) {
-  dim3 blk(TX, TY), grd((g.n[0] + TX - 1) / TX, (g.rows + TY - 1) / TY);
-  if (nd == 2) k_fn<2><<<grd, blk, 0, s>>>(g, sc, Un, fn);
-  else k_fn<3><<<grd, blk, 0, s>>>(g, sc, Un, fn);
+  const CellLaunch L = cell_launch(g);
+  if (nd == 2) k_fn<2><<<L.grd, L.blk, 0, s>>>(L.g, sc, Un, fn);
+  else k_fn<3><<<L.grd, L.blk, 0, s>>>(L.g, sc, Un, fn);
 }
 
 // ----------------------------------------------------------------------------
@@ -170,13 +225,13 @@ __global__ __launch_bounds__(256) void k_setup(Geom g, Scheme sc, Coefs<double> 
 
 void launch_setup(int nd, bool cpl, const Geom& g, const Scheme& sc, const Coefs<double>& cf, const Bdry& bd,
                   const double* Uk, const double* Un, const double* fn, hipStream_t s) {
-  dim3 blk(TX, TY), grd((g.n[0] + TX - 1) / TX, (g.rows + TY - 1) / TY);
+  const CellLaunch L = cell_launch(g);
   if (nd == 2) {
-    if (cpl) k_setup<2, true><<<grd, blk, 0, s>>>(g, sc, cf, bd, Uk, Un, fn);
-    else k_setup<2, false><<<grd, blk, 0, s>>>(g, sc, cf, bd, Uk, Un, fn);
+    if (cpl) k_setup<2, true><<<L.grd, L.blk, 0, s>>>(L.g, sc, cf, bd, Uk, Un, fn);
+    else k_setup<2, false><<<L.grd, L.blk, 0, s>>>(L.g, sc, cf, bd, Uk, Un, fn);
   } else {
-    if (cpl) k_setup<3, true><<<grd, blk, 0, s>>>(g, sc, cf, bd, Uk, Un, fn);
-    else k_setup<3, false><<<grd, blk, 0, s>>>(g, sc, cf, bd, Uk, Un, fn);
+    if (cpl) k_setup<3, true><<<L.grd, L.blk, 0, s>>>(L.g, sc, cf, bd, Uk, Un, fn);
+    else k_setup<3, false><<<L.grd, L.blk, 0, s>>>(L.g, sc, cf, bd, Uk, Un, fn);
   }
 }
 
@@ -402,25 +457,25 @@ __global__ __launch_bounds__(256) void k_setup_bj(Geom g, Scheme sc, Coefs<doubl
 
 void launch_setup_bj(int nd, bool cpl, const Geom& g, const Scheme& sc, const Coefs<double>& cf, const Bdry& bd,
                      hipStream_t s) {
-  dim3 blk(TX, TY), grd((g.n[0] + TX - 1) / TX, (g.rows + TY - 1) / TY);
+  const CellLaunch L = cell_launch(g);
   if (nd == 2) {
-    if (cpl) k_setup_bj<2, true, false><<<grd, blk, 0, s>>>(g, sc, cf, bd, nullptr);
-    else k_setup_bj<2, false, false><<<grd, blk, 0, s>>>(g, sc, cf, bd, nullptr);
+    if (cpl) k_setup_bj<2, true, false><<<L.grd, L.blk, 0, s>>>(L.g, sc, cf, bd, nullptr);
+    else k_setup_bj<2, false, false><<<L.grd, L.blk, 0, s>>>(L.g, sc, cf, bd, nullptr);
   } else {
-    if (cpl) k_setup_bj<3, true, false><<<grd, blk, 0, s>>>(g, sc, cf, bd, nullptr);
-    else k_setup_bj<3, false, false><<<grd, blk, 0, s>>>(g, sc, cf, bd, nullptr);
+    if (cpl) k_setup_bj<3, true, false><<<L.grd, L.blk, 0, s>>>(L.g, sc, cf, bd, nullptr);
+    else k_setup_bj<3, false, false><<<L.grd, L.blk, 0, s>>>(L.g, sc, cf, bd, nullptr);
   }
 }
 
 void launch_fine_stencil(int nd, bool cpl, const Geom& g, const Scheme& sc, const Coefs<double>& cf, const Bdry& bd,
                          double* S, hipStream_t s) {
-  dim3 blk(TX, TY), grd((g.n[0] + TX - 1) / TX, (g.rows + TY - 1) / TY);
+  const CellLaunch L = cell_launch(g);
   if (nd == 2) {
-    if (cpl) k_setup_bj<2, true, true><<<grd, blk, 0, s>>>(g, sc, cf, bd, S);
-    else k_setup_bj<2, false, true><<<grd, blk, 0, s>>>(g, sc, cf, bd, S);
+    if (cpl) k_setup_bj<2, true, true><<<L.grd, L.blk, 0, s>>>(L.g, sc, cf, bd, S);
+    else k_setup_bj<2, false, true><<<L.grd, L.blk, 0, s>>>(L.g, sc, cf, bd, S);
   } else {
-    if (cpl) k_setup_bj<3, true, true><<<grd, blk, 0, s>>>(g, sc, cf, bd, S);
-    else k_setup_bj<3, false, true><<<grd, blk, 0, s>>>(g, sc, cf, bd, S);
+    if (cpl) k_setup_bj<3, true, true><<<L.grd, L.blk, 0, s>>>(L.g, sc, cf, bd, S);
+    else k_setup_bj<3, false, true><<<L.grd, L.blk, 0, s>>>(L.g, sc, cf, bd, S);
   }
 }
 
@@ -627,24 +682,16 @@ __device__ __forceinline__ bool xcd_tile(int nx, int ny, int& tbx, int& tby) {
   return true;
 }
 
-// PRE = true: the input is u and the operator is applied to z = M^{-1} u, the
-// block-Jacobi solve done per staged cell (fused right preconditioning).
-template <bool CPL, int MODE, bool PRE, typename R, typename VI, typename VO>
-__global__ __launch_bounds__(kApply2dThreads) void k_apply2d_lds(Geom g, Scheme sc, Coefs<R> cf, Bdry bd, const VI* __restrict__ x,
-                                                     const double* __restrict__ b, VO* __restrict__ y,
-                                                     const int* __restrict__ skip) {
+// Stage the (LX + 2) x (LY + 2) halo tile whose corner is grid cell (i0, j0): the
+// input x of every cell, from xf(cell, i, j, xv) for grid cells (a ghost takes its
+// boundary cell's value times the ghost weights; the four corners are never read),
+// q = J x for the pressure pairs (xx, xy, yy), and sigma.
+template <typename R, typename XF>
+__device__ __forceinline__ void stage2d(const Geom& g, const Coefs<R>& cf, const Bdry& bd, int i0, int j0, XF&& xf,
+                                        R (&sx)[3][LHY][LHX], R (&sq)[3][LHY][LHX], R (&ss)[LHY][LHX]) {
   constexpr int NR = 3;
-  constexpr int NU = NR + (CPL ? 1 : 0);
-  if (skip && *skip) return;
-  __shared__ R sx[NR][LHY][LHX];
-  __shared__ R sq[3][LHY][LHX];
-  __shared__ R ss[LHY][LHX];
   const int64_t N = g.N;
   const int nx = g.n[0], ny = g.n[1];
-  int tbx, tby;
-  if (!xcd_tile(nx, ny, tbx, tby)) return;
-  const int i0 = tbx * LX - 1, j0 = tby * LY - 1;
-  // ---- stage the halo tile ----
   for (int t = threadIdx.x; t < LHX * LHY; t += kApply2dThreads) {
     const int li = t % LHX, lj = t / LHX;
     int gi = i0 + li, gj = j0 + lj;
@@ -662,21 +709,7 @@ __global__ __launch_bounds__(kApply2dThreads) void k_apply2d_lds(Geom g, Scheme 
         else { face = gj < 0 ? 2 : 3; gj = gj < 0 ? 0 : ny - 1; }
       }
       const int64_t cell = (int64_t)gj * nx + gi;
-      if (PRE) {
-        R uv[NU];
-#pragma unroll
-        for (int c = 0; c < NU; ++c) uv[c] = (R)x[c * N + cell];
-#pragma unroll
-        for (int r = 0; r < NR; ++r) {
-          R acc = (R)0;
-#pragma unroll
-          for (int c = 0; c < NU; ++c) acc += cf.bjinv[(r * NU + c) * N + cell] * uv[c];
-          xv[r] = acc;
-        }
-      } else {
-#pragma unroll
-        for (int c = 0; c < NR; ++c) xv[c] = (R)x[c * N + cell];
-      }
+      xf(cell, gi, gj, xv);
       sv = cf.sigma[cell];
       if (face < 0) {
 #pragma unroll
@@ -706,11 +739,139 @@ __global__ __launch_bounds__(kApply2dThreads) void k_apply2d_lds(Geom g, Scheme 
     for (int pq = 0; pq < 3; ++pq) sq[pq][lj][li] = qv[pq];
     ss[lj][li] = sv;
   }
-  __syncthreads();
-  // ---- fluxes: each thread handles the cells (tx, ty) and (tx, ty + 4) ----
-  const int tx = threadIdx.x % LX;
+}
+
+// ys = (A x) at grid cell (i, j), staged at (li, lj) of the halo tile; xs[NU] is the
+// cell's own input (the radiation part as staged, the temperature from the caller).
+template <bool CPL, typename R>
+__device__ __forceinline__ void apply2d_cell(const Geom& g, const Scheme& sc, const Coefs<R>& cf,
+                                             const R (&sx)[3][LHY][LHX], const R (&sq)[3][LHY][LHX],
+                                             const R (&ss)[LHY][LHX], int li, int lj, int i, int j, int64_t cell,
+                                             const R* xs, R* ys) {
+  constexpr int NR = 3;
+  constexpr int NU = NR + (CPL ? 1 : 0);
+  const int64_t N = g.N;
+  const int nx = g.n[0], ny = g.n[1];
   const R s = (R)sc.s;
   const R cdt = (R)sc.cdt;
+#pragma unroll
+  for (int c = 0; c < NR; ++c) ys[c] = xs[c];
+  if (CPL) ys[NU - 1] = (R)0;
+  const R sig = ss[lj][li];
+#pragma unroll
+  for (int d = 0; d < 2; ++d) {
+    // neighbours in LDS; pressure pair index of (d, m) in 2D: (0,0)=0 (0,1)=1 (1,1)=2
+    const int ri = d == 0 ? li + 1 : li, rj = d == 0 ? lj : lj + 1;
+    const int mi = d == 0 ? li - 1 : li, mj = d == 0 ? lj : lj - 1;
+    R xr[NR], xl[NR], qs[2], qr[2], ql[2];
+#pragma unroll
+    for (int c = 0; c < NR; ++c) { xr[c] = sx[c][rj][ri]; xl[c] = sx[c][mj][mi]; }
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      const int pq = d + m;
+      qs[m] = sq[pq][lj][li];
+      qr[m] = sq[pq][rj][ri];
+      ql[m] = sq[pq][mj][mi];
+    }
+    const R sigR = ss[rj][ri], sigL = ss[mj][mi];
+    const R ap = cf.face[(3 * d + 0) * N + cell];
+    const R ddp = cf.face[(3 * d + 1) * N + cell];
+    const R alp = cf.face[(3 * d + 2) * N + cell];
+    const R bp = (R)1 - ap;
+    R am, ddm, alm;
+    {
+      const int id = d == 0 ? i : j, n = d == 0 ? nx : ny;
+      const int64_t stride = d == 0 ? 1 : nx;
+      if (id > 0) {
+        const int64_t nb = cell - stride;
+        am = cf.face[(3 * d + 0) * N + nb]; ddm = cf.face[(3 * d + 1) * N + nb]; alm = cf.face[(3 * d + 2) * N + nb];
+      } else if (g.bc[2 * d] == BC_PERIODIC) {
+        const int64_t nb = cell + (int64_t)(n - 1) * stride;
+        am = cf.face[(3 * d + 0) * N + nb]; ddm = cf.face[(3 * d + 1) * N + nb]; alm = cf.face[(3 * d + 2) * N + nb];
+      } else {
+        const int64_t pidx = d == 0 ? (int64_t)j : (int64_t)i;
+        const int64_t pn = g.plane_n[d];
+        am = cf.lowface[cf.lowoff[d] + pidx]; ddm = cf.lowface[cf.lowoff[d] + pn + pidx];
+        alm = cf.lowface[cf.lowoff[d] + 2 * pn + pidx];
+      }
+    }
+    const R bm = (R)1 - am;
+    const R FEp = alp * (ap * xs[1 + d] + bp * xr[1 + d] + ddp * (xr[0] - xs[0]));
+    const R FEm = alm * (am * xl[1 + d] + bm * xs[1 + d] + ddm * (xs[0] - xl[0]));
+    ys[0] += s * (FEp - FEm);
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      const R FPp = ap * qs[m] + bp * qr[m] + ddp * (xr[1 + m] - xs[1 + m]);
+      const R FPm = am * ql[m] + bm * qs[m] + ddm * (xs[1 + m] - xl[1 + m]);
+      ys[1 + m] += s * (FPp - FPm);
+    }
+    if (sc.wb) {
+      R hi = (R)0.5 * (sig + sigR) * (xs[1 + d] + xr[1 + d]);
+      R lo = (R)0.5 * (sig + sigL) * (xl[1 + d] + xs[1 + d]);
+      if (sc.wbb) {
+        // boundary closure on faces to a ghost (the halo tile holds the ghost's q)
+        const int id = d == 0 ? i : j, n = d == 0 ? nx : ny;
+        if (id == n - 1 && g.bc[2 * d + 1] != BC_PERIODIC) hi = -(R)2 * (qr[d] - qs[d]) * (R)sc.inv_cdx;
+        if (id == 0 && g.bc[2 * d] != BC_PERIODIC) lo = -(R)2 * (qs[d] - ql[d]) * (R)sc.inv_cdx;
+      }
+      ys[1 + d] += (R)0.25 * cdt * (hi + lo);
+    }
+  }
+  if (!sc.wb) {
+#pragma unroll
+    for (int m = 0; m < 2; ++m) ys[1 + m] += cdt * sig * xs[1 + m];
+  }
+  if (sc.src == SRC_ABS) ys[0] += cdt * sig * xs[0];
+  if (CPL) {
+    const R T = xs[NU - 1];
+    const R exch = cdt * sig * (cf.kap[cell] * T - xs[0]);
+    ys[NU - 1] = cf.rcv[cell] * T + exch;
+    ys[0] -= exch;
+  }
+  if (sc.psi != 0.0) {
+    const R psi = (R)sc.psi;
+#pragma unroll
+    for (int c = 0; c < NR; ++c) ys[c] += psi * xs[c];
+    if (CPL) ys[NU - 1] += psi * cf.rcv[cell] * xs[NU - 1];
+  }
+}
+
+// PRE = true: the input is u and the operator is applied to z = M^{-1} u, the
+// block-Jacobi solve done per staged cell (fused right preconditioning).
+template <bool CPL, int MODE, bool PRE, typename R, typename VI, typename VO>
+__global__ __launch_bounds__(kApply2dThreads) void k_apply2d_lds(Geom g, Scheme sc, Coefs<R> cf, Bdry bd, const VI* __restrict__ x,
+                                                     const double* __restrict__ b, VO* __restrict__ y,
+                                                     const int* __restrict__ skip) {
+  constexpr int NR = 3;
+  constexpr int NU = NR + (CPL ? 1 : 0);
+  if (skip && *skip) return;
+  __shared__ R sx[NR][LHY][LHX];
+  __shared__ R sq[3][LHY][LHX];
+  __shared__ R ss[LHY][LHX];
+  const int64_t N = g.N;
+  const int nx = g.n[0], ny = g.n[1];
+  int tbx, tby;
+  if (!xcd_tile(nx, ny, tbx, tby)) return;
+  stage2d(g, cf, bd, tbx * LX - 1, tby * LY - 1, [&](int64_t cell, int, int, R* xv) {
+    if (PRE) {
+      R uv[NU];
+#pragma unroll
+      for (int c = 0; c < NU; ++c) uv[c] = (R)x[c * N + cell];
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        R acc = (R)0;
+#pragma unroll
+        for (int c = 0; c < NU; ++c) acc += cf.bjinv[(r * NU + c) * N + cell] * uv[c];
+        xv[r] = acc;
+      }
+    } else {
+#pragma unroll
+      for (int c = 0; c < NR; ++c) xv[c] = (R)x[c * N + cell];
+    }
+  }, sx, sq, ss);
+  __syncthreads();
+  // ---- fluxes: one cell per thread ----
+  const int tx = threadIdx.x % LX;
   for (int ty = threadIdx.x / LX; ty < LY; ty += kApply2dThreads / LX) {
     const int i = tbx * LX + tx, j = tby * LY + ty;
     if (i >= nx || j >= ny) continue;
@@ -718,7 +879,7 @@ __global__ __launch_bounds__(kApply2dThreads) void k_apply2d_lds(Geom g, Scheme 
     const int li = tx + 1, lj = ty + 1;
     R xs[NU], ys[NU];
 #pragma unroll
-    for (int c = 0; c < NR; ++c) { xs[c] = sx[c][lj][li]; ys[c] = xs[c]; }
+    for (int c = 0; c < NR; ++c) xs[c] = sx[c][lj][li];
     if (CPL) {
       if (PRE) {
         R acc = (R)0;
@@ -728,90 +889,124 @@ __global__ __launch_bounds__(kApply2dThreads) void k_apply2d_lds(Geom g, Scheme 
       } else {
         xs[NU - 1] = (R)x[(NU - 1) * N + cell];
       }
-      ys[NU - 1] = (R)0;
     }
-    const R sig = ss[lj][li];
-#pragma unroll
-    for (int d = 0; d < 2; ++d) {
-      // neighbours in LDS; pressure pair index of (d, m) in 2D: (0,0)=0 (0,1)=1 (1,1)=2
-      const int ri = d == 0 ? li + 1 : li, rj = d == 0 ? lj : lj + 1;
-      const int mi = d == 0 ? li - 1 : li, mj = d == 0 ? lj : lj - 1;
-      R xr[NR], xl[NR], qs[2], qr[2], ql[2];
-#pragma unroll
-      for (int c = 0; c < NR; ++c) { xr[c] = sx[c][rj][ri]; xl[c] = sx[c][mj][mi]; }
-#pragma unroll
-      for (int m = 0; m < 2; ++m) {
-        const int pq = d + m;
-        qs[m] = sq[pq][lj][li];
-        qr[m] = sq[pq][rj][ri];
-        ql[m] = sq[pq][mj][mi];
-      }
-      const R sigR = ss[rj][ri], sigL = ss[mj][mi];
-      const R ap = cf.face[(3 * d + 0) * N + cell];
-      const R ddp = cf.face[(3 * d + 1) * N + cell];
-      const R alp = cf.face[(3 * d + 2) * N + cell];
-      const R bp = (R)1 - ap;
-      R am, ddm, alm;
-      {
-        const int id = d == 0 ? i : j, n = d == 0 ? nx : ny;
-        const int64_t stride = d == 0 ? 1 : nx;
-        if (id > 0) {
-          const int64_t nb = cell - stride;
-          am = cf.face[(3 * d + 0) * N + nb]; ddm = cf.face[(3 * d + 1) * N + nb]; alm = cf.face[(3 * d + 2) * N + nb];
-        } else if (g.bc[2 * d] == BC_PERIODIC) {
-          const int64_t nb = cell + (int64_t)(n - 1) * stride;
-          am = cf.face[(3 * d + 0) * N + nb]; ddm = cf.face[(3 * d + 1) * N + nb]; alm = cf.face[(3 * d + 2) * N + nb];
-        } else {
-          const int64_t pidx = d == 0 ? (int64_t)j : (int64_t)i;
-          const int64_t pn = g.plane_n[d];
-          am = cf.lowface[cf.lowoff[d] + pidx]; ddm = cf.lowface[cf.lowoff[d] + pn + pidx];
-          alm = cf.lowface[cf.lowoff[d] + 2 * pn + pidx];
-        }
-      }
-      const R bm = (R)1 - am;
-      const R FEp = alp * (ap * xs[1 + d] + bp * xr[1 + d] + ddp * (xr[0] - xs[0]));
-      const R FEm = alm * (am * xl[1 + d] + bm * xs[1 + d] + ddm * (xs[0] - xl[0]));
-      ys[0] += s * (FEp - FEm);
-#pragma unroll
-      for (int m = 0; m < 2; ++m) {
-        const R FPp = ap * qs[m] + bp * qr[m] + ddp * (xr[1 + m] - xs[1 + m]);
-        const R FPm = am * ql[m] + bm * qs[m] + ddm * (xs[1 + m] - xl[1 + m]);
-        ys[1 + m] += s * (FPp - FPm);
-      }
-      if (sc.wb) {
-        R hi = (R)0.5 * (sig + sigR) * (xs[1 + d] + xr[1 + d]);
-        R lo = (R)0.5 * (sig + sigL) * (xl[1 + d] + xs[1 + d]);
-        if (sc.wbb) {
-          // boundary closure on faces to a ghost (the halo tile holds the ghost's q)
-          const int id = d == 0 ? i : j, n = d == 0 ? nx : ny;
-          if (id == n - 1 && g.bc[2 * d + 1] != BC_PERIODIC) hi = -(R)2 * (qr[d] - qs[d]) * (R)sc.inv_cdx;
-          if (id == 0 && g.bc[2 * d] != BC_PERIODIC) lo = -(R)2 * (qs[d] - ql[d]) * (R)sc.inv_cdx;
-        }
-        ys[1 + d] += (R)0.25 * cdt * (hi + lo);
-      }
-    }
-    if (!sc.wb) {
-#pragma unroll
-      for (int m = 0; m < 2; ++m) ys[1 + m] += cdt * sig * xs[1 + m];
-    }
-    if (sc.src == SRC_ABS) ys[0] += cdt * sig * xs[0];
-    if (CPL) {
-      const R T = xs[NU - 1];
-      const R exch = cdt * sig * (cf.kap[cell] * T - xs[0]);
-      ys[NU - 1] = cf.rcv[cell] * T + exch;
-      ys[0] -= exch;
-    }
-    if (sc.psi != 0.0) {
-      const R psi = (R)sc.psi;
-#pragma unroll
-      for (int c = 0; c < NR; ++c) ys[c] += psi * xs[c];
-      if (CPL) ys[NU - 1] += psi * cf.rcv[cell] * xs[NU - 1];
-    }
+    apply2d_cell<CPL, R>(g, sc, cf, sx, sq, ss, li, lj, i, j, cell, xs, ys);
 #pragma unroll
     for (int c = 0; c < NU; ++c) {
       R v = ys[c];
       if (MODE == 1) v = (R)b[c * N + cell] - v;
       y[c * N + cell] = (VO)v;
+    }
+  }
+}
+
+// ----------------------------------------------------------------------------
+// Multigrid, finest level in 2D: damped block-Jacobi sweeps and the restricted
+// residual on the LDS-staged operator, one kernel each.  The operator's input x is
+// formed while staging:
+//   XIN 0: x = zin;   XIN 1: x = zin + P zc (zin null: x = P zc);   XIN 2: x = omega M^{-1} r
+// and the epilogue writes
+//   OP 0: out = x + omega M^{-1} (r - A x)                     (one sweep)
+//   OP 1: b1 = P^T (r - A x), z1 = omega D1^{-1} b1 (0 if !sm)  (level 1's right-hand
+//         side and its first sweep from zero)
+// P: piecewise-constant prolongation from 2 x 2 aggregates (coarse extents
+// (n + 1) / 2, cell (i, j) in aggregate (i / 2, j / 2)).  Tile origins are even, so
+// each aggregate lies inside one tile.  M^{-1}: the block-Jacobi inverses.
+// ----------------------------------------------------------------------------
+template <bool CPL, int OP, int XIN, typename R, typename TIN>
+__global__ __launch_bounds__(kApply2dThreads) void k_mg_sweep2d(Geom g, Scheme sc, Coefs<R> cf, Bdry bd,
+                                                                const TIN* __restrict__ r, const R* __restrict__ zin,
+                                                                const R* __restrict__ zc, R omega, R* __restrict__ out,
+                                                                const R* __restrict__ dinv1, int sm, R* __restrict__ b1,
+                                                                R* __restrict__ z1, const int* __restrict__ skip) {
+  constexpr int NR = 3;
+  constexpr int NU = NR + (CPL ? 1 : 0);
+  static_assert(kApply2dThreads == LX * LY, "one cell per thread");
+  static_assert(LX % 2 == 0 && LY % 2 == 0, "aggregates inside a tile");
+  if (skip && *skip) return;
+  __shared__ R sx[NR][LHY][LHX];
+  __shared__ R sq[3][LHY][LHX];
+  __shared__ R ss[LHY][LHX];
+  const int64_t N = g.N;
+  const int nx = g.n[0], ny = g.n[1];
+  const int ncx = (nx + 1) / 2;
+  const int64_t Nc = (int64_t)ncx * ((ny + 1) / 2);
+  int tbx, tby;
+  if (!xcd_tile(nx, ny, tbx, tby)) return;
+  // input component k of grid cell (gi, gj)
+  auto xin_of = [&](int64_t cell, int gi, int gj, int k) -> R {
+    if (XIN == 0) return zin[k * N + cell];
+    if (XIN == 1) return (zin ? zin[k * N + cell] : (R)0) + zc[k * Nc + (int64_t)(gj / 2) * ncx + gi / 2];
+    R acc = (R)0;
+#pragma unroll
+    for (int c = 0; c < NU; ++c) acc += cf.bjinv[(k * NU + c) * N + cell] * (R)r[c * N + cell];
+    return omega * acc;
+  };
+  stage2d(g, cf, bd, tbx * LX - 1, tby * LY - 1, [&](int64_t cell, int gi, int gj, R* xv) {
+#pragma unroll
+    for (int c = 0; c < NR; ++c) xv[c] = xin_of(cell, gi, gj, c);
+  }, sx, sq, ss);
+  __syncthreads();
+  const int tx = threadIdx.x % LX, ty = threadIdx.x / LX;
+  const int i = tbx * LX + tx, j = tby * LY + ty;
+  const bool inside = i < nx && j < ny;
+  const int64_t cell = (int64_t)j * nx + i;
+  R res[NU];
+  if (inside) {
+    const int li = tx + 1, lj = ty + 1;
+    R xs[NU], ys[NU];
+#pragma unroll
+    for (int c = 0; c < NR; ++c) xs[c] = sx[c][lj][li];
+    if (CPL) xs[NU - 1] = xin_of(cell, i, j, NU - 1);
+    apply2d_cell<CPL, R>(g, sc, cf, sx, sq, ss, li, lj, i, j, cell, xs, ys);
+#pragma unroll
+    for (int k = 0; k < NU; ++k) res[k] = (R)r[k * N + cell] - ys[k];
+    if (OP == 0) {
+#pragma unroll
+      for (int rr = 0; rr < NU; ++rr) {
+        R acc = (R)0;
+#pragma unroll
+        for (int k = 0; k < NU; ++k) acc += cf.bjinv[(rr * NU + k) * N + cell] * res[k];
+        out[rr * N + cell] = xs[rr] + omega * acc;
+      }
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < NU; ++k) res[k] = (R)0;
+  }
+  if (OP == 1) {
+    // gather the residuals of each 2 x 2 aggregate through LDS (the halo tile is no
+    // longer read once every thread has passed the barrier)
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NU; ++k) {
+      if (k < NR) sx[k][ty][tx] = res[k];
+      else sq[0][ty][tx] = res[k];
+    }
+    __syncthreads();
+    if (inside && (tx % 2) == 0 && (ty % 2) == 0) {
+      const int64_t I = (int64_t)(j / 2) * ncx + i / 2;
+      R acc[NU];
+#pragma unroll
+      for (int k = 0; k < NU; ++k) acc[k] = (R)0;
+      for (int cy = 0; cy < 2; ++cy)
+        for (int cx = 0; cx < 2; ++cx) {
+          if (i + cx >= nx || j + cy >= ny) continue;
+#pragma unroll
+          for (int k = 0; k < NU; ++k) acc[k] += k < NR ? sx[k][ty + cy][tx + cx] : sq[0][ty + cy][tx + cx];
+        }
+#pragma unroll
+      for (int k = 0; k < NU; ++k) b1[k * Nc + I] = acc[k];
+#pragma unroll
+      for (int rr = 0; rr < NU; ++rr) {
+        R z = (R)0;
+        if (sm) {
+#pragma unroll
+          for (int k = 0; k < NU; ++k) z += dinv1[(rr * NU + k) * Nc + I] * acc[k];
+          z *= omega;
+        }
+        z1[rr * Nc + I] = z;
+      }
     }
   }
 }
@@ -837,8 +1032,8 @@ void launch_apply(int nd, bool cpl, int mode, const Geom& g, const Scheme& sc, c
 #undef M1_LDS
     return;
   }
-  dim3 blk(TX, TY), grd((g.n[0] + TX - 1) / TX, (g.rows + TY - 1) / TY);
-#define M1_ST(ND_, CPL_, MODE_) k_stencil<ND_, CPL_, MODE_, R, VI, VO><<<grd, blk, 0, s>>>(g, sc, cf, bd, x, b, nullptr, y, skip)
+  const CellLaunch L = cell_launch(g);
+#define M1_ST(ND_, CPL_, MODE_) k_stencil<ND_, CPL_, MODE_, R, VI, VO><<<L.grd, L.blk, 0, s>>>(L.g, sc, cf, bd, x, b, nullptr, y, skip)
   if (nd == 2) {
     if (cpl) { if (mode == 0) M1_ST(2, true, 0); else M1_ST(2, true, 1); }
     else { if (mode == 0) M1_ST(2, false, 0); else M1_ST(2, false, 1); }
@@ -851,15 +1046,41 @@ void launch_apply(int nd, bool cpl, int mode, const Geom& g, const Scheme& sc, c
 
 void launch_residual(int nd, bool cpl, const Geom& g, const Scheme& sc, const Coefs<double>& cf, const Bdry& bd,
                      const double* Uk, const double* Un, double* out, hipStream_t s) {
-  dim3 blk(TX, TY), grd((g.n[0] + TX - 1) / TX, (g.rows + TY - 1) / TY);
+  const CellLaunch L = cell_launch(g);
   if (nd == 2) {
-    if (cpl) k_stencil<2, true, 2, double, double, double><<<grd, blk, 0, s>>>(g, sc, cf, bd, Uk, nullptr, Un, out, nullptr);
-    else k_stencil<2, false, 2, double, double, double><<<grd, blk, 0, s>>>(g, sc, cf, bd, Uk, nullptr, Un, out, nullptr);
+    if (cpl) k_stencil<2, true, 2, double, double, double><<<L.grd, L.blk, 0, s>>>(L.g, sc, cf, bd, Uk, nullptr, Un, out, nullptr);
+    else k_stencil<2, false, 2, double, double, double><<<L.grd, L.blk, 0, s>>>(L.g, sc, cf, bd, Uk, nullptr, Un, out, nullptr);
   } else {
-    if (cpl) k_stencil<3, true, 2, double, double, double><<<grd, blk, 0, s>>>(g, sc, cf, bd, Uk, nullptr, Un, out, nullptr);
-    else k_stencil<3, false, 2, double, double, double><<<grd, blk, 0, s>>>(g, sc, cf, bd, Uk, nullptr, Un, out, nullptr);
+    if (cpl) k_stencil<3, true, 2, double, double, double><<<L.grd, L.blk, 0, s>>>(L.g, sc, cf, bd, Uk, nullptr, Un, out, nullptr);
+    else k_stencil<3, false, 2, double, double, double><<<L.grd, L.blk, 0, s>>>(L.g, sc, cf, bd, Uk, nullptr, Un, out, nullptr);
   }
 }
+
+template <typename R, typename TIN>
+bool launch_mg_sweep2d(int nd, bool cpl, int op, int xin, const Geom& g, const Scheme& sc, const Coefs<R>& cf,
+                       const Bdry& bd, const TIN* r, const R* zin, const R* zc, R omega, R* out, const R* dinv1, int sm,
+                       R* b1, R* z1, hipStream_t s, const int* skip) {
+  if (!fused_apply_available(nd) || op < 0 || op > 1 || xin < 0 || xin > 2) return false;
+  const dim3 grd2 = grid2d_xcd(g);
+#define M1_SW(CPL_, OP_, XIN_) \
+  k_mg_sweep2d<CPL_, OP_, XIN_, R, TIN><<<grd2, kApply2dThreads, 0, s>>>(g, sc, cf, bd, r, zin, zc, omega, out, dinv1, sm, b1, z1, skip)
+#define M1_SW_X(CPL_, OP_) \
+  { if (xin == 0) M1_SW(CPL_, OP_, 0); else if (xin == 1) M1_SW(CPL_, OP_, 1); else M1_SW(CPL_, OP_, 2); }
+  if (cpl) { if (op == 0) M1_SW_X(true, 0) else M1_SW_X(true, 1) }
+  else { if (op == 0) M1_SW_X(false, 0) else M1_SW_X(false, 1) }
+#undef M1_SW_X
+#undef M1_SW
+  return true;
+}
+template bool launch_mg_sweep2d<double, double>(int, bool, int, int, const Geom&, const Scheme&, const Coefs<double>&,
+                                                const Bdry&, const double*, const double*, const double*, double,
+                                                double*, const double*, int, double*, double*, hipStream_t, const int*);
+template bool launch_mg_sweep2d<float, double>(int, bool, int, int, const Geom&, const Scheme&, const Coefs<float>&,
+                                               const Bdry&, const double*, const float*, const float*, float, float*,
+                                               const float*, int, float*, float*, hipStream_t, const int*);
+template bool launch_mg_sweep2d<float, float>(int, bool, int, int, const Geom&, const Scheme&, const Coefs<float>&,
+                                              const Bdry&, const float*, const float*, const float*, float, float*,
+                                              const float*, int, float*, float*, hipStream_t, const int*);
 
 // ----------------------------------------------------------------------------
 // a4: z = M^{-1} r with the stored block inverses
@@ -1273,8 +1494,8 @@ void launch_time_step(int nd, bool cpl, bool semi, const Geom& g, const Scheme& 
 #undef M1_TS
     return;
   }
-  dim3 blk(TX, TY), grd((g.n[0] + TX - 1) / TX, (g.rows + TY - 1) / TY);
-#define M1_TD(ND_, CPL_, SEMI_) k_step_direct<ND_, CPL_, SEMI_><<<grd, blk, 0, s>>>(g, sc, cf.sigma, cf.rcv, bd, Un, Uo)
+  const CellLaunch L = cell_launch(g);
+#define M1_TD(ND_, CPL_, SEMI_) k_step_direct<ND_, CPL_, SEMI_><<<L.grd, L.blk, 0, s>>>(L.g, sc, cf.sigma, cf.rcv, bd, Un, Uo)
   if (nd == 2) {
     if (cpl) { if (semi) M1_TD(2, true, true); else M1_TD(2, true, false); }
     else { if (semi) M1_TD(2, false, true); else M1_TD(2, false, false); }

@@ -577,23 +577,52 @@ void mg_vcycle(const MgHierarchy& h, const MgFine<R>& fine, const TIN* r, R* z, 
     return;
   }
   // ---- finest level, down ----
-  if (h.nu1 > 0) {
-    run(KC_MG_FINE, fine_smooth_bytes(false, false), [&] { M1_MG_NU_SWITCH(nu, (k_mg_fine_smooth<NU, R, TIN><<<grid1(N0), kMgThreads, 0, s>>>(N0, fine.bjinv, om, r, nullptr, nullptr, z0, skip))) });
-    for (int k = 1; k < h.nu1; ++k) {
-      run(KC_APPLY, fine_apply_bytes, [&] { fine(z0, t, s, skip); });
-      run(KC_MG_FINE, fine_smooth_bytes(true, true), [&] { M1_MG_NU_SWITCH(nu, (k_mg_fine_smooth<NU, R, TIN><<<grid1(N0), kMgThreads, 0, s>>>(N0, fine.bjinv, om, r, t, z0, zp, skip))) });
+  // fused form (2D): sweeps and the restricted residual on the LDS-staged operator,
+  // the first two sweeps in one launch (its input omega M^{-1} r formed while staging)
+  const bool fused = fine.sweep != nullptr;
+  const int r64 = sizeof(TIN) == 8 ? 1 : 0;
+  const double Nc1 = (double)h.lev[1].g.N;
+  // algorithmic bytes of a fused launch: coefficients, the input (xin), r, M^{-1}, the output
+  auto sweep_bytes = [&](int op, int xin, bool with_zin, int sm1) {
+    double b = fine.coef_bytes;
+    if (xin == 0) b += N0 * cu * rs;
+    if (xin == 1) b += (with_zin ? N0 * cu * rs : 0.0) + Nc1 * cu * rs;
+    b += N0 * cu * ti;                                  // r (read once, also for xin 2)
+    if (xin == 2 || op == 0) b += N0 * bs * rs;         // M^{-1}
+    b += op == 0 ? N0 * cu * rs : Nc1 * (2.0 * cu + (sm1 ? bs : 0.0)) * rs;
+    return b;
+  };
+  const MgLevel& Lv1 = h.lev[1];
+  const int sm1 = (h.nu1c > 0 && h.nlev > 2) ? 1 : 0;
+  if (fused && h.nu1 > 0) {
+    int done = 0;
+    if (h.nu1 >= 2) {
+      run(KC_MG_FINE, sweep_bytes(0, 2, false, 0), [&] { fine.sweep(fine.self, 0, 2, r, r64, nullptr, nullptr, om, z0, nullptr, 0, nullptr, nullptr, s, skip); });
+      done = 2;
+    } else {
+      run(KC_MG_FINE, fine_smooth_bytes(false, false), [&] { M1_MG_NU_SWITCH(nu, (k_mg_fine_smooth<NU, R, TIN><<<grid1(N0), kMgThreads, 0, s>>>(N0, fine.bjinv, om, r, nullptr, nullptr, z0, skip))) });
+      done = 1;
+    }
+    for (int k = done; k < h.nu1; ++k) {
+      run(KC_MG_FINE, sweep_bytes(0, 0, true, 0), [&] { fine.sweep(fine.self, 0, 0, r, r64, z0, nullptr, om, zp, nullptr, 0, nullptr, nullptr, s, skip); });
       std::swap(z0, zp);
     }
-    run(KC_APPLY, fine_apply_bytes, [&] { fine(z0, t, s, skip); });
-  }
-  {
-    const MgLevel& L1 = h.lev[1];
-    const int sm = (h.nu1c > 0 && h.nlev > 2) ? 1 : 0;
+    run(KC_MG_FINE, sweep_bytes(1, 0, true, sm1), [&] { fine.sweep(fine.self, 1, 0, r, r64, z0, nullptr, om, nullptr, dinv<R>(Lv1), sm1, (R*)Lv1.b, (R*)Lv1.z, s, skip); });
+  } else {
+    if (h.nu1 > 0) {
+      run(KC_MG_FINE, fine_smooth_bytes(false, false), [&] { M1_MG_NU_SWITCH(nu, (k_mg_fine_smooth<NU, R, TIN><<<grid1(N0), kMgThreads, 0, s>>>(N0, fine.bjinv, om, r, nullptr, nullptr, z0, skip))) });
+      for (int k = 1; k < h.nu1; ++k) {
+        run(KC_APPLY, fine_apply_bytes, [&] { fine(z0, t, s, skip); });
+        run(KC_MG_FINE, fine_smooth_bytes(true, true), [&] { M1_MG_NU_SWITCH(nu, (k_mg_fine_smooth<NU, R, TIN><<<grid1(N0), kMgThreads, 0, s>>>(N0, fine.bjinv, om, r, t, z0, zp, skip))) });
+        std::swap(z0, zp);
+      }
+      run(KC_APPLY, fine_apply_bytes, [&] { fine(z0, t, s, skip); });
+    }
     const R* tt = h.nu1 > 0 ? t : nullptr;
-    const double bytes = (double)N0 * cu * (ti + (tt ? rs : 0.0)) + (double)L1.g.N * (2.0 * cu + (sm ? bs : 0.0)) * rs;
+    const double bytes = (double)N0 * cu * (ti + (tt ? rs : 0.0)) + Nc1 * (2.0 * cu + (sm1 ? bs : 0.0)) * rs;
     run(KC_MG_FINE, bytes, [&] {
-      if (nd == 2) { M1_MG_NU_SWITCH(nu, (k_mg_restrict_fine<2, NU, R, TIN><<<grid1(L1.g.N), kMgThreads, 0, s>>>(g0, L1.g, r, tt, dinv<R>(L1), om, sm, (R*)L1.b, (R*)L1.z, skip))) }
-      else { M1_MG_NU_SWITCH(nu, (k_mg_restrict_fine<3, NU, R, TIN><<<grid1(L1.g.N), kMgThreads, 0, s>>>(g0, L1.g, r, tt, dinv<R>(L1), om, sm, (R*)L1.b, (R*)L1.z, skip))) }
+      if (nd == 2) { M1_MG_NU_SWITCH(nu, (k_mg_restrict_fine<2, NU, R, TIN><<<grid1(Lv1.g.N), kMgThreads, 0, s>>>(g0, Lv1.g, r, tt, dinv<R>(Lv1), om, sm1, (R*)Lv1.b, (R*)Lv1.z, skip))) }
+      else { M1_MG_NU_SWITCH(nu, (k_mg_restrict_fine<3, NU, R, TIN><<<grid1(Lv1.g.N), kMgThreads, 0, s>>>(g0, Lv1.g, r, tt, dinv<R>(Lv1), om, sm1, (R*)Lv1.b, (R*)Lv1.z, skip))) }
     });
   }
   // ---- coarse levels, down ----
@@ -652,8 +681,18 @@ void mg_vcycle(const MgHierarchy& h, const MgFine<R>& fine, const TIN* r, R* z, 
   // ---- finest level, up ----
   {
     const MgLevel& L1 = h.lev[1];
-    R* out = h.nu2 > 0 ? zp : z;
     const R* zin = h.nu1 > 0 ? z0 : nullptr;
+    if (fused && h.nu2 > 0) {
+      // the first sweep's input is z0 + P z1, formed while staging
+      for (int k = 0; k < h.nu2; ++k) {
+        const R* src = k == 0 ? zin : ((k % 2 == 1) ? zp : z0);
+        R* dst = (k == h.nu2 - 1) ? z : ((k % 2 == 0) ? zp : z0);
+        if (k == 0) run(KC_MG_FINE, sweep_bytes(0, 1, zin != nullptr, 0), [&] { fine.sweep(fine.self, 0, 1, r, r64, src, zl[1], om, dst, nullptr, 0, nullptr, nullptr, s, skip); });
+        else run(KC_MG_FINE, sweep_bytes(0, 0, true, 0), [&] { fine.sweep(fine.self, 0, 0, r, r64, src, nullptr, om, dst, nullptr, 0, nullptr, nullptr, s, skip); });
+      }
+      return;
+    }
+    R* out = h.nu2 > 0 ? zp : z;
     const double bytes = ((double)N0 * ((zin ? 1.0 : 0.0) + 1.0) + (double)L1.g.N) * cu * rs;
     if (zin) {
       run(KC_MG_FINE, bytes, [&] {

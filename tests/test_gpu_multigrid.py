@@ -62,6 +62,12 @@ CYCLE_CASES = [
     ((72, 40), BC2["mixed"], "none", "wb", 3, 3, 0, 1, 1),
     ((45, 64), BC2["walls"], "absorption", "wb", 2, 1, 4, 0, 2),
     ((20, 18, 14), BC3["open"], "coupled_t", "wb", 2, 2, 0, 1, 0),
+    # 2D finest-level sweeps fused into the staged operator on 64 x 16 tiles: several
+    # tiles with ragged tails, the first two sweeps in one launch (nu1 >= 2), the
+    # coupled 4 x 4 blocks
+    ((131, 37), BC2["mixed"], "none", "wb", 4, 4, 0, 2, 2),
+    ((70, 33), BC2["walls"], "coupled_t", "wb", 2, 3, 0, -1, -1),
+    ((66, 18), BC2["periodic"], "absorption", "centered", 3, 1, 0, 1, 1),
 ]
 
 
@@ -158,6 +164,32 @@ def test_step_mixed_precision_multigrid(n, bc, src, fs, basis32):
     ref = O.implicit_step(sch, p["sigma"], p.get("rho_cv"), Un, p["dt"], rtol=1e-12, newton_rtol=1e-12,
                           newton_max=80)
     s = P.Solver(p, rtol=1e-10, newton_rtol=1e-10, newton_max=80, pc="mg", precision="mixed", basis_fp32=basis32)
+    try:
+        U = s.to_device(Un)
+        st, stats = s.implicit_step(U)
+        got = U.cpu().numpy()
+        err = _rel(got, ref.U)
+        _say(f"  error against the FP64 oracle: {err:.2e} (newton={stats['newton_iters']} krylov={stats['krylov_iters']})")
+        assert err <= 1e-8
+    finally:
+        s.close()
+
+
+@pytest.mark.parametrize("n,bc,src,fs", [((131, 37), BC2["mixed"], "none", "wb"),
+                                         ((70, 33), BC2["walls"], "coupled_t", "wb")])
+def test_step_mixed_precision_multigrid_v44(n, bc, src, fs):
+    """The benchmark's cycle, V(4, 4) with 2 + 2 sweeps below the finest level, in FP32
+    inside FP64 GMRES: within 1e-8 of the FP64 oracle."""
+    import paper_2011_13926_amd as P
+    _say("mixed-precision step, multigrid V(4,4)", n, bc, src, fs)
+    p = W.random_problem(n, 12, source=src, flux_source=fs, bc=bc, dt=2.0, fmax=0.6)
+    sch = O.Scheme.from_problem(p)
+    Un = O.state_from_problem(p, "n")
+    ref = O.implicit_step(sch, p["sigma"], p.get("rho_cv"), Un, p["dt"], rtol=1e-12, newton_rtol=1e-12,
+                          newton_max=80)
+    assert ref.converged
+    s = P.Solver(p, rtol=1e-10, newton_rtol=1e-10, newton_max=80, pc="mg", precision="mixed", mg_nu1=4, mg_nu2=4,
+                 mg_nu1_coarse=2, mg_nu2_coarse=2)
     try:
         U = s.to_device(Un)
         st, stats = s.implicit_step(U)

@@ -33,6 +33,10 @@ KERNEL_CASES += [((70, 9), BC2["mixed"], "none", "centered", "newton"),
 for bcn, bc in BC3.items():
     for src in ["none", "absorption", "coupled_t"]:
         KERNEL_CASES.append(((23, 19, 11), bc, src, "wb", "newton"))
+# 3D cell kernels run in chunks of 16 planes on 64 x 4 tiles: several x- and y-tiles
+# and z-chunks, each with a ragged tail
+KERNEL_CASES += [((70, 9, 37), BC3["mixed"], "none", "wb", "newton"),
+                 ((70, 9, 37), BC3["periodic"], "coupled_t", "wb", "newton")]
 
 
 def _say(*a):
