@@ -65,7 +65,7 @@ CLASS_KERNEL = {
     "mg_smooth": ("k_mg_smooth<", "k_mg_prolong<"),
     "mg_down": ("k_mg_down_lanes<",),
     "mg_coarse_solve": ("k_mg_coarse_solve<",),
-    "mg_setup": ("k_mg_galerkin<", "k_mg_invert<", "k_mg_dense_inverse<", "k_setup_bj<2, false, true",
+    "mg_setup": ("k_mg_galerkin<", "k_mg_invert<", "k_mg_dense_inverse<", "k_mg_dense_inverse_reg<", "k_setup_bj<2, false, true",
                  "k_setup_bj<2, true, true", "k_setup_bj<3, false, true", "k_setup_bj<3, true, true"),
 }
 
@@ -162,9 +162,12 @@ WORKLOADS = {
                                  solver=dict(rtol=1e-8, newton_rtol=1e-8, max_iters=300, newton_max=30, **GLOBALISED),
                                  cpu_sample=None),
 }
-# V(4,4) on the finest level, two sweeps each way below it: measured best of
-# (2,2)/(2,1)/(3,1)/(3,2)/(3,3)/(4,1)/(4,2) at 512^2 (1.03 s against 1.34 s for V(2,2))
-MG = dict(pc="mg", mg_nu1=4, mg_nu2=4, mg_nu1_coarse=2, mg_nu2_coarse=2, mg_omega=0.7)
+# V(8,8) on the finest level (its sweeps fused into the staged operator, the cheap
+# part of a cycle), one sweep each way below it, damping 0.9: the fastest mixed
+# step of a sweep over fine sweeps 3..8, coarse sweeps 1..3 and damping 0.7..1.1 on
+# the 512^2 Voronoi step (0.50 s against 0.82 s for V(4,4) with 2 coarse sweeps at
+# 0.7; damping 1.0 doubles the iterations and 1.1 diverges)
+MG = dict(pc="mg", mg_nu1=8, mg_nu2=8, mg_nu1_coarse=1, mg_nu2_coarse=1, mg_omega=0.9)
 VARIANTS = {
     "fp64_bj": dict(precision="fp64", pc="bj"),
     "mixed_bj": dict(precision="mixed", basis_fp32=False, inner_rtol=1e-6, pc="bj"),

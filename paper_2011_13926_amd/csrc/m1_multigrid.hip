@@ -255,6 +255,171 @@ __global__ __launch_bounds__(kGjThreads) void k_mg_dense_inverse(MgGeom g, const
     for (int c = lane; c < n; c += 64) Ainv[(int64_t)r * n + c] = W[(int64_t)r * n2 + n + c];
 }
 
+// value of lane l (uniform) of a double, read into scalar registers
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+  const unsigned long long u = __double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)u, l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// The same inversion for n <= 192 unknowns held in registers: wave w owns the
+// rows w, w + 16, ... (12 at most), lane l the columns l, l + 64, l + 128.  Per
+// column k: every wave proposes its largest |a_ik| over rows not yet used as
+// pivots (lane k % 64 holds column k), the block takes the largest (ties: the
+// smallest row), the pivot row's wave passes the row through LDS, and every row
+// is updated in place (multipliers from lane k % 64 by cross-lane reads).  Rows are
+// never moved: the pivot row of each step is recorded, and the inverse is written
+// out with the row and column permutations that the interchanges imply (row k of
+// the interchanged matrix is the k-th pivot row; the columns of the in-place result
+// are exchanged in reverse order of the row interchanges).  The whole matrix stays
+// on chip instead of streaming an n x 2n workspace through L2 once per column.
+constexpr int kGjRegRows = 12, kGjRegCols = 3;
+constexpr int kGjRegMax = 192;   // 16 waves x 12 rows = 64 lanes x 3 columns
+
+template <int ND, int NU>
+__global__ __launch_bounds__(kGjThreads) void k_mg_dense_inverse_reg(MgGeom g, const double* __restrict__ S,
+                                                                     double* __restrict__ Ainv, int* __restrict__ bad) {
+  static_assert(kGjThreads == 1024, "16 waves");
+  constexpr int BS = NU * NU;
+  const int N = (int)g.N;
+  const int n = NU * N;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  __shared__ double s_cv[2][16];
+  __shared__ int s_ci[2][16];
+  __shared__ double s_prow[2][kGjRegMax];
+  __shared__ int s_q[kGjRegMax], s_perm[kGjRegMax], s_invp[kGjRegMax], s_pk[kGjRegMax], s_src[kGjRegMax],
+      s_srcinv[kGjRegMax];
+  double a[kGjRegRows][kGjRegCols];
+  unsigned used = 0;   // bit rI: row wave + 16 rI is a pivot row already (or beyond n)
+  // the dense matrix: entry (rr * N + cell, cc * N + cj) sums the stencil blocks b
+  // (diagonal, then the face neighbours) whose cell is cj
+#pragma unroll
+  for (int rI = 0; rI < kGjRegRows; ++rI) {
+    const int i = wave + 16 * rI;
+    if (i >= n) used |= 1u << rI;
+    int rr = 0, cell = 0;
+    int nbc[1 + 2 * ND];
+    if (i < n) {
+      rr = i / N;
+      cell = i - rr * N;
+      int id[3];
+      mg_idx(g, cell, id);
+      nbc[0] = cell;
+#pragma unroll
+      for (int d = 0; d < ND; ++d)
+#pragma unroll
+        for (int side = 0; side < 2; ++side) nbc[1 + 2 * d + side] = (int)mg_nb(g, id, d, side);
+    }
+#pragma unroll
+    for (int cb = 0; cb < kGjRegCols; ++cb) {
+      const int j = lane + 64 * cb;
+      double v = 0.0;
+      if (i < n && j < n) {
+        const int cc = j / N, cj = j - cc * N;
+#pragma unroll
+        for (int b = 0; b < 1 + 2 * ND; ++b)
+          if (nbc[b] == cj) v += S[((int64_t)b * BS + rr * NU + cc) * N + cell];
+      }
+      a[rI][cb] = v;
+    }
+  }
+  for (int k = 0; k < n; ++k) {
+    const int kl = k & 63, kb = k >> 6, buf = k & 1;
+    // this wave's candidate for column k
+    double best = -1.0;
+    int bi = n;
+#pragma unroll
+    for (int rI = 0; rI < kGjRegRows; ++rI) {
+      double v = 0.0;
+#pragma unroll
+      for (int cb = 0; cb < kGjRegCols; ++cb)
+        if (cb == kb) v = a[rI][cb];
+      v = fabs(v);
+      if (!((used >> rI) & 1u) && v > best) { best = v; bi = wave + 16 * rI; }
+    }
+    best = readlane_f64(best, kl);
+    bi = __builtin_amdgcn_readlane(bi, kl);
+    if (lane == 0) { s_cv[buf][wave] = best; s_ci[buf][wave] = bi; }
+    __syncthreads();
+    double pv = -1.0;
+    int q = n;
+#pragma unroll
+    for (int w = 0; w < 16; ++w) {
+      const double v = s_cv[buf][w];
+      const int r = s_ci[buf][w];
+      if (v > pv || (v == pv && r < q)) { pv = v; q = r; }
+    }
+    if (q >= n) q = k;   // no candidate left (cannot happen with n rows and n steps)
+    if (tid == 0) {
+      s_q[k] = q;
+      if (!(pv > 0.0)) atomicOr(bad, 1);
+    }
+    if (wave == (q & 15)) {
+      const int rq = q >> 4;
+#pragma unroll
+      for (int rI = 0; rI < kGjRegRows; ++rI)
+        if (rI == rq) {
+#pragma unroll
+          for (int cb = 0; cb < kGjRegCols; ++cb)
+            if (lane + 64 * cb < kGjRegMax) s_prow[buf][lane + 64 * cb] = a[rI][cb];
+        }
+    }
+    __syncthreads();
+    const double inv = 1.0 / s_prow[buf][k];
+    double pr[kGjRegCols];
+#pragma unroll
+    for (int cb = 0; cb < kGjRegCols; ++cb) pr[cb] = s_prow[buf][lane + 64 * cb] * inv;
+#pragma unroll
+    for (int rI = 0; rI < kGjRegRows; ++rI) {
+      double m = 0.0;
+#pragma unroll
+      for (int cb = 0; cb < kGjRegCols; ++cb)
+        if (cb == kb) m = a[rI][cb];
+      m = readlane_f64(m, kl);
+      const bool pivrow = wave + 16 * rI == q;
+      if (pivrow) used |= 1u << rI;
+#pragma unroll
+      for (int cb = 0; cb < kGjRegCols; ++cb) {
+        const bool colk = lane + 64 * cb == k;
+        if (pivrow) a[rI][cb] = colk ? inv : pr[cb];
+        else a[rI][cb] = colk ? -m * inv : a[rI][cb] - m * pr[cb];
+      }
+    }
+  }
+  __syncthreads();
+  if (tid == 0) {
+    // replay the interchanges: logical row k is the physical row s_q[k]
+    for (int k = 0; k < n; ++k) { s_perm[k] = k; s_invp[k] = k; s_src[k] = k; }
+    for (int k = 0; k < n; ++k) {
+      const int p = s_invp[s_q[k]];
+      s_pk[k] = p;
+      const int a0 = s_perm[k], b0 = s_perm[p];
+      s_perm[k] = b0; s_perm[p] = a0;
+      s_invp[b0] = k; s_invp[a0] = p;
+    }
+    for (int k = n - 1; k >= 0; --k) {
+      const int p = s_pk[k];
+      const int t = s_src[k];
+      s_src[k] = s_src[p];
+      s_src[p] = t;
+    }
+    for (int j = 0; j < n; ++j) s_srcinv[s_src[j]] = j;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int rI = 0; rI < kGjRegRows; ++rI) {
+    const int i = wave + 16 * rI;
+    if (i >= n) continue;
+    const int64_t row = (int64_t)s_invp[i] * n;
+#pragma unroll
+    for (int cb = 0; cb < kGjRegCols; ++cb) {
+      const int j = lane + 64 * cb;
+      if (j < n) Ainv[row + s_srcinv[j]] = a[rI][cb];
+    }
+  }
+}
+
 // z = Ainv b on the coarsest level (one wavefront per row)
 template <typename R>
 __global__ __launch_bounds__(256) void k_mg_coarse_solve(int n, const R* __restrict__ Ainv, const R* __restrict__ b,
@@ -394,14 +559,11 @@ __device__ __forceinline__ void mg_row(const MgGeom& g, const R* __restrict__ S,
 // coarse values.  (One thread per coarse cell walked the children one after the
 // other: a four- or eight-fold longer chain of dependent loads.)
 template <int ND, int NU, typename R>
-__global__ __launch_bounds__(kMgThreads) void k_mg_down_lanes(MgGeom gf, MgGeom gc, const R* __restrict__ S,
-                                                              const R* __restrict__ bf, const R* __restrict__ zf,
-                                                              const R* __restrict__ Dinvc, R omega, int smooth,
-                                                              R* __restrict__ bc, R* __restrict__ zc,
-                                                              const int* __restrict__ skip) {
-  if (skip && *skip) return;
+__device__ __forceinline__ void mg_down_group(const MgGeom& gf, const MgGeom& gc, const R* __restrict__ S,
+                                              const R* __restrict__ bf, const R* __restrict__ zf,
+                                              const R* __restrict__ Dinvc, R omega, int smooth, R* __restrict__ bc,
+                                              R* __restrict__ zc, int64_t t) {
   constexpr int G = ND == 3 ? 8 : 4;
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t I = t / G;
   const int child = (int)(t % G);
   const bool live = I < gc.N;   // every lane of a group has the same I
@@ -443,17 +605,32 @@ __global__ __launch_bounds__(kMgThreads) void k_mg_down_lanes(MgGeom gf, MgGeom 
   }
 }
 
+// down from level l to l+1: b_{l+1} = P^T (b_l - A_l z_l), z_{l+1} = omega D^{-1} b_{l+1}
+// (or 0 without pre-smoothing).
+// One thread per child: the 2^ND children of a coarse
+// cell sit on consecutive lanes of one wavefront, each forms its own residual,
+// two or three butterfly exchanges sum them, and the group's first lane writes the
+// coarse values.  (One thread per coarse cell walked the children one after the
+// other: a four- or eight-fold longer chain of dependent loads.)
+template <int ND, int NU, typename R>
+__global__ __launch_bounds__(kMgThreads) void k_mg_down_lanes(MgGeom gf, MgGeom gc, const R* __restrict__ S,
+                                                              const R* __restrict__ bf, const R* __restrict__ zf,
+                                                              const R* __restrict__ Dinvc, R omega, int smooth,
+                                                              R* __restrict__ bc, R* __restrict__ zc,
+                                                              const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  mg_down_group<ND, NU, R>(gf, gc, S, bf, zf, Dinvc, omega, smooth, bc, zc,
+                           (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
 // one damped block-Jacobi sweep on a coarse level, with an optional
 // prolongation of the coarser correction first (zc != nullptr):
 //   zp = z + P zc,  out = zp + omega D^{-1} (b - A zp)
 template <int ND, int NU, typename R>
-__global__ __launch_bounds__(kMgThreads) void k_mg_smooth(MgGeom g, MgGeom gc, const R* __restrict__ S,
-                                                          const R* __restrict__ Dinv, R omega, const R* __restrict__ b,
-                                                          const R* __restrict__ z, const R* __restrict__ zc,
-                                                          R* __restrict__ out, const int* __restrict__ skip) {
-  if (skip && *skip) return;
-  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= g.N) return;
+__device__ __forceinline__ void mg_smooth_cell(const MgGeom& g, const MgGeom& gc, const R* __restrict__ S,
+                                               const R* __restrict__ Dinv, R omega, const R* __restrict__ b,
+                                               const R* __restrict__ z, const R* __restrict__ zc,
+                                               R* __restrict__ out, int64_t c) {
   int id[3];
   mg_idx(g, c, id);
   const int64_t N = g.N;
@@ -474,6 +651,17 @@ __global__ __launch_bounds__(kMgThreads) void k_mg_smooth(MgGeom g, MgGeom gc, c
     for (int k = 0; k < NU; ++k) acc += Dinv[(rr * NU + k) * N + c] * rv[k];
     out[rr * N + c] = zp(c, id, rr) + omega * acc;
   }
+}
+
+template <int ND, int NU, typename R>
+__global__ __launch_bounds__(kMgThreads) void k_mg_smooth(MgGeom g, MgGeom gc, const R* __restrict__ S,
+                                                          const R* __restrict__ Dinv, R omega, const R* __restrict__ b,
+                                                          const R* __restrict__ z, const R* __restrict__ zc,
+                                                          R* __restrict__ out, const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= g.N) return;
+  mg_smooth_cell<ND, NU, R>(g, gc, S, Dinv, omega, b, z, zc, out, c);
 }
 
 // out = z + P zc (prolongation without smoothing; z may be NULL for zero)
@@ -530,8 +718,13 @@ void mg_build(MgHierarchy& h, int nd, int nu, hipStream_t s) {
     M1_MG_NU_SWITCH(nu, (k_mg_invert<NU><<<grid1(h.lev[l].g.N), kMgThreads, 0, s>>>(h.lev[l].g.N, h.lev[l].S64, h.lev[l].Dinv64, h.bad)))
   }
   const MgLevel& L = h.lev[h.nlev - 1];
-  if (nd == 2) { M1_MG_NU_SWITCH(nu, (k_mg_dense_inverse<2, NU><<<1, kGjThreads, 0, s>>>(L.g, L.S64, h.work, h.Ainv64, h.bad))) }
-  else { M1_MG_NU_SWITCH(nu, (k_mg_dense_inverse<3, NU><<<1, kGjThreads, 0, s>>>(L.g, L.S64, h.work, h.Ainv64, h.bad))) }
+  if ((int64_t)nu * L.g.N <= kGjRegMax) {
+    if (nd == 2) { M1_MG_NU_SWITCH(nu, (k_mg_dense_inverse_reg<2, NU><<<1, kGjThreads, 0, s>>>(L.g, L.S64, h.Ainv64, h.bad))) }
+    else { M1_MG_NU_SWITCH(nu, (k_mg_dense_inverse_reg<3, NU><<<1, kGjThreads, 0, s>>>(L.g, L.S64, h.Ainv64, h.bad))) }
+  } else {
+    if (nd == 2) { M1_MG_NU_SWITCH(nu, (k_mg_dense_inverse<2, NU><<<1, kGjThreads, 0, s>>>(L.g, L.S64, h.work, h.Ainv64, h.bad))) }
+    else { M1_MG_NU_SWITCH(nu, (k_mg_dense_inverse<3, NU><<<1, kGjThreads, 0, s>>>(L.g, L.S64, h.work, h.Ainv64, h.bad))) }
+  }
 }
 
 template <typename R> static const R* stencil(const MgLevel& L);
