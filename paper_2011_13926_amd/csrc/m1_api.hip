@@ -487,14 +487,14 @@ void mg_fine_apply(const void* self, const R* x, R* y, hipStream_t s, const int*
 }
 
 template <typename R>
-bool mg_fine_sweep(const void* self, int op, int xin, const void* r, int r_fp64, const R* zin, const R* zc, R omega,
-                   R* out, const R* dinv1, int sm, R* b1, R* z1, hipStream_t s, const int* skip) {
+bool mg_fine_sweep(const void* self, int op, int xin, int ns, const void* r, int r_fp64, const R* zin, const R* zc,
+                   R omega, R* out, const R* dinv1, int sm, R* b1, R* z1, hipStream_t s, const int* skip) {
   const m1_ctx* c = (const m1_ctx*)self;
   if (r_fp64)
-    return launch_mg_sweep2d<R, double>(c->nd, c->cpl, op, xin, c->g, c->sc, coefs_of<R>(c), bdry(c),
+    return launch_mg_sweep2d<R, double>(c->nd, c->cpl, op, xin, ns, c->g, c->sc, coefs_of<R>(c), bdry(c),
                                         (const double*)r, zin, zc, omega, out, dinv1, sm, b1, z1, s, skip);
   if constexpr (std::is_same<R, float>::value)
-    return launch_mg_sweep2d<float, float>(c->nd, c->cpl, op, xin, c->g, c->sc, coefs_of<float>(c), bdry(c),
+    return launch_mg_sweep2d<float, float>(c->nd, c->cpl, op, xin, ns, c->g, c->sc, coefs_of<float>(c), bdry(c),
                                            (const float*)r, zin, zc, omega, out, dinv1, sm, b1, z1, s, skip);
   return false;
 }

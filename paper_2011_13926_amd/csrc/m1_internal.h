@@ -99,8 +99,8 @@ template <typename R> struct MgFine {
   void (*apply)(const void* self, const R* x, R* y, hipStream_t s, const int* skip) = nullptr;
   // fused sweep / restricted residual on the staged operator (launch_mg_sweep2d; r of
   // FP64 or FP32 type as r_fp64 says); null where not available (3D, direct apply)
-  bool (*sweep)(const void* self, int op, int xin, const void* r, int r_fp64, const R* zin, const R* zc, R omega,
-                R* out, const R* dinv1, int sm, R* b1, R* z1, hipStream_t s, const int* skip) = nullptr;
+  bool (*sweep)(const void* self, int op, int xin, int ns, const void* r, int r_fp64, const R* zin, const R* zc,
+                R omega, R* out, const R* dinv1, int sm, R* b1, R* z1, hipStream_t s, const int* skip) = nullptr;
   const void* self = nullptr;
   void operator()(const R* x, R* y, hipStream_t s, const int* skip) const { apply(self, x, y, s, skip); }
 };
@@ -136,10 +136,11 @@ void launch_apply(int nd, bool cpl, int mode, const Geom& g, const Scheme& sc, c
 bool fused_apply_available(int nd);
 // multigrid finest level in 2D (LDS-staged operator): op 0 out = x + omega M^{-1} (r - A x),
 // op 1 b1 = P^T (r - A x) and z1 = omega D1^{-1} b1 (0 unless sm); the input x is zin
-// (xin 0), zin + P zc (xin 1; zin may be null) or omega M^{-1} r (xin 2).  False when
-// not available.
+// (xin 0), zin + P zc (xin 1; zin may be null) or omega M^{-1} r (xin 2); with ns = 2 a
+// sweep x <- x + omega M^{-1} (r - A x) comes first, in the same launch.  False when not
+// available.
 template <typename R, typename TIN>
-bool launch_mg_sweep2d(int nd, bool cpl, int op, int xin, const Geom& g, const Scheme& sc, const Coefs<R>& cf,
+bool launch_mg_sweep2d(int nd, bool cpl, int op, int xin, int ns, const Geom& g, const Scheme& sc, const Coefs<R>& cf,
                        const Bdry& bd, const TIN* r, const R* zin, const R* zc, R omega, R* out, const R* dinv1, int sm,
                        R* b1, R* z1, hipStream_t s, const int* skip);
 template <typename R, typename VI, typename VO>

@@ -682,31 +682,36 @@ __device__ __forceinline__ bool xcd_tile(int nx, int ny, int& tbx, int& tby) {
   return true;
 }
 
-// Stage the (LX + 2) x (LY + 2) halo tile whose corner is grid cell (i0, j0): the
-// input x of every cell, from xf(cell, i, j, xv) for grid cells (a ghost takes its
-// boundary cell's value times the ghost weights; the four corners are never read),
-// q = J x for the pressure pairs (xx, xy, yy), and sigma.
-template <typename R, typename XF>
+// Stage the HX x HY halo tile whose corner is grid cell (i0, j0): the input x of
+// every cell, from xf(cell, i, j, xv) for grid cells (a position beyond a
+// non-periodic face takes the value of the boundary cell beside it times the ghost
+// weights, the ghost of that cell; positions outside in both directions are never
+// read), q = J x for the pressure pairs (xx, xy, yy), and sigma.
+template <int HY, int HX, typename R, typename XF>
 __device__ __forceinline__ void stage2d(const Geom& g, const Coefs<R>& cf, const Bdry& bd, int i0, int j0, XF&& xf,
-                                        R (&sx)[3][LHY][LHX], R (&sq)[3][LHY][LHX], R (&ss)[LHY][LHX]) {
+                                        R (&sx)[3][HY][HX], R (&sq)[3][HY][HX], R (&ss)[HY][HX]) {
   constexpr int NR = 3;
   const int64_t N = g.N;
   const int nx = g.n[0], ny = g.n[1];
-  for (int t = threadIdx.x; t < LHX * LHY; t += kApply2dThreads) {
-    const int li = t % LHX, lj = t / LHX;
+  for (int t = threadIdx.x; t < HX * HY; t += kApply2dThreads) {
+    const int li = t % HX, lj = t / HX;
     int gi = i0 + li, gj = j0 + lj;
-    const bool outx = gi < 0 || gi >= nx, outy = gj < 0 || gj >= ny;
+    bool outx = gi < 0 || gi >= nx, outy = gj < 0 || gj >= ny;
+    // periodic coordinates wrap first (a position outside in both directions is a grid
+    // cell, or the ghost of one, when either direction is periodic)
+    if (outx && g.bc[0] == BC_PERIODIC) { gi = (gi % nx + nx) % nx; outx = false; }
+    if (outy && g.bc[2] == BC_PERIODIC) { gj = (gj % ny + ny) % ny; outy = false; }
     R xv[NR] = {(R)0, (R)0, (R)0}, qv[3] = {(R)0, (R)0, (R)0}, sv = (R)0;
     if (!(outx && outy)) {
       int face = -1, d = 0;
       if (outx) {
         d = 0;
-        if (g.bc[0] == BC_PERIODIC) gi = (gi + nx) % nx;
-        else { face = gi < 0 ? 0 : 1; gi = gi < 0 ? 0 : nx - 1; }
+        face = gi < 0 ? 0 : 1;
+        gi = gi < 0 ? 0 : nx - 1;
       } else if (outy) {
         d = 1;
-        if (g.bc[2] == BC_PERIODIC) gj = (gj + ny) % ny;
-        else { face = gj < 0 ? 2 : 3; gj = gj < 0 ? 0 : ny - 1; }
+        face = gj < 0 ? 2 : 3;
+        gj = gj < 0 ? 0 : ny - 1;
       }
       const int64_t cell = (int64_t)gj * nx + gi;
       xf(cell, gi, gj, xv);
@@ -743,10 +748,10 @@ __device__ __forceinline__ void stage2d(const Geom& g, const Coefs<R>& cf, const
 
 // ys = (A x) at grid cell (i, j), staged at (li, lj) of the halo tile; xs[NU] is the
 // cell's own input (the radiation part as staged, the temperature from the caller).
-template <bool CPL, typename R>
+template <bool CPL, int HY, int HX, typename R>
 __device__ __forceinline__ void apply2d_cell(const Geom& g, const Scheme& sc, const Coefs<R>& cf,
-                                             const R (&sx)[3][LHY][LHX], const R (&sq)[3][LHY][LHX],
-                                             const R (&ss)[LHY][LHX], int li, int lj, int i, int j, int64_t cell,
+                                             const R (&sx)[3][HY][HX], const R (&sq)[3][HY][HX],
+                                             const R (&ss)[HY][HX], int li, int lj, int i, int j, int64_t cell,
                                              const R* xs, R* ys) {
   constexpr int NR = 3;
   constexpr int NU = NR + (CPL ? 1 : 0);
@@ -890,7 +895,7 @@ __global__ __launch_bounds__(kApply2dThreads) void k_apply2d_lds(Geom g, Scheme 
         xs[NU - 1] = (R)x[(NU - 1) * N + cell];
       }
     }
-    apply2d_cell<CPL, R>(g, sc, cf, sx, sq, ss, li, lj, i, j, cell, xs, ys);
+    apply2d_cell<CPL, LHY, LHX, R>(g, sc, cf, sx, sq, ss, li, lj, i, j, cell, xs, ys);
 #pragma unroll
     for (int c = 0; c < NU; ++c) {
       R v = ys[c];
@@ -908,7 +913,7 @@ __global__ __launch_bounds__(kApply2dThreads) void k_apply2d_lds(Geom g, Scheme 
 // and the epilogue writes
 //   OP 0: out = x + omega M^{-1} (r - A x)                     (one sweep)
 //   OP 1: b1 = P^T (r - A x), z1 = omega D1^{-1} b1 (0 if !sm)  (level 1's right-hand
-//         side and its first sweep from zero)
+//         side and its first sweep from zero); x itself goes to out unless out is null
 // P: piecewise-constant prolongation from 2 x 2 aggregates (coarse extents
 // (n + 1) / 2, cell (i, j) in aggregate (i / 2, j / 2)).  Tile origins are even, so
 // each aggregate lies inside one tile.  M^{-1}: the block-Jacobi inverses.
@@ -958,7 +963,7 @@ __global__ __launch_bounds__(kApply2dThreads) void k_mg_sweep2d(Geom g, Scheme s
 #pragma unroll
     for (int c = 0; c < NR; ++c) xs[c] = sx[c][lj][li];
     if (CPL) xs[NU - 1] = xin_of(cell, i, j, NU - 1);
-    apply2d_cell<CPL, R>(g, sc, cf, sx, sq, ss, li, lj, i, j, cell, xs, ys);
+    apply2d_cell<CPL, LHY, LHX, R>(g, sc, cf, sx, sq, ss, li, lj, i, j, cell, xs, ys);
 #pragma unroll
     for (int k = 0; k < NU; ++k) res[k] = (R)r[k * N + cell] - ys[k];
     if (OP == 0) {
@@ -975,6 +980,11 @@ __global__ __launch_bounds__(kApply2dThreads) void k_mg_sweep2d(Geom g, Scheme s
     for (int k = 0; k < NU; ++k) res[k] = (R)0;
   }
   if (OP == 1) {
+    // the operator's input is the pre-smoothed vector: written out when asked for
+    if (out && inside) {
+#pragma unroll
+      for (int k = 0; k < NU; ++k) out[k * N + cell] = k < NR ? sx[k][ty + 1][tx + 1] : xin_of(cell, i, j, NU - 1);
+    }
     // gather the residuals of each 2 x 2 aggregate through LDS (the halo tile is no
     // longer read once every thread has passed the barrier)
     __syncthreads();
@@ -1056,29 +1066,228 @@ void launch_residual(int nd, bool cpl, const Geom& g, const Scheme& sc, const Co
   }
 }
 
+// The same with two operator applications per launch: the input is staged with a
+// halo of two cells (68 x 20), the first sweep x1 = x + omega M^{-1} (r - A x) is
+// taken on the tile and its one-cell ring (66 x 18: the ring's sweep is
+// recomputed by each of the tiles that share it) and kept in LDS with q1 = J x1,
+// the ghosts beyond non-periodic faces are refreshed from the swept boundary cells,
+// and the epilogue of OP is applied to x1 on the tile.  Halves the finest-level
+// launches of a cycle.
+constexpr int L2X = LX + 4, L2Y = LY + 4;
+
+template <bool CPL, int OP, int XIN, typename R, typename TIN>
+__global__ __launch_bounds__(kApply2dThreads) void k_mg_sweep2d_x2(Geom g, Scheme sc, Coefs<R> cf, Bdry bd,
+                                                                   const TIN* __restrict__ r, const R* __restrict__ zin,
+                                                                   const R* __restrict__ zc, R omega,
+                                                                   R* __restrict__ out, const R* __restrict__ dinv1,
+                                                                   int sm, R* __restrict__ b1, R* __restrict__ z1,
+                                                                   const int* __restrict__ skip) {
+  constexpr int NR = 3;
+  constexpr int NU = NR + (CPL ? 1 : 0);
+  static_assert(kApply2dThreads == LX * LY, "one tile cell per thread");
+  if (skip && *skip) return;
+  __shared__ R sx0[NR][L2Y][L2X];
+  __shared__ R sq0[3][L2Y][L2X];
+  __shared__ R ss0[L2Y][L2X];
+  __shared__ R sx1[NR][LHY][LHX];
+  __shared__ R sq1[3][LHY][LHX];
+  __shared__ R ss1[LHY][LHX];
+  __shared__ R sT1[CPL ? LHY : 1][CPL ? LHX : 1];
+  const int64_t N = g.N;
+  const int nx = g.n[0], ny = g.n[1];
+  const int ncx = (nx + 1) / 2;
+  const int64_t Nc = (int64_t)ncx * ((ny + 1) / 2);
+  const bool perx = g.bc[0] == BC_PERIODIC, pery = g.bc[2] == BC_PERIODIC;
+  int tbx, tby;
+  if (!xcd_tile(nx, ny, tbx, tby)) return;
+  auto xin_of = [&](int64_t cell, int gi, int gj, int k) -> R {
+    if (XIN == 0) return zin[k * N + cell];
+    if (XIN == 1) return (zin ? zin[k * N + cell] : (R)0) + zc[k * Nc + (int64_t)(gj / 2) * ncx + gi / 2];
+    R acc = (R)0;
+#pragma unroll
+    for (int c = 0; c < NU; ++c) acc += cf.bjinv[(k * NU + c) * N + cell] * (R)r[c * N + cell];
+    return omega * acc;
+  };
+  stage2d(g, cf, bd, tbx * LX - 2, tby * LY - 2, [&](int64_t cell, int gi, int gj, R* xv) {
+#pragma unroll
+    for (int c = 0; c < NR; ++c) xv[c] = xin_of(cell, gi, gj, c);
+  }, sx0, sq0, ss0);
+  __syncthreads();
+  // ---- first sweep on the tile and its ring (grid cells only; ghosts below) ----
+  for (int t = threadIdx.x; t < LHX * LHY; t += kApply2dThreads) {
+    const int pi = t % LHX, pj = t / LHX;
+    int gi = tbx * LX - 1 + pi, gj = tby * LY - 1 + pj;
+    const bool outx = gi < 0 || gi >= nx, outy = gj < 0 || gj >= ny;
+    if ((outx && !perx) || (outy && !pery)) continue;   // ghost or unused corner
+    if (outx) gi = (gi + nx) % nx;
+    if (outy) gj = (gj + ny) % ny;
+    const int64_t cell = (int64_t)gj * nx + gi;
+    R xs[NU], ys[NU];
+#pragma unroll
+    for (int c = 0; c < NR; ++c) xs[c] = sx0[c][pj + 1][pi + 1];
+    if (CPL) xs[NU - 1] = xin_of(cell, gi, gj, NU - 1);
+    apply2d_cell<CPL, L2Y, L2X, R>(g, sc, cf, sx0, sq0, ss0, pi + 1, pj + 1, gi, gj, cell, xs, ys);
+    R res[NU];
+#pragma unroll
+    for (int k = 0; k < NU; ++k) res[k] = (R)r[k * N + cell] - ys[k];
+    R x1[NU];
+#pragma unroll
+    for (int rr = 0; rr < NU; ++rr) {
+      R acc = (R)0;
+#pragma unroll
+      for (int k = 0; k < NU; ++k) acc += cf.bjinv[(rr * NU + k) * N + cell] * res[k];
+      x1[rr] = xs[rr] + omega * acc;
+    }
+#pragma unroll
+    for (int c = 0; c < NR; ++c) sx1[c][pj][pi] = x1[c];
+#pragma unroll
+    for (int pq = 0; pq < 3; ++pq) {
+      R acc = (R)0;
+#pragma unroll
+      for (int k = 0; k < NR; ++k) acc += cf.jac[(pq * NR + k) * N + cell] * x1[k];
+      sq1[pq][pj][pi] = acc;
+    }
+    ss1[pj][pi] = ss0[pj + 1][pi + 1];
+    if (CPL) sT1[pj][pi] = x1[NU - 1];
+  }
+  __syncthreads();
+  // ---- ghosts of the swept boundary cells (the positions just beyond a non-periodic
+  // face; positions further out and corners are never read) ----
+  for (int t = threadIdx.x; t < LHX * LHY; t += kApply2dThreads) {
+    const int pi = t % LHX, pj = t / LHX;
+    int gi = tbx * LX - 1 + pi, gj = tby * LY - 1 + pj;
+    bool outx = gi < 0 || gi >= nx, outy = gj < 0 || gj >= ny;
+    if (outx && perx) { gi = (gi % nx + nx) % nx; outx = false; }
+    if (outy && pery) { gj = (gj % ny + ny) % ny; outy = false; }
+    if (!(outx || outy) || (outx && outy)) continue;   // a grid cell, or never read
+    if ((outx && gi != -1 && gi != nx) || (outy && gj != -1 && gj != ny)) continue;
+    int face, d, bi = pi, bj = pj;
+    int64_t pidx;
+    if (outx) {
+      d = 0;
+      face = gi < 0 ? 0 : 1;
+      bi = gi < 0 ? pi + 1 : pi - 1;
+      pidx = gj;
+    } else {
+      d = 1;
+      face = gj < 0 ? 2 : 3;
+      bj = gj < 0 ? pj + 1 : pj - 1;
+      pidx = gi;
+    }
+    const int64_t pn = g.plane_n[d];
+    R xv[NR];
+#pragma unroll
+    for (int c = 0; c < NR; ++c) xv[c] = sx1[c][bj][bi] * (R)ghost_weight(g.bc[face], d, c, bd.mask[face], pidx);
+#pragma unroll
+    for (int c = 0; c < NR; ++c) sx1[c][pj][pi] = xv[c];
+#pragma unroll
+    for (int pq = 0; pq < 3; ++pq) {
+      R acc = (R)0;
+#pragma unroll
+      for (int k = 0; k < NR; ++k) acc += cf.gjac[cf.gjoff[face] + (pq * NR + k) * pn + pidx] * xv[k];
+      sq1[pq][pj][pi] = acc;
+    }
+    ss1[pj][pi] = ss1[bj][bi];
+  }
+  __syncthreads();
+  // ---- second application on the tile ----
+  const int tx = threadIdx.x % LX, ty = threadIdx.x / LX;
+  const int i = tbx * LX + tx, j = tby * LY + ty;
+  const bool inside = i < nx && j < ny;
+  const int64_t cell = (int64_t)j * nx + i;
+  R res[NU];
+  if (inside) {
+    const int li = tx + 1, lj = ty + 1;
+    R xs[NU], ys[NU];
+#pragma unroll
+    for (int c = 0; c < NR; ++c) xs[c] = sx1[c][lj][li];
+    if (CPL) xs[NU - 1] = sT1[lj][li];
+    apply2d_cell<CPL, LHY, LHX, R>(g, sc, cf, sx1, sq1, ss1, li, lj, i, j, cell, xs, ys);
+#pragma unroll
+    for (int k = 0; k < NU; ++k) res[k] = (R)r[k * N + cell] - ys[k];
+    if (OP == 0) {
+#pragma unroll
+      for (int rr = 0; rr < NU; ++rr) {
+        R acc = (R)0;
+#pragma unroll
+        for (int k = 0; k < NU; ++k) acc += cf.bjinv[(rr * NU + k) * N + cell] * res[k];
+        out[rr * N + cell] = xs[rr] + omega * acc;
+      }
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < NU; ++k) res[k] = (R)0;
+  }
+  if (OP == 1) {
+    // the operator's input (the first sweep's result) is the pre-smoothed vector
+    if (out && inside) {
+#pragma unroll
+      for (int k = 0; k < NU; ++k) out[k * N + cell] = k < NR ? sx1[k][ty + 1][tx + 1] : sT1[CPL ? ty + 1 : 0][CPL ? tx + 1 : 0];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NU; ++k) {
+      if (k < NR) sx0[k][ty][tx] = res[k];
+      else sq0[0][ty][tx] = res[k];
+    }
+    __syncthreads();
+    if (inside && (tx % 2) == 0 && (ty % 2) == 0) {
+      const int64_t I = (int64_t)(j / 2) * ncx + i / 2;
+      R acc[NU];
+#pragma unroll
+      for (int k = 0; k < NU; ++k) acc[k] = (R)0;
+      for (int cy = 0; cy < 2; ++cy)
+        for (int cx = 0; cx < 2; ++cx) {
+          if (i + cx >= nx || j + cy >= ny) continue;
+#pragma unroll
+          for (int k = 0; k < NU; ++k) acc[k] += k < NR ? sx0[k][ty + cy][tx + cx] : sq0[0][ty + cy][tx + cx];
+        }
+#pragma unroll
+      for (int k = 0; k < NU; ++k) b1[k * Nc + I] = acc[k];
+#pragma unroll
+      for (int rr = 0; rr < NU; ++rr) {
+        R z = (R)0;
+        if (sm) {
+#pragma unroll
+          for (int k = 0; k < NU; ++k) z += dinv1[(rr * NU + k) * Nc + I] * acc[k];
+          z *= omega;
+        }
+        z1[rr * Nc + I] = z;
+      }
+    }
+  }
+}
+
 template <typename R, typename TIN>
-bool launch_mg_sweep2d(int nd, bool cpl, int op, int xin, const Geom& g, const Scheme& sc, const Coefs<R>& cf,
+bool launch_mg_sweep2d(int nd, bool cpl, int op, int xin, int ns, const Geom& g, const Scheme& sc, const Coefs<R>& cf,
                        const Bdry& bd, const TIN* r, const R* zin, const R* zc, R omega, R* out, const R* dinv1, int sm,
                        R* b1, R* z1, hipStream_t s, const int* skip) {
-  if (!fused_apply_available(nd) || op < 0 || op > 1 || xin < 0 || xin > 2) return false;
+  if (!fused_apply_available(nd) || op < 0 || op > 1 || xin < 0 || xin > 2 || ns < 1 || ns > 2) return false;
   const dim3 grd2 = grid2d_xcd(g);
-#define M1_SW(CPL_, OP_, XIN_) \
-  k_mg_sweep2d<CPL_, OP_, XIN_, R, TIN><<<grd2, kApply2dThreads, 0, s>>>(g, sc, cf, bd, r, zin, zc, omega, out, dinv1, sm, b1, z1, skip)
+#define M1_SW(CPL_, OP_, XIN_)                                                                                        \
+  {                                                                                                                   \
+    if (ns == 2)                                                                                                      \
+      k_mg_sweep2d_x2<CPL_, OP_, XIN_, R, TIN><<<grd2, kApply2dThreads, 0, s>>>(g, sc, cf, bd, r, zin, zc, omega, out, \
+                                                                                dinv1, sm, b1, z1, skip);            \
+    else                                                                                                              \
+      k_mg_sweep2d<CPL_, OP_, XIN_, R, TIN><<<grd2, kApply2dThreads, 0, s>>>(g, sc, cf, bd, r, zin, zc, omega, out,    \
+                                                                             dinv1, sm, b1, z1, skip);               \
+  }
 #define M1_SW_X(CPL_, OP_) \
-  { if (xin == 0) M1_SW(CPL_, OP_, 0); else if (xin == 1) M1_SW(CPL_, OP_, 1); else M1_SW(CPL_, OP_, 2); }
+  { if (xin == 0) M1_SW(CPL_, OP_, 0) else if (xin == 1) M1_SW(CPL_, OP_, 1) else M1_SW(CPL_, OP_, 2) }
   if (cpl) { if (op == 0) M1_SW_X(true, 0) else M1_SW_X(true, 1) }
   else { if (op == 0) M1_SW_X(false, 0) else M1_SW_X(false, 1) }
 #undef M1_SW_X
 #undef M1_SW
   return true;
 }
-template bool launch_mg_sweep2d<double, double>(int, bool, int, int, const Geom&, const Scheme&, const Coefs<double>&,
+template bool launch_mg_sweep2d<double, double>(int, bool, int, int, int, const Geom&, const Scheme&, const Coefs<double>&,
                                                 const Bdry&, const double*, const double*, const double*, double,
                                                 double*, const double*, int, double*, double*, hipStream_t, const int*);
-template bool launch_mg_sweep2d<float, double>(int, bool, int, int, const Geom&, const Scheme&, const Coefs<float>&,
+template bool launch_mg_sweep2d<float, double>(int, bool, int, int, int, const Geom&, const Scheme&, const Coefs<float>&,
                                                const Bdry&, const double*, const float*, const float*, float, float*,
                                                const float*, int, float*, float*, hipStream_t, const int*);
-template bool launch_mg_sweep2d<float, float>(int, bool, int, int, const Geom&, const Scheme&, const Coefs<float>&,
+template bool launch_mg_sweep2d<float, float>(int, bool, int, int, int, const Geom&, const Scheme&, const Coefs<float>&,
                                               const Bdry&, const float*, const float*, const float*, float, float*,
                                               const float*, int, float*, float*, hipStream_t, const int*);
 

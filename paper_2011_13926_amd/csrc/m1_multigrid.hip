@@ -20,6 +20,7 @@
 // entries and vectors are component-major (SoA) per level, so consecutive
 // threads (cells) read consecutive addresses.
 #include <algorithm>
+#include <cstdlib>
 #include <functional>
 #include <vector>
 
@@ -727,6 +728,16 @@ void mg_build(MgHierarchy& h, int nd, int nu, hipStream_t s) {
   }
 }
 
+// operator applications per fused finest-level launch (M1_MG_SWEEPS_PER_LAUNCH=1: one)
+static int g_per_launch = -1;
+static int sweeps_per_launch() {
+  if (g_per_launch < 0) {
+    const char* e = getenv("M1_MG_SWEEPS_PER_LAUNCH");
+    g_per_launch = (e && e[0] == '1') ? 1 : 2;
+  }
+  return g_per_launch;
+}
+
 template <typename R> static const R* stencil(const MgLevel& L);
 template <> const double* stencil<double>(const MgLevel& L) { return L.S64; }
 template <> const float* stencil<float>(const MgLevel& L) { return L.S32; }
@@ -773,6 +784,7 @@ void mg_vcycle(const MgHierarchy& h, const MgFine<R>& fine, const TIN* r, R* z, 
   // fused form (2D): sweeps and the restricted residual on the LDS-staged operator,
   // the first two sweeps in one launch (its input omega M^{-1} r formed while staging)
   const bool fused = fine.sweep != nullptr;
+  const int per_launch = sweeps_per_launch();
   const int r64 = sizeof(TIN) == 8 ? 1 : 0;
   const double Nc1 = (double)h.lev[1].g.N;
   // algorithmic bytes of a fused launch: coefficients, the input (xin), r, M^{-1}, the output
@@ -788,19 +800,25 @@ void mg_vcycle(const MgHierarchy& h, const MgFine<R>& fine, const TIN* r, R* z, 
   const MgLevel& Lv1 = h.lev[1];
   const int sm1 = (h.nu1c > 0 && h.nlev > 2) ? 1 : 0;
   if (fused && h.nu1 > 0) {
-    int done = 0;
-    if (h.nu1 >= 2) {
-      run(KC_MG_FINE, sweep_bytes(0, 2, false, 0), [&] { fine.sweep(fine.self, 0, 2, r, r64, nullptr, nullptr, om, z0, nullptr, 0, nullptr, nullptr, s, skip); });
-      done = 2;
-    } else {
-      run(KC_MG_FINE, fine_smooth_bytes(false, false), [&] { M1_MG_NU_SWITCH(nu, (k_mg_fine_smooth<NU, R, TIN><<<grid1(N0), kMgThreads, 0, s>>>(N0, fine.bjinv, om, r, nullptr, nullptr, z0, skip))) });
-      done = 1;
+    // the first sweep is the staged input omega M^{-1} r of the first launch; the nu1 - 1
+    // further sweeps and the restricted residual are nu1 operator applications, two per
+    // launch; the last launch restricts and writes its input, the pre-smoothed z0
+    int apps = h.nu1;
+    int xin = 2;
+    while (apps > 0) {
+      const int ns = apps >= per_launch ? per_launch : 1;
+      apps -= ns;
+      if (apps > 0) {
+        run(KC_MG_FINE, sweep_bytes(0, xin, true, 0), [&] { fine.sweep(fine.self, 0, xin, ns, r, r64, z0, nullptr, om, zp, nullptr, 0, nullptr, nullptr, s, skip); });
+        std::swap(z0, zp);
+      } else {
+        // z0 already holds the input when it came from memory (xin 0 and one application)
+        R* keep = (xin == 0 && ns == 1) ? nullptr : zp;
+        run(KC_MG_FINE, sweep_bytes(1, xin, true, sm1) + (keep ? N0 * cu * rs : 0.0), [&] { fine.sweep(fine.self, 1, xin, ns, r, r64, z0, nullptr, om, keep, dinv<R>(Lv1), sm1, (R*)Lv1.b, (R*)Lv1.z, s, skip); });
+        if (keep) std::swap(z0, zp);
+      }
+      xin = 0;
     }
-    for (int k = done; k < h.nu1; ++k) {
-      run(KC_MG_FINE, sweep_bytes(0, 0, true, 0), [&] { fine.sweep(fine.self, 0, 0, r, r64, z0, nullptr, om, zp, nullptr, 0, nullptr, nullptr, s, skip); });
-      std::swap(z0, zp);
-    }
-    run(KC_MG_FINE, sweep_bytes(1, 0, true, sm1), [&] { fine.sweep(fine.self, 1, 0, r, r64, z0, nullptr, om, nullptr, dinv<R>(Lv1), sm1, (R*)Lv1.b, (R*)Lv1.z, s, skip); });
   } else {
     if (h.nu1 > 0) {
       run(KC_MG_FINE, fine_smooth_bytes(false, false), [&] { M1_MG_NU_SWITCH(nu, (k_mg_fine_smooth<NU, R, TIN><<<grid1(N0), kMgThreads, 0, s>>>(N0, fine.bjinv, om, r, nullptr, nullptr, z0, skip))) });
@@ -876,12 +894,20 @@ void mg_vcycle(const MgHierarchy& h, const MgFine<R>& fine, const TIN* r, R* z, 
     const MgLevel& L1 = h.lev[1];
     const R* zin = h.nu1 > 0 ? z0 : nullptr;
     if (fused && h.nu2 > 0) {
-      // the first sweep's input is z0 + P z1, formed while staging
-      for (int k = 0; k < h.nu2; ++k) {
-        const R* src = k == 0 ? zin : ((k % 2 == 1) ? zp : z0);
-        R* dst = (k == h.nu2 - 1) ? z : ((k % 2 == 0) ? zp : z0);
-        if (k == 0) run(KC_MG_FINE, sweep_bytes(0, 1, zin != nullptr, 0), [&] { fine.sweep(fine.self, 0, 1, r, r64, src, zl[1], om, dst, nullptr, 0, nullptr, nullptr, s, skip); });
-        else run(KC_MG_FINE, sweep_bytes(0, 0, true, 0), [&] { fine.sweep(fine.self, 0, 0, r, r64, src, nullptr, om, dst, nullptr, 0, nullptr, nullptr, s, skip); });
+      // the first launch's input is z0 + P z1, formed while staging; two sweeps per launch
+      int left = h.nu2;
+      const R* src = zin;
+      R* bufs[2] = {zp, z0};
+      int nb2 = 0;
+      bool first = true;
+      while (left > 0) {
+        const int ns = left >= per_launch ? per_launch : 1;
+        left -= ns;
+        R* dst = left == 0 ? z : bufs[nb2++ % 2];
+        if (first) run(KC_MG_FINE, sweep_bytes(0, 1, zin != nullptr, 0), [&] { fine.sweep(fine.self, 0, 1, ns, r, r64, src, zl[1], om, dst, nullptr, 0, nullptr, nullptr, s, skip); });
+        else run(KC_MG_FINE, sweep_bytes(0, 0, true, 0), [&] { fine.sweep(fine.self, 0, 0, ns, r, r64, src, nullptr, om, dst, nullptr, 0, nullptr, nullptr, s, skip); });
+        src = dst;
+        first = false;
       }
       return;
     }

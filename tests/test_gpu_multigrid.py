@@ -68,6 +68,10 @@ CYCLE_CASES = [
     ((131, 37), BC2["mixed"], "none", "wb", 4, 4, 0, 2, 2),
     ((70, 33), BC2["walls"], "coupled_t", "wb", 2, 3, 0, -1, -1),
     ((66, 18), BC2["periodic"], "absorption", "centered", 3, 1, 0, 1, 1),
+    # two sweeps per launch with one periodic and one bounded direction: the halo's
+    # corners are grid cells or ghosts of grid cells there
+    ((70, 40), ("periodic", "periodic", "outflow", "dirichlet"), "coupled_t", "wb", 3, 2, 0, 1, 1),
+    ((70, 40), ("outflow", "reflect", "periodic", "periodic"), "none", "wb", 2, 4, 0, -1, -1),
 ]
 
 
