@@ -61,7 +61,8 @@ CLASS_KERNEL = {
     "true_residual": ("k_apply2d_lds<false, 1", "k_apply2d_lds<true, 1", "k_stencil<2, false, 1",
                       "k_stencil<2, true, 1", "k_stencil<3, false, 1", "k_stencil<3, true, 1"),
     "time_step": ("k_step2d_lds<", "k_step_direct<"),
-    "mg_fine": ("k_mg_fine_smooth<", "k_mg_restrict_fine<", "k_mg_prolong_fine<", "k_mg_cast<", "k_mg_sweep2d<"),
+    "mg_fine": ("k_mg_fine_smooth<", "k_mg_restrict_fine<", "k_mg_prolong_fine<", "k_mg_cast<", "k_mg_sweep2d<",
+                "k_mg_sweep2d_x2<"),
     "mg_smooth": ("k_mg_smooth<", "k_mg_prolong<"),
     "mg_down": ("k_mg_down_lanes<",),
     "mg_coarse_solve": ("k_mg_coarse_solve<",),
@@ -162,12 +163,12 @@ WORKLOADS = {
                                  solver=dict(rtol=1e-8, newton_rtol=1e-8, max_iters=300, newton_max=30, **GLOBALISED),
                                  cpu_sample=None),
 }
-# V(8,8) on the finest level (its sweeps fused into the staged operator, the cheap
-# part of a cycle), one sweep each way below it, damping 0.9: the fastest mixed
-# step of a sweep over fine sweeps 3..8, coarse sweeps 1..3 and damping 0.7..1.1 on
-# the 512^2 Voronoi step (0.50 s against 0.82 s for V(4,4) with 2 coarse sweeps at
-# 0.7; damping 1.0 doubles the iterations and 1.1 diverges)
-MG = dict(pc="mg", mg_nu1=8, mg_nu2=8, mg_nu1_coarse=1, mg_nu2_coarse=1, mg_omega=0.9)
+# V(12,12) on the finest level (its sweeps fused into the staged operator, two per
+# launch: the cheap part of a cycle), one sweep each way below it, damping 0.9: the
+# fastest mixed step of sweeps over fine sweeps 3..16, coarse sweeps 0..3 and damping
+# 0.7..1.1 on the 512^2 Voronoi step (0.40 s against 0.45 s for V(8,8) and 0.82 s for
+# V(4,4) with 2 coarse sweeps at 0.7; damping 1.0 doubles the iterations, 1.1 diverges)
+MG = dict(pc="mg", mg_nu1=12, mg_nu2=12, mg_nu1_coarse=1, mg_nu2_coarse=1, mg_omega=0.9)
 VARIANTS = {
     "fp64_bj": dict(precision="fp64", pc="bj"),
     "mixed_bj": dict(precision="mixed", basis_fp32=False, inner_rtol=1e-6, pc="bj"),

@@ -154,8 +154,8 @@ typedef struct {
   const char* nn_weights_path; /* host string or NULL (learned preconditioner) */
   /* aggregation multigrid (pc = M1_PC_MULTIGRID; ignored otherwise) */
   double mg_omega;         /* damping of the block-Jacobi smoother, in (0, 2) */
-  int32_t mg_nu1;          /* pre-smoothing sweeps, 0..8 */
-  int32_t mg_nu2;          /* post-smoothing sweeps, 0..8 */
+  int32_t mg_nu1;          /* pre-smoothing sweeps, 0..16 */
+  int32_t mg_nu2;          /* post-smoothing sweeps, 0..16 */
   int32_t mg_nmin;         /* coarsen while an extent exceeds this (>= 2; 0: 8 in 2D, 4 in 3D); the
                               coarsest level (solved exactly) may hold at most 512 unknowns */
   int32_t wb_boundary;     /* 1: Eq. "boundaryCondition" (Sect. 3.1.2): on every face between a cell and a

@@ -216,7 +216,7 @@ m1_status validate_config(const m1_config* c, std::string& err) {
   }
   if (c->pc == M1_PC_MULTIGRID) {
     if (!(finite(c->mg_omega) && c->mg_omega > 0 && c->mg_omega < 2)) { err = "mg_omega must be in (0, 2)"; return M1_ERR_INVALID_ARG; }
-    if (c->mg_nu1 < 0 || c->mg_nu1 > 8 || c->mg_nu2 < 0 || c->mg_nu2 > 8) { err = "mg_nu1 and mg_nu2 must be in 0..8"; return M1_ERR_INVALID_ARG; }
+    if (c->mg_nu1 < 0 || c->mg_nu1 > 16 || c->mg_nu2 < 0 || c->mg_nu2 > 16) { err = "mg_nu1 and mg_nu2 must be in 0..16"; return M1_ERR_INVALID_ARG; }
     if (c->mg_nu1_coarse < -1 || c->mg_nu1_coarse > 4 || c->mg_nu2_coarse < -1 || c->mg_nu2_coarse > 4) {
       err = "mg_nu1_coarse and mg_nu2_coarse must be in -1..4";
       return M1_ERR_INVALID_ARG;
