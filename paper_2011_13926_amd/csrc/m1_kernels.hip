@@ -664,16 +664,19 @@ __global__ __launch_bounds__(256) void k_stencil(Geom g, Scheme sc, Coefs<R> cf,
 // contiguous band of tiles and the halo lines that neighbouring tiles share
 // meet in the same L2 instead of being fetched once per XCD.
 // ----------------------------------------------------------------------------
-constexpr int LX = 64, LY = 16, LHX = LX + 2, LHY = LY + 2;
-constexpr int kApply2dThreads = 1024;  // one cell per thread: 16 waves per tile hide the staging latency
+// Tiles are LX = 64 cells wide (one wavefront per row) and TR rows high (16 or 8), one
+// cell per thread.
+constexpr int LX = 64, LHX = LX + 2;
 
-__host__ __device__ inline int tiles2d(int nx, int ny) { return ((nx + LX - 1) / LX) * ((ny + LY - 1) / LY); }
-inline dim3 grid2d_xcd(const Geom& g) { return dim3(8 * ((tiles2d(g.n[0], g.n[1]) + 7) / 8)); }
+template <int TR> __host__ __device__ inline int tiles2d(int nx, int ny) {
+  return ((nx + LX - 1) / LX) * ((ny + TR - 1) / TR);
+}
+template <int TR> inline dim3 grid2d_xcd(const Geom& g) { return dim3(8 * ((tiles2d<TR>(g.n[0], g.n[1]) + 7) / 8)); }
 
 // tile (tbx, tby) of this workgroup; false for the padding workgroups
-__device__ __forceinline__ bool xcd_tile(int nx, int ny, int& tbx, int& tby) {
+template <int TR> __device__ __forceinline__ bool xcd_tile(int nx, int ny, int& tbx, int& tby) {
   const int gx = (nx + LX - 1) / LX;
-  const int gt = tiles2d(nx, ny);
+  const int gt = tiles2d<TR>(nx, ny);
   const int per = (gt + 7) / 8;
   const int T = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
   if (T >= gt) return false;
@@ -687,13 +690,13 @@ __device__ __forceinline__ bool xcd_tile(int nx, int ny, int& tbx, int& tby) {
 // non-periodic face takes the value of the boundary cell beside it times the ghost
 // weights, the ghost of that cell; positions outside in both directions are never
 // read), q = J x for the pressure pairs (xx, xy, yy), and sigma.
-template <int HY, int HX, typename R, typename XF>
+template <int NT, int HY, int HX, typename R, typename XF>
 __device__ __forceinline__ void stage2d(const Geom& g, const Coefs<R>& cf, const Bdry& bd, int i0, int j0, XF&& xf,
                                         R (&sx)[3][HY][HX], R (&sq)[3][HY][HX], R (&ss)[HY][HX]) {
   constexpr int NR = 3;
   const int64_t N = g.N;
   const int nx = g.n[0], ny = g.n[1];
-  for (int t = threadIdx.x; t < HX * HY; t += kApply2dThreads) {
+  for (int t = threadIdx.x; t < HX * HY; t += NT) {
     const int li = t % HX, lj = t / HX;
     int gi = i0 + li, gj = j0 + lj;
     bool outx = gi < 0 || gi >= nx, outy = gj < 0 || gj >= ny;
@@ -843,21 +846,21 @@ __device__ __forceinline__ void apply2d_cell(const Geom& g, const Scheme& sc, co
 
 // PRE = true: the input is u and the operator is applied to z = M^{-1} u, the
 // block-Jacobi solve done per staged cell (fused right preconditioning).
-template <bool CPL, int MODE, bool PRE, typename R, typename VI, typename VO>
-__global__ __launch_bounds__(kApply2dThreads) void k_apply2d_lds(Geom g, Scheme sc, Coefs<R> cf, Bdry bd, const VI* __restrict__ x,
+template <int TR, bool CPL, int MODE, bool PRE, typename R, typename VI, typename VO>
+__global__ __launch_bounds__(LX * TR) void k_apply2d_lds(Geom g, Scheme sc, Coefs<R> cf, Bdry bd, const VI* __restrict__ x,
                                                      const double* __restrict__ b, VO* __restrict__ y,
                                                      const int* __restrict__ skip) {
   constexpr int NR = 3;
   constexpr int NU = NR + (CPL ? 1 : 0);
   if (skip && *skip) return;
-  __shared__ R sx[NR][LHY][LHX];
-  __shared__ R sq[3][LHY][LHX];
-  __shared__ R ss[LHY][LHX];
+  __shared__ R sx[NR][(TR + 2)][LHX];
+  __shared__ R sq[3][(TR + 2)][LHX];
+  __shared__ R ss[(TR + 2)][LHX];
   const int64_t N = g.N;
   const int nx = g.n[0], ny = g.n[1];
   int tbx, tby;
-  if (!xcd_tile(nx, ny, tbx, tby)) return;
-  stage2d(g, cf, bd, tbx * LX - 1, tby * LY - 1, [&](int64_t cell, int, int, R* xv) {
+  if (!xcd_tile<TR>(nx, ny, tbx, tby)) return;
+  stage2d<LX * TR>(g, cf, bd, tbx * LX - 1, tby * TR - 1, [&](int64_t cell, int, int, R* xv) {
     if (PRE) {
       R uv[NU];
 #pragma unroll
@@ -877,8 +880,8 @@ __global__ __launch_bounds__(kApply2dThreads) void k_apply2d_lds(Geom g, Scheme 
   __syncthreads();
   // ---- fluxes: one cell per thread ----
   const int tx = threadIdx.x % LX;
-  for (int ty = threadIdx.x / LX; ty < LY; ty += kApply2dThreads / LX) {
-    const int i = tbx * LX + tx, j = tby * LY + ty;
+  for (int ty = threadIdx.x / LX; ty < TR; ty += (LX * TR) / LX) {
+    const int i = tbx * LX + tx, j = tby * TR + ty;
     if (i >= nx || j >= ny) continue;
     const int64_t cell = (int64_t)j * nx + i;
     const int li = tx + 1, lj = ty + 1;
@@ -895,7 +898,7 @@ __global__ __launch_bounds__(kApply2dThreads) void k_apply2d_lds(Geom g, Scheme 
         xs[NU - 1] = (R)x[(NU - 1) * N + cell];
       }
     }
-    apply2d_cell<CPL, LHY, LHX, R>(g, sc, cf, sx, sq, ss, li, lj, i, j, cell, xs, ys);
+    apply2d_cell<CPL, (TR + 2), LHX, R>(g, sc, cf, sx, sq, ss, li, lj, i, j, cell, xs, ys);
 #pragma unroll
     for (int c = 0; c < NU; ++c) {
       R v = ys[c];
@@ -918,26 +921,25 @@ __global__ __launch_bounds__(kApply2dThreads) void k_apply2d_lds(Geom g, Scheme 
 // (n + 1) / 2, cell (i, j) in aggregate (i / 2, j / 2)).  Tile origins are even, so
 // each aggregate lies inside one tile.  M^{-1}: the block-Jacobi inverses.
 // ----------------------------------------------------------------------------
-template <bool CPL, int OP, int XIN, typename R, typename TIN>
-__global__ __launch_bounds__(kApply2dThreads) void k_mg_sweep2d(Geom g, Scheme sc, Coefs<R> cf, Bdry bd,
+template <int TR, bool CPL, int OP, int XIN, typename R, typename TIN>
+__global__ __launch_bounds__(LX * TR) void k_mg_sweep2d(Geom g, Scheme sc, Coefs<R> cf, Bdry bd,
                                                                 const TIN* __restrict__ r, const R* __restrict__ zin,
                                                                 const R* __restrict__ zc, R omega, R* __restrict__ out,
                                                                 const R* __restrict__ dinv1, int sm, R* __restrict__ b1,
                                                                 R* __restrict__ z1, const int* __restrict__ skip) {
   constexpr int NR = 3;
   constexpr int NU = NR + (CPL ? 1 : 0);
-  static_assert(kApply2dThreads == LX * LY, "one cell per thread");
-  static_assert(LX % 2 == 0 && LY % 2 == 0, "aggregates inside a tile");
+  static_assert(LX % 2 == 0 && TR % 2 == 0, "aggregates inside a tile");
   if (skip && *skip) return;
-  __shared__ R sx[NR][LHY][LHX];
-  __shared__ R sq[3][LHY][LHX];
-  __shared__ R ss[LHY][LHX];
+  __shared__ R sx[NR][(TR + 2)][LHX];
+  __shared__ R sq[3][(TR + 2)][LHX];
+  __shared__ R ss[(TR + 2)][LHX];
   const int64_t N = g.N;
   const int nx = g.n[0], ny = g.n[1];
   const int ncx = (nx + 1) / 2;
   const int64_t Nc = (int64_t)ncx * ((ny + 1) / 2);
   int tbx, tby;
-  if (!xcd_tile(nx, ny, tbx, tby)) return;
+  if (!xcd_tile<TR>(nx, ny, tbx, tby)) return;
   // input component k of grid cell (gi, gj)
   auto xin_of = [&](int64_t cell, int gi, int gj, int k) -> R {
     if (XIN == 0) return zin[k * N + cell];
@@ -947,13 +949,13 @@ __global__ __launch_bounds__(kApply2dThreads) void k_mg_sweep2d(Geom g, Scheme s
     for (int c = 0; c < NU; ++c) acc += cf.bjinv[(k * NU + c) * N + cell] * (R)r[c * N + cell];
     return omega * acc;
   };
-  stage2d(g, cf, bd, tbx * LX - 1, tby * LY - 1, [&](int64_t cell, int gi, int gj, R* xv) {
+  stage2d<LX * TR>(g, cf, bd, tbx * LX - 1, tby * TR - 1, [&](int64_t cell, int gi, int gj, R* xv) {
 #pragma unroll
     for (int c = 0; c < NR; ++c) xv[c] = xin_of(cell, gi, gj, c);
   }, sx, sq, ss);
   __syncthreads();
   const int tx = threadIdx.x % LX, ty = threadIdx.x / LX;
-  const int i = tbx * LX + tx, j = tby * LY + ty;
+  const int i = tbx * LX + tx, j = tby * TR + ty;
   const bool inside = i < nx && j < ny;
   const int64_t cell = (int64_t)j * nx + i;
   R res[NU];
@@ -963,7 +965,7 @@ __global__ __launch_bounds__(kApply2dThreads) void k_mg_sweep2d(Geom g, Scheme s
 #pragma unroll
     for (int c = 0; c < NR; ++c) xs[c] = sx[c][lj][li];
     if (CPL) xs[NU - 1] = xin_of(cell, i, j, NU - 1);
-    apply2d_cell<CPL, LHY, LHX, R>(g, sc, cf, sx, sq, ss, li, lj, i, j, cell, xs, ys);
+    apply2d_cell<CPL, (TR + 2), LHX, R>(g, sc, cf, sx, sq, ss, li, lj, i, j, cell, xs, ys);
 #pragma unroll
     for (int k = 0; k < NU; ++k) res[k] = (R)r[k * N + cell] - ys[k];
     if (OP == 0) {
@@ -1021,6 +1023,11 @@ __global__ __launch_bounds__(kApply2dThreads) void k_mg_sweep2d(Geom g, Scheme s
   }
 }
 
+// rows per 2D tile: 64 x 16 tiles of 1024 threads (64 x 8 tiles of 512 threads, two
+// blocks per CU, measured slower for the two-sweep multigrid kernel at 512^2 -- 17.0
+// against 15.3 us -- and equal for the fused apply at 1024^2)
+constexpr int kTileRows = 16;
+
 static int g_apply_variant = -1;  // -1: read M1_APPLY_KERNEL once ("lds" default in 2D, "direct")
 
 static bool use_lds_2d() {
@@ -1035,10 +1042,11 @@ template <typename R, typename VI, typename VO>
 void launch_apply(int nd, bool cpl, int mode, const Geom& g, const Scheme& sc, const Coefs<R>& cf, const Bdry& bd,
                   const VI* x, const double* b, VO* y, hipStream_t s, const int* skip) {
   if (nd == 2 && use_lds_2d()) {
-    const dim3 grd2 = grid2d_xcd(g);
-#define M1_LDS(CPL_, MODE_) k_apply2d_lds<CPL_, MODE_, false, R, VI, VO><<<grd2, kApply2dThreads, 0, s>>>(g, sc, cf, bd, x, b, y, skip)
-    if (cpl) { if (mode == 0) M1_LDS(true, 0); else M1_LDS(true, 1); }
-    else { if (mode == 0) M1_LDS(false, 0); else M1_LDS(false, 1); }
+#define M1_LDS(CPL_, MODE_)                                                                                  \
+  k_apply2d_lds<kTileRows, CPL_, MODE_, false, R, VI, VO><<<grid2d_xcd<kTileRows>(g), LX * kTileRows, 0, s>>>( \
+      g, sc, cf, bd, x, b, y, skip);
+    if (cpl) { if (mode == 0) M1_LDS(true, 0) else M1_LDS(true, 1) }
+    else { if (mode == 0) M1_LDS(false, 0) else M1_LDS(false, 1) }
 #undef M1_LDS
     return;
   }
@@ -1073,10 +1081,8 @@ void launch_residual(int nd, bool cpl, const Geom& g, const Scheme& sc, const Co
 // the ghosts beyond non-periodic faces are refreshed from the swept boundary cells,
 // and the epilogue of OP is applied to x1 on the tile.  Halves the finest-level
 // launches of a cycle.
-constexpr int L2X = LX + 4, L2Y = LY + 4;
-
-template <bool CPL, int OP, int XIN, typename R, typename TIN>
-__global__ __launch_bounds__(kApply2dThreads) void k_mg_sweep2d_x2(Geom g, Scheme sc, Coefs<R> cf, Bdry bd,
+template <int TR, bool CPL, int OP, int XIN, typename R, typename TIN>
+__global__ __launch_bounds__(LX * TR) void k_mg_sweep2d_x2(Geom g, Scheme sc, Coefs<R> cf, Bdry bd,
                                                                    const TIN* __restrict__ r, const R* __restrict__ zin,
                                                                    const R* __restrict__ zc, R omega,
                                                                    R* __restrict__ out, const R* __restrict__ dinv1,
@@ -1084,22 +1090,21 @@ __global__ __launch_bounds__(kApply2dThreads) void k_mg_sweep2d_x2(Geom g, Schem
                                                                    const int* __restrict__ skip) {
   constexpr int NR = 3;
   constexpr int NU = NR + (CPL ? 1 : 0);
-  static_assert(kApply2dThreads == LX * LY, "one tile cell per thread");
   if (skip && *skip) return;
-  __shared__ R sx0[NR][L2Y][L2X];
-  __shared__ R sq0[3][L2Y][L2X];
-  __shared__ R ss0[L2Y][L2X];
-  __shared__ R sx1[NR][LHY][LHX];
-  __shared__ R sq1[3][LHY][LHX];
-  __shared__ R ss1[LHY][LHX];
-  __shared__ R sT1[CPL ? LHY : 1][CPL ? LHX : 1];
+  __shared__ R sx0[NR][(TR + 4)][(LX + 4)];
+  __shared__ R sq0[3][(TR + 4)][(LX + 4)];
+  __shared__ R ss0[(TR + 4)][(LX + 4)];
+  __shared__ R sx1[NR][(TR + 2)][LHX];
+  __shared__ R sq1[3][(TR + 2)][LHX];
+  __shared__ R ss1[(TR + 2)][LHX];
+  __shared__ R sT1[CPL ? (TR + 2) : 1][CPL ? LHX : 1];
   const int64_t N = g.N;
   const int nx = g.n[0], ny = g.n[1];
   const int ncx = (nx + 1) / 2;
   const int64_t Nc = (int64_t)ncx * ((ny + 1) / 2);
   const bool perx = g.bc[0] == BC_PERIODIC, pery = g.bc[2] == BC_PERIODIC;
   int tbx, tby;
-  if (!xcd_tile(nx, ny, tbx, tby)) return;
+  if (!xcd_tile<TR>(nx, ny, tbx, tby)) return;
   auto xin_of = [&](int64_t cell, int gi, int gj, int k) -> R {
     if (XIN == 0) return zin[k * N + cell];
     if (XIN == 1) return (zin ? zin[k * N + cell] : (R)0) + zc[k * Nc + (int64_t)(gj / 2) * ncx + gi / 2];
@@ -1108,15 +1113,15 @@ __global__ __launch_bounds__(kApply2dThreads) void k_mg_sweep2d_x2(Geom g, Schem
     for (int c = 0; c < NU; ++c) acc += cf.bjinv[(k * NU + c) * N + cell] * (R)r[c * N + cell];
     return omega * acc;
   };
-  stage2d(g, cf, bd, tbx * LX - 2, tby * LY - 2, [&](int64_t cell, int gi, int gj, R* xv) {
+  stage2d<LX * TR>(g, cf, bd, tbx * LX - 2, tby * TR - 2, [&](int64_t cell, int gi, int gj, R* xv) {
 #pragma unroll
     for (int c = 0; c < NR; ++c) xv[c] = xin_of(cell, gi, gj, c);
   }, sx0, sq0, ss0);
   __syncthreads();
   // ---- first sweep on the tile and its ring (grid cells only; ghosts below) ----
-  for (int t = threadIdx.x; t < LHX * LHY; t += kApply2dThreads) {
+  for (int t = threadIdx.x; t < LHX * (TR + 2); t += (LX * TR)) {
     const int pi = t % LHX, pj = t / LHX;
-    int gi = tbx * LX - 1 + pi, gj = tby * LY - 1 + pj;
+    int gi = tbx * LX - 1 + pi, gj = tby * TR - 1 + pj;
     const bool outx = gi < 0 || gi >= nx, outy = gj < 0 || gj >= ny;
     if ((outx && !perx) || (outy && !pery)) continue;   // ghost or unused corner
     if (outx) gi = (gi + nx) % nx;
@@ -1126,7 +1131,7 @@ __global__ __launch_bounds__(kApply2dThreads) void k_mg_sweep2d_x2(Geom g, Schem
 #pragma unroll
     for (int c = 0; c < NR; ++c) xs[c] = sx0[c][pj + 1][pi + 1];
     if (CPL) xs[NU - 1] = xin_of(cell, gi, gj, NU - 1);
-    apply2d_cell<CPL, L2Y, L2X, R>(g, sc, cf, sx0, sq0, ss0, pi + 1, pj + 1, gi, gj, cell, xs, ys);
+    apply2d_cell<CPL, (TR + 4), (LX + 4), R>(g, sc, cf, sx0, sq0, ss0, pi + 1, pj + 1, gi, gj, cell, xs, ys);
     R res[NU];
 #pragma unroll
     for (int k = 0; k < NU; ++k) res[k] = (R)r[k * N + cell] - ys[k];
@@ -1153,9 +1158,9 @@ __global__ __launch_bounds__(kApply2dThreads) void k_mg_sweep2d_x2(Geom g, Schem
   __syncthreads();
   // ---- ghosts of the swept boundary cells (the positions just beyond a non-periodic
   // face; positions further out and corners are never read) ----
-  for (int t = threadIdx.x; t < LHX * LHY; t += kApply2dThreads) {
+  for (int t = threadIdx.x; t < LHX * (TR + 2); t += (LX * TR)) {
     const int pi = t % LHX, pj = t / LHX;
-    int gi = tbx * LX - 1 + pi, gj = tby * LY - 1 + pj;
+    int gi = tbx * LX - 1 + pi, gj = tby * TR - 1 + pj;
     bool outx = gi < 0 || gi >= nx, outy = gj < 0 || gj >= ny;
     if (outx && perx) { gi = (gi % nx + nx) % nx; outx = false; }
     if (outy && pery) { gj = (gj % ny + ny) % ny; outy = false; }
@@ -1192,7 +1197,7 @@ __global__ __launch_bounds__(kApply2dThreads) void k_mg_sweep2d_x2(Geom g, Schem
   __syncthreads();
   // ---- second application on the tile ----
   const int tx = threadIdx.x % LX, ty = threadIdx.x / LX;
-  const int i = tbx * LX + tx, j = tby * LY + ty;
+  const int i = tbx * LX + tx, j = tby * TR + ty;
   const bool inside = i < nx && j < ny;
   const int64_t cell = (int64_t)j * nx + i;
   R res[NU];
@@ -1202,7 +1207,7 @@ __global__ __launch_bounds__(kApply2dThreads) void k_mg_sweep2d_x2(Geom g, Schem
 #pragma unroll
     for (int c = 0; c < NR; ++c) xs[c] = sx1[c][lj][li];
     if (CPL) xs[NU - 1] = sT1[lj][li];
-    apply2d_cell<CPL, LHY, LHX, R>(g, sc, cf, sx1, sq1, ss1, li, lj, i, j, cell, xs, ys);
+    apply2d_cell<CPL, (TR + 2), LHX, R>(g, sc, cf, sx1, sq1, ss1, li, lj, i, j, cell, xs, ys);
 #pragma unroll
     for (int k = 0; k < NU; ++k) res[k] = (R)r[k * N + cell] - ys[k];
     if (OP == 0) {
@@ -1263,22 +1268,23 @@ bool launch_mg_sweep2d(int nd, bool cpl, int op, int xin, int ns, const Geom& g,
                        const Bdry& bd, const TIN* r, const R* zin, const R* zc, R omega, R* out, const R* dinv1, int sm,
                        R* b1, R* z1, hipStream_t s, const int* skip) {
   if (!fused_apply_available(nd) || op < 0 || op > 1 || xin < 0 || xin > 2 || ns < 1 || ns > 2) return false;
-  const dim3 grd2 = grid2d_xcd(g);
-#define M1_SW(CPL_, OP_, XIN_)                                                                                        \
+#define M1_SW_T(TY_, CPL_, OP_, XIN_)                                                                                 \
   {                                                                                                                   \
     if (ns == 2)                                                                                                      \
-      k_mg_sweep2d_x2<CPL_, OP_, XIN_, R, TIN><<<grd2, kApply2dThreads, 0, s>>>(g, sc, cf, bd, r, zin, zc, omega, out, \
-                                                                                dinv1, sm, b1, z1, skip);            \
+      k_mg_sweep2d_x2<TY_, CPL_, OP_, XIN_, R, TIN><<<grid2d_xcd<TY_>(g), LX * TY_, 0, s>>>(                          \
+          g, sc, cf, bd, r, zin, zc, omega, out, dinv1, sm, b1, z1, skip);                                            \
     else                                                                                                              \
-      k_mg_sweep2d<CPL_, OP_, XIN_, R, TIN><<<grd2, kApply2dThreads, 0, s>>>(g, sc, cf, bd, r, zin, zc, omega, out,    \
-                                                                             dinv1, sm, b1, z1, skip);               \
+      k_mg_sweep2d<TY_, CPL_, OP_, XIN_, R, TIN><<<grid2d_xcd<TY_>(g), LX * TY_, 0, s>>>(                             \
+          g, sc, cf, bd, r, zin, zc, omega, out, dinv1, sm, b1, z1, skip);                                            \
   }
+#define M1_SW(CPL_, OP_, XIN_) M1_SW_T(kTileRows, CPL_, OP_, XIN_)
 #define M1_SW_X(CPL_, OP_) \
   { if (xin == 0) M1_SW(CPL_, OP_, 0) else if (xin == 1) M1_SW(CPL_, OP_, 1) else M1_SW(CPL_, OP_, 2) }
   if (cpl) { if (op == 0) M1_SW_X(true, 0) else M1_SW_X(true, 1) }
   else { if (op == 0) M1_SW_X(false, 0) else M1_SW_X(false, 1) }
 #undef M1_SW_X
 #undef M1_SW
+#undef M1_SW_T
   return true;
 }
 template bool launch_mg_sweep2d<double, double>(int, bool, int, int, int, const Geom&, const Scheme&, const Coefs<double>&,
@@ -1343,9 +1349,9 @@ bool launch_apply_pre(int nd, bool cpl, const Geom& g, const Scheme& sc, const C
                       const VI* u, VO* y, hipStream_t s, const int* skip) {
   if (!use_lds_2d()) return false;
   if (nd != 2) return false;
-  const dim3 grd2 = grid2d_xcd(g);
-  if (cpl) k_apply2d_lds<true, 0, true, R, VI, VO><<<grd2, kApply2dThreads, 0, s>>>(g, sc, cf, bd, u, nullptr, y, skip);
-  else k_apply2d_lds<false, 0, true, R, VI, VO><<<grd2, kApply2dThreads, 0, s>>>(g, sc, cf, bd, u, nullptr, y, skip);
+  const dim3 grd2 = grid2d_xcd<kTileRows>(g);
+  if (cpl) k_apply2d_lds<kTileRows, true, 0, true, R, VI, VO><<<grd2, LX * kTileRows, 0, s>>>(g, sc, cf, bd, u, nullptr, y, skip);
+  else k_apply2d_lds<kTileRows, false, 0, true, R, VI, VO><<<grd2, LX * kTileRows, 0, s>>>(g, sc, cf, bd, u, nullptr, y, skip);
   return true;
 }
 
