@@ -694,9 +694,19 @@ template <int NT, int HY, int HX, typename R, typename XF>
 __device__ __forceinline__ void stage2d(const Geom& g, const Coefs<R>& cf, const Bdry& bd, int i0, int j0, XF&& xf,
                                         R (&sx)[3][HY][HX], R (&sq)[3][HY][HX], R (&ss)[HY][HX]) {
   constexpr int NR = 3;
+  constexpr int NP = (HX * HY + NT - 1) / NT;   // positions per thread
   const int64_t N = g.N;
   const int nx = g.n[0], ny = g.n[1];
-  for (int t = threadIdx.x; t < HX * HY; t += NT) {
+  // first every position's loads (all positions of a thread in flight together; a
+  // ghost reads its boundary cell like an interior position), then the ghosts' fix-up
+  // and the stores
+  R xv[NP][NR], qv[NP][3], sv[NP];
+  int face[NP], dd[NP];
+  bool valid[NP];
+  int64_t pidx[NP];
+#pragma unroll
+  for (int u = 0; u < NP; ++u) {
+    const int t = threadIdx.x + u * NT;
     const int li = t % HX, lj = t / HX;
     int gi = i0 + li, gj = j0 + lj;
     bool outx = gi < 0 || gi >= nx, outy = gj < 0 || gj >= ny;
@@ -704,58 +714,97 @@ __device__ __forceinline__ void stage2d(const Geom& g, const Coefs<R>& cf, const
     // cell, or the ghost of one, when either direction is periodic)
     if (outx && g.bc[0] == BC_PERIODIC) { gi = (gi % nx + nx) % nx; outx = false; }
     if (outy && g.bc[2] == BC_PERIODIC) { gj = (gj % ny + ny) % ny; outy = false; }
-    R xv[NR] = {(R)0, (R)0, (R)0}, qv[3] = {(R)0, (R)0, (R)0}, sv = (R)0;
-    if (!(outx && outy)) {
-      int face = -1, d = 0;
-      if (outx) {
-        d = 0;
-        face = gi < 0 ? 0 : 1;
-        gi = gi < 0 ? 0 : nx - 1;
-      } else if (outy) {
-        d = 1;
-        face = gj < 0 ? 2 : 3;
-        gj = gj < 0 ? 0 : ny - 1;
-      }
+    valid[u] = t < HX * HY && !(outx && outy);
+    face[u] = -1;
+    dd[u] = 0;
+    if (outx) {
+      dd[u] = 0;
+      face[u] = gi < 0 ? 0 : 1;
+      gi = gi < 0 ? 0 : nx - 1;
+    } else if (outy) {
+      dd[u] = 1;
+      face[u] = gj < 0 ? 2 : 3;
+      gj = gj < 0 ? 0 : ny - 1;
+    }
+    pidx[u] = dd[u] == 0 ? (int64_t)gj : (int64_t)gi;
+#pragma unroll
+    for (int c = 0; c < NR; ++c) xv[u][c] = (R)0;
+#pragma unroll
+    for (int pq = 0; pq < 3; ++pq) qv[u][pq] = (R)0;
+    sv[u] = (R)0;
+    if (valid[u]) {
       const int64_t cell = (int64_t)gj * nx + gi;
-      xf(cell, gi, gj, xv);
-      sv = cf.sigma[cell];
-      if (face < 0) {
+      xf(cell, gi, gj, xv[u]);
+      sv[u] = cf.sigma[cell];
 #pragma unroll
-        for (int pq = 0; pq < 3; ++pq) {
-          R acc = (R)0;
+      for (int pq = 0; pq < 3; ++pq) {
+        R acc = (R)0;
 #pragma unroll
-          for (int k = 0; k < NR; ++k) acc += cf.jac[(pq * NR + k) * N + cell] * xv[k];
-          qv[pq] = acc;
-        }
-      } else {
-        const int64_t pidx = d == 0 ? (int64_t)gj : (int64_t)gi;
-        const int64_t pn = g.plane_n[d];
+        for (int k = 0; k < NR; ++k) acc += cf.jac[(pq * NR + k) * N + cell] * xv[u][k];
+        qv[u][pq] = acc;
+      }
+    }
+  }
 #pragma unroll
-        for (int c = 0; c < NR; ++c) xv[c] *= (R)ghost_weight(g.bc[face], d, c, bd.mask[face], pidx);
+  for (int u = 0; u < NP; ++u) {
+    const int t = threadIdx.x + u * NT;
+    if (t >= HX * HY) continue;
+    const int li = t % HX, lj = t / HX;
+    if (valid[u] && face[u] >= 0) {
+      const int f = face[u], d = dd[u];
+      const int64_t pn = g.plane_n[d];
 #pragma unroll
-        for (int pq = 0; pq < 3; ++pq) {
-          R acc = (R)0;
+      for (int c = 0; c < NR; ++c) xv[u][c] *= (R)ghost_weight(g.bc[f], d, c, bd.mask[f], pidx[u]);
 #pragma unroll
-          for (int k = 0; k < NR; ++k) acc += cf.gjac[cf.gjoff[face] + (pq * NR + k) * pn + pidx] * xv[k];
-          qv[pq] = acc;
-        }
+      for (int pq = 0; pq < 3; ++pq) {
+        R acc = (R)0;
+#pragma unroll
+        for (int k = 0; k < NR; ++k) acc += cf.gjac[cf.gjoff[f] + (pq * NR + k) * pn + pidx[u]] * xv[u][k];
+        qv[u][pq] = acc;
       }
     }
 #pragma unroll
-    for (int c = 0; c < NR; ++c) sx[c][lj][li] = xv[c];
+    for (int c = 0; c < NR; ++c) sx[c][lj][li] = xv[u][c];
 #pragma unroll
-    for (int pq = 0; pq < 3; ++pq) sq[pq][lj][li] = qv[pq];
-    ss[lj][li] = sv;
+    for (int pq = 0; pq < 3; ++pq) sq[pq][lj][li] = qv[u][pq];
+    ss[lj][li] = sv[u];
+  }
+}
+
+// (a, dd, alpha) of the four faces of grid cell (i, j): its own +x and +y faces, then
+// its -x and -y faces (the lower neighbours' + faces, or the boundary planes); loaded
+// before the halo tile is staged, so that these loads overlap the staging's
+template <typename R>
+__device__ __forceinline__ void faces2d(const Geom& g, const Coefs<R>& cf, int i, int j, int64_t cell, R (&fc)[12]) {
+  const int64_t N = g.N;
+  const int nx = g.n[0], ny = g.n[1];
+#pragma unroll
+  for (int d = 0; d < 2; ++d) {
+#pragma unroll
+    for (int e = 0; e < 3; ++e) fc[3 * d + e] = cf.face[(3 * d + e) * N + cell];
+    const int id = d == 0 ? i : j, n = d == 0 ? nx : ny;
+    const int64_t stride = d == 0 ? 1 : nx;
+    if (id > 0 || g.bc[2 * d] == BC_PERIODIC) {
+      const int64_t nb = id > 0 ? cell - stride : cell + (int64_t)(n - 1) * stride;
+#pragma unroll
+      for (int e = 0; e < 3; ++e) fc[6 + 3 * d + e] = cf.face[(3 * d + e) * N + nb];
+    } else {
+      const int64_t pidx = d == 0 ? (int64_t)j : (int64_t)i;
+      const int64_t pn = g.plane_n[d];
+#pragma unroll
+      for (int e = 0; e < 3; ++e) fc[6 + 3 * d + e] = cf.lowface[cf.lowoff[d] + e * pn + pidx];
+    }
   }
 }
 
 // ys = (A x) at grid cell (i, j), staged at (li, lj) of the halo tile; xs[NU] is the
-// cell's own input (the radiation part as staged, the temperature from the caller).
+// cell's own input (the radiation part as staged, the temperature from the caller),
+// fc its face coefficients (faces2d).
 template <bool CPL, int HY, int HX, typename R>
 __device__ __forceinline__ void apply2d_cell(const Geom& g, const Scheme& sc, const Coefs<R>& cf,
                                              const R (&sx)[3][HY][HX], const R (&sq)[3][HY][HX],
                                              const R (&ss)[HY][HX], int li, int lj, int i, int j, int64_t cell,
-                                             const R* xs, R* ys) {
+                                             const R (&fc)[12], const R* xs, R* ys) {
   constexpr int NR = 3;
   constexpr int NU = NR + (CPL ? 1 : 0);
   const int64_t N = g.N;
@@ -782,27 +831,9 @@ __device__ __forceinline__ void apply2d_cell(const Geom& g, const Scheme& sc, co
       ql[m] = sq[pq][mj][mi];
     }
     const R sigR = ss[rj][ri], sigL = ss[mj][mi];
-    const R ap = cf.face[(3 * d + 0) * N + cell];
-    const R ddp = cf.face[(3 * d + 1) * N + cell];
-    const R alp = cf.face[(3 * d + 2) * N + cell];
+    const R ap = fc[3 * d + 0], ddp = fc[3 * d + 1], alp = fc[3 * d + 2];
+    const R am = fc[6 + 3 * d + 0], ddm = fc[6 + 3 * d + 1], alm = fc[6 + 3 * d + 2];
     const R bp = (R)1 - ap;
-    R am, ddm, alm;
-    {
-      const int id = d == 0 ? i : j, n = d == 0 ? nx : ny;
-      const int64_t stride = d == 0 ? 1 : nx;
-      if (id > 0) {
-        const int64_t nb = cell - stride;
-        am = cf.face[(3 * d + 0) * N + nb]; ddm = cf.face[(3 * d + 1) * N + nb]; alm = cf.face[(3 * d + 2) * N + nb];
-      } else if (g.bc[2 * d] == BC_PERIODIC) {
-        const int64_t nb = cell + (int64_t)(n - 1) * stride;
-        am = cf.face[(3 * d + 0) * N + nb]; ddm = cf.face[(3 * d + 1) * N + nb]; alm = cf.face[(3 * d + 2) * N + nb];
-      } else {
-        const int64_t pidx = d == 0 ? (int64_t)j : (int64_t)i;
-        const int64_t pn = g.plane_n[d];
-        am = cf.lowface[cf.lowoff[d] + pidx]; ddm = cf.lowface[cf.lowoff[d] + pn + pidx];
-        alm = cf.lowface[cf.lowoff[d] + 2 * pn + pidx];
-      }
-    }
     const R bm = (R)1 - am;
     const R FEp = alp * (ap * xs[1 + d] + bp * xr[1 + d] + ddp * (xr[0] - xs[0]));
     const R FEm = alm * (am * xl[1 + d] + bm * xs[1 + d] + ddm * (xs[0] - xl[0]));
@@ -860,6 +891,13 @@ __global__ __launch_bounds__(LX * TR) void k_apply2d_lds(Geom g, Scheme sc, Coef
   const int nx = g.n[0], ny = g.n[1];
   int tbx, tby;
   if (!xcd_tile<TR>(nx, ny, tbx, tby)) return;
+  // one cell per thread; its face coefficients are loaded with the staging
+  const int tx = threadIdx.x % LX, ty = threadIdx.x / LX;
+  const int i = tbx * LX + tx, j = tby * TR + ty;
+  const bool inside = i < nx && j < ny;
+  const int64_t cell = (int64_t)j * nx + i;
+  R fc[12];
+  if (inside) faces2d(g, cf, i, j, cell, fc);
   stage2d<LX * TR>(g, cf, bd, tbx * LX - 1, tby * TR - 1, [&](int64_t cell, int, int, R* xv) {
     if (PRE) {
       R uv[NU];
@@ -878,12 +916,8 @@ __global__ __launch_bounds__(LX * TR) void k_apply2d_lds(Geom g, Scheme sc, Coef
     }
   }, sx, sq, ss);
   __syncthreads();
-  // ---- fluxes: one cell per thread ----
-  const int tx = threadIdx.x % LX;
-  for (int ty = threadIdx.x / LX; ty < TR; ty += (LX * TR) / LX) {
-    const int i = tbx * LX + tx, j = tby * TR + ty;
-    if (i >= nx || j >= ny) continue;
-    const int64_t cell = (int64_t)j * nx + i;
+  // ---- fluxes ----
+  if (inside) {
     const int li = tx + 1, lj = ty + 1;
     R xs[NU], ys[NU];
 #pragma unroll
@@ -898,7 +932,7 @@ __global__ __launch_bounds__(LX * TR) void k_apply2d_lds(Geom g, Scheme sc, Coef
         xs[NU - 1] = (R)x[(NU - 1) * N + cell];
       }
     }
-    apply2d_cell<CPL, (TR + 2), LHX, R>(g, sc, cf, sx, sq, ss, li, lj, i, j, cell, xs, ys);
+    apply2d_cell<CPL, (TR + 2), LHX, R>(g, sc, cf, sx, sq, ss, li, lj, i, j, cell, fc, xs, ys);
 #pragma unroll
     for (int c = 0; c < NU; ++c) {
       R v = ys[c];
@@ -949,15 +983,17 @@ __global__ __launch_bounds__(LX * TR) void k_mg_sweep2d(Geom g, Scheme sc, Coefs
     for (int c = 0; c < NU; ++c) acc += cf.bjinv[(k * NU + c) * N + cell] * (R)r[c * N + cell];
     return omega * acc;
   };
+  const int tx = threadIdx.x % LX, ty = threadIdx.x / LX;
+  const int i = tbx * LX + tx, j = tby * TR + ty;
+  const bool inside = i < nx && j < ny;
+  const int64_t cell = (int64_t)j * nx + i;
+  R fc[12];
+  if (inside) faces2d(g, cf, i, j, cell, fc);
   stage2d<LX * TR>(g, cf, bd, tbx * LX - 1, tby * TR - 1, [&](int64_t cell, int gi, int gj, R* xv) {
 #pragma unroll
     for (int c = 0; c < NR; ++c) xv[c] = xin_of(cell, gi, gj, c);
   }, sx, sq, ss);
   __syncthreads();
-  const int tx = threadIdx.x % LX, ty = threadIdx.x / LX;
-  const int i = tbx * LX + tx, j = tby * TR + ty;
-  const bool inside = i < nx && j < ny;
-  const int64_t cell = (int64_t)j * nx + i;
   R res[NU];
   if (inside) {
     const int li = tx + 1, lj = ty + 1;
@@ -965,7 +1001,7 @@ __global__ __launch_bounds__(LX * TR) void k_mg_sweep2d(Geom g, Scheme sc, Coefs
 #pragma unroll
     for (int c = 0; c < NR; ++c) xs[c] = sx[c][lj][li];
     if (CPL) xs[NU - 1] = xin_of(cell, i, j, NU - 1);
-    apply2d_cell<CPL, (TR + 2), LHX, R>(g, sc, cf, sx, sq, ss, li, lj, i, j, cell, xs, ys);
+    apply2d_cell<CPL, (TR + 2), LHX, R>(g, sc, cf, sx, sq, ss, li, lj, i, j, cell, fc, xs, ys);
 #pragma unroll
     for (int k = 0; k < NU; ++k) res[k] = (R)r[k * N + cell] - ys[k];
     if (OP == 0) {
@@ -1131,7 +1167,9 @@ __global__ __launch_bounds__(LX * TR) void k_mg_sweep2d_x2(Geom g, Scheme sc, Co
 #pragma unroll
     for (int c = 0; c < NR; ++c) xs[c] = sx0[c][pj + 1][pi + 1];
     if (CPL) xs[NU - 1] = xin_of(cell, gi, gj, NU - 1);
-    apply2d_cell<CPL, (TR + 4), (LX + 4), R>(g, sc, cf, sx0, sq0, ss0, pi + 1, pj + 1, gi, gj, cell, xs, ys);
+    R fr[12];
+    faces2d(g, cf, gi, gj, cell, fr);
+    apply2d_cell<CPL, (TR + 4), (LX + 4), R>(g, sc, cf, sx0, sq0, ss0, pi + 1, pj + 1, gi, gj, cell, fr, xs, ys);
     R res[NU];
 #pragma unroll
     for (int k = 0; k < NU; ++k) res[k] = (R)r[k * N + cell] - ys[k];
@@ -1207,7 +1245,9 @@ __global__ __launch_bounds__(LX * TR) void k_mg_sweep2d_x2(Geom g, Scheme sc, Co
 #pragma unroll
     for (int c = 0; c < NR; ++c) xs[c] = sx1[c][lj][li];
     if (CPL) xs[NU - 1] = sT1[lj][li];
-    apply2d_cell<CPL, (TR + 2), LHX, R>(g, sc, cf, sx1, sq1, ss1, li, lj, i, j, cell, xs, ys);
+    R fc[12];
+    faces2d(g, cf, i, j, cell, fc);   // read by the first sweep just before: cache hits
+    apply2d_cell<CPL, (TR + 2), LHX, R>(g, sc, cf, sx1, sq1, ss1, li, lj, i, j, cell, fc, xs, ys);
 #pragma unroll
     for (int k = 0; k < NU; ++k) res[k] = (R)r[k * N + cell] - ys[k];
     if (OP == 0) {
