@@ -2,9 +2,10 @@
 // 2x2 average pooling, nearest upsampling with skip concatenation, 1x1 head)
 // with BF16 MFMA (FP32 accumulate) forward, input-gradient and weight-gradient
 // kernels, and Adam on FP32 master weights.  The convolutions run on gfx950's
-// v_mfma_f32_16x16x32_bf16 with weights staged in LDS (k_conv3x32); the K = 16
-// kernel (v_mfma_f32_16x16x16_bf16) remains for the weight gradient and as the
-// fallback of the convolution.
+// v_mfma_f32_16x16x32_bf16 with the input tile and the weights staged in LDS
+// (k_conv3t); the K = 16 kernel (v_mfma_f32_16x16x16_bf16) remains for the weight
+// gradient and as the fallback of the convolution (inputs of other than a multiple
+// of 16 channels: the first layer).
 //
 // Activations are NHWC.  A 3x3 convolution is an implicit GEMM: M = pixels,
 // N = output channels, K = 9 taps x input channels (in chunks of 16).  The input
@@ -125,18 +126,12 @@ __global__ __launch_bounds__(256) void k_conv3(int H, int W, const TIN* __restri
 }
 
 // ---------------------------------------------------------------------------
-// The same convolution on gfx950's K = 32 MFMA (v_mfma_f32_16x16x32_bf16): each
-// lane supplies 8 consecutive channels of one pixel (A) and of one output
-// channel's weights (B); the sum over k is the same whatever order the hardware
-// pairs the lanes' k slots in, since A and B use one convention.  A block is 4
-// waves; wave w computes 64 pixels of row 4 blockIdx.y + w for 64 output channels
-// (4 x 4 tiles of 16 x 16).  For every tap the block stages that tap's 64 x Cin
-// weights in LDS once (16-byte loads, rows padded by 8 channels against bank
-// conflicts), so the weights are read from L2 once per 256 pixels instead of once
-// per 16.  Requires Cin % 16 == 0 (a 32-channel step may be half valid).
+// gfx950's K = 32 MFMA (v_mfma_f32_16x16x32_bf16): each lane supplies 8 consecutive
+// channels of one pixel (A) and of one output channel's weights (B); the sum over k
+// is the same whatever order the hardware pairs the lanes' k slots in, since A and B
+// use one convention.
 // ---------------------------------------------------------------------------
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-constexpr int kConvCinMax = 256;
 
 __device__ __forceinline__ bf16x8 load8(const uint16_t* p) {
   return __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(p));
@@ -152,85 +147,134 @@ __device__ __forceinline__ bf16x8 load8(const float* p) {
   return __builtin_bit_cast(bf16x8, r);
 }
 
-template <typename TIN, typename TOUT>
-__global__ __launch_bounds__(256) void k_conv3x32(int H, int W, const TIN* __restrict__ x0, int C0, int up0,
-                                                  const TIN* __restrict__ x1, int C1, const uint16_t* __restrict__ w,
-                                                  const float* __restrict__ bias, int Cout, TOUT* __restrict__ y,
-                                                  int relu, const int* __restrict__ skip) {
+// ---------------------------------------------------------------------------
+// The convolution with the input tile and all nine taps' weights in LDS, one
+// 32-channel slice of the input at a time: a block (4 waves) computes 4 RW rows x 64
+// pixels x 16 NT output channels.  Per slice it stages the (4 RW + 2) x 66 input
+// pixels around the tile and the 9 x 16 NT weight rows, then each wave runs 9 taps x
+// RW x 4 x NT MFMAs (16x16x32 bf16, same operand convention as above) from LDS: two barriers
+// per 32 input channels, and every input element is read from memory once per
+// block (a per-tap form, which staged one tap's weights at a time and read the input
+// from memory once per tap, took two barriers per tap and was no faster than the
+// K = 16 kernel).  Requires C0 % 8 == 0 and Cin % 16 == 0.
+// ---------------------------------------------------------------------------
+constexpr int kCT = 32;            // input channels per slice
+constexpr int kCTP = kCT + 8;      // padded LDS row (bf16), against bank conflicts
+constexpr int kConvRowsPerWave = 1;  // output rows per wavefront (two measured slower: 0.62 against 0.46 ms per pass)
+
+template <int NT, int RW, typename TIN, typename TOUT>
+__global__ __launch_bounds__(256) void k_conv3t(int H, int W, const TIN* __restrict__ x0, int C0, int up0,
+                                                const TIN* __restrict__ x1, int C1, const uint16_t* __restrict__ w,
+                                                const float* __restrict__ bias, int Cout, TOUT* __restrict__ y,
+                                                int relu, const int* __restrict__ skip) {
+  constexpr int ROWS = 4 * RW;          // output rows of the block (RW per wave)
+  constexpr int IR = ROWS + 2;          // input rows staged
   if (skip && *skip) return;
-  __shared__ __align__(16) uint16_t sw[64 * (kConvCinMax + 8)];
+  __shared__ __align__(16) uint16_t sx[IR * 66 * kCTP];
+  __shared__ __align__(16) uint16_t swt[9 * 16 * NT * kCTP];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int h = blockIdx.y * 4 + wv;
+  const int h0 = blockIdx.y * ROWS;
   const int pbase = blockIdx.x * 64;
-  const int co_base = blockIdx.z * 64;
+  const int co_base = blockIdx.z * 16 * NT;
   const int Cin = C0 + C1;
-  const int ld = Cin + 8;                      // LDS row stride (bf16)
   const int W0 = up0 ? (W >> 1) : W;
   const int kq = (lane >> 4) * 8;
-  const bool row_ok = h < H;
-  f32x4 acc[4][4];
+  f32x4 acc[RW][4][NT];
 #pragma unroll
-  for (int g = 0; g < 4; ++g)
-#pragma unroll
-    for (int t = 0; t < 4; ++t) acc[g][t] = f32x4{0.f, 0.f, 0.f, 0.f};
-  const bf16x8 zero = __builtin_bit_cast(bf16x8, make_uint4(0u, 0u, 0u, 0u));
-  const int ngrp = Cin / 8;                    // 16-byte groups per weight row
-  for (int tap = 0; tap < 9; ++tap) {
-    __syncthreads();
-    // stage this tap's weights of the block's 64 output channels: sw[co][ci]
-    for (int e = threadIdx.x; e < 64 * ngrp; e += 256) {
-      const int col = e / ngrp, gi = e - col * ngrp;
-      const int co = co_base + col;
-      uint4 v = make_uint4(0u, 0u, 0u, 0u);
-      if (co < Cout) v = *reinterpret_cast<const uint4*>(w + ((int64_t)tap * Cout + co) * Cin + gi * 8);
-      *reinterpret_cast<uint4*>(sw + col * ld + gi * 8) = v;
-    }
-    __syncthreads();
-    if (!row_ok) continue;
-    const int hh = h + tap / 3 - 1;
-    const bool hin = hh >= 0 && hh < H;
-    for (int c0 = 0; c0 < Cin; c0 += 32) {
-      const int k = c0 + kq;                   // this lane's 8 channels
-      const bool kin = k < Cin;
-      bf16x8 A[4];
-#pragma unroll
-      for (int g = 0; g < 4; ++g) {
-        const int ww = pbase + g * 16 + (lane & 15) + tap % 3 - 1;
-        A[g] = zero;
-        if (kin && hin && ww >= 0 && ww < W) {
-          if (k < C0) {
-            const int sh = up0 ? (hh >> 1) : hh, sw0 = up0 ? (ww >> 1) : ww;
-            A[g] = load8(x0 + ((int64_t)sh * W0 + sw0) * C0 + k);
-          } else {
-            A[g] = load8(x1 + ((int64_t)hh * W + ww) * C1 + (k - C0));
-          }
-        }
-      }
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const bf16x8 B = kin ? __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(sw + (t * 16 + (lane & 15)) * ld + k))
-                             : zero;
-#pragma unroll
-        for (int g = 0; g < 4; ++g) acc[g][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[g], B, acc[g][t], 0, 0, 0);
-      }
-    }
-  }
-  if (!row_ok) return;
-#pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    const int co = co_base + t * 16 + (lane & 15);
-    if (co >= Cout) continue;
-    const float b = bias ? bias[co] : 0.f;
+  for (int q = 0; q < RW; ++q)
 #pragma unroll
     for (int g = 0; g < 4; ++g)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int px = pbase + g * 16 + (lane >> 4) * 4 + r;
-        if (px >= W) continue;
-        float v = acc[g][t][r] + b;
-        if (relu) v = fmaxf(v, 0.f);
-        store1(y + ((int64_t)h * W + px) * Cout + co, v);
+      for (int t = 0; t < NT; ++t) acc[q][g][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const bf16x8 zero = __builtin_bit_cast(bf16x8, make_uint4(0u, 0u, 0u, 0u));
+  for (int c0 = 0; c0 < Cin; c0 += kCT) {
+    __syncthreads();   // the previous slice is consumed
+    // input rows h0 - 1 .. h0 + ROWS, pixels pbase - 1 .. pbase + 64 (zero outside the
+    // image), channels c0 .. c0 + 31 in four 8-channel groups
+    for (int e = threadIdx.x; e < IR * 66 * 4; e += 256) {
+      const int grp = e & 3, pix = e >> 2;
+      const int r = pix / 66, p = pix - r * 66;
+      const int hh = h0 - 1 + r, ww = pbase - 1 + p;
+      const int k = c0 + grp * 8;
+      bf16x8 v = zero;
+      if (k < Cin && hh >= 0 && hh < H && ww >= 0 && ww < W) {
+        if (k < C0) {
+          const int sh = up0 ? (hh >> 1) : hh, sw0 = up0 ? (ww >> 1) : ww;
+          v = load8(x0 + ((int64_t)sh * W0 + sw0) * C0 + k);
+        } else {
+          v = load8(x1 + ((int64_t)hh * W + ww) * C1 + (k - C0));
+        }
       }
+      *reinterpret_cast<bf16x8*>(sx + pix * kCTP + grp * 8) = v;
+    }
+    // weights of the nine taps for the block's output channels: swt[tap][col][ci]
+    for (int e = threadIdx.x; e < 9 * 16 * NT * 4; e += 256) {
+      const int grp = e & 3, row = e >> 2;
+      const int tap = row / (16 * NT), col = row - tap * (16 * NT);
+      const int co = co_base + col, k = c0 + grp * 8;
+      uint4 v = make_uint4(0u, 0u, 0u, 0u);
+      if (co < Cout && k < Cin) v = *reinterpret_cast<const uint4*>(w + ((int64_t)tap * Cout + co) * Cin + k);
+      *reinterpret_cast<uint4*>(swt + row * kCTP + grp * 8) = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap) {
+      const int dy = tap / 3, dx = tap % 3;
+      bf16x8 B[NT];
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+        B[t] = *reinterpret_cast<const bf16x8*>(swt + (tap * 16 * NT + t * 16 + (lane & 15)) * kCTP + kq);
+#pragma unroll
+      for (int q = 0; q < RW; ++q) {
+        const int rloc = wv * RW + q;   // output row within the block
+        if (h0 + rloc >= H) continue;
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+          const bf16x8 A =
+              *reinterpret_cast<const bf16x8*>(sx + ((rloc + dy) * 66 + g * 16 + (lane & 15) + dx) * kCTP + kq);
+#pragma unroll
+          for (int t = 0; t < NT; ++t) acc[q][g][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, B[t], acc[q][g][t], 0, 0, 0);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < RW; ++q) {
+    const int h = h0 + wv * RW + q;
+    if (h >= H) continue;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const int co = co_base + t * 16 + (lane & 15);
+      if (co >= Cout) continue;
+      const float b = bias ? bias[co] : 0.f;
+#pragma unroll
+      for (int g = 0; g < 4; ++g)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int px = pbase + g * 16 + (lane >> 4) * 4 + r;
+          if (px >= W) continue;
+          float v = acc[q][g][t][r] + b;
+          if (relu) v = fmaxf(v, 0.f);
+          store1(y + ((int64_t)h * W + px) * Cout + co, v);
+        }
+    }
+  }
+}
+
+// output-channel tiles per block for Cout channels: 16 NT channels, NT <= 4
+static inline int conv_nt(int cout) { return cout >= 64 ? 4 : (cout + 15) / 16; }
+
+template <typename TIN, typename TOUT>
+static void launch_conv3t(int H, int W, const TIN* x0, int C0, int up0, const TIN* x1, int C1, const uint16_t* w,
+                          const float* bias, int Cout, TOUT* y, int relu, const int* skip, hipStream_t s) {
+  const int nt = conv_nt(Cout);
+  constexpr int RW = kConvRowsPerWave;
+  dim3 grd((W + 63) / 64, (H + 4 * RW - 1) / (4 * RW), (Cout + 16 * nt - 1) / (16 * nt));
+  switch (nt) {
+    case 1: k_conv3t<1, RW, TIN, TOUT><<<grd, 256, 0, s>>>(H, W, x0, C0, up0, x1, C1, w, bias, Cout, y, relu, skip); break;
+    case 2: k_conv3t<2, RW, TIN, TOUT><<<grd, 256, 0, s>>>(H, W, x0, C0, up0, x1, C1, w, bias, Cout, y, relu, skip); break;
+    case 3: k_conv3t<3, RW, TIN, TOUT><<<grd, 256, 0, s>>>(H, W, x0, C0, up0, x1, C1, w, bias, Cout, y, relu, skip); break;
+    default: k_conv3t<4, RW, TIN, TOUT><<<grd, 256, 0, s>>>(H, W, x0, C0, up0, x1, C1, w, bias, Cout, y, relu, skip); break;
   }
 }
 
@@ -633,15 +677,14 @@ static bool use_k32(int cin) {
     const char* e = getenv("M1_CONV_KERNEL");
     v = (e && std::string(e) == "k16") ? 0 : 1;
   }
-  return v == 1 && cin % 16 == 0 && cin <= kConvCinMax;
+  return v == 1 && cin % 16 == 0;
 }
 
 void conv3(m1nn* n, int H, int W, const uint16_t* x0, int C0, int up0, const uint16_t* x1, int C1, const ConvLayer& c,
            uint16_t* y, int relu) {
-  if (use_k32(C0 + C1)) {
-    dim3 grd((W + 63) / 64, (H + 3) / 4, (c.cout + 63) / 64);
-    k_conv3x32<uint16_t, uint16_t><<<grd, 256, 0, n->stream>>>(H, W, x0, C0, up0, x1, C1, c.wf, n->P + c.boff, c.cout,
-                                                               y, relu, n->skip);
+  if (use_k32(C0 + C1) && C0 % 8 == 0) {
+    launch_conv3t<uint16_t, uint16_t>(H, W, x0, C0, up0, x1, C1, c.wf, n->P + c.boff, c.cout, y, relu, n->skip,
+                                      n->stream);
     return;
   }
   dim3 grd((W + 63) / 64, H, (c.cout + 63) / 64);
@@ -652,9 +695,7 @@ void conv3(m1nn* n, int H, int W, const uint16_t* x0, int C0, int up0, const uin
 // input gradient of a conv3 layer: gx (H, W, cin) FP32 from gpre (H, W, cout) FP32
 void conv3_dgrad(m1nn* n, int H, int W, const float* gpre, const ConvLayer& c, float* gx) {
   if (use_k32(c.cout)) {
-    dim3 grd((W + 63) / 64, (H + 3) / 4, (c.cin + 63) / 64);
-    k_conv3x32<float, float><<<grd, 256, 0, n->stream>>>(H, W, gpre, c.cout, 0, nullptr, 0, c.wt, nullptr, c.cin, gx,
-                                                         0, nullptr);
+    launch_conv3t<float, float>(H, W, gpre, c.cout, 0, nullptr, 0, c.wt, nullptr, c.cin, gx, 0, nullptr, n->stream);
     return;
   }
   dim3 grd((W + 63) / 64, H, (c.cin + 63) / 64);
