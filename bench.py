@@ -302,9 +302,11 @@ def summarize_profiles(d, workload, commands):
         os.makedirs(PROFILES, exist_ok=True)
         with open(tpath, "w") as fh:
             json.dump(traffic, fh, indent=1)
-    with open(tpath) as fh:
-        traffic = json.load(fh)
-    kernels = traffic["kernels"]
+    traffic = None
+    if os.path.exists(tpath):
+        with open(tpath) as fh:
+            traffic = json.load(fh)
+    kernels = traffic["kernels"] if traffic else {}
     fam = {}
     for r in rows:
         cls = kernel_class(r["Name"])
@@ -319,7 +321,7 @@ def summarize_profiles(d, workload, commands):
         b[1] += v["hbm_bytes_per_dispatch"] * v["dispatches"]
     lines = [f"# rocprofv3 kernel statistics: {workload}", "", "Commands (run from the repository root; `<raw>` is a "
              "scratch directory for rocprofv3's CSV output):", "", "```", commands.strip(), "```", "",
-             f"HIP sources SHA-256 when taken: `{traffic['source_sha256']}`", "",
+             f"HIP sources SHA-256 when taken: `{traffic['source_sha256'] if traffic else source_hash()}`", "",
              "## By kernel class", "", "| class | calls | total ms | avg us | % of GPU time | HBM MB/dispatch |",
              "|---|---|---|---|---|---|"]
     for cls, (n, t) in sorted(fam.items(), key=lambda kv: -kv[1][1]):
@@ -330,17 +332,18 @@ def summarize_profiles(d, workload, commands):
     for r in rows[:16]:
         lines.append(f"| `{_kname(r['Name'])[:100]}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.2f} | "
                      f"{float(r['AverageNs']) / 1e3:.2f} | {float(r['Percentage']):.1f} |")
-    lines += ["", f"## HBM traffic (FETCH_SIZE, WRITE_SIZE)", "",
-              f"Copy calibration (1 GiB read + 1 GiB written per launch, `{traffic['copy_kernel']}`): FETCH_SIZE "
-              f"{traffic['copy_fetch_kib']:.0f} KiB, WRITE_SIZE {traffic['copy_write_kib']:.0f} KiB per dispatch -> "
-              f"scale {traffic['scale_fetch']:.4f} (fetch), {traffic['scale_write']:.4f} (write).", "",
-              "| kernel | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB | HBM MB/dispatch |", "|---|---|---|---|---|"]
-    for nm, v in sorted(kernels.items(), key=lambda kv: -kv[1]["hbm_bytes_per_dispatch"] * kv[1]["dispatches"])[:12]:
-        lines.append(f"| `{_kname(nm)[:100]}` | {v['dispatches']} | {v['fetch_kib']:.0f} | {v['write_kib']:.0f} | "
-                     f"{v['hbm_bytes_per_dispatch'] / 1e6:.2f} |")
+    if traffic:
+        lines += ["", f"## HBM traffic (FETCH_SIZE, WRITE_SIZE)", "",
+                  f"Copy calibration (1 GiB read + 1 GiB written per launch, `{traffic['copy_kernel']}`): FETCH_SIZE "
+                  f"{traffic['copy_fetch_kib']:.0f} KiB, WRITE_SIZE {traffic['copy_write_kib']:.0f} KiB per dispatch -> "
+                  f"scale {traffic['scale_fetch']:.4f} (fetch), {traffic['scale_write']:.4f} (write).", "",
+                  "| kernel | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB | HBM MB/dispatch |", "|---|---|---|---|---|"]
+        for nm, v in sorted(kernels.items(), key=lambda kv: -kv[1]["hbm_bytes_per_dispatch"] * kv[1]["dispatches"])[:12]:
+            lines.append(f"| `{_kname(nm)[:100]}` | {v['dispatches']} | {v['fetch_kib']:.0f} | {v['write_kib']:.0f} | "
+                         f"{v['hbm_bytes_per_dispatch'] / 1e6:.2f} |")
     with open(os.path.join(PROFILES, f"{workload}_kernels.md"), "w") as fh:
         fh.write("\n".join(lines) + "\n")
-    print(json.dumps({"wrote": [f"profiles/{workload}_kernels.md", f"profiles/{workload}_traffic.json"]}))
+    print(json.dumps({"wrote": [f"profiles/{workload}_kernels.md"] + ([f"profiles/{workload}_traffic.json"] if traffic else [])}))
 
 
 def measured_traffic(workload, cls):
