@@ -53,12 +53,12 @@ CSRC = os.path.join(ROOT, "paper_2011_13926_amd", "csrc")
 
 # profiler kernel class -> prefixes of the HIP kernels' names (without "void " and "m1::")
 CLASS_KERNEL = {
-    "apply_bj_fused": ("k_apply2d_lds<false, 0, true", "k_apply2d_lds<true, 0, true"),
-    "apply": ("k_apply2d_lds<false, 0, false", "k_apply2d_lds<true, 0, false", "k_stencil<2, false, 0",
+    "apply_bj_fused": ("k_apply2d_lds<16, false, 0, true", "k_apply2d_lds<16, true, 0, true"),
+    "apply": ("k_apply2d_lds<16, false, 0, false", "k_apply2d_lds<16, true, 0, false", "k_stencil<2, false, 0",
               "k_stencil<2, true, 0", "k_stencil<3, false, 0", "k_stencil<3, true, 0"),
     "arnoldi_dot": ("k_dot<", "k_dot4<"), "arnoldi_update": ("k_update<", "k_update4<"), "arnoldi_scalar": ("k_scalar",),
     "x_update": ("k_xupdate<",), "block_jacobi": ("k_bj<",),
-    "true_residual": ("k_apply2d_lds<false, 1", "k_apply2d_lds<true, 1", "k_stencil<2, false, 1",
+    "true_residual": ("k_apply2d_lds<16, false, 1", "k_apply2d_lds<16, true, 1", "k_stencil<2, false, 1",
                       "k_stencil<2, true, 1", "k_stencil<3, false, 1", "k_stencil<3, true, 1"),
     "time_step": ("k_step2d_lds<", "k_step_direct<"),
     "mg_fine": ("k_mg_fine_smooth<", "k_mg_restrict_fine<", "k_mg_prolong_fine<", "k_mg_cast<", "k_mg_sweep2d<",
