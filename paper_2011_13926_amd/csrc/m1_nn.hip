@@ -338,12 +338,234 @@ __global__ __launch_bounds__(256) void k_wgrad3(int H, int W, const uint16_t* __
   }
 }
 
-// sum over chunks in a fixed order: out[i] = sum_c part[c * n + i]
-__global__ void k_sum_chunks(const float* __restrict__ part, int nchunks, int64_t n, float* __restrict__ out) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    float s = 0.f;
-    for (int c = 0; c < nchunks; ++c) s += part[(int64_t)c * n + i];
-    out[i] = s;
+// ---------------------------------------------------------------------------
+// Weight and bias gradient on the K = 32 MFMA: part[chunk][tap][co][ci] =
+// sum_{p in chunk} gT[co][p] * x(p shifted by the tap)[ci], bpart[chunk][co] =
+// sum_{p in chunk} gT[co][p].  M = output channels, N = input channels, K = pixels:
+// each lane supplies 8 consecutive pixels of one output channel (A) and of one input
+// channel (B), as 16-byte loads.  The input comes as three copies shifted by dx =
+// -1, 0, +1 within each row (zero beyond the row's ends), so that every tap's B is an
+// aligned 8-pixel run of one copy at an offset of dy rows.  A block owns 64 output x 16
+// input channels and one pixel chunk; each of its four waves takes every fourth
+// 32-pixel step of the chunk for all nine taps (36 accumulator tiles, so one A load
+// serves nine taps and one B load four output tiles), loading the next step while the
+// current one multiplies, and the waves are summed through LDS in a fixed order.
+// Requires W % 8 == 0 and chunk % 128 == 0.
+// ---------------------------------------------------------------------------
+constexpr int kWgradBlocks = 512;   // workgroups a weight-gradient launch aims for
+
+__global__ __launch_bounds__(256) void k_wgrad3t(int H, int W, const uint16_t* __restrict__ xTs, int Cin,
+                                                 const uint16_t* __restrict__ gT, int Cout, int chunk,
+                                                 float* __restrict__ part, float* __restrict__ bpart) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int nco = (Cout + 63) / 64;
+  const int co_blk = blockIdx.x % nco, ci_blk = blockIdx.x / nco;
+  const int64_t HW = (int64_t)H * W;
+  const int64_t p0 = (int64_t)blockIdx.z * chunk;
+  const int64_t p1 = min(p0 + (int64_t)chunk, HW);
+  const int kq = (lane >> 4) * 8;
+  const int ci = ci_blk * 16 + (lane & 15);
+  const bool ci_ok = ci < Cin;
+  const bool do_bias = ci_blk == 0;
+  const uint16_t* arow[4];
+  bool co_ok[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int co = co_blk * 64 + t * 16 + (lane & 15);
+    co_ok[t] = co < Cout;
+    arow[t] = gT + (int64_t)(co_ok[t] ? co : 0) * HW;
+  }
+  const uint16_t* brow[3];
+#pragma unroll
+  for (int s = 0; s < 3; ++s) brow[s] = xTs + ((int64_t)s * Cin + (ci_ok ? ci : 0)) * HW;
+  const bf16x8 zero = __builtin_bit_cast(bf16x8, make_uint4(0u, 0u, 0u, 0u));
+  // one 32-pixel step: this lane's 8 pixels (within one row, as W % 8 == 0), masked
+  // outside the chunk, the channel range and the image rows
+  auto load_step = [&](int64_t pk, bf16x8(&A)[4], bf16x8(&B)[9]) {
+    const int64_t p = pk + kq;
+    const bool p_ok = p < p1;
+    const int h = (int)(p / W);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) A[t] = (p_ok && co_ok[t]) ? load8(arow[t] + p) : zero;
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy) {
+      const bool row_ok = p_ok && ci_ok && h + dy >= 0 && h + dy < H;
+#pragma unroll
+      for (int s = 0; s < 3; ++s) B[(dy + 1) * 3 + s] = row_ok ? load8(brow[s] + p + (int64_t)dy * W) : zero;
+    }
+  };
+  f32x4 acc[9][4];
+#pragma unroll
+  for (int tp = 0; tp < 9; ++tp)
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[tp][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+  float bsum[4] = {0.f, 0.f, 0.f, 0.f};
+  bf16x8 A[4], B[9];
+  int64_t pk = p0 + wv * 32;
+  load_step(pk, A, B);
+  for (; pk < p1; pk += 128) {
+    bf16x8 An[4], Bn[9];
+    load_step(pk + 128, An, Bn);
+    if (do_bias) {
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) bsum[t] += (float)A[t][e];
+    }
+#pragma unroll
+    for (int tp = 0; tp < 9; ++tp)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) acc[tp][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[t], B[tp], acc[tp][t], 0, 0, 0);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) A[t] = An[t];
+#pragma unroll
+    for (int b = 0; b < 9; ++b) B[b] = Bn[b];
+  }
+  // sum the four waves, one tap at a time: accumulator r of tile t in lane l is
+  // output channel t*16 + (l/16)*4 + r and input channel l % 16
+  __shared__ float red[4][64][17];
+  for (int tp = 0; tp < 9; ++tp) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) red[wv][lane][t * 4 + r] = acc[tp][t][r];
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int e = threadIdx.x + 256 * j;
+      const int ci_l = e & 15, co_l = e >> 4;
+      const int src = ((co_l >> 2) & 3) * 16 + ci_l, slot = (co_l >> 4) * 4 + (co_l & 3);
+      const float v = red[0][src][slot] + red[1][src][slot] + red[2][src][slot] + red[3][src][slot];
+      const int co = co_blk * 64 + co_l, cig = ci_blk * 16 + ci_l;
+      if (co < Cout && cig < Cin) part[(((int64_t)blockIdx.z * 9 + tp) * Cout + co) * Cin + cig] = v;
+    }
+    __syncthreads();
+  }
+  if (do_bias) {
+    // lanes l, l ^ 16, l ^ 32, l ^ 48 hold the same output channel's sums over their pixels
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      float v = bsum[t];
+      v += __shfl_xor(v, 16, 64);
+      v += __shfl_xor(v, 32, 64);
+      if (lane < 16) red[wv][t * 16 + lane][0] = v;
+    }
+    __syncthreads();
+    const int co = co_blk * 64 + (int)threadIdx.x;
+    if (threadIdx.x < 64 && co < Cout)
+      bpart[(int64_t)blockIdx.z * Cout + co] =
+          red[0][threadIdx.x][0] + red[1][threadIdx.x][0] + red[2][threadIdx.x][0] + red[3][threadIdx.x][0];
+  }
+}
+
+// Channel-major copies for the weight gradients, through a 64-pixel x 32-channel LDS
+// tile so that reads (pixel-major rows of channels) and writes (channel-major runs of
+// pixels) are both 16-byte and coalesced.  Pixels p0 .. p0 + 63 of the flattened image
+// plus one pixel either side; grid (ceil(HW / 64), ceil(C / 32)).  Requires W % 8 == 0
+// and channel counts that are multiples of 8.
+constexpr int kTrPix = 64, kTrCh = 32, kTrPad = kTrCh + 2;
+
+__device__ __forceinline__ uint4 pack8(const uint16_t (&v)[8]) {
+  return make_uint4(v[0] | ((uint32_t)v[1] << 16), v[2] | ((uint32_t)v[3] << 16), v[4] | ((uint32_t)v[5] << 16),
+                    v[6] | ((uint32_t)v[7] << 16));
+}
+
+// the input of a conv3 layer (x0, optionally 2x-upsampled, concatenated with x1) as three
+// channel-major copies shifted by dx = -1, 0, +1 within each row:
+// out[s][c][p] = x(h, w + s - 1)[c], zero beyond the row's ends
+__global__ __launch_bounds__(256) void k_to_chw3(int H, int W, const uint16_t* __restrict__ x0, int C0, int up0,
+                                                 const uint16_t* __restrict__ x1, int C1, uint16_t* __restrict__ out) {
+  __shared__ uint16_t tile[kTrPix + 2][kTrPad];
+  const int HW = H * W, C = C0 + C1, W0 = up0 ? W / 2 : W;
+  const int p0 = blockIdx.x * kTrPix, c0 = blockIdx.y * kTrCh;
+  for (int i = threadIdx.x; i < (kTrPix + 2) * (kTrCh / 8); i += 256) {
+    const int q = p0 - 1 + i / (kTrCh / 8), k = c0 + (i % (kTrCh / 8)) * 8;
+    uint4 v = make_uint4(0u, 0u, 0u, 0u);
+    if (q >= 0 && q < HW && k < C) {
+      const int h = q / W, w = q % W;
+      if (k < C0) v = *reinterpret_cast<const uint4*>(x0 + (up0 ? (int64_t)(h / 2) * W0 + w / 2 : (int64_t)q) * C0 + k);
+      else v = *reinterpret_cast<const uint4*>(x1 + (int64_t)q * C1 + (k - C0));
+    }
+    uint16_t* t = &tile[i / (kTrCh / 8)][(i % (kTrCh / 8)) * 8];
+    t[0] = v.x & 0xffff; t[1] = v.x >> 16; t[2] = v.y & 0xffff; t[3] = v.y >> 16;
+    t[4] = v.z & 0xffff; t[5] = v.z >> 16; t[6] = v.w & 0xffff; t[7] = v.w >> 16;
+  }
+  __syncthreads();
+  // 3 copies x 32 channels x 8 groups of 8 pixels
+  for (int i = threadIdx.x; i < 3 * kTrCh * (kTrPix / 8); i += 256) {
+    const int g = i % (kTrPix / 8), c = (i / (kTrPix / 8)) % kTrCh, s = i / (kTrCh * (kTrPix / 8));
+    const int p = p0 + g * 8;
+    if (p >= HW || c0 + c >= C) continue;
+    const int w = p % W;   // the 8 pixels share a row (W % 8 == 0)
+    uint16_t v[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int ws = w + e + s - 1;
+      v[e] = (ws >= 0 && ws < W) ? tile[g * 8 + e + s][c] : (uint16_t)0;
+    }
+    *reinterpret_cast<uint4*>(out + ((int64_t)s * C + c0 + c) * HW + p) = pack8(v);
+  }
+}
+
+// ReLU backward with the channel-major BF16 copy for the weight gradient:
+// gpre = g where the layer's output is positive, else 0 (pixel-major, FP32), and
+// gT[c][p] = bf16(gpre[p][c]).  Same tiling as k_to_chw3 (no halo); requires HW % 8 == 0
+// and C % 8 == 0.
+__global__ __launch_bounds__(256) void k_relu_grad_t(int HW, int C, const float* __restrict__ g,
+                                                     const uint16_t* __restrict__ outv, float* __restrict__ gpre,
+                                                     uint16_t* __restrict__ gT) {
+  __shared__ uint16_t tile[kTrPix][kTrPad];
+  const int p0 = blockIdx.x * kTrPix, c0 = blockIdx.y * kTrCh;
+  // 64 pixels x 32 channels, 4 channels per thread and pass
+  for (int i = threadIdx.x; i < kTrPix * (kTrCh / 4); i += 256) {
+    const int pl = i / (kTrCh / 4), k = (i % (kTrCh / 4)) * 4;
+    const int p = p0 + pl, c = c0 + k;
+    if (p >= HW || c >= C) continue;
+    const int64_t o = (int64_t)p * C + c;
+    const float4 gv = *reinterpret_cast<const float4*>(g + o);
+    const uint2 ov = *reinterpret_cast<const uint2*>(outv + o);
+    float4 r;
+    r.x = bf2f(ov.x & 0xffff) > 0.f ? gv.x : 0.f;
+    r.y = bf2f(ov.x >> 16) > 0.f ? gv.y : 0.f;
+    r.z = bf2f(ov.y & 0xffff) > 0.f ? gv.z : 0.f;
+    r.w = bf2f(ov.y >> 16) > 0.f ? gv.w : 0.f;
+    *reinterpret_cast<float4*>(gpre + o) = r;
+    tile[pl][k] = f2bf(r.x); tile[pl][k + 1] = f2bf(r.y); tile[pl][k + 2] = f2bf(r.z); tile[pl][k + 3] = f2bf(r.w);
+  }
+  __syncthreads();
+  // 32 channels x 8 groups of 8 pixels
+  {
+    const int i = threadIdx.x;
+    const int gp = i % (kTrPix / 8), c = i / (kTrPix / 8);
+    const int p = p0 + gp * 8;
+    if (p < HW && c0 + c < C) {
+      uint16_t v[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) v[e] = tile[gp * 8 + e][c];
+      *reinterpret_cast<uint4*>(gT + (int64_t)(c0 + c) * HW + p) = pack8(v);
+    }
+  }
+}
+
+// sum over chunks in a fixed order: out[i] = sum_c part[c * n + i].  A block covers 32
+// consecutive i; its 8 thread rows take every eighth chunk and meet in LDS.
+__global__ __launch_bounds__(256) void k_sum_chunks(const float* __restrict__ part, int nchunks, int64_t n,
+                                                    float* __restrict__ out) {
+  const int tx = threadIdx.x & 31, gr = threadIdx.x >> 5;
+  const int64_t i = (int64_t)blockIdx.x * 32 + tx;
+  float s = 0.f;
+  if (i < n) {
+#pragma unroll 4
+    for (int c = gr; c < nchunks; c += 8) s += part[(int64_t)c * n + i];
+  }
+  __shared__ float red[8][33];
+  red[gr][tx] = s;
+  __syncthreads();
+  if (gr == 0 && i < n) {
+    float t = red[0][tx];
+#pragma unroll
+    for (int k = 1; k < 8; ++k) t += red[k][tx];
+    out[i] = t;
   }
 }
 
@@ -457,16 +679,30 @@ __global__ void k_pool_back_add(int H, int W, int C, const float* __restrict__ g
 }
 
 // 1x1 head (FP32): y[p][co] = b[co] + sum_ci x[p][ci] * w[co][ci]
-__global__ void k_head_fwd(int64_t npix, const uint16_t* __restrict__ x, int Cin, const float* __restrict__ w,
-                           const float* __restrict__ b, int Cout, float* __restrict__ y,
-                           const int* __restrict__ skip) {
+// 1x1 head: y[p][co] = b[co] + sum_ci x[p][ci] w[co][ci], summed in channel order.  One
+// pixel per thread, its channels as 16-byte loads; MAXCO bounds Cout.  Requires Cin % 8 == 0.
+template <int MAXCO>
+__global__ __launch_bounds__(256) void k_head_fwd(int64_t npix, const uint16_t* __restrict__ x, int Cin,
+                                                  const float* __restrict__ w, const float* __restrict__ b, int Cout,
+                                                  float* __restrict__ y, const int* __restrict__ skip) {
   if (skip && *skip) return;
   for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < npix; p += (int64_t)gridDim.x * blockDim.x) {
-    for (int co = 0; co < Cout; ++co) {
-      float s = b[co];
-      for (int ci = 0; ci < Cin; ++ci) s += bf2f(x[p * Cin + ci]) * w[co * Cin + ci];
-      y[p * Cout + co] = s;
+    float s[MAXCO];
+#pragma unroll
+    for (int co = 0; co < MAXCO; ++co) s[co] = co < Cout ? b[co] : 0.f;
+    for (int c8 = 0; c8 < Cin; c8 += 8) {
+      const bf16x8 xv = load8(x + p * Cin + c8);
+#pragma unroll
+      for (int co = 0; co < MAXCO; ++co) {
+        if (co < Cout) {
+#pragma unroll
+          for (int e = 0; e < 8; ++e) s[co] += (float)xv[e] * w[co * Cin + c8 + e];
+        }
+      }
     }
+#pragma unroll
+    for (int co = 0; co < MAXCO; ++co)
+      if (co < Cout) y[p * Cout + co] = s[co];
   }
 }
 
@@ -482,22 +718,53 @@ __global__ void k_head_dx(int64_t npix, const float* __restrict__ gy, int Cout, 
 }
 
 // head weight/bias gradient: one block per (co, ci) pair (ci = Cin means the bias)
-__global__ void k_head_dw(int64_t npix, const float* __restrict__ gy, int Cout, const uint16_t* __restrict__ x,
-                          int Cin, float* __restrict__ gw, float* __restrict__ gb) {
-  const int co = blockIdx.x / (Cin + 1), ci = blockIdx.x % (Cin + 1);
-  float s = 0.f;
-  for (int64_t p = threadIdx.x; p < npix; p += blockDim.x)
-    s += gy[p * Cout + co] * (ci < Cin ? bf2f(x[p * Cin + ci]) : 1.f);
-  __shared__ float red[256];
-  red[threadIdx.x] = s;
-  __syncthreads();
-  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
-    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
-    __syncthreads();
+// Head (1x1) weight and bias gradient partials over a pixel range of ppb pixels:
+// part[blk][co * Cin + ci] = sum_p gy[p][co] x[p][ci] and part[blk][Cout * Cin + co] =
+// sum_p gy[p][co].  blockIdx.y picks an 8-channel slice of x (one 16-byte load per
+// pixel, consecutive threads on consecutive pixels); the bias sums ride on slice 0.
+// MAXCO bounds Cout.  Requires Cin % 8 == 0.
+template <int MAXCO>
+__global__ __launch_bounds__(256) void k_head_dw_part(int64_t npix, int ppb, const float* __restrict__ gy, int Cout,
+                                                      const uint16_t* __restrict__ x, int Cin,
+                                                      float* __restrict__ part) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int c0 = blockIdx.y * 8;
+  const int64_t p0 = (int64_t)blockIdx.x * ppb;
+  const int64_t p1 = min(p0 + (int64_t)ppb, npix);
+  float acc[MAXCO][9];
+#pragma unroll
+  for (int co = 0; co < MAXCO; ++co)
+#pragma unroll
+    for (int e = 0; e < 9; ++e) acc[co][e] = 0.f;
+  for (int64_t p = p0 + threadIdx.x; p < p1; p += 256) {
+    const bf16x8 xv = load8(x + p * Cin + c0);
+#pragma unroll
+    for (int co = 0; co < MAXCO; ++co) {
+      const float g = co < Cout ? gy[p * Cout + co] : 0.f;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) acc[co][e] += g * (float)xv[e];
+      acc[co][8] += g;
+    }
   }
-  if (threadIdx.x == 0) {
-    if (ci < Cin) gw[co * Cin + ci] = red[0];
-    else gb[co] = red[0];
+  __shared__ float red[4][MAXCO * 9];
+#pragma unroll
+  for (int co = 0; co < MAXCO; ++co)
+#pragma unroll
+    for (int e = 0; e < 9; ++e) {
+      float v = acc[co][e];
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+      if (lane == 0) red[wv][co * 9 + e] = v;
+    }
+  __syncthreads();
+  const int i = threadIdx.x;
+  if (i < MAXCO * 9) {
+    const int co = i / 9, e = i % 9;
+    if (co < Cout && (e < 8 || blockIdx.y == 0)) {
+      const float v = red[0][i] + red[1][i] + red[2][i] + red[3][i];
+      const int64_t base = (int64_t)blockIdx.x * (Cout * Cin + Cout);
+      part[base + (e < 8 ? (int64_t)co * Cin + c0 + e : (int64_t)Cout * Cin + co)] = v;
+    }
   }
 }
 
@@ -527,15 +794,26 @@ __global__ void k_loss_part(int64_t n, const float* __restrict__ y, const float*
   }
 }
 
-__global__ void k_loss_final(const double* __restrict__ part, int nb, double* __restrict__ out) {
-  if (threadIdx.x == 0) {
-    double a = 0.0, b = 0.0;
-    for (int i = 0; i < nb; ++i) {
-      a += part[2 * i];
-      b += part[2 * i + 1];
+__global__ __launch_bounds__(256) void k_loss_final(const double* __restrict__ part, int nb, double* __restrict__ out) {
+  double a = 0.0, b = 0.0;
+  for (int i = threadIdx.x; i < nb; i += 256) {
+    a += part[2 * i];
+    b += part[2 * i + 1];
+  }
+  __shared__ double ra[256], rb[256];
+  ra[threadIdx.x] = a;
+  rb[threadIdx.x] = b;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      ra[threadIdx.x] += ra[threadIdx.x + o];
+      rb[threadIdx.x] += rb[threadIdx.x + o];
     }
-    out[0] = b > 0 ? a / b : 0.0;
-    out[1] = b;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = rb[0] > 0 ? ra[0] / rb[0] : 0.0;
+    out[1] = rb[0];
   }
 }
 
@@ -574,6 +852,8 @@ __global__ void k_weights_bf16(int Cout, int Cin, const float* __restrict__ wm, 
 }
 
 static int64_t grid_for(int64_t n) { return std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 8192)); }
+// k_sum_chunks: one block per 32 outputs
+static unsigned sum_grid(int64_t n) { return (unsigned)std::max<int64_t>(1, (n + 31) / 32); }
 
 }  // namespace m1
 
@@ -624,6 +904,7 @@ struct m1nn {
   uint16_t* gT = nullptr;   // channel-major gradient copy for wgrad
   float* wpart = nullptr;
   int64_t wpart_len = 0;
+  float* bpart = nullptr;   // per-chunk bias-gradient partials
   double* loss_part = nullptr;
   double* loss_out = nullptr;
   const int* skip = nullptr;  // device flag: forward kernels return at once when it is set
@@ -654,7 +935,7 @@ void nn_free(m1nn* n) {
   auto f = [](void* p) { if (p) hipFree(p); };
   for (auto& c : n->conv) { f(c.wf); f(c.wt); }
   f(n->P); f(n->G); f(n->Mo); f(n->Vo); f(n->in); f(n->y); f(n->gy); f(n->gbuf0); f(n->gbuf1); f(n->gbuf2);
-  f(n->gpre); f(n->xT); f(n->gT); f(n->wpart); f(n->loss_part); f(n->loss_out);
+  f(n->gpre); f(n->xT); f(n->gT); f(n->wpart); f(n->bpart); f(n->loss_part); f(n->loss_out);
   for (auto* p : n->ha) f(p);
   for (auto* p : n->e) f(p);
   for (auto* p : n->a) f(p);
@@ -703,18 +984,49 @@ void conv3_dgrad(m1nn* n, int H, int W, const float* gpre, const ConvLayer& c, f
                                                     nullptr);
 }
 
-// weight and bias gradient of a conv3 layer from xT (cin x HW) and gT (cout x HW)
+// the K = 32 weight gradient applies when image rows are whole 8-pixel groups
+static bool wgrad_k32(int W) { return W % 8 == 0; }
+
+// pixel chunk of the K = 32 weight gradient: a multiple of 128 pixels (a 32-pixel step
+// for each of a block's four waves) such that blocks x chunks is about kWgradBlocks;
+// the number of chunks is at most max(1, kWgradBlocks / blocks)
+static int wgrad_chunk(int64_t HW, int blocks, int* nch) {
+  const int64_t target = std::max<int64_t>(1, kWgradBlocks / blocks);
+  int64_t chunk = (HW + target - 1) / target;
+  chunk = std::max<int64_t>(128, (chunk + 127) / 128 * 128);
+  *nch = (int)((HW + chunk - 1) / chunk);
+  return (int)chunk;
+}
+
+// pixels per block of the head weight gradient: at most 256 blocks
+static int head_ppb(int64_t npix) { return (int)std::max<int64_t>(256, ((npix + 255) / 256 + 255) / 256 * 256); }
+
+// weight and bias gradient of a conv3 layer from xT (cin x HW, or its three dx-shifted
+// copies for the K = 32 kernel) and gT (cout x HW)
 void conv3_wgrad(m1nn* n, int H, int W, const ConvLayer& c) {
-  const int HW = H * W;
-  const int chunk = 4096;
-  const int nch = (HW + chunk - 1) / chunk;
-  const int blocks = ((c.cout + 63) / 64) * ((c.cin + 63) / 64);
-  dim3 grd(blocks, 9, nch);
-  k_wgrad3<<<grd, 256, 0, n->stream>>>(H, W, n->xT, c.cin, n->gT, c.cout, chunk, n->wpart);
+  const int64_t HW = (int64_t)H * W;
   const int64_t nw = (int64_t)9 * c.cout * c.cin;
-  k_sum_chunks<<<grid_for(nw), 256, 0, n->stream>>>(n->wpart, nch, nw, n->G + c.woff);
+  if (wgrad_k32(W)) {
+    const int blocks = ((c.cout + 63) / 64) * ((c.cin + 15) / 16);
+    int nch = 0;
+    const int chunk = wgrad_chunk(HW, blocks, &nch);
+    k_wgrad3t<<<dim3(blocks, 1, nch), 256, 0, n->stream>>>(H, W, n->xT, c.cin, n->gT, c.cout, chunk, n->wpart,
+                                                            n->bpart);
+    k_sum_chunks<<<sum_grid(nw), 256, 0, n->stream>>>(n->wpart, nch, nw, n->G + c.woff);
+    k_sum_chunks<<<sum_grid(c.cout), 256, 0, n->stream>>>(n->bpart, nch, c.cout, n->G + c.boff);
+    return;
+  }
+  const int chunk = 4096;
+  const int nch = (int)((HW + chunk - 1) / chunk);
+  const int blocks = ((c.cout + 63) / 64) * ((c.cin + 63) / 64);
+  k_wgrad3<<<dim3(blocks, 9, nch), 256, 0, n->stream>>>(H, W, n->xT, c.cin, n->gT, c.cout, chunk, n->wpart);
+  k_sum_chunks<<<sum_grid(nw), 256, 0, n->stream>>>(n->wpart, nch, nw, n->G + c.woff);
   k_rowsum<<<c.cout, 256, 0, n->stream>>>(n->gT, HW, n->G + c.boff);
 }
+
+// the features the 1x1 head reads: the top decoder output, or with a single level
+// (no decoder) the top encoder output, as d_{L-1} = e_{L-1} at the bottom
+static const uint16_t* head_input(const m1nn* n) { return n->L > 1 ? n->d[0] : n->e[0]; }
 
 void forward_impl(m1nn* n, int H, int W) {
   const int L = n->L;
@@ -743,8 +1055,12 @@ void forward_impl(m1nn* n, int H, int W) {
     dnext = n->d[l];
   }
   const int64_t npix = (int64_t)H * W;
-  k_head_fwd<<<grid_for(npix), 256, 0, n->stream>>>(npix, n->d[0], n->ch[0], n->P + n->head_w, n->P + n->head_b,
-                                                    n->cout, n->y, n->skip);
+  if (n->cout <= 4)
+    k_head_fwd<4><<<grid_for(npix), 256, 0, n->stream>>>(npix, head_input(n), n->ch[0], n->P + n->head_w,
+                                                         n->P + n->head_b, n->cout, n->y, n->skip);
+  else
+    k_head_fwd<16><<<grid_for(npix), 256, 0, n->stream>>>(npix, head_input(n), n->ch[0], n->P + n->head_w,
+                                                          n->P + n->head_b, n->cout, n->y, n->skip);
 }
 
 // backward of o = relu(conv3(x)) given g = dL/do (FP32, H x W x cout):
@@ -752,8 +1068,15 @@ void forward_impl(m1nn* n, int H, int W) {
 void conv_layer_backward(m1nn* n, int H, int W, const float* g, const uint16_t* o, const uint16_t* x0, int C0,
                          int up0, const uint16_t* x1, int C1, const ConvLayer& c, float* gx) {
   const int64_t HW = (int64_t)H * W;
-  k_relu_grad<<<grid_for(HW * c.cout), 256, 0, n->stream>>>(HW, c.cout, g, o, n->gpre, n->gT);
-  k_to_chw<<<grid_for(HW * (C0 + C1)), 256, 0, n->stream>>>(H, W, x0, C0, up0, x1, C1, n->xT);
+  if (wgrad_k32(W)) {
+    const unsigned tiles = (unsigned)((HW + kTrPix - 1) / kTrPix);
+    k_relu_grad_t<<<dim3(tiles, (c.cout + kTrCh - 1) / kTrCh), 256, 0, n->stream>>>((int)HW, c.cout, g, o, n->gpre,
+                                                                                    n->gT);
+    k_to_chw3<<<dim3(tiles, (C0 + C1 + kTrCh - 1) / kTrCh), 256, 0, n->stream>>>(H, W, x0, C0, up0, x1, C1, n->xT);
+  } else {
+    k_relu_grad<<<grid_for(HW * c.cout), 256, 0, n->stream>>>(HW, c.cout, g, o, n->gpre, n->gT);
+    k_to_chw<<<grid_for(HW * (C0 + C1)), 256, 0, n->stream>>>(H, W, x0, C0, up0, x1, C1, n->xT);
+  }
   conv3_wgrad(n, H, W, c);
   if (gx) conv3_dgrad(n, H, W, n->gpre, c, gx);
 }
@@ -762,8 +1085,18 @@ void backward_impl(m1nn* n, int H, int W) {
   const int L = n->L;
   const int64_t npix = (int64_t)H * W;
   // head
-  k_head_dw<<<n->cout * (n->ch[0] + 1), 256, 0, n->stream>>>(npix, n->gy, n->cout, n->d[0], n->ch[0],
-                                                              n->G + n->head_w, n->G + n->head_b);
+  {
+    // head_b follows head_w in the slab: one sum over the partials writes both
+    const int ppb = head_ppb(npix);
+    const int nblk = (int)((npix + ppb - 1) / ppb);
+    const dim3 grd(nblk, n->ch[0] / 8);
+    if (n->cout <= 4)
+      k_head_dw_part<4><<<grd, 256, 0, n->stream>>>(npix, ppb, n->gy, n->cout, head_input(n), n->ch[0], n->wpart);
+    else
+      k_head_dw_part<16><<<grd, 256, 0, n->stream>>>(npix, ppb, n->gy, n->cout, head_input(n), n->ch[0], n->wpart);
+    const int64_t nh = (int64_t)n->cout * n->ch[0] + n->cout;
+    k_sum_chunks<<<sum_grid(nh), 256, 0, n->stream>>>(n->wpart, nblk, nh, n->G + n->head_w);
+  }
   float* gd = n->gbuf0;  // gradient w.r.t. d_l (FP32)
   k_head_dx<<<grid_for(npix * n->ch[0]), 256, 0, n->stream>>>(npix, n->gy, n->cout, n->P + n->head_w, n->ch[0], gd);
   // decoder, level 0 upward
@@ -891,11 +1224,19 @@ m1_status m1nn_create(int32_t cin, int32_t cout, int32_t levels, const int32_t* 
     if (good && l < levels - 1) good = alloc(n, &n->hd[l], hw * channels[l]) && alloc(n, &n->d[l], hw * channels[l]);
   }
   good = good && alloc(n, &n->gbuf0, HW * cmax) && alloc(n, &n->gbuf1, HW * cmax) && alloc(n, &n->gbuf2, HW * cmax) &&
-         alloc(n, &n->gpre, HW * cmax) && alloc(n, &n->xT, HW * cmax) && alloc(n, &n->gT, HW * cmax);
-  int64_t wmax = 0;
-  for (auto& c : n->conv) wmax = std::max(wmax, c.wsize);
-  n->wpart_len = ((HW + 4095) / 4096) * wmax;
-  good = good && alloc(n, &n->wpart, n->wpart_len) && alloc(n, &n->loss_part, 2 * 1024) && alloc(n, &n->loss_out, 2);
+         alloc(n, &n->gpre, HW * cmax) && alloc(n, &n->xT, 3 * HW * cmax) && alloc(n, &n->gT, HW * cmax);
+  // partial sums: the K = 32 weight gradient takes at most max(1, kWgradBlocks / blocks)
+  // chunks, the other one ceil(HW / 4096), the head at most 256 blocks
+  int64_t wlen = 256 * ((int64_t)cout * channels[0] + cout), blen = 0;
+  for (auto& c : n->conv) {
+    const int64_t blocks = ((c.cout + 63) / 64) * ((c.cin + 15) / 16);
+    const int64_t nk32 = std::max<int64_t>(1, kWgradBlocks / blocks);
+    wlen = std::max(wlen, c.wsize * std::max(nk32, (HW + 4095) / 4096));
+    blen = std::max(blen, (int64_t)c.cout * nk32);
+  }
+  n->wpart_len = wlen;
+  good = good && alloc(n, &n->wpart, n->wpart_len) && alloc(n, &n->bpart, blen) &&
+         alloc(n, &n->loss_part, 2 * 1024) && alloc(n, &n->loss_out, 2);
   if (!good) {
     nn_free(n);
     delete n;
@@ -1033,7 +1374,7 @@ m1_status m1nn_backward(m1nn* n, const float* x, const float* target, int32_t H,
   forward_impl(n, H, W);
   const int nb = (int)std::min<int64_t>(1024, (ny + 255) / 256);
   k_loss_part<<<nb, 256, 0, n->stream>>>(ny, n->y, target, n->loss_part);
-  k_loss_final<<<1, 64, 0, n->stream>>>(n->loss_part, nb, n->loss_out);
+  k_loss_final<<<1, 256, 0, n->stream>>>(n->loss_part, nb, n->loss_out);
   k_loss_grad<<<grid_for(ny), 256, 0, n->stream>>>(ny, n->y, target, n->loss_out, n->gy);
   backward_impl(n, H, W);
   double lh[2] = {0, 0};
