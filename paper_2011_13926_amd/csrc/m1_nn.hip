@@ -169,7 +169,6 @@ __global__ __launch_bounds__(256) void k_conv3t(int H, int W, const TIN* __restr
                                                 int relu, const int* __restrict__ skip) {
   constexpr int ROWS = 4 * RW;          // output rows of the block (RW per wave)
   constexpr int IR = ROWS + 2;          // input rows staged
-  if (skip && *skip) return;
   __shared__ __align__(16) uint16_t sx[IR * 66 * kCTP];
   __shared__ __align__(16) uint16_t swt[9 * 16 * NT * kCTP];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -187,36 +186,65 @@ __global__ __launch_bounds__(256) void k_conv3t(int H, int W, const TIN* __restr
 #pragma unroll
       for (int t = 0; t < NT; ++t) acc[q][g][t] = f32x4{0.f, 0.f, 0.f, 0.f};
   const bf16x8 zero = __builtin_bit_cast(bf16x8, make_uint4(0u, 0u, 0u, 0u));
-  for (int c0 = 0; c0 < Cin; c0 += kCT) {
-    __syncthreads();   // the previous slice is consumed
-    // input rows h0 - 1 .. h0 + ROWS, pixels pbase - 1 .. pbase + 64 (zero outside the
-    // image), channels c0 .. c0 + 31 in four 8-channel groups
-    for (int e = threadIdx.x; e < IR * 66 * 4; e += 256) {
+  // staging work per 32-channel slice: input rows h0 - 1 .. h0 + ROWS, pixels pbase - 1 ..
+  // pbase + 64 (zero outside the image), four 8-channel groups; the nine taps' weights of
+  // the block's output channels, swt[tap][col][ci].  A thread issues all of its loads
+  // before it stores any, and the next slice's loads are issued before the current
+  // slice's MFMAs, so the slices' memory round trips overlap the arithmetic.
+  constexpr int NIN = IR * 66 * 4, NWT = 9 * 16 * NT * 4;
+  constexpr int PIN = (NIN + 255) / 256, PWT = (NWT + 255) / 256;
+  bf16x8 vin[PIN];
+  uint4 vwt[PWT];
+  auto load_slice = [&](int c0) {
+#pragma unroll
+    for (int it = 0; it < PIN; ++it) {
+      const int e = threadIdx.x + it * 256;
       const int grp = e & 3, pix = e >> 2;
       const int r = pix / 66, p = pix - r * 66;
       const int hh = h0 - 1 + r, ww = pbase - 1 + p;
       const int k = c0 + grp * 8;
-      bf16x8 v = zero;
-      if (k < Cin && hh >= 0 && hh < H && ww >= 0 && ww < W) {
+      vin[it] = zero;
+      if (e < NIN && k < Cin && hh >= 0 && hh < H && ww >= 0 && ww < W) {
         if (k < C0) {
           const int sh = up0 ? (hh >> 1) : hh, sw0 = up0 ? (ww >> 1) : ww;
-          v = load8(x0 + ((int64_t)sh * W0 + sw0) * C0 + k);
+          vin[it] = load8(x0 + ((int64_t)sh * W0 + sw0) * C0 + k);
         } else {
-          v = load8(x1 + ((int64_t)hh * W + ww) * C1 + (k - C0));
+          vin[it] = load8(x1 + ((int64_t)hh * W + ww) * C1 + (k - C0));
         }
       }
-      *reinterpret_cast<bf16x8*>(sx + pix * kCTP + grp * 8) = v;
     }
-    // weights of the nine taps for the block's output channels: swt[tap][col][ci]
-    for (int e = threadIdx.x; e < 9 * 16 * NT * 4; e += 256) {
+#pragma unroll
+    for (int it = 0; it < PWT; ++it) {
+      const int e = threadIdx.x + it * 256;
       const int grp = e & 3, row = e >> 2;
       const int tap = row / (16 * NT), col = row - tap * (16 * NT);
       const int co = co_base + col, k = c0 + grp * 8;
-      uint4 v = make_uint4(0u, 0u, 0u, 0u);
-      if (co < Cout && k < Cin) v = *reinterpret_cast<const uint4*>(w + ((int64_t)tap * Cout + co) * Cin + k);
-      *reinterpret_cast<uint4*>(swt + row * kCTP + grp * 8) = v;
+      vwt[it] = make_uint4(0u, 0u, 0u, 0u);
+      if (e < NWT && co < Cout && k < Cin) vwt[it] = *reinterpret_cast<const uint4*>(w + ((int64_t)tap * Cout + co) * Cin + k);
+    }
+  };
+  load_slice(0);
+  float bv[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int co = co_base + t * 16 + (lane & 15);
+    bv[t] = (bias && co < Cout) ? bias[co] : 0.f;
+  }
+  if (skip && *skip) return;   // the flag is uniform: the whole block leaves
+  for (int c0 = 0; c0 < Cin; c0 += kCT) {
+    __syncthreads();   // the previous slice is consumed
+#pragma unroll
+    for (int it = 0; it < PIN; ++it) {
+      const int e = threadIdx.x + it * 256;
+      if (e < NIN) *reinterpret_cast<bf16x8*>(sx + (e >> 2) * kCTP + (e & 3) * 8) = vin[it];
+    }
+#pragma unroll
+    for (int it = 0; it < PWT; ++it) {
+      const int e = threadIdx.x + it * 256;
+      if (e < NWT) *reinterpret_cast<uint4*>(swt + (e >> 2) * kCTP + (e & 3) * 8) = vwt[it];
     }
     __syncthreads();
+    if (c0 + kCT < Cin) load_slice(c0 + kCT);
 #pragma unroll
     for (int tap = 0; tap < 9; ++tap) {
       const int dy = tap / 3, dx = tap % 3;
@@ -246,7 +274,7 @@ __global__ __launch_bounds__(256) void k_conv3t(int H, int W, const TIN* __restr
     for (int t = 0; t < NT; ++t) {
       const int co = co_base + t * 16 + (lane & 15);
       if (co >= Cout) continue;
-      const float b = bias ? bias[co] : 0.f;
+      const float b = bv[t];
 #pragma unroll
       for (int g = 0; g < 4; ++g)
 #pragma unroll
@@ -262,12 +290,21 @@ __global__ __launch_bounds__(256) void k_conv3t(int H, int W, const TIN* __restr
 }
 
 // output-channel tiles per block for Cout channels: 16 NT channels, NT <= 4
-static inline int conv_nt(int cout) { return cout >= 64 ? 4 : (cout + 15) / 16; }
+// output-channel tile (16 nt channels) of a convolution: the widest that covers Cout,
+// narrowed while the launch has fewer than 256 blocks (the lower levels of the network
+// would otherwise leave most CUs idle: 16 blocks for 64 x 64 channels at 64^2)
+static inline int conv_nt(int H, int W, int cout) {
+  int nt = cout >= 64 ? 4 : (cout + 15) / 16;
+  const int64_t px_blocks =
+      (int64_t)((W + 63) / 64) * ((H + 4 * kConvRowsPerWave - 1) / (4 * kConvRowsPerWave));
+  while (nt > 1 && px_blocks * ((cout + 16 * nt - 1) / (16 * nt)) < 256) nt = nt == 4 ? 2 : 1;
+  return nt;
+}
 
 template <typename TIN, typename TOUT>
 static void launch_conv3t(int H, int W, const TIN* x0, int C0, int up0, const TIN* x1, int C1, const uint16_t* w,
                           const float* bias, int Cout, TOUT* y, int relu, const int* skip, hipStream_t s) {
-  const int nt = conv_nt(Cout);
+  const int nt = conv_nt(H, W, Cout);
   constexpr int RW = kConvRowsPerWave;
   dim3 grd((W + 63) / 64, (H + 4 * RW - 1) / (4 * RW), (Cout + 16 * nt - 1) / (16 * nt));
   switch (nt) {

@@ -155,9 +155,13 @@ def test_mfma_network_gradients_match_oracle(H, Wd):
 # kernel for any width; 40x24 and 72x64 the one for widths in whole 8-pixel groups, the
 # latter over two pixel chunks; 40 input channels pad to 48 and 80 output channels
 # span two 64-channel blocks, both partial; 6 outputs take the head gradient kernel
-# for more than 4 output channels.
+# for more than 4 output channels.  The convolution narrows its output-channel tile on
+# small images; 64x512 and 64x1024 are large enough to keep the 32-, 48- and 64-channel
+# tiles (forward and input gradient).
 @pytest.mark.parametrize("cin,ch,cout,H,Wd", [(9, [32], 3, 33, 37), (40, [48], 3, 40, 24),
-                                              (40, [80], 3, 72, 64), (64, [64], 6, 16, 8)])
+                                              (40, [80], 3, 72, 64), (64, [64], 6, 16, 8),
+                                              (9, [32], 3, 64, 512), (9, [48], 3, 64, 1024),
+                                              (64, [64], 3, 64, 1024)])
 def test_single_level_network_gradients_match_oracle(cin, ch, cout, H, Wd):
     _say(f"nn one-level gradients cin {cin} ch {ch} cout {cout} {H}x{Wd}")
     params, flat = _random_net_params(11, cin, ch, cout)
