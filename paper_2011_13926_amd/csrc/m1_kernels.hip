@@ -1155,11 +1155,18 @@ __global__ __launch_bounds__(LX * TR) void k_mg_sweep2d_x2(Geom g, Scheme sc, Co
   }, sx0, sq0, ss0);
   __syncthreads();
   // ---- first sweep on the tile and its ring (grid cells only; ghosts below) ----
-  for (int t = threadIdx.x; t < LHX * (TR + 2); t += (LX * TR)) {
-    const int pi = t % LHX, pj = t / LHX;
+  // Thread t sweeps its own tile cell first (the cell of its second application) and,
+  // for t < the ring's 2 (LX + 2) + 2 TR positions, one ring cell.  In FP32 the own
+  // cell's face coefficients, right-hand side and block inverse stay in registers for
+  // the second application instead of being read again.
+  constexpr bool KEEP = sizeof(R) == 4;
+  constexpr int NRING = 2 * LHX + 2 * TR;
+  const int tx = threadIdx.x % LX, ty = threadIdx.x / LX;
+  R kf[KEEP ? 12 : 1], kr[KEEP ? NU : 1], kb[KEEP ? NU * NU : 1];
+  auto sweep1 = [&](int pi, int pj, bool keep) {
     int gi = tbx * LX - 1 + pi, gj = tby * TR - 1 + pj;
     const bool outx = gi < 0 || gi >= nx, outy = gj < 0 || gj >= ny;
-    if ((outx && !perx) || (outy && !pery)) continue;   // ghost or unused corner
+    if ((outx && !perx) || (outy && !pery)) return;   // ghost or unused corner
     if (outx) gi = (gi + nx) % nx;
     if (outy) gj = (gj + ny) % ny;
     const int64_t cell = (int64_t)gj * nx + gi;
@@ -1170,15 +1177,20 @@ __global__ __launch_bounds__(LX * TR) void k_mg_sweep2d_x2(Geom g, Scheme sc, Co
     R fr[12];
     faces2d(g, cf, gi, gj, cell, fr);
     apply2d_cell<CPL, (TR + 4), (LX + 4), R>(g, sc, cf, sx0, sq0, ss0, pi + 1, pj + 1, gi, gj, cell, fr, xs, ys);
+    R rv[NU], bj[NU * NU];
+#pragma unroll
+    for (int k = 0; k < NU; ++k) rv[k] = (R)r[k * N + cell];
+#pragma unroll
+    for (int k = 0; k < NU * NU; ++k) bj[k] = cf.bjinv[k * N + cell];
     R res[NU];
 #pragma unroll
-    for (int k = 0; k < NU; ++k) res[k] = (R)r[k * N + cell] - ys[k];
+    for (int k = 0; k < NU; ++k) res[k] = rv[k] - ys[k];
     R x1[NU];
 #pragma unroll
     for (int rr = 0; rr < NU; ++rr) {
       R acc = (R)0;
 #pragma unroll
-      for (int k = 0; k < NU; ++k) acc += cf.bjinv[(rr * NU + k) * N + cell] * res[k];
+      for (int k = 0; k < NU; ++k) acc += bj[rr * NU + k] * res[k];
       x1[rr] = xs[rr] + omega * acc;
     }
 #pragma unroll
@@ -1192,6 +1204,24 @@ __global__ __launch_bounds__(LX * TR) void k_mg_sweep2d_x2(Geom g, Scheme sc, Co
     }
     ss1[pj][pi] = ss0[pj + 1][pi + 1];
     if (CPL) sT1[pj][pi] = x1[NU - 1];
+    if (KEEP && keep) {
+#pragma unroll
+      for (int k = 0; k < 12; ++k) kf[k % (KEEP ? 12 : 1)] = fr[k];
+#pragma unroll
+      for (int k = 0; k < NU; ++k) kr[k % (KEEP ? NU : 1)] = rv[k];
+#pragma unroll
+      for (int k = 0; k < NU * NU; ++k) kb[k % (KEEP ? NU * NU : 1)] = bj[k];
+    }
+  };
+  sweep1(tx + 1, ty + 1, true);
+  if ((int)threadIdx.x < NRING) {
+    const int k = threadIdx.x;
+    int pi, pj;
+    if (k < LHX) { pi = k; pj = 0; }
+    else if (k < 2 * LHX) { pi = k - LHX; pj = TR + 1; }
+    else if (k < 2 * LHX + TR) { pi = 0; pj = k - 2 * LHX + 1; }
+    else { pi = LHX - 1; pj = k - 2 * LHX - TR + 1; }
+    sweep1(pi, pj, false);
   }
   __syncthreads();
   // ---- ghosts of the swept boundary cells (the positions just beyond a non-periodic
@@ -1234,7 +1264,6 @@ __global__ __launch_bounds__(LX * TR) void k_mg_sweep2d_x2(Geom g, Scheme sc, Co
   }
   __syncthreads();
   // ---- second application on the tile ----
-  const int tx = threadIdx.x % LX, ty = threadIdx.x / LX;
   const int i = tbx * LX + tx, j = tby * TR + ty;
   const bool inside = i < nx && j < ny;
   const int64_t cell = (int64_t)j * nx + i;
@@ -1246,16 +1275,22 @@ __global__ __launch_bounds__(LX * TR) void k_mg_sweep2d_x2(Geom g, Scheme sc, Co
     for (int c = 0; c < NR; ++c) xs[c] = sx1[c][lj][li];
     if (CPL) xs[NU - 1] = sT1[lj][li];
     R fc[12];
-    faces2d(g, cf, i, j, cell, fc);   // read by the first sweep just before: cache hits
+    if (KEEP) {
+#pragma unroll
+      for (int k = 0; k < 12; ++k) fc[k] = kf[k % (KEEP ? 12 : 1)];
+    } else {
+      faces2d(g, cf, i, j, cell, fc);   // read by the first sweep just before: cache hits
+    }
     apply2d_cell<CPL, (TR + 2), LHX, R>(g, sc, cf, sx1, sq1, ss1, li, lj, i, j, cell, fc, xs, ys);
 #pragma unroll
-    for (int k = 0; k < NU; ++k) res[k] = (R)r[k * N + cell] - ys[k];
+    for (int k = 0; k < NU; ++k) res[k] = (KEEP ? kr[k % (KEEP ? NU : 1)] : (R)r[k * N + cell]) - ys[k];
     if (OP == 0) {
 #pragma unroll
       for (int rr = 0; rr < NU; ++rr) {
         R acc = (R)0;
 #pragma unroll
-        for (int k = 0; k < NU; ++k) acc += cf.bjinv[(rr * NU + k) * N + cell] * res[k];
+        for (int k = 0; k < NU; ++k)
+          acc += (KEEP ? kb[(rr * NU + k) % (KEEP ? NU * NU : 1)] : cf.bjinv[(rr * NU + k) * N + cell]) * res[k];
         out[rr * N + cell] = xs[rr] + omega * acc;
       }
     }
