@@ -74,8 +74,9 @@ def test_learned_preconditioner_on_heldout_diffusive_field(seed):
     fields 1000-1003 the flexible solve converges without falling back, needs fewer GMRES
     iterations than block-Jacobi (the network is applied to each cycle's restart
     residual; measured 190/195/152/196 against 203/229/194/229), and meets the same
-    true-residual tolerance.  (It is not faster: a 256^2 forward pass costs about as much
-    as the iterations it saves.)"""
+    true-residual tolerance.  (It is not faster: measured solve times are 1.00-1.11x the
+    block-Jacobi ones, a network application at 256^2 costing about as much as the
+    iterations it saves.)"""
     import torch
     import paper_2011_13926_amd as P
     p = W.diffusive_lognormal(n=(256, 256), seed=seed)
