@@ -285,7 +285,9 @@ __global__ __launch_bounds__(kGjThreads) void k_mg_dense_inverse_reg(MgGeom g, c
   constexpr int BS = NU * NU;
   const int N = (int)g.N;
   const int n = NU * N;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // the wave index as a scalar: it and every address derived from it stay out of the
+  // vector registers (which the matrix fills)
+  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   __shared__ double s_cv[2][16];
   __shared__ int s_ci[2][16];
   __shared__ double s_prow[2][kGjRegMax];
