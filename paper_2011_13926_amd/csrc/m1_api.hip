@@ -35,8 +35,11 @@ struct Profiler {
   // iter >= 0: a launch inside a GMRES cycle that may have returned at once after
   // the cycle converged; resolved against the cycle's column count (prof_resolve).
   // phase 0: before the Hessenberg step of iteration `iter`, 1: after it, 2: final step.
-  struct Rec { int kc; hipEvent_t a, b; double bytes; int iter; int phase; bool valid; };
+  // n: launches the record spans (consecutive launches of one multigrid class share
+  // one event pair; see timed)
+  struct Rec { int kc; hipEvent_t a, b; double bytes; int iter; int phase; bool valid; int n; };
   std::vector<Rec> pending;
+  int open = -1;   // index in pending of a record whose end event is not yet recorded
   int64_t seen[KC_COUNT] = {};   // launches issued while profiling, sampled or not
   int64_t launches[KC_COUNT] = {};
   double ms[KC_COUNT] = {};
@@ -130,6 +133,24 @@ bool per_iteration_class(int kc) {
          kc == KC_APPLY_PC || kc == KC_MG_FINE || kc == KC_MG_SMOOTH || kc == KC_MG_DOWN || kc == KC_MG_COARSE;
 }
 
+// The multigrid classes come in runs of consecutive launches (a cycle's finest-level
+// sweeps of one leg, its restrictions, its prolongations): a sampled launch of such a
+// class keeps its interval open, and the following launches of the same class join it
+// until another launch or prof_close ends it.  One event pair then spans several
+// kernels, so the dispatch that the events add is spread over them instead of being
+// charged to each.
+bool grouped_class(int kc) {
+  return kc == KC_MG_FINE || kc == KC_MG_SMOOTH || kc == KC_MG_DOWN || kc == KC_MG_COARSE;
+}
+
+// end an open interval (before any stream work that is not launched through timed)
+void prof_close(m1_ctx* c) {
+  Profiler& p = c->prof;
+  if (p.open < 0) return;
+  hipEventRecord(p.pending[p.open].b, c->stream);
+  p.open = -1;
+}
+
 // Launch with optional HIP-event timing; `bytes` is the launch's algorithmic
 // HBM traffic (each array element the kernel must read or write, once).
 template <typename F>
@@ -138,7 +159,19 @@ void timed(m1_ctx* c, int kc, double bytes, F&& launch, int iter = -1, int phase
     launch();
     return;
   }
-  const int64_t seq = c->prof.seen[kc]++;
+  Profiler& p = c->prof;
+  if (p.open >= 0) {
+    Profiler::Rec& r = p.pending[p.open];
+    if (r.kc == kc && r.iter == iter && r.phase == phase) {
+      p.seen[kc]++;
+      launch();
+      r.bytes += bytes;
+      r.n += 1;
+      return;
+    }
+    prof_close(c);
+  }
+  const int64_t seq = p.seen[kc]++;
   if (per_iteration_class(kc) && seq % 13 != 0) {
     launch();
     return;
@@ -146,8 +179,10 @@ void timed(m1_ctx* c, int kc, double bytes, F&& launch, int iter = -1, int phase
   hipEvent_t a = prof_event(c), b = prof_event(c);
   if (a) hipEventRecord(a, c->stream);
   launch();
-  if (b) hipEventRecord(b, c->stream);
-  if (a && b) c->prof.pending.push_back({kc, a, b, bytes, iter, phase, true});
+  if (!(a && b)) return;
+  p.pending.push_back({kc, a, b, bytes, iter, phase, true, 1});
+  if (grouped_class(kc)) p.open = (int)p.pending.size() - 1;
+  else hipEventRecord(b, c->stream);
 }
 
 // Drop the records of launches that returned at once because the cycle had
@@ -162,12 +197,13 @@ void prof_resolve(m1_ctx* c, int k, int steps) {
 
 void prof_collect(m1_ctx* c) {
   Profiler& p = c->prof;
+  prof_close(c);   // normally closed before the synchronisation that precedes this
   if (p.pending.empty()) return;
   hipEventSynchronize(p.pending.back().b);
   for (auto& r : p.pending) {
     float ms = 0.f;
     if (r.valid && hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
-      p.launches[r.kc] += 1;
+      p.launches[r.kc] += r.n;
       p.ms[r.kc] += ms;
       p.bytes[r.kc] += r.bytes;
     }
@@ -677,6 +713,7 @@ m1_status gmres(m1_ctx* c, double bnorm, SolveResult& res, const Coefs<R>& cfi) 
       {
         const MgWrap wrap = [&](int kc, double bytes, const std::function<void()>& launch) { timed(c, kc, bytes, launch); };
         mg_vcycle<R, double>(c->mg, mgf, c->xw, z, c->stream, nullptr, c->prof.on ? &wrap : nullptr);
+        prof_close(c);
       }
       mg_axpy<R>(z, c->x, n, c->stream);
     } else {
@@ -691,6 +728,7 @@ m1_status gmres(m1_ctx* c, double bnorm, SolveResult& res, const Coefs<R>& cfi) 
       launch_reduce(c->part, 1, c->nb, c->dscal + 1, c->stream);
     });
     HIPCHK(c, hipGetLastError());
+    prof_close(c);
     HIPCHK(c, hipMemcpyAsync(c->hscal, c->dscal + 1, sizeof(double), hipMemcpyDeviceToHost, c->stream));
     int hk[4];
     HIPCHK(c, hipMemcpyAsync(hk, c->gs, sizeof(int) * 4, hipMemcpyDeviceToHost, c->stream));
@@ -1235,6 +1273,7 @@ m1_status m1_precondition(m1_ctx* c, const double* r, double* z) {
     const MgFine<double> f = mg_fine<double>(c);
     const MgWrap wrap = [&](int kc, double bytes, const std::function<void()>& launch) { timed(c, kc, bytes, launch); };
     mg_vcycle<double, double>(c->mg, f, r, z, c->stream, nullptr, c->prof.on ? &wrap : nullptr);
+    prof_close(c);
   } else {
     timed(c, KC_BJ, bytes_bj(c, 8, 8, 8), [&] { launch_bj<double, double, double>(c->nd, c->cpl, c->g, c->cf64, r, z, c->stream); });
   }
