@@ -166,7 +166,7 @@ template <int NT, int RW, typename TIN, typename TOUT>
 __global__ __launch_bounds__(256) void k_conv3t(int H, int W, const TIN* __restrict__ x0, int C0, int up0,
                                                 const TIN* __restrict__ x1, int C1, const uint16_t* __restrict__ w,
                                                 const float* __restrict__ bias, int Cout, TOUT* __restrict__ y,
-                                                int relu, const int* __restrict__ skip) {
+                                                int relu, const int* __restrict__ skip, TOUT* __restrict__ ypool) {
   constexpr int ROWS = 4 * RW;          // output rows of the block (RW per wave)
   constexpr int IR = ROWS + 2;          // input rows staged
   __shared__ __align__(16) uint16_t sx[IR * 66 * kCTP];
@@ -287,6 +287,61 @@ __global__ __launch_bounds__(256) void k_conv3t(int H, int W, const TIN* __restr
         }
     }
   }
+  if (RW == 1 && ypool) {
+    // 2 x 2 average pooling of the stored (rounded) output into ypool (H/2 x W/2), in
+    // the order of the separate pooling kernel: s = 0; s += y(2i, 2j), y(2i, 2j+1),
+    // y(2i+1, 2j), y(2i+1, 2j+1); out = round(s / 4).  Wave w holds row h0 + w: the odd
+    // wave of each pair passes its rounded values to the even one through the input
+    // tile's LDS, which the last slice's MFMAs no longer read.
+    uint16_t* xch = sx;   // [2 pairs][4 pixel groups][NT][4][64 lanes]
+    const int pair = wv >> 1;
+    __syncthreads();
+    if (wv & 1) {
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const int co = co_base + t * 16 + (lane & 15);
+        const float b = bv[t];
+#pragma unroll
+        for (int g = 0; g < 4; ++g)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            float v = acc[0][g][t][r] + b;
+            if (relu) v = fmaxf(v, 0.f);
+            xch[(((pair * 4 + g) * NT + t) * 4 + r) * 64 + lane] = co < Cout ? f2bf(v) : (uint16_t)0;
+          }
+      }
+    }
+    __syncthreads();
+    const int h = h0 + wv;
+    if (!(wv & 1) && h + 1 < H) {
+      const int Wo = W >> 1;
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const int co = co_base + t * 16 + (lane & 15);
+        if (co >= Cout) continue;
+        const float b = bv[t];
+#pragma unroll
+        for (int g = 0; g < 4; ++g)
+#pragma unroll
+          for (int r = 0; r < 4; r += 2) {
+            const int px = pbase + g * 16 + (lane >> 4) * 4 + r;
+            if (px + 1 >= W) continue;
+            float v0 = acc[0][g][t][r] + b, v1 = acc[0][g][t][r + 1] + b;
+            if (relu) {
+              v0 = fmaxf(v0, 0.f);
+              v1 = fmaxf(v1, 0.f);
+            }
+            const int base = (((pair * 4 + g) * NT + t) * 4 + r) * 64 + lane;
+            float sum = 0.f;
+            sum += bf2f(f2bf(v0));
+            sum += bf2f(f2bf(v1));
+            sum += bf2f(xch[base]);
+            sum += bf2f(xch[base + 64]);
+            store1(ypool + ((int64_t)(h >> 1) * Wo + (px >> 1)) * Cout + co, 0.25f * sum);
+          }
+      }
+    }
+  }
 }
 
 // output-channel tiles per block for Cout channels: 16 NT channels, NT <= 4
@@ -303,15 +358,16 @@ static inline int conv_nt(int H, int W, int cout) {
 
 template <typename TIN, typename TOUT>
 static void launch_conv3t(int H, int W, const TIN* x0, int C0, int up0, const TIN* x1, int C1, const uint16_t* w,
-                          const float* bias, int Cout, TOUT* y, int relu, const int* skip, hipStream_t s) {
+                          const float* bias, int Cout, TOUT* y, int relu, const int* skip, hipStream_t s,
+                          TOUT* ypool = nullptr) {
   const int nt = conv_nt(H, W, Cout);
   constexpr int RW = kConvRowsPerWave;
   dim3 grd((W + 63) / 64, (H + 4 * RW - 1) / (4 * RW), (Cout + 16 * nt - 1) / (16 * nt));
   switch (nt) {
-    case 1: k_conv3t<1, RW, TIN, TOUT><<<grd, 256, 0, s>>>(H, W, x0, C0, up0, x1, C1, w, bias, Cout, y, relu, skip); break;
-    case 2: k_conv3t<2, RW, TIN, TOUT><<<grd, 256, 0, s>>>(H, W, x0, C0, up0, x1, C1, w, bias, Cout, y, relu, skip); break;
-    case 3: k_conv3t<3, RW, TIN, TOUT><<<grd, 256, 0, s>>>(H, W, x0, C0, up0, x1, C1, w, bias, Cout, y, relu, skip); break;
-    default: k_conv3t<4, RW, TIN, TOUT><<<grd, 256, 0, s>>>(H, W, x0, C0, up0, x1, C1, w, bias, Cout, y, relu, skip); break;
+    case 1: k_conv3t<1, RW, TIN, TOUT><<<grd, 256, 0, s>>>(H, W, x0, C0, up0, x1, C1, w, bias, Cout, y, relu, skip, ypool); break;
+    case 2: k_conv3t<2, RW, TIN, TOUT><<<grd, 256, 0, s>>>(H, W, x0, C0, up0, x1, C1, w, bias, Cout, y, relu, skip, ypool); break;
+    case 3: k_conv3t<3, RW, TIN, TOUT><<<grd, 256, 0, s>>>(H, W, x0, C0, up0, x1, C1, w, bias, Cout, y, relu, skip, ypool); break;
+    default: k_conv3t<4, RW, TIN, TOUT><<<grd, 256, 0, s>>>(H, W, x0, C0, up0, x1, C1, w, bias, Cout, y, relu, skip, ypool); break;
   }
 }
 
@@ -998,16 +1054,19 @@ static bool use_k32(int cin) {
   return v == 1 && cin % 16 == 0;
 }
 
-void conv3(m1nn* n, int H, int W, const uint16_t* x0, int C0, int up0, const uint16_t* x1, int C1, const ConvLayer& c,
-           uint16_t* y, int relu) {
+// y = relu(conv3(x)); with ypool (H and W even), also its 2 x 2 average pooling.
+// Returns whether ypool was written (the K = 16 kernel leaves it to the caller).
+bool conv3(m1nn* n, int H, int W, const uint16_t* x0, int C0, int up0, const uint16_t* x1, int C1, const ConvLayer& c,
+           uint16_t* y, int relu, uint16_t* ypool = nullptr) {
   if (use_k32(C0 + C1) && C0 % 8 == 0) {
     launch_conv3t<uint16_t, uint16_t>(H, W, x0, C0, up0, x1, C1, c.wf, n->P + c.boff, c.cout, y, relu, n->skip,
-                                      n->stream);
-    return;
+                                      n->stream, ypool);
+    return ypool != nullptr;
   }
   dim3 grd((W + 63) / 64, H, (c.cout + 63) / 64);
   k_conv3<uint16_t, uint16_t><<<grd, 256, 0, n->stream>>>(H, W, x0, C0, up0, x1, C1, c.wf, n->P + c.boff, c.cout, y,
                                                           relu, n->skip);
+  return false;
 }
 
 // input gradient of a conv3 layer: gx (H, W, cin) FP32 from gpre (H, W, cout) FP32
@@ -1074,10 +1133,13 @@ void forward_impl(m1nn* n, int H, int W) {
     const ConvLayer& ca = n->conv[conv_index(n, 'e', l, 0)];
     const ConvLayer& cb = n->conv[conv_index(n, 'e', l, 1)];
     conv3(n, Hl, Wl, a, cprev, 0, nullptr, 0, ca, n->ha[l], 1);
-    conv3(n, Hl, Wl, n->ha[l], n->ch[l], 0, nullptr, 0, cb, n->e[l], 1);
+    // the level's output, pooled in the same launch for the next level
+    const bool pooled = conv3(n, Hl, Wl, n->ha[l], n->ch[l], 0, nullptr, 0, cb, n->e[l], 1,
+                              l < L - 1 ? n->a[l + 1] : nullptr);
     if (l < L - 1) {
       const int64_t cnt = (int64_t)(Hl / 2) * (Wl / 2) * n->ch[l];
-      k_pool2<<<grid_for(cnt), 256, 0, n->stream>>>(Hl / 2, Wl / 2, n->ch[l], n->e[l], n->a[l + 1], n->skip);
+      if (!pooled)
+        k_pool2<<<grid_for(cnt), 256, 0, n->stream>>>(Hl / 2, Wl / 2, n->ch[l], n->e[l], n->a[l + 1], n->skip);
       a = n->a[l + 1];
       cprev = n->ch[l];
     }
