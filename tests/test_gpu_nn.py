@@ -179,6 +179,27 @@ def test_single_level_network_gradients_match_oracle(cin, ch, cout, H, Wd):
     _say(f"  worst per-tensor gradient error / tolerance: {worst:.2f}")
 
 
+# two levels at 64x1024: the top level keeps its 32-, 48- and 64-channel output tiles
+# (256 pixel blocks), so the pooling written by the second convolution's epilogue is
+# checked on the tile widths the 512^2 network uses
+@pytest.mark.parametrize("ch", [[32, 48], [48, 64], [64, 64]])
+def test_two_level_network_wide_tiles_match_oracle(ch):
+    _say(f"nn two-level {ch} 64x1024")
+    params, flat = _random_net_params(21, CIN, ch)
+    rng = np.random.default_rng(22)
+    x = rng.standard_normal((64, 1024, CIN)).astype(np.float32)
+    t = rng.standard_normal((64, 1024, COUT)).astype(np.float32)
+    y, loss, g = _gpu_forward_backward(flat, x, t, CIN, ch, COUT)
+    x64, t64 = x.astype(np.float64), t.astype(np.float64)
+    yref, lref, gref = _oracle(params, x64, t64, ch)
+    fspread, spread = _rounding_spread(params, x64, t64, ch)
+    _say(f"  forward {_rel(y, yref):.2e}, oracle rounding spread {fspread:.2e}")
+    assert _rel(y, yref) <= 2 * fspread + 1e-4
+    assert loss == pytest.approx(lref, rel=1e-3)
+    worst = _check_grads(g, gref, CIN, ch, COUT, lambda k: 2 * spread[k] + BF16_GRAD_TOL)
+    _say(f"  worst per-tensor gradient error / tolerance: {worst:.2f}")
+
+
 def test_adam_step_matches_oracle():
     """Two Adam steps on the GPU (FP32 master weights and moments) against the oracle's
     Adam in FP64 fed with the same gradients."""
